@@ -1,0 +1,145 @@
+"""FP64 CPU oracle of the CollisionSplatting metric — TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  It wraps `oracle.c` (plain C + OpenMP,
+double precision) with ctypes and numpy; it shares nothing with the HIP
+library.  See `oracle.c` for the definition and its citations of the paper.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_HDR = os.path.join(_HERE, "oracle.h")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (-O2, OpenMP, strict IEEE: no fast-math)."""
+    if force or not os.path.exists(_LIB) or \
+            os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_HDR)):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Reduce(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("tau", ctypes.c_double), ("r_nbr", ctypes.c_double),
+                ("d_max", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("s_min", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or \
+                os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_HDR)):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_prepare_scene.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_int,
+                                             ctypes.c_double, ctypes.c_double, P, P, P, P]
+        lib.oracle_prepare_scene.restype = ctypes.c_int
+        lib.oracle_eval.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, P, ctypes.c_int32,
+                                    P, ctypes.POINTER(_Reduce)] + [P] * 12 + [ctypes.c_int]
+        lib.oracle_eval.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def prepare_scene(means, quats, scales, opacity, raw_mode=False, alpha_f=0.0, extent_f=0.0):
+    """Returns (kept_index, mu (n,3) f64, sigma (n,3,3) f64)."""
+    lib = _load()
+    means = np.ascontiguousarray(means, np.float32)
+    quats = np.ascontiguousarray(quats, np.float32)
+    scales = np.ascontiguousarray(scales, np.float32)
+    opacity = np.ascontiguousarray(opacity, np.float32)
+    n = means.shape[0]
+    kept = np.empty(n, np.int64)
+    mu = np.empty((max(n, 1), 3), np.float64)
+    sig = np.empty((max(n, 1), 9), np.float64)
+    nk = ctypes.c_int64(0)
+    rc = lib.oracle_prepare_scene(n, _ptr(means), _ptr(quats), _ptr(scales), _ptr(opacity),
+                                  int(bool(raw_mode)), float(alpha_f), float(extent_f),
+                                  ctypes.byref(nk), _ptr(kept), _ptr(mu), _ptr(sig))
+    if rc != 0:
+        raise OracleError(f"oracle_prepare_scene failed ({rc})")
+    k = nk.value
+    return kept[:k].copy(), mu[:k].copy(), sig[:k].reshape(k, 3, 3).copy()
+
+
+def sphere_bodies(radii):
+    """A_j = I / r_j^2 (Eq. 6 with a = b = c = r), in double precision."""
+    r = np.asarray(radii, np.float64)
+    A = np.zeros((r.size, 3, 3))
+    inv = 1.0 / (r * r)
+    A[:, 0, 0] = inv
+    A[:, 1, 1] = inv
+    A[:, 2, 2] = inv
+    return A
+
+
+def ellipsoid_bodies(rot, semi_axes):
+    """A_j = R_E diag(1/a^2, 1/b^2, 1/c^2) R_E^T (Eq. 5-6)."""
+    rot = np.asarray(rot, np.float64)
+    ax = np.asarray(semi_axes, np.float64)
+    P = np.zeros(ax.shape[:-1] + (3, 3))
+    for k in range(3):
+        P[..., k, k] = 1.0 / (ax[..., k] ** 2)
+    return rot @ P @ np.swapaxes(rot, -1, -2)
+
+
+def evaluate(mu, sigma, centers, A, n_sigma, k=0, tau=0.0, r_nbr=math.inf, d_max=1.0,
+             gamma=1.0, s_min=1.0, eps=1e-5, nthreads=0):
+    """Evaluate all outputs.  Returns a dict of (q, m) arrays plus `nbr` (q,)."""
+    lib = _load()
+    mu = np.ascontiguousarray(mu, np.float64).reshape(-1, 3)
+    sigma = np.ascontiguousarray(sigma, np.float64).reshape(-1, 9)
+    centers = np.ascontiguousarray(centers, np.float64).reshape(-1, 3)
+    A = np.ascontiguousarray(A, np.float64).reshape(-1, 9)
+    ns = np.ascontiguousarray(np.atleast_1d(n_sigma), np.float64)
+    n, q, m = mu.shape[0], centers.shape[0], ns.size
+    if A.shape[0] != q:
+        raise ValueError("one body matrix per query")
+    out = dict(count=np.zeros((q, m), np.int32), label=np.zeros((q, m), np.uint8),
+               min=np.zeros((q, m)), softmin=np.zeros((q, m)), cost=np.zeros((q, m)),
+               nbr=np.zeros(q, np.int64), count_lo=np.zeros((q, m), np.int32),
+               count_hi=np.zeros((q, m), np.int32), ambiguous=np.zeros((q, m), np.uint8),
+               tstar=np.zeros((q, m)), tsoft=np.zeros((q, m)), tcost=np.zeros((q, m)))
+    red = _Reduce(int(k), float(tau), float(r_nbr), float(d_max), float(gamma), float(s_min),
+                  float(eps))
+    rc = lib.oracle_eval(n, _ptr(mu), _ptr(sigma), q, _ptr(centers), _ptr(A), m, _ptr(ns),
+                         ctypes.byref(red), _ptr(out["count"]), _ptr(out["label"]),
+                         _ptr(out["min"]), _ptr(out["softmin"]), _ptr(out["cost"]),
+                         _ptr(out["nbr"]), _ptr(out["count_lo"]), _ptr(out["count_hi"]),
+                         _ptr(out["ambiguous"]), _ptr(out["tstar"]), _ptr(out["tsoft"]),
+                         _ptr(out["tcost"]), int(nthreads))
+    if rc != 0:
+        raise OracleError(f"oracle_eval failed ({rc})")
+    return out
+
+
+def evaluate_spheres(scene, queries, n_sigma, raw_mode=False, alpha_f=0.0, extent_f=0.0,
+                     **reduce):
+    """Convenience: prepare a float32 scene and evaluate float32 query spheres."""
+    _, mu, sig = prepare_scene(scene.means, scene.quats, scene.scales, scene.opacity,
+                               raw_mode=raw_mode, alpha_f=alpha_f, extent_f=extent_f)
+    return evaluate(mu, sig, queries.centers.astype(np.float64), sphere_bodies(queries.radii),
+                    n_sigma, **reduce)
