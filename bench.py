@@ -1,0 +1,177 @@
+"""Throughput of the CollisionSplatting metric on one MI355X.
+
+One step = one evaluation of the whole hot path (query preparation, the
+float32 pair kernel with every per-query reduction for the m conservatism
+values, and the split combine) over the MPPI-shaped navigation workload:
+1M Gaussians (room scene) x 32,768 robot spheres (1,024 rollouts x 32 steps,
+r = 0.2 m), n_sigma in {0, 1, 2}, neighbourhood ball 1 m, k = 2, tau = 0.1.
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  The value is sphere-Gaussian pair evaluations per
+second, counted as Q x N_kept per batch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sphere-Gaussian pair evals/s + queries/s at stated label accuracy; p50/p99 latency"
+PEAK_VALU = 256 * 4 * 16 * 2.4e9   # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz (one VALU slot per lane-cycle)
+OPS_ALL_PAIRS = 7                  # d (3), |d|^2 (3), ball test (1)
+OPS_IN_BALL_SHARED = 17            # M d (9), V (3), sqrt (4 slots), ball count (1)
+OPS_IN_BALL_PER_NSIGMA = 19        # s~^2 (2), label (2), min (1), softmin (exp 4 + 2), cost (exp 4 + 4)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the CPU-oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by queries with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2609_35619_amd as cs
+    from workloads import config
+
+    cs.load_library()
+    log("bench: generating the mppi_nav workload")
+    sc, qs, p = config("mppi_nav")
+    dev = 0
+    eng = cs.Engine(dev)
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
+    n_kept, scene_bytes = cs.csplat_scene_info(h)
+    eng.set_conservatism(p["n_sigma"])
+    m = len(p["n_sigma"])
+    opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"],
+                          s_min=p["s_min"])
+    c = torch.from_numpy(qs.centers).to(f"cuda:{dev}")
+    r = torch.from_numpy(qs.radii).to(f"cuda:{dev}")
+    out = eng.alloc_outputs(qs.q)
+    torch.cuda.synchronize()
+    log(f"bench: {n_kept} kept Gaussians, {qs.q} queries, m={m}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        eng.evaluate(h, c, r, opts, out=out)
+    torch.cuda.synchronize()
+
+    # timed region: K steps bracketed by synchronisations
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eng.evaluate(h, c, r, opts, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_s = (t1 - t0) / args.steps
+
+    # per-step latency and the pair kernel's own duration (HIP events on the
+    # context stream), outside the throughput window
+    cs.csplat_ctx_set_timing(eng.ctx, True)
+    lat, kms = [], []
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        eng.evaluate(h, c, r, opts, out=out)
+        st = cs.csplat_last_stats(eng.ctx)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+        kms.append(st["kernel_ms"])
+    cs.csplat_ctx_set_timing(eng.ctx, False)
+    kernel_s = float(np.mean(kms)) / 1e3
+    gpu = {k: v.cpu().numpy() for k, v in out.items()}
+    nbr_total = int(gpu["nbr"].astype(np.int64).sum())
+    pairs = qs.q * n_kept
+    ops = OPS_ALL_PAIRS * pairs + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr_total
+    achieved = ops / kernel_s
+    res = {
+        "metric": METRIC,
+        "value": pairs / step_s,
+        "unit": "pair evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mppi_nav: 1M-Gaussian room scene (80% walls/floor, 20% in 50 clusters), "
+                               "1024 rollouts x 32 steps x 1 sphere r=0.2 m, n_sigma {0,1,2}, "
+                               "neighbourhood ball 1 m, k=2, tau=0.1, d_max=1, gamma=1, s_min=1; "
+                               "outputs label, count, min, softmin, cost, nbr",
+                   "n_gaussians": int(sc.n), "n_kept": int(n_kept), "queries": int(qs.q), "m": m,
+                   "global_batch": int(qs.q), "parallelism": "single GPU"},
+        "queries_per_s": qs.q / step_s,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "vram_bytes": {"scene": int(scene_bytes)},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU / 1e9, "unit": "Gop/s",
+                     "frac": achieved / PEAK_VALU, "traffic": None,
+                     "kernel": "pair_kernel<3,full,ball>", "kernel_ms": kernel_s * 1e3,
+                     "ops_per_launch": ops, "in_ball_pairs": nbr_total},
+    }
+    cs.csplat_scene_free(h)
+    eng.close()
+
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"], res["label_accuracy"] = cpu_baseline(sc, qs, p, gpu, args.cpu_seconds, n_kept)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(sc, qs, p, gpu, target_s, n_kept):
+    """The FP64 oracle on the host cores over a bounded sample of the same
+    queries (full scene); also the label agreement of the GPU on that sample."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import compare
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.build(force=False)
+    _, mu, sig = oracle.prepare_scene(sc.means, sc.quats, sc.scales, sc.opacity,
+                                      alpha_f=p["alpha_f"], extent_f=p["extent_f"])
+    rng = np.random.default_rng(11)
+    order = rng.permutation(qs.q)
+    kw = dict(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"], s_min=p["s_min"])
+    n_s = 64
+    while True:
+        idx = np.sort(order[:n_s])
+        sub = qs.subset(idx)
+        t0 = time.perf_counter()
+        ref = oracle.evaluate(mu, sig, sub.centers, oracle.sphere_bodies(sub.radii), p["n_sigma"],
+                              nthreads=threads, **kw)
+        dt = time.perf_counter() - t0
+        if dt >= target_s or n_s >= qs.q:
+            break
+        n_s = min(qs.q, max(n_s * 2, int(n_s * target_s / max(dt, 1e-3) * 1.1)))
+        log(f"bench: cpu baseline sample -> {n_s} queries")
+    st = compare({k: v[idx] for k, v in gpu.items()}, ref, tau=p["tau"], gamma=p["gamma"], d_max=p["d_max"],
+                 where="bench")
+    amb = ref["ambiguous"].astype(bool)
+    agree = float(((gpu["label"][idx] == ref["label"]) | amb).mean())
+    base = {"value": n_s * n_kept / dt, "unit": "pair evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_s} of {qs.q} queries (seeded) against all {n_kept} kept Gaussians, all outputs, FP64",
+            "seconds": dt, "queries_per_s": n_s / dt}
+    acc = {"labels_equal_outside_eps_band": agree, "ambiguous_queries": int(amb.sum()),
+           "sample_queries": int(n_s), "eps": 1e-5, **st}
+    return base, acc
+
+
+if __name__ == "__main__":
+    main()

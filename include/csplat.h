@@ -1,0 +1,173 @@
+/*
+ * csplat — CollisionSplatting robot-versus-3DGS metric on one MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes; no exceptions cross it; every call returns
+ * a csplat_status (0 = OK) and leaves a thread-local message for
+ * csplat_last_error() on failure.  All floating-point inputs are IEEE float32,
+ * row-major, little-endian.  Every allocation is owned by a context, scene or
+ * server and released by its destroy/free call.
+ *
+ * The method (Sec. II-B of the paper): each Gaussian i (mean mu_i, covariance
+ * Sigma_i = R_i S_i S_i^T R_i^T, Eq. 2) is treated as an uncertain point
+ * obstacle.  For a robot sphere j (centre c_j, radius r_j; the ellipsoid of
+ * Eq. 5-6 with a = b = c = r_j) the scaling-function distance is
+ * s^2 = |mu_i - c_j|^2 / r_j^2 (Eq. 5); its linearised variance is
+ * sigma^2 = g^T Sigma_i g with g = 2 (mu_i - c_j) / r_j^2 (Eq. 7); the
+ * conservative metric is s~^2 = max(0, s^2 - n_sigma sqrt(sigma^2)) (Eq. 8).
+ * Per query the pairs are reduced over the neighbourhood ball
+ * N_j = { i : |mu_i - c_j| <= neighbor_radius }:
+ *   count = #{ i in N_j : s~^2 < 1 },  label = count > k       (Sec. II-E)
+ *   min   = min over N_j of s~^2 (+inf if N_j is empty)
+ *   softmin = -tau log sum exp(-s~^2 / tau), evaluated about the minimum
+ *             (the numerically stable softmin of Sec. II-B; tau = 0: min)
+ *   cost  = mean over N_j of d_max exp(-gamma max(s~^2 - s_min, 0))
+ *           (Eq. 11, averaged over neighbouring splats, Sec. II-D; 0 if empty)
+ * Results are in s~^2 units (dimensionless, collision threshold 1).
+ *
+ * Evaluation calls: `centers`, `radii` and every non-NULL output must be all
+ * device pointers or all host pointers.  Device pointers run asynchronously
+ * on the context's stream; host pointers are staged through device memory and
+ * the call returns when the outputs are written.  Outputs are query-major:
+ * element [j * m + v] belongs to query j and conservatism value v.  All checks
+ * run before any device work; on error no output is written.  q = 0 is a
+ * no-op returning CSPLAT_OK.
+ */
+#ifndef CSPLAT_H
+#define CSPLAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t csplat_status;
+#define CSPLAT_OK 0
+#define CSPLAT_E_INVALID 1   /* bad argument or input value */
+#define CSPLAT_E_OOM 2       /* device or host allocation failed */
+#define CSPLAT_E_DEVICE 3    /* HIP runtime error */
+#define CSPLAT_E_BUSY 4      /* server: the request can never fit the budget */
+#define CSPLAT_E_NOT_FOUND 5 /* server: unknown ticket or scene id */
+#define CSPLAT_E_PENDING 6   /* server poll: not finished yet */
+#define CSPLAT_E_CANCELLED 7 /* server: the request was cancelled */
+
+#define CSPLAT_MAX_M 8 /* conservatism values per evaluation */
+
+typedef struct csplat_ctx csplat_ctx;
+typedef struct csplat_scene csplat_scene;
+typedef struct csplat_server csplat_server;
+
+/* Scene parameter conventions. */
+#define CSPLAT_PARAM_ACTIVATED 0 /* linear scales (std. dev.), opacity in [0, 1] */
+#define CSPLAT_PARAM_RAW_3DGS 1  /* log-scales and opacity logits (3DGS storage) */
+
+/* Arithmetic of an evaluation. */
+#define CSPLAT_PRECISION_FP32 0         /* plain float32 pair kernel */
+#define CSPLAT_PRECISION_BF16_RECHECK 1 /* bf16 MFMA + certified fp32/fp64 recheck */
+#define CSPLAT_PRECISION_FP16_RECHECK 2 /* fp16 MFMA + certified fp32/fp64 recheck */
+
+/* Bits of csplat_scene_opts.precision_features. */
+#define CSPLAT_FEATURES_BF16 1u
+#define CSPLAT_FEATURES_FP16 2u
+
+typedef struct {
+    int32_t param_mode;          /* CSPLAT_PARAM_* */
+    float floater_opacity_max;   /* alpha_f: drop i iff alpha_i < alpha_f and  */
+    float floater_extent_min;    /* max_k s_ik > e_f (Sec. II-C); alpha_f <= 0 disables */
+    uint32_t precision_features; /* CSPLAT_FEATURES_* to build at load time */
+} csplat_scene_opts;
+
+typedef struct {
+    int32_t k;             /* label = count > k (k >= 0; Sec. II-E "more than a small number") */
+    float softmin_tau;     /* tau >= 0; 0 reports the hard minimum as softmin */
+    float neighbor_radius; /* > 0, or +INFINITY for every kept Gaussian */
+    float d_max;           /* Eq. 11, > 0 */
+    float gamma;           /* Eq. 11, >= 0 */
+    float s_min;           /* Eq. 11, the paper uses 1 */
+    int32_t precision;     /* CSPLAT_PRECISION_*; the MFMA forms compute labels/counts */
+} csplat_reduce_opts;
+
+/* Outputs of one evaluation; every pointer is nullable (not computed/written). */
+typedef struct {
+    uint8_t *label;  /* q x m, count > k */
+    int32_t *count;  /* q x m */
+    float *min;      /* q x m, s~^2 units */
+    float *softmin;  /* q x m */
+    float *cost;     /* q x m */
+    int32_t *nbr;    /* q, |N_j| (size of the neighbourhood ball) */
+} csplat_outputs;
+
+/* Statistics of the last evaluation on a context. */
+typedef struct {
+    int64_t pairs;          /* q * n_kept */
+    int64_t flagged;        /* precision forms: queries rechecked in fp32 */
+    int64_t flagged_fp64;   /* precision forms: queries rechecked in fp64 */
+    int32_t splits;         /* Gaussian ranges evaluated side by side */
+    int32_t queries_per_lane;
+    int64_t kernel_pairs;   /* pairs the dominant kernel evaluated (after any culling) */
+    float kernel_ms;        /* with timing on: duration of the dominant (pair) kernel,
+                               measured with HIP events on the context stream; else -1 */
+} csplat_eval_stats;
+
+/* Context: a device, a stream (its own if hip_stream is NULL, else the given
+ * hipStream_t is borrowed and never destroyed) and a workspace that grows on
+ * demand.  Not thread-safe: one context per thread of use. */
+csplat_status csplat_ctx_create(int32_t device, void *hip_stream, csplat_ctx **out);
+csplat_status csplat_ctx_destroy(csplat_ctx *ctx);
+
+/* Load a 3DGS scene (Sec. II-A): n Gaussians with means (n x 3), quaternions
+ * (n x 4, (w, x, y, z), any nonzero norm; normalised here), scales (n x 3) and
+ * opacity (n).  Host pointers only; the inputs are copied and may be freed
+ * after return.  On the device the parameters are validated and activated,
+ * the floater filter applied, Sigma_i factored as M_i = diag(s_i) R_i^T and
+ * the survivors sorted along a Morton curve.  n = 0 is allowed.
+ * Errors: CSPLAT_E_INVALID (n < 0, NULL pointer with n > 0, a non-finite
+ * value, a zero quaternion, a negative linear scale), CSPLAT_E_OOM,
+ * CSPLAT_E_DEVICE.  opts may be NULL (activated, no filter, no features). */
+csplat_status csplat_scene_load(csplat_ctx *ctx, int64_t n, const float *means,
+                                const float *quats, const float *scales,
+                                const float *opacity, const csplat_scene_opts *opts,
+                                csplat_scene **out);
+/* Kept Gaussians and device bytes held by the scene (the VRAM figure). */
+csplat_status csplat_scene_info(const csplat_scene *scene, int64_t *n_kept,
+                                uint64_t *device_bytes);
+csplat_status csplat_scene_free(csplat_scene *scene);
+
+/* The conservatism n_sigma of Eq. 8: m values (1..8), each finite and >= 0.
+ * Stored in the context for later evaluations; on error the context is left
+ * unchanged. */
+csplat_status csplat_set_conservatism(csplat_ctx *ctx, const float *n_sigma, int32_t m);
+
+/* Evaluate q query spheres (centres q x 3, radii q, each finite and > 0)
+ * against the scene for the context's m conservatism values, computing only
+ * the non-NULL outputs. */
+csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
+                          const float *centers, const float *radii,
+                          const csplat_reduce_opts *opts, const csplat_outputs *out);
+/* Labels (and optionally counts) only: csplat_eval with label/count set. */
+csplat_status csplat_eval_labels(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
+                                 const float *centers, const float *radii,
+                                 const csplat_reduce_opts *opts, uint8_t *label,
+                                 int32_t *count);
+/* Distances: min (required), softmin and cost (nullable). */
+csplat_status csplat_eval_distance(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
+                                   const float *centers, const float *radii,
+                                   const csplat_reduce_opts *opts, float *min,
+                                   float *softmin, float *cost);
+
+/* Timing mode (off by default): when on, every evaluation records HIP events
+ * around its dominant kernel and csplat_last_stats waits for the second one. */
+csplat_status csplat_ctx_set_timing(csplat_ctx *ctx, int32_t enable);
+/* Statistics of the last evaluation (with timing on, waits for its kernel). */
+csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats);
+/* Wait for all work queued on the context's stream. */
+csplat_status csplat_synchronize(csplat_ctx *ctx);
+/* Message of the last failed call on this thread ("" if none); valid until
+ * the next csplat call on the same thread. */
+const char *csplat_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -35,7 +35,8 @@ def build(force: bool = True) -> str:
 class _Reduce(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("tau", ctypes.c_double), ("r_nbr", ctypes.c_double),
                 ("d_max", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("s_min", ctypes.c_double), ("eps", ctypes.c_double)]
+                ("s_min", ctypes.c_double), ("eps", ctypes.c_double),
+                ("eps_ball", ctypes.c_double)]
 
 
 def _load():
@@ -50,7 +51,7 @@ def _load():
                                              ctypes.c_double, ctypes.c_double, P, P, P, P]
         lib.oracle_prepare_scene.restype = ctypes.c_int
         lib.oracle_eval.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, P, ctypes.c_int32,
-                                    P, ctypes.POINTER(_Reduce)] + [P] * 12 + [ctypes.c_int]
+                                    P, ctypes.POINTER(_Reduce)] + [P] * 14 + [ctypes.c_int]
         lib.oracle_eval.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -107,7 +108,7 @@ def ellipsoid_bodies(rot, semi_axes):
 
 
 def evaluate(mu, sigma, centers, A, n_sigma, k=0, tau=0.0, r_nbr=math.inf, d_max=1.0,
-             gamma=1.0, s_min=1.0, eps=1e-5, nthreads=0):
+             gamma=1.0, s_min=1.0, eps=1e-5, eps_ball=1e-6, nthreads=0):
     """Evaluate all outputs.  Returns a dict of (q, m) arrays plus `nbr` (q,)."""
     lib = _load()
     mu = np.ascontiguousarray(mu, np.float64).reshape(-1, 3)
@@ -120,15 +121,17 @@ def evaluate(mu, sigma, centers, A, n_sigma, k=0, tau=0.0, r_nbr=math.inf, d_max
         raise ValueError("one body matrix per query")
     out = dict(count=np.zeros((q, m), np.int32), label=np.zeros((q, m), np.uint8),
                min=np.zeros((q, m)), softmin=np.zeros((q, m)), cost=np.zeros((q, m)),
-               nbr=np.zeros(q, np.int64), count_lo=np.zeros((q, m), np.int32),
+               nbr=np.zeros(q, np.int64), nbr_lo=np.zeros(q, np.int64),
+               nbr_hi=np.zeros(q, np.int64), count_lo=np.zeros((q, m), np.int32),
                count_hi=np.zeros((q, m), np.int32), ambiguous=np.zeros((q, m), np.uint8),
                tstar=np.zeros((q, m)), tsoft=np.zeros((q, m)), tcost=np.zeros((q, m)))
     red = _Reduce(int(k), float(tau), float(r_nbr), float(d_max), float(gamma), float(s_min),
-                  float(eps))
+                  float(eps), float(eps_ball))
     rc = lib.oracle_eval(n, _ptr(mu), _ptr(sigma), q, _ptr(centers), _ptr(A), m, _ptr(ns),
                          ctypes.byref(red), _ptr(out["count"]), _ptr(out["label"]),
                          _ptr(out["min"]), _ptr(out["softmin"]), _ptr(out["cost"]),
-                         _ptr(out["nbr"]), _ptr(out["count_lo"]), _ptr(out["count_hi"]),
+                         _ptr(out["nbr"]), _ptr(out["nbr_lo"]), _ptr(out["nbr_hi"]),
+                         _ptr(out["count_lo"]), _ptr(out["count_hi"]),
                          _ptr(out["ambiguous"]), _ptr(out["tstar"]), _ptr(out["tsoft"]),
                          _ptr(out["tcost"]), int(nthreads))
     if rc != 0:

@@ -33,9 +33,12 @@
  * min = softmin = +inf and cost = 0.
  *
  * Diagnostics for tolerances: per pair T_ij = s^2 + n_sigma sqrt(sigma^2),
- * the magnitude before the cancellation in Eq. 8.  count_lo / count_hi count
- * pairs with s~^2 < 1 -/+ eps T_ij; a query is ambiguous iff the labels of
- * count_lo and count_hi differ.
+ * the magnitude before the cancellation in Eq. 8.  count_lo counts pairs with
+ * s~^2 < 1 - eps T_ij that lie inside the ball by more than eps_ball
+ * (|d|^2 <= r_nbr^2 (1 - eps_ball)); count_hi counts pairs with
+ * s~^2 < 1 + eps T_ij and |d|^2 <= r_nbr^2 (1 + eps_ball).  A query is
+ * ambiguous iff the labels of count_lo and count_hi differ.  nbr_lo / nbr_hi
+ * bracket the ball size the same way.
  */
 #include <math.h>
 #include <stdint.h>
@@ -150,7 +153,8 @@ int oracle_eval(int64_t n, const double *mu, const double *sigma, int64_t q,
                 const double *centers, const double *A, int32_t m,
                 const double *n_sigma, const oracle_reduce *o, int32_t *count,
                 uint8_t *label, double *dmin, double *softmin, double *cost,
-                int64_t *nbr, int32_t *count_lo, int32_t *count_hi,
+                int64_t *nbr, int64_t *nbr_lo, int64_t *nbr_hi,
+                int32_t *count_lo, int32_t *count_hi,
                 uint8_t *ambiguous, double *tstar, double *tsoft, double *tcost,
                 int nthreads)
 {
@@ -162,6 +166,9 @@ int oracle_eval(int64_t n, const double *mu, const double *sigma, int64_t q,
     if (o->k < 0 || !(o->tau >= 0.0) || !(o->r_nbr > 0.0) || !(o->gamma >= 0.0))
         return ORACLE_E_INVALID;
     const double r2nbr = isinf(o->r_nbr) ? INFINITY : o->r_nbr * o->r_nbr;
+    /* ball membership within eps_ball of the boundary is a rounding-level call */
+    const double r2lo = isinf(o->r_nbr) ? INFINITY : r2nbr * (1.0 - o->eps_ball);
+    const double r2hi = isinf(o->r_nbr) ? INFINITY : r2nbr * (1.0 + o->eps_ball);
     int err = 0;
 
 #ifdef _OPENMP
@@ -173,7 +180,8 @@ int oracle_eval(int64_t n, const double *mu, const double *sigma, int64_t q,
         /* per-thread scratch: s~^2 and T for every neighbouring pair */
         double *st = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)m);
         double *tt = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)m);
-        if (!st || !tt) {
+        unsigned char *bb = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
+        if (!st || !tt || !bb) {
 #ifdef _OPENMP
 #pragma omp atomic write
 #endif
@@ -183,16 +191,21 @@ int oracle_eval(int64_t n, const double *mu, const double *sigma, int64_t q,
 #pragma omp for schedule(static)
 #endif
         for (int64_t j = 0; j < q; ++j) {
-            if (!st || !tt)
+            if (!st || !tt || !bb)
                 continue;
             const double *c = centers + 3 * j;
             const double *Aj = A + 9 * j;
-            int64_t nn = 0;
+            int64_t nn = 0, nlo = 0, nhi = 0, nin = 0;
             for (int64_t i = 0; i < n; ++i) {
                 double d[3] = {mu[3 * i] - c[0], mu[3 * i + 1] - c[1], mu[3 * i + 2] - c[2]};
                 double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                if (!(dd <= r2nbr))
-                    continue; /* outside the neighbourhood ball */
+                if (!(dd <= r2hi))
+                    continue; /* outside the neighbourhood ball (and its band) */
+                /* bit 0: in the ball; bit 1: in for certain; bit 2: in the upper band */
+                bb[nn] = (unsigned char)((dd <= r2nbr) | ((dd <= r2lo) << 1) | 4);
+                nin += dd <= r2nbr;
+                nlo += dd <= r2lo;
+                nhi += 1;
                 double s2 = quad3(Aj, d, d); /* Eq. 5 at X = mu_i */
                 double g[3];                 /* gradient of s^2 at X = mu_i */
                 for (int a = 0; a < 3; ++a)
@@ -207,16 +220,46 @@ int oracle_eval(int64_t n, const double *mu, const double *sigma, int64_t q,
                 ++nn;
             }
             if (nbr)
-                nbr[j] = nn;
+                nbr[j] = nin;
+            if (nbr_lo)
+                nbr_lo[j] = nlo;
+            if (nbr_hi)
+                nbr_hi[j] = nhi;
+            /* count diagnostics over the candidates of the widened ball */
+            int64_t cand = nn;
             for (int v = 0; v < m; ++v) {
                 const double *x = st + (size_t)v * n;
                 const double *T = tt + (size_t)v * n;
-                int64_t cnt = 0, clo = 0, chi = 0;
+                int64_t clo = 0, chi = 0;
+                for (int64_t i = 0; i < cand; ++i) {
+                    clo += (bb[i] & 2) && x[i] < 1.0 - o->eps * T[i];
+                    chi += x[i] < 1.0 + o->eps * T[i];
+                }
+                if (count_lo)
+                    count_lo[(size_t)j * m + v] = (int32_t)clo;
+                if (count_hi)
+                    count_hi[(size_t)j * m + v] = (int32_t)chi;
+                if (ambiguous)
+                    ambiguous[(size_t)j * m + v] = (clo > o->k) != (chi > o->k);
+            }
+            /* keep the pairs of the ball itself, in order, for the reductions */
+            nn = 0;
+            for (int64_t i = 0; i < cand; ++i) {
+                if (!(bb[i] & 1))
+                    continue;
+                for (int v = 0; v < m; ++v) {
+                    st[(size_t)v * n + nn] = st[(size_t)v * n + i];
+                    tt[(size_t)v * n + nn] = tt[(size_t)v * n + i];
+                }
+                ++nn;
+            }
+            for (int v = 0; v < m; ++v) {
+                const double *x = st + (size_t)v * n;
+                const double *T = tt + (size_t)v * n;
+                int64_t cnt = 0;
                 double mn = INFINITY;
                 for (int64_t i = 0; i < nn; ++i) {
                     cnt += x[i] < 1.0;
-                    clo += x[i] < 1.0 - o->eps * T[i];
-                    chi += x[i] < 1.0 + o->eps * T[i];
                     if (x[i] < mn)
                         mn = x[i];
                 }
@@ -256,12 +299,6 @@ int oracle_eval(int64_t n, const double *mu, const double *sigma, int64_t q,
                     count[oi] = (int32_t)cnt;
                 if (label)
                     label[oi] = cnt > o->k;
-                if (count_lo)
-                    count_lo[oi] = (int32_t)clo;
-                if (count_hi)
-                    count_hi[oi] = (int32_t)chi;
-                if (ambiguous)
-                    ambiguous[oi] = (clo > o->k) != (chi > o->k);
                 if (dmin)
                     dmin[oi] = mn;
                 if (softmin)
@@ -278,6 +315,7 @@ int oracle_eval(int64_t n, const double *mu, const double *sigma, int64_t q,
         }
         free(st);
         free(tt);
+        free(bb);
     }
     return err ? ORACLE_E_OOM : ORACLE_OK;
 }

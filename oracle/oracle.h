@@ -23,7 +23,8 @@ typedef struct {
     double d_max;   /* Eq. 11 */
     double gamma;   /* Eq. 11 */
     double s_min;   /* Eq. 11 */
-    double eps;     /* relative band for count_lo / count_hi */
+    double eps;     /* relative band (in units of T) for count_lo / count_hi */
+    double eps_ball; /* relative band of the ball boundary |d|^2 = r_nbr^2 */
 } oracle_reduce;
 
 /* Activate, filter and form Sigma for n Gaussians (float inputs, as stored).
@@ -37,12 +38,14 @@ int oracle_prepare_scene(int64_t n, const float *means, const float *quats,
 
 /* Evaluate q robot bodies (centres q x 3, body matrices A q x 9) against the
  * n prepared Gaussians for m conservatism values.  Every output is q x m
- * (query-major) except nbr (q); any output pointer may be NULL. */
+ * (query-major) except nbr, nbr_lo, nbr_hi (q); any output pointer may be
+ * NULL. */
 int oracle_eval(int64_t n, const double *mu, const double *sigma, int64_t q,
                 const double *centers, const double *A, int32_t m,
                 const double *n_sigma, const oracle_reduce *o, int32_t *count,
                 uint8_t *label, double *dmin, double *softmin, double *cost,
-                int64_t *nbr, int32_t *count_lo, int32_t *count_hi,
+                int64_t *nbr, int64_t *nbr_lo, int64_t *nbr_hi,
+                int32_t *count_lo, int32_t *count_hi,
                 uint8_t *ambiguous, double *tstar, double *tsoft, double *tcost,
                 int nthreads);
 

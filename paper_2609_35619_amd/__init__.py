@@ -1,0 +1,306 @@
+"""csplat: the CollisionSplatting robot-versus-3DGS metric on MI355X (gfx950).
+
+A thin ctypes binding of the C ABI in include/csplat.h.  Functions keep the C
+names (csplat_ctx_create, csplat_scene_load, csplat_set_conservatism,
+csplat_eval, ...); they only marshal arguments.  Every step of the metric runs
+in the HIP kernels of libcsplat.so; there is no CPU fallback: importing works
+without the library, but every call raises if it is missing.
+
+Device memory and streams come from PyTorch: pass torch CUDA tensors to run
+asynchronously on the context's stream (by default torch's current stream),
+or numpy arrays to run synchronously through staging buffers.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsplat.so")
+
+CSPLAT_OK = 0
+CSPLAT_E_INVALID = 1
+CSPLAT_E_OOM = 2
+CSPLAT_E_DEVICE = 3
+CSPLAT_E_BUSY = 4
+CSPLAT_E_NOT_FOUND = 5
+CSPLAT_E_PENDING = 6
+CSPLAT_E_CANCELLED = 7
+CSPLAT_MAX_M = 8
+CSPLAT_PARAM_ACTIVATED = 0
+CSPLAT_PARAM_RAW_3DGS = 1
+CSPLAT_PRECISION_FP32 = 0
+CSPLAT_PRECISION_BF16_RECHECK = 1
+CSPLAT_PRECISION_FP16_RECHECK = 2
+CSPLAT_FEATURES_BF16 = 1
+CSPLAT_FEATURES_FP16 = 2
+
+# every symbol declared in include/csplat.h (checked by the test suite)
+EXPORTS = (
+    "csplat_ctx_create", "csplat_ctx_destroy", "csplat_scene_load", "csplat_scene_info",
+    "csplat_scene_free", "csplat_set_conservatism", "csplat_eval", "csplat_eval_labels",
+    "csplat_eval_distance", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
+    "csplat_last_error",
+)
+
+
+class CsplatError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"csplat error {status}: {msg}")
+        self.status = status
+
+
+class SceneOpts(ctypes.Structure):
+    _fields_ = [("param_mode", ctypes.c_int32), ("floater_opacity_max", ctypes.c_float),
+                ("floater_extent_min", ctypes.c_float), ("precision_features", ctypes.c_uint32)]
+
+
+class ReduceOpts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("softmin_tau", ctypes.c_float),
+                ("neighbor_radius", ctypes.c_float), ("d_max", ctypes.c_float),
+                ("gamma", ctypes.c_float), ("s_min", ctypes.c_float), ("precision", ctypes.c_int32)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("label", ctypes.c_void_p), ("count", ctypes.c_void_p), ("min", ctypes.c_void_p),
+                ("softmin", ctypes.c_void_p), ("cost", ctypes.c_void_p), ("nbr", ctypes.c_void_p)]
+
+
+class EvalStats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("flagged", ctypes.c_int64),
+                ("flagged_fp64", ctypes.c_int64), ("splits", ctypes.c_int32),
+                ("queries_per_lane", ctypes.c_int32), ("kernel_pairs", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_float)]
+
+
+_lib = None
+
+
+def library_loaded() -> bool:
+    return _lib is not None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcsplat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise CsplatError(-1, f"{path} is missing: build it with paper_2609_35619_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "csplat_ctx_create": [I32, P, P],
+        "csplat_ctx_destroy": [P],
+        "csplat_scene_load": [P, I64, P, P, P, P, P, P],
+        "csplat_scene_info": [P, P, P],
+        "csplat_scene_free": [P],
+        "csplat_set_conservatism": [P, P, I32],
+        "csplat_eval": [P, P, I64, P, P, P, P],
+        "csplat_eval_labels": [P, P, I64, P, P, P, P, P],
+        "csplat_eval_distance": [P, P, I64, P, P, P, P, P, P],
+        "csplat_ctx_set_timing": [P, I32],
+        "csplat_last_stats": [P, P],
+        "csplat_synchronize": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    lib.csplat_last_error.argtypes = []
+    lib.csplat_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != CSPLAT_OK:
+        msg = _lib.csplat_last_error().decode(errors="replace")
+        raise CsplatError(status, msg)
+
+
+def _addr(x):
+    """Address of a torch tensor or numpy array (None -> NULL)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return ctypes.c_void_p(x.data_ptr())
+    return x.ctypes.data_as(ctypes.c_void_p)
+
+
+def _is_torch_cuda(x):
+    return hasattr(x, "is_cuda") and x.is_cuda
+
+
+# --- C names ---------------------------------------------------------------
+
+def csplat_ctx_create(device: int = 0, stream=None):
+    """Create a context on `device`.  `stream`: a torch.cuda.Stream or a raw
+    hipStream_t integer to borrow, or None to let the library own a stream."""
+    lib = load_library()
+    handle = 0
+    if stream is not None:
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    out = ctypes.c_void_p()
+    _check(lib.csplat_ctx_create(device, ctypes.c_void_p(handle) if handle else None, ctypes.byref(out)))
+    return out
+
+
+def csplat_ctx_destroy(ctx):
+    _check(load_library().csplat_ctx_destroy(ctx))
+
+
+def csplat_scene_load(ctx, means, quats, scales, opacity, param_mode=CSPLAT_PARAM_ACTIVATED,
+                      floater_opacity_max=0.0, floater_extent_min=0.0, precision_features=0):
+    lib = load_library()
+    arrs = [np.ascontiguousarray(a, np.float32) for a in (means, quats, scales, opacity)]
+    n = arrs[0].shape[0]
+    opts = SceneOpts(param_mode, floater_opacity_max, floater_extent_min, precision_features)
+    out = ctypes.c_void_p()
+    _check(lib.csplat_scene_load(ctx, n, *[_addr(a) if n else None for a in arrs], ctypes.byref(opts),
+                                 ctypes.byref(out)))
+    return out
+
+
+def csplat_scene_info(scene):
+    n = ctypes.c_int64()
+    b = ctypes.c_uint64()
+    _check(load_library().csplat_scene_info(scene, ctypes.byref(n), ctypes.byref(b)))
+    return n.value, b.value
+
+
+def csplat_scene_free(scene):
+    _check(load_library().csplat_scene_free(scene))
+
+
+def csplat_set_conservatism(ctx, n_sigma):
+    ns = np.ascontiguousarray(np.atleast_1d(n_sigma), np.float32)
+    _check(load_library().csplat_set_conservatism(ctx, _addr(ns), ns.size))
+
+
+def reduce_opts(k=0, tau=0.0, r_nbr=math.inf, d_max=1.0, gamma=1.0, s_min=1.0,
+                precision=CSPLAT_PRECISION_FP32) -> ReduceOpts:
+    return ReduceOpts(int(k), float(tau), float(r_nbr), float(d_max), float(gamma), float(s_min),
+                      int(precision))
+
+
+def csplat_eval(ctx, scene, centers, radii, opts: ReduceOpts, label=None, count=None, min=None,
+                softmin=None, cost=None, nbr=None):
+    """Evaluate into caller-provided outputs (all torch CUDA tensors or all
+    numpy arrays, matching centers/radii)."""
+    q = int(centers.shape[0])
+    o = Outputs(*[_addr(x) for x in (label, count, min, softmin, cost, nbr)])
+    _check(load_library().csplat_eval(ctx, scene, q, _addr(centers), _addr(radii), ctypes.byref(opts),
+                                      ctypes.byref(o)))
+
+
+def csplat_eval_labels(ctx, scene, centers, radii, opts: ReduceOpts, label, count=None):
+    q = int(centers.shape[0])
+    _check(load_library().csplat_eval_labels(ctx, scene, q, _addr(centers), _addr(radii),
+                                             ctypes.byref(opts), _addr(label), _addr(count)))
+
+
+def csplat_eval_distance(ctx, scene, centers, radii, opts: ReduceOpts, min, softmin=None, cost=None):
+    q = int(centers.shape[0])
+    _check(load_library().csplat_eval_distance(ctx, scene, q, _addr(centers), _addr(radii),
+                                               ctypes.byref(opts), _addr(min), _addr(softmin),
+                                               _addr(cost)))
+
+
+def csplat_ctx_set_timing(ctx, enable: bool):
+    _check(load_library().csplat_ctx_set_timing(ctx, 1 if enable else 0))
+
+
+def csplat_last_stats(ctx) -> dict:
+    st = EvalStats()
+    _check(load_library().csplat_last_stats(ctx, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in EvalStats._fields_}
+
+
+def csplat_synchronize(ctx):
+    _check(load_library().csplat_synchronize(ctx))
+
+
+def csplat_last_error() -> str:
+    return load_library().csplat_last_error().decode(errors="replace")
+
+
+# --- convenience ------------------------------------------------------------
+
+ALL_OUTPUTS = ("label", "count", "min", "softmin", "cost", "nbr")
+
+
+class Engine:
+    """One context on its own torch stream + its conservatism values.
+
+    Evaluations on torch tensors are ordered after the work already queued on
+    torch's current stream, and torch's current stream waits for them, so the
+    results can be used like any other torch tensor."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.ctx = csplat_ctx_create(device, self.stream)
+        self.m = 1
+
+    def close(self):
+        if self.ctx is not None:
+            csplat_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def load_scene(self, scene, **kw):
+        return csplat_scene_load(self.ctx, scene.means, scene.quats, scene.scales, scene.opacity, **kw)
+
+    def set_conservatism(self, n_sigma):
+        csplat_set_conservatism(self.ctx, n_sigma)
+        self.m = int(np.atleast_1d(n_sigma).size)
+
+    def alloc_outputs(self, q, want=ALL_OUTPUTS, like="cuda"):
+        """Output buffers: torch CUDA tensors (like="cuda") or numpy arrays."""
+        m = self.m
+        shapes = dict(label=((q, m), "u8"), count=((q, m), "i32"), min=((q, m), "f32"),
+                      softmin=((q, m), "f32"), cost=((q, m), "f32"), nbr=((q,), "i32"))
+        out = {}
+        if like == "cuda":
+            import torch
+            dt = dict(u8=torch.uint8, i32=torch.int32, f32=torch.float32)
+            for k in want:
+                s, t = shapes[k]
+                out[k] = torch.empty(s, dtype=dt[t], device=f"cuda:{self.device}")
+        else:
+            dt = dict(u8=np.uint8, i32=np.int32, f32=np.float32)
+            for k in want:
+                s, t = shapes[k]
+                out[k] = np.empty(s, dtype=dt[t])
+        return out
+
+    def evaluate(self, scene, centers, radii, opts: ReduceOpts, want=ALL_OUTPUTS, out=None):
+        like = "cuda" if _is_torch_cuda(centers) else "host"
+        if out is None:
+            out = self.alloc_outputs(int(centers.shape[0]), want, like)
+        if like == "cuda":
+            cur = self.torch.cuda.current_stream(self.device)
+            self.stream.wait_stream(cur)
+            for t in (centers, radii, *out.values()):
+                t.record_stream(self.stream)
+        csplat_eval(self.ctx, scene, centers, radii, opts, **out)
+        if like == "cuda":
+            self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def stats(self):
+        return csplat_last_stats(self.ctx)
+
+    def synchronize(self):
+        csplat_synchronize(self.ctx)

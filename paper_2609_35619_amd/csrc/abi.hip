@@ -1,0 +1,414 @@
+// The C ABI of the library: argument validation, ownership and dispatch.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+namespace csplat {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+csplat_status fail(csplat_status code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+csplat_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? CSPLAT_E_OOM : CSPLAT_E_DEVICE;
+}
+
+hipError_t DevBuf::reserve(size_t want)
+{
+    if (want <= bytes) return hipSuccess;
+    release();
+    size_t grow = want + want / 4;
+    hipError_t e = hipMalloc(&ptr, grow);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        bytes = 0;
+        return e;
+    }
+    bytes = grow;
+    return hipSuccess;
+}
+
+void DevBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+namespace {
+
+// Set the context's device as current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// 0: host, 1: device, -1: unknown/invalid
+int pointer_kind(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return 1;
+    return 0;
+}
+
+csplat_status build_params(const csplat_ctx *ctx, const csplat_reduce_opts &o, EvalParams &p)
+{
+    if (o.k < 0) return fail(CSPLAT_E_INVALID, "reduce opts: k must be >= 0");
+    if (!(o.softmin_tau >= 0.f) || !std::isfinite(o.softmin_tau))
+        return fail(CSPLAT_E_INVALID, "reduce opts: softmin_tau must be finite and >= 0");
+    if (!(o.neighbor_radius > 0.f))
+        return fail(CSPLAT_E_INVALID, "reduce opts: neighbor_radius must be > 0 (or +inf)");
+    if (!(o.d_max > 0.f) || !std::isfinite(o.d_max))
+        return fail(CSPLAT_E_INVALID, "reduce opts: d_max must be finite and > 0");
+    if (!(o.gamma >= 0.f) || !std::isfinite(o.gamma))
+        return fail(CSPLAT_E_INVALID, "reduce opts: gamma must be finite and >= 0");
+    if (!std::isfinite(o.s_min)) return fail(CSPLAT_E_INVALID, "reduce opts: s_min must be finite");
+    if (o.precision < CSPLAT_PRECISION_FP32 || o.precision > CSPLAT_PRECISION_FP16_RECHECK)
+        return fail(CSPLAT_E_INVALID, "reduce opts: unknown precision");
+    std::memset(&p, 0, sizeof(p));
+    p.m = ctx->m;
+    p.k = o.k;
+    for (int v = 0; v < ctx->m; ++v) {
+        double n = ctx->n_sigma[v];
+        p.two_n[v] = (float)(2.0 * n);
+        p.four_n2[v] = (float)(4.0 * n * n);
+    }
+    p.soft = o.softmin_tau > 0.f;
+    // t = s~^2 * kt; the softmin sum is sum 2^(t_min - t), so kt = log2(e) / tau
+    double kt = p.soft ? 1.4426950408889634 / (double)o.softmin_tau : 1.0;
+    if (!std::isfinite((float)kt)) return fail(CSPLAT_E_INVALID, "reduce opts: softmin_tau too small");
+    p.kt = (float)kt;
+    p.inv_kt = (float)(1.0 / kt);
+    // cost term d_max exp(-gamma max(s~^2 - s_min, 0)) = d_max 2^min(g0 - g1 t, 0)
+    p.g1 = (float)((double)o.gamma * 1.4426950408889634 / kt);
+    p.g0 = (float)((double)o.gamma * 1.4426950408889634 * (double)o.s_min);
+    p.d_max = o.d_max;
+    p.rn2 = std::isinf(o.neighbor_radius) ? INFINITY
+                                          : (float)((double)o.neighbor_radius * o.neighbor_radius);
+    return CSPLAT_OK;
+}
+
+// Query spheres must have finite centres and finite radii > 0.  Host arrays
+// are checked here; device arrays by check_queries_kernel before any output
+// is written.
+bool queries_valid_host(int64_t q, const float *c, const float *r)
+{
+    for (int64_t j = 0; j < q; ++j) {
+        if (!std::isfinite(c[3 * j]) || !std::isfinite(c[3 * j + 1]) || !std::isfinite(c[3 * j + 2]))
+            return false;
+        if (!(r[j] > 0.f) || !std::isfinite(r[j])) return false;
+    }
+    return true;
+}
+
+__global__ void check_queries_kernel(int64_t q, const float *__restrict__ c, const float *__restrict__ r,
+                                     int *bad)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    bool ok = isfinite(c[3 * j]) && isfinite(c[3 * j + 1]) && isfinite(c[3 * j + 2]) && r[j] > 0.f &&
+              isfinite(r[j]);
+    if (!ok) atomicOr(bad, 1);
+}
+
+}  // namespace
+}  // namespace csplat
+
+using namespace csplat;
+
+extern "C" {
+
+const char *csplat_last_error(void) { return g_last_error.c_str(); }
+
+csplat_status csplat_ctx_create(int32_t device, void *hip_stream, csplat_ctx **out)
+{
+    if (!out) return fail(CSPLAT_E_INVALID, "ctx_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(CSPLAT_E_INVALID, "ctx_create: no such device");
+    DeviceGuard g(device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    csplat_ctx *ctx = new (std::nothrow) csplat_ctx();
+    if (!ctx) return fail(CSPLAT_E_OOM, "ctx_create: host allocation");
+    ctx->device = device;
+    if (hip_stream) {
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete ctx;
+            return hip_fail(e, "hipStreamCreate");
+        }
+        ctx->own_stream = true;
+    }
+    ctx->m = 1;
+    ctx->n_sigma[0] = 1.0f;
+    *out = ctx;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_ctx_destroy(csplat_ctx *ctx)
+{
+    if (!ctx) return CSPLAT_OK;
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->partial.release();
+    ctx->staging.release();
+    ctx->flags.release();
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_scene_load(csplat_ctx *ctx, int64_t n, const float *means, const float *quats,
+                                const float *scales, const float *opacity,
+                                const csplat_scene_opts *opts, csplat_scene **out)
+{
+    if (!ctx || !out) return fail(CSPLAT_E_INVALID, "scene_load: NULL ctx or out");
+    *out = nullptr;
+    if (n < 0) return fail(CSPLAT_E_INVALID, "scene_load: n < 0");
+    if (n > 0 && (!means || !quats || !scales || !opacity))
+        return fail(CSPLAT_E_INVALID, "scene_load: NULL input array");
+    csplat_scene_opts o{};
+    o.param_mode = CSPLAT_PARAM_ACTIVATED;
+    if (opts) o = *opts;
+    if (o.param_mode != CSPLAT_PARAM_ACTIVATED && o.param_mode != CSPLAT_PARAM_RAW_3DGS)
+        return fail(CSPLAT_E_INVALID, "scene_load: unknown param_mode");
+    if (!std::isfinite(o.floater_opacity_max) || !std::isfinite(o.floater_extent_min))
+        return fail(CSPLAT_E_INVALID, "scene_load: non-finite floater thresholds");
+    if (o.precision_features & ~(CSPLAT_FEATURES_BF16 | CSPLAT_FEATURES_FP16))
+        return fail(CSPLAT_E_INVALID, "scene_load: unknown precision feature bits");
+    if (n > 0) {  // the scene arrays are host arrays: reject device pointers early
+        if (pointer_kind(means) || pointer_kind(quats) || pointer_kind(scales) || pointer_kind(opacity))
+            return fail(CSPLAT_E_INVALID, "scene_load: inputs must be host pointers");
+    }
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    csplat_scene *sc = new (std::nothrow) csplat_scene();
+    if (!sc) return fail(CSPLAT_E_OOM, "scene_load: host allocation");
+    csplat_status s = scene_build(ctx, n, means, quats, scales, opacity, o, sc);
+    if (s == CSPLAT_OK && o.precision_features && sc->n > 0)
+        s = precision_build(ctx, sc, o.precision_features);
+    if (s != CSPLAT_OK) {
+        scene_release(sc);
+        delete sc;
+        return s;
+    }
+    *out = sc;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_scene_info(const csplat_scene *sc, int64_t *n_kept, uint64_t *device_bytes)
+{
+    if (!sc) return fail(CSPLAT_E_INVALID, "scene_info: NULL scene");
+    if (n_kept) *n_kept = sc->n;
+    if (device_bytes) *device_bytes = sc->device_bytes;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_scene_free(csplat_scene *sc)
+{
+    if (!sc) return CSPLAT_OK;
+    DeviceGuard g(sc->device);
+    (void)hipDeviceSynchronize();
+    scene_release(sc);
+    delete sc;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_set_conservatism(csplat_ctx *ctx, const float *n_sigma, int32_t m)
+{
+    if (!ctx || !n_sigma) return fail(CSPLAT_E_INVALID, "set_conservatism: NULL argument");
+    if (m < 1 || m > CSPLAT_MAX_M) return fail(CSPLAT_E_INVALID, "set_conservatism: m must be in 1..8");
+    for (int v = 0; v < m; ++v)
+        if (!(n_sigma[v] >= 0.f) || !std::isfinite(n_sigma[v]))
+            return fail(CSPLAT_E_INVALID, "set_conservatism: n_sigma must be finite and >= 0");
+    ctx->m = m;
+    for (int v = 0; v < m; ++v) ctx->n_sigma[v] = n_sigma[v];
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const float *centers,
+                          const float *radii, const csplat_reduce_opts *opts,
+                          const csplat_outputs *out)
+{
+    if (!ctx || !sc || !opts || !out) return fail(CSPLAT_E_INVALID, "eval: NULL argument");
+    if (q < 0) return fail(CSPLAT_E_INVALID, "eval: q < 0");
+    if (q > (int64_t)0x7FFFFFFF / 8) return fail(CSPLAT_E_INVALID, "eval: q too large");
+    if (sc->device != ctx->device) return fail(CSPLAT_E_INVALID, "eval: scene on another device");
+    EvalParams p;
+    csplat_status s = build_params(ctx, *opts, p);
+    if (s != CSPLAT_OK) return s;
+    const bool want_dist = out->min || out->softmin || out->cost || out->nbr;
+    if (!want_dist && !out->label && !out->count) return fail(CSPLAT_E_INVALID, "eval: no output requested");
+    if (opts->precision != CSPLAT_PRECISION_FP32) {
+        if (want_dist)
+            return fail(CSPLAT_E_INVALID, "eval: the MFMA precision forms compute labels and counts only");
+        uint32_t need = opts->precision == CSPLAT_PRECISION_BF16_RECHECK ? CSPLAT_FEATURES_BF16
+                                                                          : CSPLAT_FEATURES_FP16;
+        void *f = need == CSPLAT_FEATURES_BF16 ? sc->feat_bf16 : sc->feat_fp16;
+        if (sc->n > 0 && !f)
+            return fail(CSPLAT_E_INVALID, "eval: scene was loaded without the requested precision features");
+    }
+    if (q == 0) return CSPLAT_OK;
+    if (!centers || !radii) return fail(CSPLAT_E_INVALID, "eval: NULL centers or radii");
+    const void *ptrs[] = {centers, radii, out->label, out->count, out->min, out->softmin, out->cost, out->nbr};
+    int kind = -2;
+    for (const void *ptr : ptrs) {
+        if (!ptr) continue;
+        int k = pointer_kind(ptr);
+        if (kind == -2) kind = k;
+        else if (kind != k)
+            return fail(CSPLAT_E_INVALID, "eval: mix of host and device pointers");
+    }
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const int m = ctx->m;
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    ctx->stats.pairs = q * sc->n;
+    ctx->timed = false;
+    if (kind == 1) {
+        // device inputs: check them on the device before any output is touched
+        int *bad = nullptr;
+        hipError_t e = ctx->flags.reserve(64);
+        if (e != hipSuccess) return hip_fail(e, "flag workspace");
+        bad = ctx->flags.as<int>();
+        CSPLAT_HIP(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+        check_queries_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, radii, bad);
+        CSPLAT_HIP(hipGetLastError());
+        int hbad = 0;
+        CSPLAT_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        CSPLAT_HIP(hipStreamSynchronize(ctx->stream));
+        if (hbad) return fail(CSPLAT_E_INVALID, "eval: query centres must be finite and radii finite and > 0");
+        EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr};
+        if (opts->precision != CSPLAT_PRECISION_FP32)
+            return precision_eval(ctx, sc, q, centers, radii, p, eo, opts->precision);
+        return fp32_eval(ctx, sc, q, centers, radii, p, eo, !want_dist);
+    }
+    // host pointers: validate, stage, run, copy back, synchronise
+    if (!queries_valid_host(q, centers, radii))
+        return fail(CSPLAT_E_INVALID, "eval: query centres must be finite and radii finite and > 0");
+    const size_t qm = (size_t)q * m;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_c = take((size_t)q * 12), o_r = take((size_t)q * 4);
+    const size_t o_lab = out->label ? take(qm) : 0, o_cnt = out->count ? take(qm * 4) : 0;
+    const size_t o_min = out->min ? take(qm * 4) : 0, o_sm = out->softmin ? take(qm * 4) : 0;
+    const size_t o_cs = out->cost ? take(qm * 4) : 0, o_nb = out->nbr ? take((size_t)q * 4) : 0;
+    hipError_t e = ctx->staging.reserve(off);
+    if (e != hipSuccess) return hip_fail(e, "staging workspace");
+    char *b = ctx->staging.as<char>();
+    hipStream_t st = ctx->stream;
+    CSPLAT_HIP(hipMemcpyAsync(b + o_c, centers, (size_t)q * 12, hipMemcpyHostToDevice, st));
+    CSPLAT_HIP(hipMemcpyAsync(b + o_r, radii, (size_t)q * 4, hipMemcpyHostToDevice, st));
+    EvalOut eo{out->label ? (uint8_t *)(b + o_lab) : nullptr, out->count ? (int32_t *)(b + o_cnt) : nullptr,
+               out->min ? (float *)(b + o_min) : nullptr, out->softmin ? (float *)(b + o_sm) : nullptr,
+               out->cost ? (float *)(b + o_cs) : nullptr, out->nbr ? (int32_t *)(b + o_nb) : nullptr};
+    if (opts->precision != CSPLAT_PRECISION_FP32)
+        s = precision_eval(ctx, sc, q, (const float *)(b + o_c), (const float *)(b + o_r), p, eo,
+                           opts->precision);
+    else
+        s = fp32_eval(ctx, sc, q, (const float *)(b + o_c), (const float *)(b + o_r), p, eo, !want_dist);
+    if (s != CSPLAT_OK) return s;
+    if (out->label) CSPLAT_HIP(hipMemcpyAsync(out->label, eo.label, qm, hipMemcpyDeviceToHost, st));
+    if (out->count) CSPLAT_HIP(hipMemcpyAsync(out->count, eo.count, qm * 4, hipMemcpyDeviceToHost, st));
+    if (out->min) CSPLAT_HIP(hipMemcpyAsync(out->min, eo.min, qm * 4, hipMemcpyDeviceToHost, st));
+    if (out->softmin) CSPLAT_HIP(hipMemcpyAsync(out->softmin, eo.softmin, qm * 4, hipMemcpyDeviceToHost, st));
+    if (out->cost) CSPLAT_HIP(hipMemcpyAsync(out->cost, eo.cost, qm * 4, hipMemcpyDeviceToHost, st));
+    if (out->nbr) CSPLAT_HIP(hipMemcpyAsync(out->nbr, eo.nbr, (size_t)q * 4, hipMemcpyDeviceToHost, st));
+    CSPLAT_HIP(hipStreamSynchronize(st));
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_eval_labels(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const float *centers,
+                                 const float *radii, const csplat_reduce_opts *opts, uint8_t *label,
+                                 int32_t *count)
+{
+    if (!label) return fail(CSPLAT_E_INVALID, "eval_labels: label is NULL");
+    csplat_outputs o{};
+    o.label = label;
+    o.count = count;
+    return csplat_eval(ctx, sc, q, centers, radii, opts, &o);
+}
+
+csplat_status csplat_eval_distance(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const float *centers,
+                                   const float *radii, const csplat_reduce_opts *opts, float *min,
+                                   float *softmin, float *cost)
+{
+    if (!min) return fail(CSPLAT_E_INVALID, "eval_distance: min is NULL");
+    csplat_outputs o{};
+    o.min = min;
+    o.softmin = softmin;
+    o.cost = cost;
+    return csplat_eval(ctx, sc, q, centers, radii, opts, &o);
+}
+
+csplat_status csplat_ctx_set_timing(csplat_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return fail(CSPLAT_E_INVALID, "set_timing: NULL ctx");
+    DeviceGuard g(ctx->device);
+    if (enable && !ctx->ev0) {
+        CSPLAT_HIP(hipEventCreate(&ctx->ev0));
+        CSPLAT_HIP(hipEventCreate(&ctx->ev1));
+    }
+    ctx->timing = enable != 0;
+    ctx->timed = false;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats)
+{
+    if (!ctx || !stats) return fail(CSPLAT_E_INVALID, "last_stats: NULL argument");
+    *stats = ctx->stats;
+    stats->kernel_ms = -1.f;
+    if (ctx->timing && ctx->timed) {
+        DeviceGuard g(ctx->device);
+        CSPLAT_HIP(hipEventSynchronize(ctx->ev1));
+        float ms = 0.f;
+        CSPLAT_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        stats->kernel_ms = ms;
+    }
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_synchronize(csplat_ctx *ctx)
+{
+    if (!ctx) return fail(CSPLAT_E_INVALID, "synchronize: NULL ctx");
+    DeviceGuard g(ctx->device);
+    CSPLAT_HIP(hipStreamSynchronize(ctx->stream));
+    return CSPLAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,291 @@
+// The float32 pair kernel: every (query sphere, kept Gaussian) pair of the
+// neighbourhood ball evaluated with Eq. 5, 7, 8 and folded into per-query
+// reductions (count/label of Sec. II-E, min and the stable softmin of
+// Sec. II-B, the averaged cost of Eq. 11).
+//
+// Layout and mapping on gfx950:
+//  * one query per lane, 256 lanes (4 waves) per block; the query's centre,
+//    r^2 and accumulators live in VGPRs;
+//  * the Gaussian records are wave-uniform: every lane of a wave needs the
+//    same Gaussian at the same time, so they are fetched with scalar loads
+//    into SGPRs and used directly as VALU operands (no LDS round trip, no
+//    VGPRs spent on them, no bank conflicts);
+//  * the Gaussian list is cut into `splits` contiguous ranges so that small
+//    query batches still fill the 256 CUs; blocks are mapped XCD-major so the
+//    blocks of one XCD share a range in their L2; partial reductions are
+//    merged in a fixed order by combine_kernel (bit-reproducible results).
+#include <cmath>
+
+#include "internal.h"
+
+namespace csplat {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kChunk = 512;  // Gaussians per first-level softmin/cost sum
+
+__device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+struct Part {
+    int32_t *cnt;  // [split][v][q]
+    float *mt;     // running minimum of t = s~^2 * kt
+    float *sm;     // sum of 2^(mt - t)
+    float *cs;     // sum of the base-2 cost terms
+    int32_t *nb;   // [split][q] neighbourhood size
+};
+
+// Ball membership and the per-pair metric.  Terms in "r^2 units": with
+// d = mu - c, D = |d|^2 and V = |M d|^2 = d^T Sigma d,
+//   r^2 s^2 = D,  r^2 n sqrt(sigma^2) = 2 n sqrt(V),  r^2 s~^2 = max(0, D - 2 n sqrt(V)).
+template <int M, bool FULL, bool BALL>
+__global__ void __launch_bounds__(kBlock)
+pair_kernel(const float *__restrict__ gs, int n, int per_split, int n_tiles,
+            const float *__restrict__ centers, const float *__restrict__ radii, int q,
+            const EvalParams p, Part part)
+{
+    int b = blockIdx.x;
+    const int B = gridDim.x;
+    if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few ranges
+    const int split = b / n_tiles;
+    const int tile = b - split * n_tiles;
+    const int j = tile * kBlock + (int)threadIdx.x;
+    const int jj = j < q ? j : q - 1;  // lanes past the end evaluate a real query, write nothing
+    const float cx = centers[3 * jj], cy = centers[3 * jj + 1], cz = centers[3 * jj + 2];
+    const float r = radii[jj];
+    const float r2 = r * r;
+    const float kq = p.kt / r2;  // t = max(0, r^2 s~^2) * kq = s~^2 * kt
+
+    int cnt[M];
+    float mt[M], sm[M], cs[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        cnt[v] = 0;
+        mt[v] = INFINITY;
+        sm[v] = 0.f;
+        cs[v] = 0.f;
+    }
+    int nb = 0;
+
+    const int g0 = split * per_split;
+    const int g1 = min(n, g0 + per_split);
+    // The softmin and cost sums are accumulated per chunk of kChunk Gaussians
+    // and folded into the lane totals at the end of each chunk (two-level
+    // summation keeps the float32 rounding of long sums near sqrt(kChunk) ulps).
+    for (int c0 = g0; c0 < g1; c0 += kChunk) {
+        const int c1 = min(g1, c0 + kChunk);
+        float cmt[M], csm[M], ccs[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            cmt[v] = INFINITY;
+            csm[v] = 0.f;
+            ccs[v] = 0.f;
+        }
+        const float *gp = gs + (size_t)kGaussFloats * c0;
+        for (int g = c0; g < c1; ++g, gp += kGaussFloats) {
+            const float dx = gp[0] - cx, dy = gp[1] - cy, dz = gp[2] - cz;
+            if constexpr (FULL) {
+                const float D = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (!BALL || D <= p.rn2) {
+                    ++nb;
+                    const float e0 = fmaf(gp[5], dz, fmaf(gp[4], dy, gp[3] * dx));
+                    const float e1 = fmaf(gp[8], dz, fmaf(gp[7], dy, gp[6] * dx));
+                    const float e2 = fmaf(gp[11], dz, fmaf(gp[10], dy, gp[9] * dx));
+                    const float sv = fast_sqrt(fmaf(e2, e2, fmaf(e1, e1, e0 * e0)));
+#pragma unroll
+                    for (int v = 0; v < M; ++v) {
+                        const float x = fmaf(-p.two_n[v], sv, D);  // r^2 (s^2 - n sqrt(sigma^2))
+                        cnt[v] += x < r2;                           // s~^2 < 1
+                        const float t = fmaxf(x, 0.f) * kq;
+                        // stable log-sum-exp about the running chunk minimum (one exp per pair)
+                        const float e = fast_exp2(-fabsf(t - cmt[v]));
+                        const bool lower = t < cmt[v];
+                        csm[v] = lower ? fmaf(csm[v], e, 1.f) : csm[v] + e;
+                        cmt[v] = lower ? t : cmt[v];
+                        ccs[v] += fast_exp2(fminf(fmaf(t, -p.g1, p.g0), 0.f));
+                    }
+                }
+            } else {
+                // labels only: s~^2 < 1  <=>  a |a| < 4 n^2 V  with a = D - r^2 (exact rewrite)
+                const float a = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -r2)));
+                const float e0 = fmaf(gp[5], dz, fmaf(gp[4], dy, gp[3] * dx));
+                const float e1 = fmaf(gp[8], dz, fmaf(gp[7], dy, gp[6] * dx));
+                const float e2 = fmaf(gp[11], dz, fmaf(gp[10], dy, gp[9] * dx));
+                const float V = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
+                const float aa = a * fabsf(a);
+                bool in = true;
+                if constexpr (BALL) in = a + r2 <= p.rn2;
+#pragma unroll
+                for (int v = 0; v < M; ++v) cnt[v] += in && (aa < p.four_n2[v] * V);
+            }
+        }
+        if constexpr (FULL) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                cs[v] += ccs[v];
+                if (cmt[v] < mt[v]) {
+                    sm[v] = fmaf(sm[v], fast_exp2(mt[v] == INFINITY ? -INFINITY : cmt[v] - mt[v]), csm[v]);
+                    mt[v] = cmt[v];
+                } else if (cmt[v] < INFINITY) {
+                    sm[v] = fmaf(csm[v], fast_exp2(mt[v] - cmt[v]), sm[v]);
+                }
+            }
+        }
+    }
+    if (j >= q) return;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        const size_t o = ((size_t)split * M + v) * q + j;
+        part.cnt[o] = cnt[v];
+        if constexpr (FULL) {
+            part.mt[o] = mt[v];
+            part.sm[o] = sm[v];
+            part.cs[o] = cs[v];
+        }
+    }
+    if constexpr (FULL) part.nb[(size_t)split * q + j] = nb;
+}
+
+// Merge the split partials in split order and finalise every output.
+template <int M, bool FULL>
+__global__ void __launch_bounds__(256)
+combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    int nb = 0;
+    if constexpr (FULL)
+        for (int s = 0; s < S; ++s) nb += part.nb[(size_t)s * q + j];
+    if (out.nbr) out.nbr[j] = nb;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        int cnt = 0;
+        float mt = INFINITY, sm = 0.f, cs = 0.f;
+        for (int s = 0; s < S; ++s) {
+            const size_t o = ((size_t)s * M + v) * q + j;
+            cnt += part.cnt[o];
+            if constexpr (FULL) {
+                const float bm = part.mt[o], bs = part.sm[o];
+                cs += part.cs[o];
+                if (bm < INFINITY) {
+                    if (bm < mt) {
+                        sm = fmaf(sm, fast_exp2(mt == INFINITY ? -INFINITY : bm - mt), bs);
+                        mt = bm;
+                    } else {
+                        sm = fmaf(bs, fast_exp2(mt - bm), sm);
+                    }
+                }
+            }
+        }
+        const size_t o = (size_t)j * p.m + v;
+        if (out.count) out.count[o] = cnt;
+        if (out.label) out.label[o] = cnt > p.k ? 1 : 0;
+        if constexpr (FULL) {
+            const float mn = mt * p.inv_kt;
+            if (out.min) out.min[o] = mn;
+            if (out.softmin)
+                out.softmin[o] = (!p.soft || mt == INFINITY) ? mn : (mt - fast_log2(sm)) * p.inv_kt;
+            if (out.cost) out.cost[o] = nb > 0 ? p.d_max * (cs / (float)nb) : 0.f;
+        }
+    }
+}
+
+template <int M, bool FULL, bool BALL>
+void launch_pair(dim3 grid, hipStream_t st, const float *gs, int n, int per_split, int n_tiles,
+                 const float *c, const float *r, int q, const EvalParams &p, const Part &part)
+{
+    pair_kernel<M, FULL, BALL><<<grid, kBlock, 0, st>>>(gs, n, per_split, n_tiles, c, r, q, p, part);
+}
+
+template <int M>
+void launch_m(csplat_ctx *ctx, bool full, bool ball, dim3 grid, hipStream_t st, const float *gs, int n,
+              int per_split, int n_tiles, const float *c, const float *r, int q,
+              const EvalParams &p, const Part &part, int S, const EvalOut &out)
+{
+    if (n > 0) {
+        timing_begin(ctx);
+        if (full && ball) launch_pair<M, true, true>(grid, st, gs, n, per_split, n_tiles, c, r, q, p, part);
+        else if (full) launch_pair<M, true, false>(grid, st, gs, n, per_split, n_tiles, c, r, q, p, part);
+        else if (ball) launch_pair<M, false, true>(grid, st, gs, n, per_split, n_tiles, c, r, q, p, part);
+        else launch_pair<M, false, false>(grid, st, gs, n, per_split, n_tiles, c, r, q, p, part);
+        timing_end(ctx);
+    }
+    const int cb = (q + 255) / 256;
+    if (full) combine_kernel<M, true><<<cb, 256, 0, st>>>(q, S, p, part, out);
+    else combine_kernel<M, false><<<cb, 256, 0, st>>>(q, S, p, part, out);
+}
+
+int device_cus(int dev)
+{
+    static int cache[64] = {0};
+    if (dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+}  // namespace
+
+csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
+                        const float *radii, const EvalParams &p, const EvalOut &out,
+                        bool labels_only)
+{
+    const int q = (int)q64;
+    const int n = (int)sc->n;
+    const bool full = !labels_only;
+    const bool ball = std::isfinite(p.rn2);
+    const int n_tiles = (q + kBlock - 1) / kBlock;
+    // enough blocks to fill every CU several times over, ranges of >= 1024 Gaussians
+    const int target = device_cus(ctx->device) * 8;
+    int S = 1;
+    if (n > 0) {
+        S = (target + n_tiles - 1) / n_tiles;
+        S = std::max(1, std::min(S, (n + 1023) / 1024));
+    }
+    const int per_split = n > 0 ? (n + S - 1) / S : 0;
+    if (n > 0) S = (n + per_split - 1) / per_split;
+    const int M = p.m;
+    const size_t per = (size_t)S * q;
+    const size_t words = per * (size_t)M * (full ? 4 : 1) + (full ? per : 0);
+    if (words > 0) {
+        hipError_t e = ctx->partial.reserve(words * 4);
+        if (e != hipSuccess) return hip_fail(e, "partial workspace");
+    }
+    char *base = ctx->partial.as<char>();
+    Part part{};
+    part.cnt = reinterpret_cast<int32_t *>(base);
+    if (full) {
+        part.mt = reinterpret_cast<float *>(base + per * M * 4);
+        part.sm = reinterpret_cast<float *>(base + per * M * 8);
+        part.cs = reinterpret_cast<float *>(base + per * M * 12);
+        part.nb = reinterpret_cast<int32_t *>(base + per * M * 16);
+    }
+    ctx->stats.splits = S;
+    ctx->stats.queries_per_lane = 1;
+    ctx->stats.kernel_pairs = (int64_t)q * n;
+    dim3 grid((unsigned)(n_tiles * S));
+    hipStream_t st = ctx->stream;
+    const float *gs = sc->gauss;
+    const int S_used = n > 0 ? S : 0;
+    switch (M) {
+    case 1: launch_m<1>(ctx, full, ball, grid, st, gs, n, per_split, n_tiles, centers, radii, q, p, part, S_used, out); break;
+    case 2: launch_m<2>(ctx, full, ball, grid, st, gs, n, per_split, n_tiles, centers, radii, q, p, part, S_used, out); break;
+    case 3: launch_m<3>(ctx, full, ball, grid, st, gs, n, per_split, n_tiles, centers, radii, q, p, part, S_used, out); break;
+    case 4: launch_m<4>(ctx, full, ball, grid, st, gs, n, per_split, n_tiles, centers, radii, q, p, part, S_used, out); break;
+    case 5: launch_m<5>(ctx, full, ball, grid, st, gs, n, per_split, n_tiles, centers, radii, q, p, part, S_used, out); break;
+    case 6: launch_m<6>(ctx, full, ball, grid, st, gs, n, per_split, n_tiles, centers, radii, q, p, part, S_used, out); break;
+    case 7: launch_m<7>(ctx, full, ball, grid, st, gs, n, per_split, n_tiles, centers, radii, q, p, part, S_used, out); break;
+    case 8: launch_m<8>(ctx, full, ball, grid, st, gs, n, per_split, n_tiles, centers, radii, q, p, part, S_used, out); break;
+    default: return fail(CSPLAT_E_INVALID, "m out of range");
+    }
+    CSPLAT_HIP(hipGetLastError());
+    return CSPLAT_OK;
+}
+
+}  // namespace csplat

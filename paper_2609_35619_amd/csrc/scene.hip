@@ -1,0 +1,286 @@
+// Scene loading on the device: validation, activation, the floater filter,
+// the M = diag(s) R^T factorisation of Sigma (Eq. 2) and a Morton-order
+// layout of the kept Gaussians.
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace csplat {
+
+namespace {
+
+// Order-preserving map of a float onto a signed int, for atomic min/max.
+__device__ inline int float_key(float f)
+{
+    int i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+
+__host__ __device__ inline float key_float(int k)
+{
+    int i = k >= 0 ? k : k ^ 0x7FFFFFFF;
+    float f;
+    memcpy(&f, &i, sizeof(f));
+    return f;
+}
+
+enum : int { kErrNonFinite = 1, kErrZeroQuat = 2, kErrNegScale = 4 };
+
+struct PrepOut {
+    float *rec;          // n x 12
+    uint32_t *keep;      // n (0/1)
+    int *err;            // error bits
+    int *bbox;           // 6 keys: min xyz, max xyz (kept only)
+    unsigned long long *n_kept;
+};
+
+// One thread per input Gaussian: validate, activate (raw 3DGS: exp of the
+// log-scale and sigmoid of the logit), apply the floater filter of Sec. II-C
+// and write the float32 record (mu, M = diag(s) R^T) computed in double.
+__global__ void __launch_bounds__(256) prep_kernel(int64_t n, const float *__restrict__ means,
+                                                   const float *__restrict__ quats,
+                                                   const float *__restrict__ scales,
+                                                   const float *__restrict__ opacity, int raw,
+                                                   float alpha_f, float extent_f, PrepOut o)
+{
+    __shared__ int s_box[6][8];
+    __shared__ unsigned s_cnt[8];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int lane_box[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+    unsigned kept = 0;
+    if (i < n) {
+        float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+        float qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+        float s0 = scales[3 * i], s1 = scales[3 * i + 1], s2 = scales[3 * i + 2];
+        float op = opacity[i];
+        int err = 0;
+        if (!isfinite(mx) || !isfinite(my) || !isfinite(mz) || !isfinite(qw) || !isfinite(qx) ||
+            !isfinite(qy) || !isfinite(qz) || !isfinite(s0) || !isfinite(s1) || !isfinite(s2) ||
+            !isfinite(op))
+            err |= kErrNonFinite;
+        double qq = (double)qw * qw + (double)qx * qx + (double)qy * qy + (double)qz * qz;
+        if (qq == 0.0)
+            err |= kErrZeroQuat;
+        if (!raw && (s0 < 0.f || s1 < 0.f || s2 < 0.f))
+            err |= kErrNegScale;
+        if (err) {
+            atomicOr(o.err, err);
+            o.keep[i] = 0;
+        } else {
+            double s[3] = {s0, s1, s2};
+            double alpha = op;
+            if (raw) {
+                for (int k = 0; k < 3; ++k) s[k] = exp(s[k]);
+                alpha = 1.0 / (1.0 + exp(-alpha));
+            }
+            double smax = fmax(s[0], fmax(s[1], s[2]));
+            bool drop = alpha_f > 0.f && alpha < (double)alpha_f && smax > (double)extent_f;
+            o.keep[i] = drop ? 0u : 1u;
+            if (!drop) {
+                double inv = 1.0 / sqrt(qq);
+                double w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
+                // R(q), (w, x, y, z) Hamilton convention; column k is the local axis k
+                double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                                  {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                                  {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+                float *r = o.rec + (size_t)12 * i;
+                r[0] = mx;
+                r[1] = my;
+                r[2] = mz;
+                for (int k = 0; k < 3; ++k)       // row k of M = s_k * (column k of R)^T
+                    for (int c = 0; c < 3; ++c) r[3 + 3 * k + c] = (float)(s[k] * R[c][k]);
+                lane_box[0] = lane_box[3] = float_key(mx);
+                lane_box[1] = lane_box[4] = float_key(my);
+                lane_box[2] = lane_box[5] = float_key(mz);
+                kept = 1;
+            }
+        }
+    }
+    // wave then block reduction of the bounding box and the kept count
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int k = 0; k < 3; ++k) lane_box[k] = min(lane_box[k], __shfl_xor(lane_box[k], off));
+        for (int k = 3; k < 6; ++k) lane_box[k] = max(lane_box[k], __shfl_xor(lane_box[k], off));
+        kept += __shfl_xor(kept, off);
+    }
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        for (int k = 0; k < 6; ++k) s_box[k][wave] = lane_box[k];
+        s_cnt[wave] = kept;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nw = blockDim.x >> 6;
+        unsigned c = 0;
+        for (int w = 0; w < nw; ++w) c += s_cnt[w];
+        if (c) {
+            atomicAdd(o.n_kept, (unsigned long long)c);
+            for (int k = 0; k < 3; ++k) {
+                int a = s_box[k][0], b = s_box[k + 3][0];
+                for (int w = 1; w < nw; ++w) {
+                    a = min(a, s_box[k][w]);
+                    b = max(b, s_box[k + 3][w]);
+                }
+                atomicMin(o.bbox + k, a);
+                atomicMax(o.bbox + k + 3, b);
+            }
+        }
+    }
+}
+
+__device__ inline uint32_t spread3(uint32_t v)  // 10 bits -> every third bit
+{
+    v &= 0x3FF;
+    v = (v | (v << 16)) & 0x030000FF;
+    v = (v | (v << 8)) & 0x0300F00F;
+    v = (v | (v << 4)) & 0x030C30C3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+}
+
+// 30-bit Morton code of the kept means over the kept bounding box; dropped
+// Gaussians get 0xFFFFFFFF and sort behind every kept one.
+__global__ void morton_kernel(int64_t n, const float *__restrict__ rec, const uint32_t *__restrict__ keep,
+                              float3 lo, float3 scale, uint32_t *__restrict__ code,
+                              uint32_t *__restrict__ idx)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c = 0xFFFFFFFFu;
+    if (keep[i]) {
+        const float *r = rec + (size_t)12 * i;
+        float fx = (r[0] - lo.x) * scale.x, fy = (r[1] - lo.y) * scale.y, fz = (r[2] - lo.z) * scale.z;
+        uint32_t ix = (uint32_t)fminf(fmaxf(fx, 0.f), 1023.f);
+        uint32_t iy = (uint32_t)fminf(fmaxf(fy, 0.f), 1023.f);
+        uint32_t iz = (uint32_t)fminf(fmaxf(fz, 0.f), 1023.f);
+        c = spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2);
+    }
+    code[i] = c;
+    idx[i] = (uint32_t)i;
+}
+
+__global__ void gather_kernel(int64_t n_kept, const float *__restrict__ rec,
+                              const uint32_t *__restrict__ order, float *__restrict__ out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one float per thread
+    if (t >= n_kept * 12) return;
+    int64_t k = t / 12;
+    int c = (int)(t - k * 12);
+    out[t] = rec[(size_t)12 * order[k] + c];
+}
+
+struct Tmp {
+    std::vector<void *> ptrs;
+    ~Tmp()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <class T> hipError_t alloc(T **p, size_t bytes)
+    {
+        void *v = nullptr;
+        hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+        if (e == hipSuccess) ptrs.push_back(v);
+        *p = static_cast<T *>(v);
+        return e;
+    }
+};
+
+}  // namespace
+
+csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const float *quats,
+                          const float *scales, const float *opacity,
+                          const csplat_scene_opts &opts, csplat_scene *sc)
+{
+    hipStream_t st = ctx->stream;
+    sc->device = ctx->device;
+    sc->n_input = n;
+    sc->n = 0;
+    if (n == 0) return CSPLAT_OK;
+    if (n > (int64_t)0x7FFFFFFF)
+        return fail(CSPLAT_E_INVALID, "scene_load: more than 2^31-1 Gaussians");
+    Tmp tmp;
+    float *d_in = nullptr, *d_rec = nullptr;
+    uint32_t *d_keep = nullptr, *d_code = nullptr, *d_idx = nullptr, *d_code2 = nullptr,
+             *d_idx2 = nullptr;
+    int *d_misc = nullptr;  // err, bbox[6]
+    unsigned long long *d_cnt = nullptr;
+    size_t nn = (size_t)n;
+    if (tmp.alloc(&d_in, nn * 11 * sizeof(float)) != hipSuccess ||
+        tmp.alloc(&d_rec, nn * 12 * sizeof(float)) != hipSuccess ||
+        tmp.alloc(&d_keep, nn * 4) != hipSuccess || tmp.alloc(&d_code, nn * 4) != hipSuccess ||
+        tmp.alloc(&d_idx, nn * 4) != hipSuccess || tmp.alloc(&d_code2, nn * 4) != hipSuccess ||
+        tmp.alloc(&d_idx2, nn * 4) != hipSuccess || tmp.alloc(&d_misc, 8 * sizeof(int)) != hipSuccess ||
+        tmp.alloc(&d_cnt, sizeof(unsigned long long)) != hipSuccess)
+        return fail(CSPLAT_E_OOM, "scene_load: device allocation failed");
+    float *d_means = d_in, *d_quats = d_in + 3 * nn, *d_scales = d_in + 7 * nn, *d_op = d_in + 10 * nn;
+    CSPLAT_HIP(hipMemcpyAsync(d_means, means, nn * 12, hipMemcpyHostToDevice, st));
+    CSPLAT_HIP(hipMemcpyAsync(d_quats, quats, nn * 16, hipMemcpyHostToDevice, st));
+    CSPLAT_HIP(hipMemcpyAsync(d_scales, scales, nn * 12, hipMemcpyHostToDevice, st));
+    CSPLAT_HIP(hipMemcpyAsync(d_op, opacity, nn * 4, hipMemcpyHostToDevice, st));
+    int init[8] = {0, INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN, 0};
+    CSPLAT_HIP(hipMemcpyAsync(d_misc, init, sizeof(init), hipMemcpyHostToDevice, st));
+    CSPLAT_HIP(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), st));
+    PrepOut po{d_rec, d_keep, d_misc, d_misc + 1, d_cnt};
+    int blocks = (int)((n + 255) / 256);
+    prep_kernel<<<blocks, 256, 0, st>>>(n, d_means, d_quats, d_scales, d_op,
+                                        opts.param_mode == CSPLAT_PARAM_RAW_3DGS,
+                                        opts.floater_opacity_max, opts.floater_extent_min, po);
+    CSPLAT_HIP(hipGetLastError());
+    int misc[8];
+    unsigned long long kept = 0;
+    CSPLAT_HIP(hipMemcpyAsync(misc, d_misc, sizeof(misc), hipMemcpyDeviceToHost, st));
+    CSPLAT_HIP(hipMemcpyAsync(&kept, d_cnt, sizeof(kept), hipMemcpyDeviceToHost, st));
+    CSPLAT_HIP(hipStreamSynchronize(st));
+    if (misc[0]) {
+        std::string why;
+        if (misc[0] & kErrNonFinite) why += " non-finite value;";
+        if (misc[0] & kErrZeroQuat) why += " zero quaternion;";
+        if (misc[0] & kErrNegScale) why += " negative scale;";
+        return fail(CSPLAT_E_INVALID, "scene_load: invalid Gaussian parameters:" + why);
+    }
+    sc->n = (int64_t)kept;
+    if (kept == 0) return CSPLAT_OK;
+    float lo[3], hi[3], scl[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = key_float(misc[1 + k]);
+        hi[k] = key_float(misc[4 + k]);
+        float ext = hi[k] - lo[k];
+        scl[k] = ext > 0.f ? 1023.999f / ext : 0.f;
+    }
+    morton_kernel<<<blocks, 256, 0, st>>>(n, d_rec, d_keep, make_float3(lo[0], lo[1], lo[2]),
+                                          make_float3(scl[0], scl[1], scl[2]), d_code, d_idx);
+    CSPLAT_HIP(hipGetLastError());
+    size_t tbytes = 0;
+    CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, d_code, d_code2, d_idx, d_idx2,
+                                                  (int)n, 0, 32, st));
+    void *d_tmp = nullptr;
+    if (tmp.alloc(&d_tmp, tbytes) != hipSuccess)
+        return fail(CSPLAT_E_OOM, "scene_load: sort workspace");
+    CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(d_tmp, tbytes, d_code, d_code2, d_idx, d_idx2,
+                                                  (int)n, 0, 32, st));
+    float *g = nullptr;
+    if (hipMalloc(&g, (size_t)kept * 12 * sizeof(float)) != hipSuccess)
+        return fail(CSPLAT_E_OOM, "scene_load: scene allocation");
+    sc->gauss = g;
+    sc->device_bytes += (uint64_t)kept * 12 * sizeof(float);
+    int64_t tot = (int64_t)kept * 12;
+    gather_kernel<<<(int)((tot + 255) / 256), 256, 0, st>>>((int64_t)kept, d_rec, d_idx2, g);
+    CSPLAT_HIP(hipGetLastError());
+    CSPLAT_HIP(hipStreamSynchronize(st));
+    return CSPLAT_OK;
+}
+
+void scene_release(csplat_scene *sc)
+{
+    if (!sc) return;
+    void *ptrs[] = {sc->gauss, sc->tile_origin, sc->tile_bound, sc->feat_bf16, sc->feat_fp16};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    sc->gauss = nullptr;
+    sc->tile_origin = sc->tile_bound = nullptr;
+    sc->feat_bf16 = sc->feat_fp16 = nullptr;
+}
+
+}  // namespace csplat

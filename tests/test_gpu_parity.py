@@ -1,0 +1,266 @@
+"""Parity of the float32 HIP path (through the C ABI) with the FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from parity import compare
+from workloads import Queries, Scene, common_attrs, config, uniform_box_scene, uniform_queries
+
+pytestmark = pytest.mark.gpu
+
+ALL = ("label", "count", "min", "softmin", "cost", "nbr")
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2609_35619_amd as cs
+    cs.load_library()
+    return cs
+
+
+@pytest.fixture(scope="module")
+def eng(cs):
+    e = cs.Engine(0)
+    yield e
+    e.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(cs, eng, scene, queries, p, want=ALL, scene_handle=None, host=False, raw=False):
+    import torch
+    sc = scene_handle
+    if sc is None:
+        sc = eng.load_scene(scene, floater_opacity_max=p.get("alpha_f", 0.0),
+                            floater_extent_min=p.get("extent_f", 0.0),
+                            param_mode=cs.CSPLAT_PARAM_RAW_3DGS if raw else cs.CSPLAT_PARAM_ACTIVATED)
+    eng.set_conservatism(p["n_sigma"])
+    opts = cs.reduce_opts(k=p.get("k", 0), tau=p.get("tau", 0.0), r_nbr=p.get("r_nbr", math.inf),
+                          d_max=p.get("d_max", 1.0), gamma=p.get("gamma", 1.0), s_min=p.get("s_min", 1.0))
+    if host:
+        out = eng.evaluate(sc, queries.centers, queries.radii, opts, want)
+        res = {k: np.array(v) for k, v in out.items()}
+    else:
+        c = torch.from_numpy(queries.centers).cuda()
+        r = torch.from_numpy(queries.radii).cuda()
+        out = eng.evaluate(sc, c, r, opts, want)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.items()}
+    if scene_handle is None:
+        cs.csplat_scene_free(sc)
+    return res
+
+
+def _oracle(oracle_mod, scene, queries, p, raw=False):
+    return oracle_mod.evaluate_spheres(scene, queries, p["n_sigma"], raw_mode=raw,
+                                       alpha_f=p.get("alpha_f", 0.0), extent_f=p.get("extent_f", 0.0),
+                                       k=p.get("k", 0), tau=p.get("tau", 0.0),
+                                       r_nbr=p.get("r_nbr", math.inf), d_max=p.get("d_max", 1.0),
+                                       gamma=p.get("gamma", 1.0), s_min=p.get("s_min", 1.0))
+
+
+def _check(gpu, ref, p, where):
+    st = compare(gpu, ref, tau=p.get("tau", 0.0), gamma=p.get("gamma", 1.0), d_max=p.get("d_max", 1.0),
+                 where=where)
+    _say(f"{where}: {st}")
+    return st
+
+
+# --- the small configuration, every query, every output ----------------------
+
+def test_tiny_every_output(cs, eng, oracle_mod):
+    _say("case: tiny config, 10k Gaussians x 4096 queries, all outputs")
+    sc, qs, p = config("tiny")
+    gpu = _run(cs, eng, sc, qs, p)
+    ref = _oracle(oracle_mod, sc, qs, p)
+    _check(gpu, ref, p, "tiny")
+
+
+@pytest.mark.parametrize("name,scale", [("mppi_nav", 0.02), ("manip", 0.004), ("precision", 0.002)])
+def test_scaled_configs(cs, eng, oracle_mod, name, scale):
+    _say(f"case: {name} at scale {scale}")
+    sc, qs, p = config(name, scale)
+    gpu = _run(cs, eng, sc, qs, p)
+    ref = _oracle(oracle_mod, sc, qs, p)
+    _check(gpu, ref, p, f"{name}@{scale}")
+
+
+@pytest.mark.parametrize("r_nbr", [math.inf, 0.4])
+def test_labels_only_path(cs, eng, oracle_mod, r_nbr):
+    _say(f"case: labels-only kernel, r_nbr={r_nbr}")
+    sc = uniform_box_scene(3000, seed=201, box=(2, 2, 1))
+    qs = uniform_queries(777, seed=202, box=(2, 2, 1), radius=0.12)
+    p = dict(n_sigma=[0.0, 0.5, 1.0, 3.0], k=1, r_nbr=r_nbr)
+    gpu = _run(cs, eng, sc, qs, p, want=("label", "count"))
+    ref = _oracle(oracle_mod, sc, qs, p)
+    _check(gpu, ref, p, "labels-only")
+
+
+def test_host_and_device_pointers_agree(cs, eng):
+    _say("case: host vs device pointers")
+    sc, qs, p = config("mppi_nav", 0.01)
+    a = _run(cs, eng, sc, qs, p)
+    b = _run(cs, eng, sc, qs, p, host=True)
+    for k in ALL:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_bit_reproducible(cs, eng):
+    _say("case: repeat runs are bit-identical")
+    sc, qs, p = config("tiny", 0.5)
+    a = _run(cs, eng, sc, qs, p)
+    b = _run(cs, eng, sc, qs, p)
+    for k in ALL:
+        assert np.array_equal(a[k], b[k]), k
+
+
+# --- edge cases ---------------------------------------------------------------
+
+def _scene(means, quats, scales, opacity=None):
+    means = np.asarray(means, np.float32).reshape(-1, 3)
+    n = means.shape[0]
+    if opacity is None:
+        opacity = np.full(n, 0.9, np.float32)
+    return Scene(means, np.asarray(quats, np.float32).reshape(n, 4),
+                 np.asarray(scales, np.float32).reshape(n, 3), np.asarray(opacity, np.float32))
+
+
+def test_empty_scene_and_filtered_scene(cs, eng, oracle_mod):
+    _say("case: empty scene, fully filtered scene")
+    qs = uniform_queries(300, seed=5)
+    p = dict(n_sigma=[1.0], tau=0.1, k=0)
+    empty = _scene(np.zeros((0, 3)), np.zeros((0, 4)), np.zeros((0, 3)), np.zeros(0))
+    gpu = _run(cs, eng, empty, qs, p)
+    assert np.all(gpu["count"] == 0) and np.all(gpu["label"] == 0) and np.all(gpu["nbr"] == 0)
+    assert np.all(np.isinf(gpu["min"])) and np.all(np.isinf(gpu["softmin"])) and np.all(gpu["cost"] == 0)
+    floaters = _scene(np.random.default_rng(0).uniform(0, 4, (50, 3)), np.tile([1, 0, 0, 0], (50, 1)),
+                      np.full((50, 3), 0.5), np.full(50, 0.01))
+    p2 = dict(p, alpha_f=0.05, extent_f=0.1)
+    gpu = _run(cs, eng, floaters, qs, p2)
+    ref = _oracle(oracle_mod, floaters, qs, p2)
+    assert np.all(ref["nbr"] == 0)
+    _check(gpu, ref, p2, "filtered")
+
+
+def test_single_query_and_degenerate_pairs(cs, eng, oracle_mod):
+    _say("case: one query; a query on a Gaussian mean; zero-scale axes; far queries")
+    rng = np.random.default_rng(3)
+    q, s, o = common_attrs(rng, 500)
+    s[:100, 0] = 0.0          # flat (2DGS-like) Gaussians
+    s[100:150] = 0.0          # point Gaussians
+    m = rng.uniform(0, 1, (500, 3)).astype(np.float32)
+    sc = Scene(m, q, s, o)
+    centers = np.concatenate([m[:3], m[100:103], rng.uniform(0, 1, (5, 3)), [[50.0, 50.0, 50.0]]]).astype(np.float32)
+    qs = Queries(centers, np.full(centers.shape[0], 0.07, np.float32))
+    p = dict(n_sigma=[0.0, 1.0, 2.5], tau=0.05, k=0, gamma=2.0, d_max=3.0)
+    gpu = _run(cs, eng, sc, qs, p)
+    ref = _oracle(oracle_mod, sc, qs, p)
+    _check(gpu, ref, p, "degenerate")
+    one = qs.subset([4])
+    gpu1 = _run(cs, eng, sc, one, p)
+    _check(gpu1, _oracle(oracle_mod, sc, one, p), p, "single")
+
+
+@pytest.mark.parametrize("variant", ["m8", "tau0", "gamma0", "tiny_ball", "raw", "big_tau"])
+def test_parameter_variants(cs, eng, oracle_mod, variant):
+    _say(f"case: variant {variant}")
+    sc, qs, p = config("tiny", 0.1)
+    p = dict(p)
+    raw = False
+    if variant == "m8":
+        p["n_sigma"] = [0.0, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0, 4.0]
+    elif variant == "tau0":
+        p["tau"] = 0.0
+    elif variant == "gamma0":
+        p["gamma"] = 0.0
+    elif variant == "tiny_ball":
+        p["r_nbr"] = 0.05
+    elif variant == "big_tau":
+        p["tau"] = 7.5
+    elif variant == "raw":
+        raw = True
+        sc = Scene(sc.means, sc.quats, np.log(sc.scales.astype(np.float64)).astype(np.float32),
+                   np.log(sc.opacity.astype(np.float64) / (1 - sc.opacity.astype(np.float64))).astype(np.float32))
+    gpu = _run(cs, eng, sc, qs, p, raw=raw)
+    ref = _oracle(oracle_mod, sc, qs, p, raw=raw)
+    _check(gpu, ref, p, variant)
+
+
+def test_invalid_inputs_are_rejected_without_writing(cs, eng):
+    import torch
+    _say("case: invalid inputs")
+    sc, qs, p = config("tiny", 0.05)
+    h = eng.load_scene(sc)
+    eng.set_conservatism([1.0])
+    opts = cs.reduce_opts(k=0)
+    for bad in ("nan_center", "zero_radius", "neg_radius"):
+        c = qs.centers.copy()
+        r = qs.radii.copy()
+        if bad == "nan_center":
+            c[3, 1] = np.nan
+        elif bad == "zero_radius":
+            r[7] = 0
+        else:
+            r[0] = -1
+        for dev in (False, True):
+            lab = np.full((qs.q, 1), 7, np.uint8)
+            if dev:
+                cc, rr, ll = torch.from_numpy(c).cuda(), torch.from_numpy(r).cuda(), torch.from_numpy(lab).cuda()
+            else:
+                cc, rr, ll = c, r, lab
+            with pytest.raises(cs.CsplatError) as ei:
+                cs.csplat_eval_labels(eng.ctx, h, cc, rr, opts, ll)
+            assert ei.value.status == cs.CSPLAT_E_INVALID
+            got = ll.cpu().numpy() if dev else ll
+            assert np.all(got == 7), "outputs written on error"
+    for ns in ([-1.0], [float("nan")], [1.0] * 9):
+        with pytest.raises(cs.CsplatError):
+            cs.csplat_set_conservatism(eng.ctx, ns)
+    with pytest.raises(cs.CsplatError):
+        cs.csplat_eval_labels(eng.ctx, h, qs.centers, qs.radii, cs.reduce_opts(k=-1), np.zeros((qs.q, 1), np.uint8))
+    with pytest.raises(cs.CsplatError):
+        cs.csplat_eval_labels(eng.ctx, h, qs.centers, qs.radii, cs.reduce_opts(r_nbr=0.0), np.zeros((qs.q, 1), np.uint8))
+    bad_q = sc.quats.copy()
+    bad_q[5] = 0
+    with pytest.raises(cs.CsplatError) as ei:
+        cs.csplat_scene_load(eng.ctx, sc.means, bad_q, sc.scales, sc.opacity)
+    assert ei.value.status == cs.CSPLAT_E_INVALID
+    neg = sc.scales.copy()
+    neg[2, 1] = -0.1
+    with pytest.raises(cs.CsplatError):
+        cs.csplat_scene_load(eng.ctx, sc.means, sc.quats, neg, sc.opacity)
+    # q = 0 is a no-op
+    cs.csplat_eval_labels(eng.ctx, h, np.zeros((0, 3), np.float32), np.zeros(0, np.float32), opts,
+                          np.zeros((0, 1), np.uint8))
+    cs.csplat_scene_free(h)
+
+
+# --- full-size workloads in the launch configuration the benchmark times -------
+
+@pytest.mark.parametrize("name,sample", [("mppi_nav", 384), ("manip", 384), ("precision", 96)])
+def test_full_size_sampled(cs, eng, oracle_mod, name, sample):
+    import torch
+    _say(f"case: full-size {name}, oracle on {sample} sampled queries")
+    sc, qs, p = config(name)
+    want = ALL if name != "precision" else ("label", "count", "min")
+    gpu = _run(cs, eng, sc, qs, p, want=want)
+    idx = np.sort(np.random.default_rng(7).choice(qs.q, sample, replace=False))
+    # the last query is always checked (ragged tail of the final tile)
+    idx = np.unique(np.concatenate([idx, [qs.q - 1]]))
+    ref = _oracle(oracle_mod, sc, qs.subset(idx), p)
+    _check({k: v[idx] for k, v in gpu.items()}, ref, p, f"{name} full")
+    # properties that hold for every query at any size
+    if "count" in gpu:
+        assert np.array_equal(gpu["label"], (gpu["count"] > p["k"]).astype(np.uint8))
+        if gpu["count"].shape[1] > 1:
+            assert np.all(np.diff(gpu["count"], axis=1) >= 0)   # monotone in n_sigma
+    if "min" in gpu and gpu["min"].shape[1] > 1:
+        assert np.all(np.diff(gpu["min"], axis=1) <= 0)
+    del torch

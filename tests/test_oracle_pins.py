@@ -481,3 +481,13 @@ def test_strict_threshold_tie_is_free(oracle_mod):
     out = oracle_mod.evaluate_spheres(sc, qq, [0.0], k=0)
     assert out["min"][0, 0] == 1.0 and out["count"][0, 0] == 0
     assert out["count"][1, 0] == 1
+
+
+def test_ball_band_brackets_ball(oracle_mod):
+    sc = _random_scene(3000, seed=121)
+    qs = uniform_queries(100, seed=122, box=(1, 1, 1), radius=0.05)
+    out = oracle_mod.evaluate_spheres(sc, qs, [1.0], r_nbr=0.3, eps_ball=1e-2)
+    d2 = ((sc.means.astype(np.float64)[None] - qs.centers.astype(np.float64)[:, None]) ** 2).sum(2)
+    assert np.array_equal(out["nbr"], (d2 <= 0.09).sum(1))
+    assert np.array_equal(out["nbr_lo"], (d2 <= 0.09 * (1 - 1e-2)).sum(1))
+    assert np.array_equal(out["nbr_hi"], (d2 <= 0.09 * (1 + 1e-2)).sum(1))
