@@ -53,8 +53,8 @@ def compare(gpu: dict, ref: dict, tau: float, gamma: float, d_max: float = 1.0, 
         stats["softmin_max_rel"] = float(np.max(err / (tol / rtol), initial=0))
     if "cost" in gpu:
         g, o = np.asarray(gpu["cost"], np.float64), ref["cost"]
-        nb_g = np.asarray(gpu["nbr"], np.float64) if "nbr" in gpu else ref["nbr"].astype(np.float64)
-        nb_o = ref["nbr"].astype(np.float64)
+        nb_g = (np.asarray(gpu["nbr"], np.float64) if "nbr" in gpu else ref["nbr"].astype(np.float64))[:, None]
+        nb_o = ref["nbr"].astype(np.float64)[:, None]
         sg, so = g * nb_g, o * nb_o
         # pairs on the ball boundary contribute at most d_max exp(-gamma (s~^2 - 1)) each;
         # bound that by d_max per differing pair times their tiny weight via the band size
@@ -62,6 +62,6 @@ def compare(gpu: dict, ref: dict, tau: float, gamma: float, d_max: float = 1.0, 
         tol = rtol * np.abs(so) * np.maximum(1.0, gamma * ref["tcost"]) + 1e-30 * d_max + extra
         err = np.abs(sg - so)
         assert np.all(err <= tol), f"{where}: cost err {np.max(err / tol):.3g} x tol"
-        nz = so > 0
+        nz = so > 1e-30
         stats["cost_max_rel"] = float(np.max(err[nz] / so[nz], initial=0))
     return stats

@@ -234,10 +234,11 @@ def _axis_rot(axis: str, ang: np.ndarray) -> np.ndarray:
     return np.moveaxis(np.array(m), (0, 1), (-2, -1))
 
 
-def chain_queries(configs: int, steps: int, seed: int, base=(0.75, -0.3, 0.0)) -> Queries:
+def chain_queries(configs: int, steps: int, seed: int, base=(0.75, 0.1, 0.1)) -> Queries:
     """A random 7-link revolute chain (axes z,y,y,z,y,z,y; link lengths
-    U[0.1,0.2] along the local z axis) with 48 spheres placed at equal
-    fractions along the links; joint paths q0 ~ U(-pi/2, pi/2)^7,
+    U[0.1,0.2] along the local z axis) on a 10 cm pedestal near the table's
+    near edge, with 48 spheres placed at equal fractions along the links;
+    joint paths q0 ~ U(-pi/2, pi/2)^7,
     q_{t+1} = q_t + N(0, 0.05^2).  Index = (config * steps + step) * 48 + sphere."""
     rng = _rng(seed)
     lengths = rng.uniform(0.1, 0.2, 7)
