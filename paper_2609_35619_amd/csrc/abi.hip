@@ -24,9 +24,42 @@ csplat_status hip_fail(hipError_t e, const char *what)
     return e == hipErrorOutOfMemory ? CSPLAT_E_OOM : CSPLAT_E_DEVICE;
 }
 
+int target_blocks(int dev)
+{
+    static int cache[64] = {0};
+    if (dev < 0 || dev >= 64) return 2048;
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cache[dev] = v * 8;
+    }
+    return cache[dev];
+}
+
+namespace {
+__global__ void zero_kernel(int32_t *p, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+}  // namespace
+
+hipError_t zero_words(int32_t *p, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    zero_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
 hipError_t DevBuf::reserve(size_t want)
 {
     if (want <= bytes) return hipSuccess;
+    // earlier asynchronous work may still use the old buffer: wait for it
+    if (ptr) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+    }
     release();
     size_t grow = want + want / 4;
     hipError_t e = hipMalloc(&ptr, grow);
@@ -94,6 +127,7 @@ csplat_status build_params(const csplat_ctx *ctx, const csplat_reduce_opts &o, E
     p.k = o.k;
     for (int v = 0; v < ctx->m; ++v) {
         double n = ctx->n_sigma[v];
+        p.n_sigma[v] = ctx->n_sigma[v];
         p.two_n[v] = (float)(2.0 * n);
         p.four_n2[v] = (float)(4.0 * n * n);
     }
@@ -295,13 +329,15 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     std::memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->stats.pairs = q * sc->n;
     ctx->timed = false;
+    ctx->flag_counts = nullptr;
+    ctx->flag_m = 0;
     if (kind == 1) {
         // device inputs: check them on the device before any output is touched
         int *bad = nullptr;
         hipError_t e = ctx->flags.reserve(64);
         if (e != hipSuccess) return hip_fail(e, "flag workspace");
         bad = ctx->flags.as<int>();
-        CSPLAT_HIP(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+        CSPLAT_HIP(zero_words(bad, 1, ctx->stream));
         check_queries_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, radii, bad);
         CSPLAT_HIP(hipGetLastError());
         int hbad = 0;
@@ -393,6 +429,19 @@ csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats)
     if (!ctx || !stats) return fail(CSPLAT_E_INVALID, "last_stats: NULL argument");
     *stats = ctx->stats;
     stats->kernel_ms = -1.f;
+    if (ctx->flag_counts && ctx->flag_m > 0) {  // precision forms: rechecked queries
+        DeviceGuard g(ctx->device);
+        int32_t h[CSPLAT_MAX_M] = {0};
+        CSPLAT_HIP(hipMemcpyAsync(h, ctx->flag_counts, sizeof(int32_t) * ctx->flag_m, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+        CSPLAT_HIP(hipStreamSynchronize(ctx->stream));
+        int64_t tot = 0;
+        for (int v = 0; v < ctx->flag_m; ++v) tot += h[v];
+        stats->flagged = tot;
+        stats->flagged_fp64 = tot;
+        ctx->stats.flagged = tot;
+        ctx->stats.flagged_fp64 = tot;
+    }
     if (ctx->timing && ctx->timed) {
         DeviceGuard g(ctx->device);
         CSPLAT_HIP(hipEventSynchronize(ctx->ev1));

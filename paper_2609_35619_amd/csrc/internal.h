@@ -10,15 +10,11 @@
 
 namespace csplat {
 
-// Per-Gaussian record of the float32 pair kernel: 12 floats, read by scalar
-// (wave-uniform) loads.  M = diag(s) R^T, so that for d = mu - c the
-// linearised variance term V = d^T Sigma d = |M d|^2 is a sum of squares.
-constexpr int kGaussFloats = 12;  // mx my mz | M00 M01 M02 | M10 M11 M12 | M20 M21 M22
-
-// Per-Gaussian record of the MFMA precision form, in tile-local coordinates
-// about the tile origin o_T (16 bf16 or fp16 values per feature row).
-constexpr int kTile = 64;         // Gaussians per precision tile
-constexpr int kFeat = 16;         // padded feature length (K of the contraction)
+// Per-Gaussian record of the float32 pair kernel: 16 floats (64 B), read by
+// scalar (wave-uniform) loads.  M = diag(s) R^T, so that for d = mu - c the
+// linearised variance term V = d^T Sigma d = |M d|^2 is a sum of squares;
+// -2 mu and |mu|^2 serve the neighbourhood pre-test |mu|^2 - 2 mu.c + |c|^2.
+constexpr int kGaussFloats = 16;  // mx my mz | M00..M22 (row-major) | -2mx -2my -2mz | |mu|^2
 
 void set_error(const std::string &msg);
 csplat_status fail(csplat_status code, const std::string &msg);
@@ -45,13 +41,16 @@ struct csplat_scene {
     int device = 0;
     int64_t n_input = 0;
     int64_t n = 0;            // kept Gaussians
-    float *gauss = nullptr;   // n x 12 float32 records, Morton order
-    // precision form (optional)
+    float *gauss = nullptr;   // n x 16 float32 records, Morton order
+    float mu_max = 0.f;       // max |mu| over the kept Gaussians
+    // precision form (optional): per tile of 512 Gaussians the packed MFMA
+    // operands (96 B per Gaussian) and 20 floats of metadata (origin, scale,
+    // coefficient maxima), one set per dtype
     int64_t n_tiles = 0;
-    float *tile_origin = nullptr;   // n_tiles x 4 (ox, oy, oz, 0)
-    float *tile_bound = nullptr;    // n_tiles x 4: max |mu'|, max s, max |Sigma|, max |Sigma mu'|
-    void *feat_bf16 = nullptr;      // n_tiles*kTile x 2 x kFeat bf16 (D row, V row)
+    void *feat_bf16 = nullptr;
+    float *meta_bf16 = nullptr;
     void *feat_fp16 = nullptr;
+    float *meta_fp16 = nullptr;
     uint64_t device_bytes = 0;
 };
 
@@ -63,8 +62,10 @@ struct csplat_ctx {
     float n_sigma[CSPLAT_MAX_M] = {1.0f};
     csplat::DevBuf partial;    // split-N partial reductions
     csplat::DevBuf staging;    // host-pointer staging (inputs + outputs)
-    csplat::DevBuf flags;      // precision form: flagged-query list and counters
+    csplat::DevBuf flags;      // validation flag; precision form: recheck counters
     csplat_eval_stats stats{};
+    int32_t *flag_counts = nullptr;  // device: rechecked queries per n_sigma (last eval)
+    int32_t flag_m = 0;
     bool timing = false;
     bool timed = false;         // events of the last evaluation were recorded
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -85,6 +86,13 @@ inline void timing_end(csplat_ctx *ctx)
     }
 }
 
+// Blocks that fill the device several times over (8 per compute unit).
+int target_blocks(int device);
+inline int ctx_target_blocks(const csplat_ctx *ctx) { return target_blocks(ctx->device); }
+
+// Zero n int32 words on the stream with a kernel (safe under graph capture).
+hipError_t zero_words(int32_t *p, size_t n, hipStream_t st);
+
 // scene.hip
 csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const float *quats,
                           const float *scales, const float *opacity,
@@ -103,6 +111,7 @@ struct EvalParams {
     float d_max;
     float rn2;                    // neighbour radius squared (+inf: all)
     int32_t soft;                 // tau > 0
+    float n_sigma[CSPLAT_MAX_M];  // the conservatism values as given
 };
 
 struct EvalOut {

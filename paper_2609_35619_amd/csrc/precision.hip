@@ -1,17 +1,546 @@
-// MFMA precision form (placeholder until the kernels land).
+// The MFMA precision form of the label path (labels and counts).
+//
+// For a sphere the two quantities that decide a pair are quadratic forms in
+// the query centre (Eq. 5, 7 with A = I / r^2):
+//   a = |mu - c|^2 - r^2                       (r^2 (s^2 - 1))
+//   w = 4 n^2 (mu - c)^T Sigma (mu - c)        (r^4 n^2 sigma^2)
+// and s~^2 < 1  <=>  a |a| < w (Eq. 8 without the square root).  About a
+// tile-local origin o (mu' = mu - o, c' = c - o) both are dot products of
+// query features with per-Gaussian coefficients:
+//   a = [1, c'x, c'y, c'z, |c'|^2 - r^2] . [|mu'|^2, -2mu', 1]
+//   w = 4n^2 [1, c', c'x^2, c'y^2, c'z^2, c'x c'y, c'x c'z, c'y c'z]
+//          . [mu'^T Sigma mu', -2 Sigma mu', Sxx, Syy, Szz, 2Sxy, 2Sxz, 2Syz]
+// so a tile of 32 Gaussians x 32 queries is a dense [32 x K] x [K x 32]
+// contraction on the matrix cores.  Each feature x is split into x_hi + x_lo
+// in bf16 (or fp16) and the contraction sums hi*hi + hi*lo + lo*hi in fp32
+// (three products per feature: K = 15 for a, 30 for w), which brings the
+// representation error to ~3u^2 of each product.  A certified per-pair
+// bound B decides every pair whose |w - a|a|| exceeds it; the counts of
+// certain and of possible collisions bracket the exact count, and only
+// queries whose label the bracket cannot decide are re-evaluated in fp64.
+#include <cmath>
+
 #include "internal.h"
 
 namespace csplat {
 
-csplat_status precision_build(csplat_ctx *, csplat_scene *, uint32_t)
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kPT = 512;             // Gaussians per tile (one origin)
+constexpr int kRB = kPT / 32;        // row blocks (MFMA rows) per tile
+constexpr int kOps = 3;              // operands per row block: a, w0, w1
+constexpr int kMeta = 20;            // floats per tile: o(3), 1/scale, M1[5], M2[10], 0
+constexpr int kLanes = 64;
+constexpr float kU32 = 5.9604645e-08f;  // 2^-24
+
+template <int P>
+struct Prec;
+
+template <>
+struct Prec<CSPLAT_PRECISION_BF16_RECHECK> {
+    using vec = bf16x8;
+    using elem = __bf16;
+    static constexpr float u = 0.00390625f;      // 2^-8: bf16 rounding error bound
+    static constexpr float eta = 0.f;            // no subnormal loss in the bf16 range used
+    static constexpr float far = 1099511627776.f;  // 2^40: padding rows, a = far
+    __device__ static f32x16 mfma(vec a, vec b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Prec<CSPLAT_PRECISION_FP16_RECHECK> {
+    using vec = f16x8;
+    using elem = _Float16;
+    static constexpr float u = 0.00048828125f;   // 2^-11
+    static constexpr float eta = 5.9604645e-08f; // 2^-24: absolute loss of subnormal halves
+    static constexpr float far = 32768.f;
+    __device__ static f32x16 mfma(vec a, vec b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Slot order of the three products inside the K dimension.
+//   a  (16 slots): hi.hi (5) | hi.lo (5) | lo.hi (5) | 0
+//   w  (32 slots): hi.hi (10) | hi.lo (10) | lo.hi (10) | 0 0
+// Gaussian side (A operand) value of slot s, query side (B operand) value:
+__host__ __device__ inline int slot_feat_a(int s) { return s < 15 ? s % 5 : -1; }
+__host__ __device__ inline int slot_part_g_a(int s) { return s < 5 ? 0 : (s < 10 ? 1 : 0); }  // 0 hi, 1 lo
+__host__ __device__ inline int slot_part_q_a(int s) { return s < 10 ? 0 : 1; }
+__host__ __device__ inline int slot_feat_w(int s) { return s < 30 ? s % 10 : -1; }
+__host__ __device__ inline int slot_part_g_w(int s) { return (s >= 10 && s < 20) ? 1 : 0; }
+__host__ __device__ inline int slot_part_q_w(int s) { return s >= 20 ? 1 : 0; }
+
+// ---------------------------------------------------------------------------
+// Load time: one block per tile; thread i holds Gaussian i of the tile.
+template <int P>
+__global__ void __launch_bounds__(kPT)
+build_tiles_kernel(const float *__restrict__ gauss, int64_t n, float *__restrict__ meta,
+                   typename Prec<P>::vec *__restrict__ feat)
 {
-    return fail(CSPLAT_E_INVALID, "precision features are not available in this build");
+    using T = Prec<P>;
+    using elem = typename T::elem;
+    using vec = typename T::vec;
+    __shared__ float red[15][kPT];
+    __shared__ float box[6];
+    __shared__ double s_scale;
+    const int64_t t = blockIdx.x;
+    const int i = threadIdx.x;
+    const int64_t gi = t * kPT + i;
+    const bool valid = gi < n;
+    const float *r = gauss + (size_t)kGaussFloats * (valid ? gi : 0);
+    float mu[3] = {r[0], r[1], r[2]};
+    // tile origin: centre of the bounding box of the tile's means (float32)
+    for (int k = 0; k < 3; ++k) {
+        red[k][i] = valid ? mu[k] : INFINITY;
+        red[3 + k][i] = valid ? mu[k] : -INFINITY;
+    }
+    __syncthreads();
+    if (i < 6) {
+        float v = red[i][0];
+        for (int j = 1; j < kPT; ++j) v = i < 3 ? fminf(v, red[i][j]) : fmaxf(v, red[i][j]);
+        box[i] = v;
+    }
+    __syncthreads();
+    const float o[3] = {0.5f * box[0] + 0.5f * box[3], 0.5f * box[1] + 0.5f * box[4],
+                        0.5f * box[2] + 0.5f * box[5]};
+    double p1[5] = {0, 0, 0, 0, 0}, p2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid) {
+        double mp[3], S[9];
+        for (int k = 0; k < 3; ++k) mp[k] = (double)mu[k] - (double)o[k];  // exact
+        for (int a = 0; a < 3; ++a)  // Sigma = M^T M, M = diag(s) R^T
+            for (int b = 0; b < 3; ++b) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += (double)r[3 + 3 * k + a] * (double)r[3 + 3 * k + b];
+                S[3 * a + b] = acc;
+            }
+        double Sm[3];
+        for (int a = 0; a < 3; ++a) Sm[a] = S[3 * a] * mp[0] + S[3 * a + 1] * mp[1] + S[3 * a + 2] * mp[2];
+        p1[0] = mp[0] * mp[0] + mp[1] * mp[1] + mp[2] * mp[2];
+        p1[1] = -2.0 * mp[0];
+        p1[2] = -2.0 * mp[1];
+        p1[3] = -2.0 * mp[2];
+        p1[4] = 1.0;
+        p2[0] = mp[0] * Sm[0] + mp[1] * Sm[1] + mp[2] * Sm[2];
+        p2[1] = -2.0 * Sm[0];
+        p2[2] = -2.0 * Sm[1];
+        p2[3] = -2.0 * Sm[2];
+        p2[4] = S[0];
+        p2[5] = S[4];
+        p2[6] = S[8];
+        p2[7] = 2.0 * S[1];
+        p2[8] = 2.0 * S[2];
+        p2[9] = 2.0 * S[5];
+    } else {
+        p1[0] = T::far;  // padding row: a = far, w = 0, certainly free
+    }
+    // per-tile power-of-two scale of the w coefficients (keeps fp16 away from
+    // its subnormal range; exact, undone on the query side)
+    double mx2 = 0.0;
+    for (int k = 0; k < 10; ++k) mx2 = fmax(mx2, fabs(p2[k]));
+    red[0][i] = (float)mx2;
+    __syncthreads();
+    if (i == 0) {
+        float v = 0.f;
+        for (int j = 0; j < kPT; ++j) v = fmaxf(v, red[0][j]);
+        s_scale = v > 0.f ? ldexp(1.0, 4 - ilogb((double)v)) : 1.0;
+    }
+    __syncthreads();
+    const double scale = s_scale;
+    for (int k = 0; k < 10; ++k) p2[k] *= scale;
+    // hi/lo split
+    float h1[5], l1[5], h2[10], l2[10];
+    for (int k = 0; k < 5; ++k) {
+        float x = (float)p1[k];
+        h1[k] = (float)(elem)x;
+        l1[k] = (float)(elem)(float)(p1[k] - (double)h1[k]);
+    }
+    for (int k = 0; k < 10; ++k) {
+        float x = (float)p2[k];
+        h2[k] = (float)(elem)x;
+        l2[k] = (float)(elem)(float)(p2[k] - (double)h2[k]);
+    }
+    // packed operand layout: row block rb = i / 32, row m = i % 32; lane m + 32 h
+    // holds K slots 8h .. 8h+7 of each operand
+    const int rb = i >> 5, m = i & 31;
+    for (int h = 0; h < 2; ++h) {
+        const int lane = m + 32 * h;
+        vec va, vw0, vw1;
+        for (int j = 0; j < 8; ++j) {
+            const int sa = 8 * h + j;
+            const int fa = slot_feat_a(sa);
+            va[j] = (elem)(fa < 0 ? 0.f : (slot_part_g_a(sa) ? l1[fa] : h1[fa]));
+            const int s0 = 8 * h + j, s1 = 16 + 8 * h + j;
+            const int f0 = slot_feat_w(s0), f1 = slot_feat_w(s1);
+            vw0[j] = (elem)(f0 < 0 ? 0.f : (slot_part_g_w(s0) ? l2[f0] : h2[f0]));
+            vw1[j] = (elem)(f1 < 0 ? 0.f : (slot_part_g_w(s1) ? l2[f1] : h2[f1]));
+        }
+        const size_t base = ((size_t)(t * kRB + rb) * kOps) * kLanes + lane;
+        feat[base] = va;
+        feat[base + kLanes] = vw0;
+        feat[base + 2 * kLanes] = vw1;
+    }
+    // tile maxima of |hi| over the real rows, for the error bounds
+    __syncthreads();
+    for (int k = 0; k < 5; ++k) red[k][i] = valid ? fabsf(h1[k]) : 0.f;
+    for (int k = 0; k < 10; ++k) red[5 + k][i] = valid ? fabsf(h2[k]) : 0.f;
+    __syncthreads();
+    if (i < 15) {
+        float v = 0.f;
+        for (int j = 0; j < kPT; ++j) v = fmaxf(v, red[i][j]);
+        meta[t * kMeta + 4 + i] = v;
+    }
+    if (i == 0) {
+        meta[t * kMeta + 0] = o[0];
+        meta[t * kMeta + 1] = o[1];
+        meta[t * kMeta + 2] = o[2];
+        meta[t * kMeta + 3] = (float)(1.0 / scale);
+        meta[t * kMeta + 19] = 0.f;
+    }
 }
 
-csplat_status precision_eval(csplat_ctx *, const csplat_scene *, int64_t, const float *, const float *,
-                             const EvalParams &, const EvalOut &, int)
+// ---------------------------------------------------------------------------
+// Query features of one lane (query column, K half h) relative to a tile.
+template <int P>
+struct QFeat {
+    typename Prec<P>::vec a, w0, w1;
+    float two_ea, c0;
+    bool bad;
+};
+
+template <int P>
+__device__ __forceinline__ void build_query(float cx, float cy, float cz, float r2, float four_n2,
+                                            const float *__restrict__ mt, int h, QFeat<P> &Q)
 {
-    return fail(CSPLAT_E_INVALID, "precision forms are not available in this build");
+    using T = Prec<P>;
+    using elem = typename T::elem;
+    const float xp = cx - mt[0], yp = cy - mt[1], zp = cz - mt[2];
+    const float c2 = fmaf(zp, zp, fmaf(yp, yp, xp * xp));
+    const float ph[5] = {1.f, xp, yp, zp, c2 - r2};
+    const float g = four_n2 * mt[3];
+    const float gx = g * xp, gy = g * yp, gz = g * zp;
+    const float ch[10] = {g, gx, gy, gz, gx * xp, gy * yp, gz * zp, gx * yp, gx * zp, gy * zp};
+    float h1[5], l1[5], h2[10], l2[10];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        h1[k] = (float)(elem)ph[k];
+        l1[k] = (float)(elem)(ph[k] - h1[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        h2[k] = (float)(elem)ch[k];
+        l2[k] = (float)(elem)(ch[k] - h2[k]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        // both halves' slot values, then the lane's half
+        const int sa0 = j, sa1 = 8 + j;
+        const int fa0 = slot_feat_a(sa0), fa1 = slot_feat_a(sa1);
+        const float va0 = fa0 < 0 ? 0.f : (slot_part_q_a(sa0) ? l1[fa0] : h1[fa0]);
+        const float va1 = fa1 < 0 ? 0.f : (slot_part_q_a(sa1) ? l1[fa1] : h1[fa1]);
+        Q.a[j] = (elem)(h ? va1 : va0);
+        const int s00 = j, s01 = 8 + j, s10 = 16 + j, s11 = 24 + j;
+        const int f00 = slot_feat_w(s00), f01 = slot_feat_w(s01), f10 = slot_feat_w(s10), f11 = slot_feat_w(s11);
+        const float w00 = f00 < 0 ? 0.f : (slot_part_q_w(s00) ? l2[f00] : h2[f00]);
+        const float w01 = f01 < 0 ? 0.f : (slot_part_q_w(s01) ? l2[f01] : h2[f01]);
+        const float w10 = f10 < 0 ? 0.f : (slot_part_q_w(s10) ? l2[f10] : h2[f10]);
+        const float w11 = f11 < 0 ? 0.f : (slot_part_q_w(s11) ? l2[f11] : h2[f11]);
+        Q.w0[j] = (elem)(h ? w01 : w00);
+        Q.w1[j] = (elem)(h ? w11 : w10);
+    }
+    // certified error bounds of the computed a and w for this (query, tile):
+    // per feature 3.1 u^2 |phi||psi| (split residuals and the dropped lo*lo),
+    // an absolute eta per value (fp16 subnormal halves), 48 u32 for the float32
+    // query features and the fp32 accumulation of up to 31 products, and the
+    // rounding of |c'|^2 - r^2
+    const float ue = 3.1f * T::u * T::u + 48.f * kU32;
+    float sa = 0.f, sa_abs = 0.f, sw = 0.f, sw_abs = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        sa = fmaf(fabsf(h1[k]), mt[4 + k], sa);
+        sa_abs += fabsf(h1[k]) + mt[4 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        sw = fmaf(fabsf(h2[k]), mt[9 + k], sw);
+        sw_abs += fabsf(h2[k]) + mt[9 + k];
+    }
+    const float ea = 1.1f * (ue * sa + T::eta * sa_abs + 4.f * kU32 * (c2 + r2));
+    const float ew = 1.1f * (ue * sw + T::eta * sw_abs);
+    Q.two_ea = 2.f * ea;
+    Q.c0 = fmaf(ea, ea, ew) * 1.0001f;
+    Q.bad = !(isfinite(Q.two_ea) && isfinite(Q.c0) && isfinite(sa) && isfinite(sw));
+}
+
+// ---------------------------------------------------------------------------
+// Certification kernel: block = 4 waves x 64 queries (two 32-query column
+// blocks per wave); grid = query blocks x tile ranges.
+template <int P>
+__global__ void __launch_bounds__(256)
+mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *__restrict__ meta,
+                  int n_tiles, int tiles_per_split, int n_qblocks, const float *__restrict__ centers,
+                  const float *__restrict__ radii, int q, float four_n2, int32_t *__restrict__ lo_out,
+                  int32_t *__restrict__ hi_out)
+{
+    using T = Prec<P>;
+    using vec = typename T::vec;
+    int b = blockIdx.x;
+    const int B = gridDim.x;
+    if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few tile ranges
+    const int split = b / n_qblocks;
+    const int qb = b - split * n_qblocks;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
+    float cx[2], cy[2], cz[2], r2[2];
+    int jq[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        jq[cb] = qb * 256 + wave * 64 + cb * 32 + col;
+        const int jj = jq[cb] < q ? jq[cb] : q - 1;
+        cx[cb] = centers[3 * jj];
+        cy[cb] = centers[3 * jj + 1];
+        cz[cb] = centers[3 * jj + 2];
+        const float r = radii[jj];
+        r2[cb] = r * r;
+    }
+    int lo[2] = {0, 0}, hi[2] = {0, 0};
+    bool bad[2] = {false, false};
+    const int t0 = split * tiles_per_split;
+    const int t1 = min(n_tiles, t0 + tiles_per_split);
+    const f32x16 zero = {};
+    for (int t = t0; t < t1; ++t) {
+        const float *mt = meta + (size_t)t * kMeta;  // wave-uniform: scalar loads
+        QFeat<P> Q[2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            build_query<P>(cx[cb], cy[cb], cz[cb], r2[cb], four_n2, mt, h, Q[cb]);
+            bad[cb] |= Q[cb].bad;
+        }
+        const vec *fp = feat + (size_t)t * kRB * kOps * kLanes + lane;
+        for (int rb = 0; rb < kRB; ++rb, fp += kOps * kLanes) {
+            const vec Aa = fp[0], Aw0 = fp[kLanes], Aw1 = fp[2 * kLanes];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const f32x16 A = T::mfma(Aa, Q[cb].a, zero);
+                f32x16 W = T::mfma(Aw0, Q[cb].w0, zero);
+                W = T::mfma(Aw1, Q[cb].w1, W);
+                const float te = Q[cb].two_ea, c0 = Q[cb].c0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const float a = A[i], aa = fabsf(a);
+                    const float f = fmaf(-a, aa, W[i]);   // w - a|a|: > 0 iff collision
+                    const float bnd = fmaf(aa, te, c0);   // certified |f - f_exact| bound
+                    lo[cb] += f > bnd;                    // certainly in collision
+                    hi[cb] += f > -bnd;                   // possibly in collision
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        lo[cb] += __shfl_xor(lo[cb], 32);
+        hi[cb] += __shfl_xor(hi[cb], 32);
+        const bool anybad = bad[cb] || __shfl_xor((int)bad[cb], 32) != 0;
+        if (h == 0 && jq[cb] < q) {
+            lo_out[(size_t)split * q + jq[cb]] = lo[cb];
+            hi_out[(size_t)split * q + jq[cb]] = anybad ? (1 << 29) : hi[cb];
+        }
+    }
+}
+
+// Merge the splits, decide certified labels, list the rest for the recheck.
+__global__ void __launch_bounds__(256)
+decide_kernel(int q, int S, int m, int v, int k, bool want_count, const int32_t *__restrict__ lo_in,
+              const int32_t *__restrict__ hi_in, uint8_t *label, int32_t *count,
+              int32_t *__restrict__ list, int32_t *__restrict__ n_list)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    int lo = 0, hi = 0;
+    for (int s = 0; s < S; ++s) {
+        lo += lo_in[(size_t)s * q + j];
+        hi = min(hi + hi_in[(size_t)s * q + j], 1 << 29);
+    }
+    const bool certain = (lo > k || hi <= k) && (!want_count || lo == hi);
+    if (certain) {
+        if (label) label[(size_t)j * m + v] = lo > k ? 1 : 0;
+        if (count) count[(size_t)j * m + v] = lo;
+    } else {
+        list[atomicAdd(n_list, 1)] = j;
+    }
+}
+
+// fp64 recheck of the listed queries: work item = (listed query, chunk of
+// Gaussians); lanes walk the chunk's Gaussians, the block sums its count.
+constexpr int kRecheckChunk = 16384;
+
+__global__ void __launch_bounds__(256)
+recheck_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restrict__ centers,
+                    const float *__restrict__ radii, double four_n2, const int32_t *__restrict__ list,
+                    const int32_t *__restrict__ n_list, int32_t *__restrict__ exact)
+{
+    __shared__ int s_cnt[4];
+    const int nl = *n_list;
+    const int chunks = (n + kRecheckChunk - 1) / kRecheckChunk;
+    const long total = (long)nl * chunks;
+    for (long item = blockIdx.x; item < total; item += gridDim.x) {
+        const int li = (int)(item / chunks), ch = (int)(item - (long)li * chunks);
+        const int j = list[li];
+        const double cx = centers[3 * j], cy = centers[3 * j + 1], cz = centers[3 * j + 2];
+        const double r = radii[j];
+        const double r2 = r * r;
+        const int g0 = ch * kRecheckChunk, g1 = min(n, g0 + kRecheckChunk);
+        int cnt = 0;
+        for (int g = g0 + (int)threadIdx.x; g < g1; g += blockDim.x) {
+            const float *p = gauss + (size_t)kGaussFloats * g;
+            const double dx = (double)p[0] - cx, dy = (double)p[1] - cy, dz = (double)p[2] - cz;
+            const double a = dx * dx + dy * dy + dz * dz - r2;
+            const double e0 = (double)p[3] * dx + (double)p[4] * dy + (double)p[5] * dz;
+            const double e1 = (double)p[6] * dx + (double)p[7] * dy + (double)p[8] * dz;
+            const double e2 = (double)p[9] * dx + (double)p[10] * dy + (double)p[11] * dz;
+            const double V = e0 * e0 + e1 * e1 + e2 * e2;
+            cnt += a * fabs(a) < four_n2 * V;
+        }
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(exact + li, s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
+        __syncthreads();
+    }
+}
+
+__global__ void finish_kernel(int m, int v, int k, const int32_t *__restrict__ list,
+                              const int32_t *__restrict__ n_list, const int32_t *__restrict__ exact,
+                              uint8_t *label, int32_t *count)
+{
+    const int li = blockIdx.x * blockDim.x + threadIdx.x;
+    if (li >= *n_list) return;
+    const int j = list[li];
+    if (label) label[(size_t)j * m + v] = exact[li] > k ? 1 : 0;
+    if (count) count[(size_t)j * m + v] = exact[li];
+}
+
+template <int P>
+csplat_status build_one(csplat_ctx *ctx, csplat_scene *sc, void **feat_out)
+{
+    using vec = typename Prec<P>::vec;
+    const int64_t nt = (sc->n + kPT - 1) / kPT;
+    // the per-tile scale and coefficient maxima are dtype specific: each dtype
+    // owns its metadata
+    float *meta = nullptr;
+    CSPLAT_HIP(hipMalloc(&meta, (size_t)nt * kMeta * sizeof(float)));
+    vec *feat = nullptr;
+    const size_t fbytes = (size_t)nt * kRB * kOps * kLanes * sizeof(vec);
+    hipError_t e = hipMalloc(&feat, fbytes);
+    if (e != hipSuccess) {
+        (void)hipFree(meta);
+        return hip_fail(e, "precision features");
+    }
+    build_tiles_kernel<P><<<(unsigned)nt, kPT, 0, ctx->stream>>>(sc->gauss, sc->n, meta, feat);
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) le = hipStreamSynchronize(ctx->stream);
+    if (le != hipSuccess) {
+        (void)hipFree(meta);
+        (void)hipFree(feat);
+        return hip_fail(le, "build_tiles_kernel");
+    }
+    feat_out[0] = feat;
+    feat_out[1] = meta;
+    sc->device_bytes += fbytes + (uint64_t)nt * kMeta * sizeof(float);
+    return CSPLAT_OK;
+}
+
+}  // namespace
+
+csplat_status precision_build(csplat_ctx *ctx, csplat_scene *sc, uint32_t features)
+{
+    sc->n_tiles = (sc->n + kPT - 1) / kPT;
+    if (features & CSPLAT_FEATURES_BF16) {
+        void *out[2];
+        csplat_status s = build_one<CSPLAT_PRECISION_BF16_RECHECK>(ctx, sc, out);
+        if (s != CSPLAT_OK) return s;
+        sc->feat_bf16 = out[0];
+        sc->meta_bf16 = static_cast<float *>(out[1]);
+    }
+    if (features & CSPLAT_FEATURES_FP16) {
+        void *out[2];
+        csplat_status s = build_one<CSPLAT_PRECISION_FP16_RECHECK>(ctx, sc, out);
+        if (s != CSPLAT_OK) return s;
+        sc->feat_fp16 = out[0];
+        sc->meta_fp16 = static_cast<float *>(out[1]);
+    }
+    return CSPLAT_OK;
+}
+
+csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
+                             const float *radii, const EvalParams &p, const EvalOut &out, int precision)
+{
+    const int q = (int)q64;
+    const int n = (int)sc->n;
+    const int m = p.m;
+    hipStream_t st = ctx->stream;
+    const int n_tiles = (int)sc->n_tiles;
+    const int n_qblocks = (q + 255) / 256;
+    int S = 1;
+    if (n_tiles > 0) {
+        S = (ctx_target_blocks(ctx) + n_qblocks - 1) / n_qblocks;
+        S = std::max(1, std::min(S, n_tiles));
+    }
+    const int tps = n_tiles > 0 ? (n_tiles + S - 1) / S : 0;
+    if (n_tiles > 0) S = (n_tiles + tps - 1) / tps;
+    // workspace: lo/hi partials, the recheck list, its length, exact counts
+    const size_t part = (size_t)S * q;
+    const size_t words = 2 * part + 2 * (size_t)q + 64;
+    hipError_t e = ctx->partial.reserve(words * 4);
+    if (e != hipSuccess) return hip_fail(e, "precision workspace");
+    int32_t *lo = ctx->partial.as<int32_t>();
+    int32_t *hi = lo + part;
+    int32_t *list = hi + part;
+    int32_t *exact = list + q;
+    e = ctx->flags.reserve((size_t)CSPLAT_MAX_M * sizeof(int32_t) + 64);
+    if (e != hipSuccess) return hip_fail(e, "flag counters");
+    int32_t *n_list = ctx->flags.as<int32_t>();
+    CSPLAT_HIP(zero_words(n_list, CSPLAT_MAX_M, st));
+    ctx->stats.splits = S;
+    ctx->stats.queries_per_lane = 2;
+    ctx->stats.kernel_pairs = (int64_t)q * n;
+    ctx->flag_counts = n_list;
+    ctx->flag_m = m;
+    const bool want_count = out.count != nullptr;
+    const int rc_grid = 2048;
+    for (int v = 0; v < m; ++v) {
+        if (n_tiles > 0) {
+            if (v == 0) timing_begin(ctx);
+            dim3 grid((unsigned)(n_qblocks * S));
+            if (precision == CSPLAT_PRECISION_BF16_RECHECK)
+                mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK><<<grid, 256, 0, st>>>(
+                    static_cast<const bf16x8 *>(sc->feat_bf16), sc->meta_bf16, n_tiles, tps, n_qblocks, centers,
+                    radii, q, p.four_n2[v], lo, hi);
+            else
+                mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK><<<grid, 256, 0, st>>>(
+                    static_cast<const f16x8 *>(sc->feat_fp16), sc->meta_fp16, n_tiles, tps, n_qblocks, centers,
+                    radii, q, p.four_n2[v], lo, hi);
+            if (v == 0) timing_end(ctx);
+            CSPLAT_HIP(hipGetLastError());
+        }
+        decide_kernel<<<(unsigned)((q + 255) / 256), 256, 0, st>>>(q, n_tiles > 0 ? S : 0, m, v, p.k, want_count,
+                                                                   lo, hi, out.label, out.count, list, n_list + v);
+        CSPLAT_HIP(hipGetLastError());
+        CSPLAT_HIP(zero_words(exact, (size_t)q, st));
+        const double nv = p.n_sigma[v];
+        if (n > 0)
+            recheck_fp64_kernel<<<rc_grid, 256, 0, st>>>(sc->gauss, n, centers, radii, 4.0 * nv * nv, list,
+                                                         n_list + v, exact);
+        finish_kernel<<<(unsigned)((q + 255) / 256), 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, out.label,
+                                                                  out.count);
+        CSPLAT_HIP(hipGetLastError());
+    }
+    return CSPLAT_OK;
 }
 
 }  // namespace csplat

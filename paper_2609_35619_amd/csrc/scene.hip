@@ -30,7 +30,7 @@ __host__ __device__ inline float key_float(int k)
 enum : int { kErrNonFinite = 1, kErrZeroQuat = 2, kErrNegScale = 4 };
 
 struct PrepOut {
-    float *rec;          // n x 12
+    float *rec;          // n x kGaussFloats
     uint32_t *keep;      // n (0/1)
     int *err;            // error bits
     int *bbox;           // 6 keys: min xyz, max xyz (kept only)
@@ -86,12 +86,16 @@ __global__ void __launch_bounds__(256) prep_kernel(int64_t n, const float *__res
                 double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
                                   {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
                                   {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
-                float *r = o.rec + (size_t)12 * i;
+                float *r = o.rec + (size_t)kGaussFloats * i;
                 r[0] = mx;
                 r[1] = my;
                 r[2] = mz;
                 for (int k = 0; k < 3; ++k)       // row k of M = s_k * (column k of R)^T
                     for (int c = 0; c < 3; ++c) r[3 + 3 * k + c] = (float)(s[k] * R[c][k]);
+                r[12] = -2.f * mx;  // exact
+                r[13] = -2.f * my;
+                r[14] = -2.f * mz;
+                r[15] = (float)((double)mx * mx + (double)my * my + (double)mz * mz);
                 lane_box[0] = lane_box[3] = float_key(mx);
                 lane_box[1] = lane_box[4] = float_key(my);
                 lane_box[2] = lane_box[5] = float_key(mz);
@@ -150,7 +154,7 @@ __global__ void morton_kernel(int64_t n, const float *__restrict__ rec, const ui
     if (i >= n) return;
     uint32_t c = 0xFFFFFFFFu;
     if (keep[i]) {
-        const float *r = rec + (size_t)12 * i;
+        const float *r = rec + (size_t)kGaussFloats * i;
         float fx = (r[0] - lo.x) * scale.x, fy = (r[1] - lo.y) * scale.y, fz = (r[2] - lo.z) * scale.z;
         uint32_t ix = (uint32_t)fminf(fmaxf(fx, 0.f), 1023.f);
         uint32_t iy = (uint32_t)fminf(fmaxf(fy, 0.f), 1023.f);
@@ -165,10 +169,10 @@ __global__ void gather_kernel(int64_t n_kept, const float *__restrict__ rec,
                               const uint32_t *__restrict__ order, float *__restrict__ out)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one float per thread
-    if (t >= n_kept * 12) return;
-    int64_t k = t / 12;
-    int c = (int)(t - k * 12);
-    out[t] = rec[(size_t)12 * order[k] + c];
+    if (t >= n_kept * kGaussFloats) return;
+    int64_t k = t / kGaussFloats;
+    int c = (int)(t - k * kGaussFloats);
+    out[t] = rec[(size_t)kGaussFloats * order[k] + c];
 }
 
 struct Tmp {
@@ -208,7 +212,7 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
     unsigned long long *d_cnt = nullptr;
     size_t nn = (size_t)n;
     if (tmp.alloc(&d_in, nn * 11 * sizeof(float)) != hipSuccess ||
-        tmp.alloc(&d_rec, nn * 12 * sizeof(float)) != hipSuccess ||
+        tmp.alloc(&d_rec, nn * kGaussFloats * sizeof(float)) != hipSuccess ||
         tmp.alloc(&d_keep, nn * 4) != hipSuccess || tmp.alloc(&d_code, nn * 4) != hipSuccess ||
         tmp.alloc(&d_idx, nn * 4) != hipSuccess || tmp.alloc(&d_code2, nn * 4) != hipSuccess ||
         tmp.alloc(&d_idx2, nn * 4) != hipSuccess || tmp.alloc(&d_misc, 8 * sizeof(int)) != hipSuccess ||
@@ -243,12 +247,16 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
     sc->n = (int64_t)kept;
     if (kept == 0) return CSPLAT_OK;
     float lo[3], hi[3], scl[3];
+    double corner2 = 0.0;
     for (int k = 0; k < 3; ++k) {
         lo[k] = key_float(misc[1 + k]);
         hi[k] = key_float(misc[4 + k]);
         float ext = hi[k] - lo[k];
         scl[k] = ext > 0.f ? 1023.999f / ext : 0.f;
+        double c = std::max(std::fabs((double)lo[k]), std::fabs((double)hi[k]));
+        corner2 += c * c;
     }
+    sc->mu_max = (float)(std::sqrt(corner2) * (1.0 + 1e-6));
     morton_kernel<<<blocks, 256, 0, st>>>(n, d_rec, d_keep, make_float3(lo[0], lo[1], lo[2]),
                                           make_float3(scl[0], scl[1], scl[2]), d_code, d_idx);
     CSPLAT_HIP(hipGetLastError());
@@ -261,11 +269,11 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
     CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(d_tmp, tbytes, d_code, d_code2, d_idx, d_idx2,
                                                   (int)n, 0, 32, st));
     float *g = nullptr;
-    if (hipMalloc(&g, (size_t)kept * 12 * sizeof(float)) != hipSuccess)
+    if (hipMalloc(&g, (size_t)kept * kGaussFloats * sizeof(float)) != hipSuccess)
         return fail(CSPLAT_E_OOM, "scene_load: scene allocation");
     sc->gauss = g;
-    sc->device_bytes += (uint64_t)kept * 12 * sizeof(float);
-    int64_t tot = (int64_t)kept * 12;
+    sc->device_bytes += (uint64_t)kept * kGaussFloats * sizeof(float);
+    int64_t tot = (int64_t)kept * kGaussFloats;
     gather_kernel<<<(int)((tot + 255) / 256), 256, 0, st>>>((int64_t)kept, d_rec, d_idx2, g);
     CSPLAT_HIP(hipGetLastError());
     CSPLAT_HIP(hipStreamSynchronize(st));
@@ -275,12 +283,12 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
 void scene_release(csplat_scene *sc)
 {
     if (!sc) return;
-    void *ptrs[] = {sc->gauss, sc->tile_origin, sc->tile_bound, sc->feat_bf16, sc->feat_fp16};
+    void *ptrs[] = {sc->gauss, sc->feat_bf16, sc->meta_bf16, sc->feat_fp16, sc->meta_fp16};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     sc->gauss = nullptr;
-    sc->tile_origin = sc->tile_bound = nullptr;
     sc->feat_bf16 = sc->feat_fp16 = nullptr;
+    sc->meta_bf16 = sc->meta_fp16 = nullptr;
 }
 
 }  // namespace csplat

@@ -1,0 +1,197 @@
+"""The MFMA precision form (bf16/fp16 hi-lo features, certified bound, fp64
+recheck) against the FP64 oracle and the float32 path."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from parity import compare
+from workloads import Queries, Scene, common_attrs, config, uniform_box_scene, uniform_queries
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ("bf16", "fp16")
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2609_35619_amd as cs
+    cs.load_library()
+    return cs
+
+
+@pytest.fixture(scope="module")
+def eng(cs):
+    e = cs.Engine(0)
+    yield e
+    e.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _prec(cs, name):
+    return cs.CSPLAT_PRECISION_BF16_RECHECK if name == "bf16" else cs.CSPLAT_PRECISION_FP16_RECHECK
+
+
+def _load(cs, eng, scene, p):
+    return eng.load_scene(scene, floater_opacity_max=p.get("alpha_f", 0.0),
+                          floater_extent_min=p.get("extent_f", 0.0),
+                          precision_features=cs.CSPLAT_FEATURES_BF16 | cs.CSPLAT_FEATURES_FP16)
+
+
+def _eval(cs, eng, h, queries, p, precision, want=("label", "count")):
+    import torch
+    eng.set_conservatism(p["n_sigma"])
+    opts = cs.reduce_opts(k=p.get("k", 0), r_nbr=math.inf, precision=precision)
+    c = torch.from_numpy(queries.centers).cuda()
+    r = torch.from_numpy(queries.radii).cuda()
+    out = eng.evaluate(h, c, r, opts, want)
+    torch.cuda.synchronize()
+    st = eng.stats()
+    return {k: v.cpu().numpy() for k, v in out.items()}, st
+
+
+def _oracle(oracle_mod, scene, queries, p):
+    return oracle_mod.evaluate_spheres(scene, queries, p["n_sigma"], alpha_f=p.get("alpha_f", 0.0),
+                                       extent_f=p.get("extent_f", 0.0), k=p.get("k", 0))
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_precision_small_scene(cs, eng, oracle_mod, prec):
+    _say(f"case: precision {prec}, uniform box 20k x 3000, n_sigma 0/1/2")
+    sc = uniform_box_scene(20_000, seed=301, box=(3, 3, 1.5))
+    qs = uniform_queries(3000, seed=302, box=(3, 3, 1.5), radius=0.08)
+    p = dict(n_sigma=[0.0, 1.0, 2.0], k=2)
+    h = _load(cs, eng, sc, p)
+    gpu, st = _eval(cs, eng, h, qs, p, _prec(cs, prec))
+    cs.csplat_scene_free(h)
+    ref = _oracle(oracle_mod, sc, qs, p)
+    s = compare(gpu, ref, tau=0.0, gamma=1.0, where=f"precision-{prec}")
+    _say(f"{prec}: {s} rechecked={st['flagged']} of {qs.q * 3}")
+    # counts were requested: every count must be exact (certified or rechecked in fp64)
+    assert np.array_equal(gpu["count"], ref["count"]) or np.all(
+        (gpu["count"] == ref["count"]) | ref["ambiguous"].astype(bool))
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_precision_labels_only_and_mix_with_fp32(cs, eng, oracle_mod, prec):
+    _say(f"case: precision {prec} labels only vs float32 path, room scene")
+    sc, qs, p = config("precision", 0.01)
+    p = dict(p)
+    h = _load(cs, eng, sc, p)
+    gpu, st = _eval(cs, eng, h, qs, p, _prec(cs, prec), want=("label",))
+    f32, _ = _eval(cs, eng, h, qs, p, cs.CSPLAT_PRECISION_FP32, want=("label", "count"))
+    cs.csplat_scene_free(h)
+    ref = _oracle(oracle_mod, sc, qs, p)
+    compare(gpu, ref, tau=0.0, gamma=1.0, where=f"labels-{prec}")
+    amb = ref["ambiguous"].astype(bool)
+    assert np.all((gpu["label"] == f32["label"]) | amb)
+    _say(f"{prec}: rechecked {st['flagged']} of {qs.q}")
+
+
+def _isotropic_threshold_scene(n_pairs, s_iso, r, n_sigma, rel, seed):
+    """Gaussian i sits at rho*(1 + rel_i) from query i (far from the others)."""
+    rng = np.random.default_rng(seed)
+    rho = n_sigma * s_iso + math.sqrt(n_sigma ** 2 * s_iso ** 2 + r * r)
+    # pairs 0.5 m apart on a compact grid: float32 keeps positions to ~5e-7 m
+    i = np.arange(n_pairs)
+    centers = np.stack([(i % 12) * 0.5, ((i // 12) % 12) * 0.5, (i // 144) * 0.5], 1)
+    u = rng.normal(size=(n_pairs, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    means = centers + u * (rho * (1 + rel))[:, None]
+    q, _, _ = common_attrs(rng, n_pairs)
+    sc = Scene(means.astype(np.float32), q, np.full((n_pairs, 3), s_iso, np.float32),
+               np.full(n_pairs, 0.9, np.float32))
+    return sc, Queries(centers.astype(np.float32), np.full(n_pairs, r, np.float32))
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_precision_adversarial_near_threshold(cs, eng, oracle_mod, prec):
+    _say(f"case: precision {prec}, queries at rho*(1 +- delta)")
+    rels = np.concatenate([np.full(200, 1e-3), np.full(200, -1e-3), np.full(200, 1e-5), np.full(200, -1e-5),
+                           np.full(200, 3e-7), np.full(200, -3e-7)])
+    sc, qs = _isotropic_threshold_scene(rels.size, 0.03, 0.03, 1.0, rels, seed=5)
+    p = dict(n_sigma=[1.0], k=0)
+    h = _load(cs, eng, sc, p)
+    gpu, st = _eval(cs, eng, h, qs, p, _prec(cs, prec))
+    cs.csplat_scene_free(h)
+    ref = _oracle(oracle_mod, sc, qs, p)
+    compare(gpu, ref, tau=0.0, gamma=1.0, where=f"adversarial-{prec}")
+    # pairs displaced by 1e-3 of rho* lie clearly on their side of the threshold
+    amb = ref["ambiguous"][:, 0].astype(bool)
+    clear = np.abs(rels) >= 1e-4
+    assert np.all(gpu["label"][clear, 0] == (rels[clear] < 0))
+    _say(f"{prec}: rechecked {st['flagged']} of {qs.q}, ambiguous {amb.sum()}")
+    assert st["flagged"] >= 200   # the 3e-7 pairs cannot be certified by the MFMA bound
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_precision_degenerate_gaussians(cs, eng, oracle_mod, prec):
+    _say(f"case: precision {prec}, flat and point Gaussians, small radii")
+    rng = np.random.default_rng(9)
+    q, s, o = common_attrs(rng, 6000)
+    s[:1500, 2] = 0.0
+    s[1500:2000] = 0.0
+    s[2000:2500] *= 8.0   # very large, anisotropic
+    m = rng.uniform(0, 1.5, (6000, 3)).astype(np.float32)
+    sc = Scene(m, q, s, o)
+    qs = uniform_queries(1500, seed=10, box=(1.5, 1.5, 1.5), radius=0.03)
+    qs = Queries(qs.centers, rng.choice(np.array([0.03, 0.05, 0.1], np.float32), qs.q))
+    p = dict(n_sigma=[0.5, 2.0], k=1)
+    h = _load(cs, eng, sc, p)
+    gpu, st = _eval(cs, eng, h, qs, p, _prec(cs, prec))
+    cs.csplat_scene_free(h)
+    ref = _oracle(oracle_mod, sc, qs, p)
+    s_ = compare(gpu, ref, tau=0.0, gamma=1.0, where=f"degenerate-{prec}")
+    _say(f"{prec}: {s_} rechecked {st['flagged']}")
+
+
+def test_precision_requires_features(cs, eng):
+    sc, qs, p = config("tiny", 0.05)
+    h = eng.load_scene(sc)   # no precision features
+    eng.set_conservatism([1.0])
+    with pytest.raises(cs.CsplatError):
+        cs.csplat_eval_labels(eng.ctx, h, qs.centers, qs.radii,
+                              cs.reduce_opts(precision=cs.CSPLAT_PRECISION_BF16_RECHECK),
+                              np.zeros((qs.q, 1), np.uint8))
+    with pytest.raises(cs.CsplatError):   # distances are float32-path outputs
+        h2 = _load(cs, eng, sc, p)
+        try:
+            cs.csplat_eval_distance(eng.ctx, h2, qs.centers, qs.radii,
+                                    cs.reduce_opts(precision=cs.CSPLAT_PRECISION_BF16_RECHECK),
+                                    np.zeros((qs.q, 1), np.float32))
+        finally:
+            cs.csplat_scene_free(h2)
+    cs.csplat_scene_free(h)
+
+
+def test_precision_full_size_sampled(cs, eng, oracle_mod):
+    """4M Gaussians x 262,144 grid spheres: labels of both precision forms
+    equal the float32 path except on oracle-ambiguous queries; a seeded sample
+    is checked against the oracle."""
+    import torch
+    _say("case: full-size precision workload (4M x 262144)")
+    sc, qs, p = config("precision")
+    h = _load(cs, eng, sc, p)
+    res = {}
+    for name, prec in (("fp32", cs.CSPLAT_PRECISION_FP32), ("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK),
+                       ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK)):
+        res[name], st = _eval(cs, eng, h, qs, p, prec, want=("label",))
+        _say(f"{name}: rechecked {st['flagged']} of {qs.q}")
+    cs.csplat_scene_free(h)
+    idx = np.sort(np.random.default_rng(3).choice(qs.q, 96, replace=False))
+    diff = np.zeros(qs.q, bool)
+    for name in ("bf16", "fp16"):
+        diff |= (res[name]["label"] != res["fp32"]["label"])[:, 0]
+    idx = np.unique(np.concatenate([idx, np.nonzero(diff)[0][:64], [qs.q - 1]]))
+    ref = _oracle(oracle_mod, sc, qs.subset(idx), p)
+    for name in res:
+        compare({"label": res[name]["label"][idx]}, ref, tau=0.0, gamma=1.0, where=f"full-{name}")
+    assert diff.sum() <= 64, f"{diff.sum()} label disagreements between precision forms and float32"
+    del torch
