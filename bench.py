@@ -43,6 +43,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-form comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serving-requests", type=int, default=60)
+    ap.add_argument("--serving-full", action="store_true",
+                    help="serve the full-size request law (MPPI K up to 4096 x 32 x 48; long)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -127,12 +132,131 @@ def main():
                      "kernel": "pair_kernel<3,full,ball>", "kernel_ms": kernel_s * 1e3,
                      "ops_per_launch": ops, "in_ball_pairs": nbr_total},
     }
-    cs.csplat_scene_free(h)
-    eng.close()
-
     if not args.no_cpu_baseline:
         res["cpu_baseline"], res["label_accuracy"] = cpu_baseline(sc, qs, p, gpu, args.cpu_seconds, n_kept)
+    if not args.no_precision:
+        res["precision_form"] = precision_form(cs, eng)
+    if not args.no_serving:
+        res["serving"] = serving(cs, eng, sc, h, args.serving_requests, args.serving_full)
+    cs.csplat_scene_free(h)
+    eng.close()
     print(json.dumps(res), flush=True)
+
+
+def _time_eval(eng, h, c, r, opts, want, reps=3):
+    import torch
+    out = eng.alloc_outputs(c.shape[0], want)
+    eng.evaluate(h, c, r, opts, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        eng.evaluate(h, c, r, opts, out=out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def precision_form(cs, eng):
+    """Labels of the 4M-Gaussian x 262,144-sphere grid workload: float32 pair
+    kernel vs the bf16 / fp16 MFMA forms (certified, rechecked in fp64)."""
+    import torch
+    from workloads import config
+    log("bench: precision form (4M Gaussians x 262,144 grid spheres, labels)")
+    sc, qs, p = config("precision")
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"],
+                       precision_features=cs.CSPLAT_FEATURES_BF16 | cs.CSPLAT_FEATURES_FP16)
+    n_kept, nbytes = cs.csplat_scene_info(h)
+    eng.set_conservatism(p["n_sigma"])
+    c = torch.from_numpy(qs.centers).cuda()
+    r = torch.from_numpy(qs.radii).cuda()
+    out = {"workload": "precision: 4M-Gaussian room scene, 64^3 grid spheres in 4 radius classes "
+                       "{0.05,0.1,0.2,0.4} m, n_sigma 1, k=2, labels", "n_kept": int(n_kept),
+           "queries": int(qs.q), "scene_bytes_with_features": int(nbytes)}
+    labels = {}
+    for name, prec in (("fp32", cs.CSPLAT_PRECISION_FP32), ("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK),
+                       ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK)):
+        opts = cs.reduce_opts(k=p["k"], r_nbr=math.inf, precision=prec)
+        dt, res = _time_eval(eng, h, c, r, opts, ("label",))
+        cs.csplat_ctx_set_timing(eng.ctx, True)
+        eng.evaluate(h, c, r, opts, want=("label",))
+        st = cs.csplat_last_stats(eng.ctx)
+        cs.csplat_ctx_set_timing(eng.ctx, False)
+        labels[name] = res["label"][:, 0]
+        flagged = int(st["flagged"])
+        per_class = {}
+        if prec != cs.CSPLAT_PRECISION_FP32:
+            per_class = {"rechecked_fraction": flagged / qs.q}
+        out[name] = {"ms": dt * 1e3, "pair_evals_per_s": qs.q * n_kept / dt, "kernel_ms": st["kernel_ms"],
+                     "rechecked_queries": flagged, **per_class}
+        log(f"bench: precision {name}: {dt*1e3:.1f} ms")
+    for name in ("bf16", "fp16"):
+        out[name]["label_disagreements_vs_fp32"] = int((labels[name] != labels["fp32"]).sum())
+        out[name]["speedup_vs_fp32"] = out["fp32"]["ms"] / out[name]["ms"]
+    # the certified-bound flag rate per radius class (one extra launch per dtype
+    # with counts off: the decide step lists the undecided queries)
+    radii = np.unique(qs.radii)
+    for name, prec in (("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK), ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK)):
+        cls = {}
+        for rv in radii:
+            sel = np.nonzero(qs.radii == rv)[0]
+            cc, rr = c[torch.from_numpy(sel).cuda()], r[torch.from_numpy(sel).cuda()]
+            eng.evaluate(h, cc.contiguous(), rr.contiguous(), cs.reduce_opts(k=p["k"], r_nbr=math.inf, precision=prec),
+                         want=("label",))
+            torch.cuda.synchronize()
+            cls[f"r={rv:.2f}"] = cs.csplat_last_stats(eng.ctx)["flagged"] / sel.size
+        out[name]["rechecked_fraction_per_radius_class"] = cls
+    cs.csplat_scene_free(h)
+    return out
+
+
+def serving(cs, eng, sc_nav, h_nav, n_requests, full):
+    """The serving form with the 1M (navigation) and 4M (room) scenes resident:
+    a Poisson stream mixing MPPI batches and RRT edge checks.  The saturated
+    request rate is measured first (all requests at once); the stream then
+    arrives at half that rate and p50/p99 latency is reported."""
+    from workloads import config, serving_stream
+    log("bench: serving (1M + 4M resident scenes)")
+    sc4, _, p4 = config("precision")
+    h4 = eng.load_scene(sc4, floater_opacity_max=p4["alpha_f"], floater_extent_min=p4["extent_f"])
+    kw = dict(max_mppi_k=4096, max_rrt_points=10000, max_spheres=48) if full else \
+        dict(max_mppi_k=512, max_rrt_points=4000, max_spheres=8)
+    mppi_opts = cs.reduce_opts(k=2, tau=0.1, r_nbr=1.0, d_max=1.0, gamma=1.0, s_min=1.0)
+    rrt_opts = cs.reduce_opts(k=2, r_nbr=math.inf)
+    n_scene = [cs.csplat_scene_info(h_nav)[0], cs.csplat_scene_info(h4)[0]]
+
+    def run(reqs, rate_scale):
+        srv = cs.csplat_server_create(0, 4 << 30, 16)
+        ids = [cs.csplat_server_add_scene(srv, h_nav), cs.csplat_server_add_scene(srv, h4)]
+        t0 = time.perf_counter()
+        tickets = []
+        for rq in reqs:
+            while rate_scale and time.perf_counter() - t0 < rq["t"] * rate_scale:
+                time.sleep(0.0002)
+            kind = cs.CSPLAT_SERVE_COST if rq["kind"] == "mppi" else cs.CSPLAT_SERVE_LABELS
+            tickets.append((cs.csplat_server_submit(srv, ids[rq["scene"]], kind, rq["centers"], rq["radii"],
+                                                    mppi_opts if kind == 0 else rrt_opts, rq["n_sigma"]),
+                            kind, rq["centers"].shape[0]))
+        for t, kind, q in tickets:
+            cs.csplat_server_wait(srv, t, q, kind)
+        wall = time.perf_counter() - t0
+        st = cs.csplat_server_stats(srv)
+        cs.csplat_server_destroy(srv)
+        return st, wall
+
+    reqs = serving_stream(n_requests, seed=105, rate_hz=1.0, **kw)
+    pairs = sum(rq["centers"].shape[0] * n_scene[rq["scene"]] for rq in reqs)
+    sat, wall = run(reqs, 0)           # saturated: every request at t = 0
+    sat_rate = len(reqs) / wall
+    lam = 0.5 * sat_rate
+    reqs2 = serving_stream(n_requests, seed=105, rate_hz=lam, **kw)
+    st, wall2 = run(reqs2, 1.0)
+    cs.csplat_scene_free(h4)
+    return {"workload": ("full" if full else "reduced") + " serving law: 1M and 4M room scenes resident, "
+            f"{n_requests} requests (MPPI K<={kw['max_mppi_k']} x 32 x <= {kw['max_spheres']} spheres, "
+            f"RRT <= {kw['max_rrt_points']} points x <= {kw['max_spheres']} spheres), HBM budget 4 GiB, 16 slots",
+            "saturated_requests_per_s": sat_rate, "saturated_pair_evals_per_s": pairs / wall,
+            "rate_requests_per_s": lam, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+            "max_ms": st["max_ms"], "pair_evals_per_s": st["pairs_per_s"], "steps": st["steps"],
+            "completed": st["completed"]}
 
 
 def cpu_baseline(sc, qs, p, gpu, target_s, n_kept):

@@ -160,6 +160,69 @@ csplat_status csplat_eval_distance(csplat_ctx *ctx, const csplat_scene *scene, i
 csplat_status csplat_ctx_set_timing(csplat_ctx *ctx, int32_t enable);
 /* Statistics of the last evaluation (with timing on, waits for its kernel). */
 csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats);
+/* ---------------------------------------------------------------------------
+ * Serving form: resident scenes and continuous batching of planner requests
+ * (MPPI rollout batches of shape (K, T, N_link), Sec. II-D, and RRT edge
+ * checks of shape N_batch x N_strides x N_links, Sec. II-E).
+ *
+ * A server owns one device stream, a worker thread, a device arena of
+ * `hbm_budget` bytes (query inputs and partial reductions of admitted
+ * requests) and a pinned host arena of the same size (input staging and
+ * outputs), both allocated at creation: serving itself allocates nothing.
+ * Requests are admitted in arrival order while a slot and memory are free
+ * (a request that does not fit yet does not block smaller later ones), cut
+ * into work items (query tile x Gaussian range) and evaluated in bounded
+ * steps together with whatever else is admitted; each step is a replay of a
+ * captured HIP graph.  A request's results never depend on what it shares
+ * the device with: they are bit-identical to csplat_eval on a context of the
+ * same device with the same conservatism value and options.
+ * Thread-safe: submit, poll, wait and cancel may be called from any thread.
+ */
+#define CSPLAT_SERVE_COST 0   /* label, count, min, softmin, cost, nbr (MPPI) */
+#define CSPLAT_SERVE_LABELS 1 /* label, count (RRT edge checks) */
+
+typedef struct {
+    int64_t submitted, completed, cancelled, refused;
+    int64_t steps;            /* graph replays issued */
+    double p50_ms, p99_ms;    /* submit -> results in host memory, completed requests */
+    double mean_ms, max_ms;
+    double pairs_per_s;       /* Q x N_kept of completed requests / serving wall time */
+    double busy_s;            /* first admission to last completion */
+} csplat_serving_stats;
+
+/* Create a server on `device` with `hbm_budget` bytes of device arena (and as
+ * much pinned host memory) and at most `slots` (1..64) requests on the device
+ * at a time.  Errors: CSPLAT_E_INVALID, CSPLAT_E_OOM, CSPLAT_E_DEVICE. */
+csplat_status csplat_server_create(int32_t device, uint64_t hbm_budget, int32_t slots,
+                                   csplat_server **out);
+/* Stop the worker (in-flight steps finish first) and free everything. */
+csplat_status csplat_server_destroy(csplat_server *srv);
+/* Serve a loaded scene (same device; it must outlive the server). */
+csplat_status csplat_server_add_scene(csplat_server *srv, const csplat_scene *scene,
+                                      int32_t *scene_id);
+/* Submit q query spheres (host arrays, copied before return) for `kind`
+ * against scene `scene_id` with one conservatism value n_sigma (m must be 1)
+ * and float32 options.  Returns a ticket.  CSPLAT_E_BUSY if the request can
+ * never fit the budgets; CSPLAT_E_INVALID for bad arguments (the same checks
+ * as csplat_eval); CSPLAT_E_NOT_FOUND for an unknown scene id. */
+csplat_status csplat_server_submit(csplat_server *srv, int32_t scene_id, int32_t kind, int64_t q,
+                                   const float *centers, const float *radii,
+                                   const csplat_reduce_opts *opts, const float *n_sigma,
+                                   int32_t m, uint64_t *ticket);
+/* Non-blocking: CSPLAT_E_PENDING while queued or running; CSPLAT_OK once
+ * done, after copying the non-NULL outputs (host pointers, q x 1 each) and
+ * forgetting the ticket; CSPLAT_E_CANCELLED (ticket forgotten);
+ * CSPLAT_E_NOT_FOUND for an unknown ticket. */
+csplat_status csplat_server_poll(csplat_server *srv, uint64_t ticket, const csplat_outputs *out);
+/* Like poll, but blocks until the request is done or cancelled, or until
+ * timeout_ms (< 0: no limit) has passed (then CSPLAT_E_PENDING). */
+csplat_status csplat_server_wait(csplat_server *srv, uint64_t ticket, const csplat_outputs *out,
+                                 int64_t timeout_ms);
+/* Cancel a queued or running request (a running one stops after its
+ * in-flight step).  CSPLAT_E_NOT_FOUND if unknown or already finished. */
+csplat_status csplat_server_cancel(csplat_server *srv, uint64_t ticket);
+csplat_status csplat_server_stats(csplat_server *srv, csplat_serving_stats *stats);
+
 /* Wait for all work queued on the context's stream. */
 csplat_status csplat_synchronize(csplat_ctx *ctx);
 /* Message of the last failed call on this thread ("" if none); valid until

@@ -44,8 +44,12 @@ EXPORTS = (
     "csplat_ctx_create", "csplat_ctx_destroy", "csplat_scene_load", "csplat_scene_info",
     "csplat_scene_free", "csplat_set_conservatism", "csplat_eval", "csplat_eval_labels",
     "csplat_eval_distance", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
-    "csplat_last_error",
+    "csplat_last_error", "csplat_server_create", "csplat_server_destroy", "csplat_server_add_scene",
+    "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
+    "csplat_server_stats",
 )
+CSPLAT_SERVE_COST = 0
+CSPLAT_SERVE_LABELS = 1
 
 
 class CsplatError(RuntimeError):
@@ -77,6 +81,13 @@ class EvalStats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_float)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("refused", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("pairs_per_s", ctypes.c_double), ("busy_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -106,6 +117,14 @@ def load_library(path: str = LIB_PATH):
         "csplat_ctx_set_timing": [P, I32],
         "csplat_last_stats": [P, P],
         "csplat_synchronize": [P],
+        "csplat_server_create": [I32, ctypes.c_uint64, I32, P],
+        "csplat_server_destroy": [P],
+        "csplat_server_add_scene": [P, P, P],
+        "csplat_server_submit": [P, I32, I32, I64, P, P, P, P, I32, P],
+        "csplat_server_poll": [P, ctypes.c_uint64, P],
+        "csplat_server_wait": [P, ctypes.c_uint64, P, I64],
+        "csplat_server_cancel": [P, ctypes.c_uint64],
+        "csplat_server_stats": [P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -227,6 +246,70 @@ def csplat_synchronize(ctx):
 
 def csplat_last_error() -> str:
     return load_library().csplat_last_error().decode(errors="replace")
+
+
+def csplat_server_create(device: int, hbm_budget: int, slots: int):
+    out = ctypes.c_void_p()
+    _check(load_library().csplat_server_create(device, int(hbm_budget), slots, ctypes.byref(out)))
+    return out
+
+
+def csplat_server_destroy(srv):
+    _check(load_library().csplat_server_destroy(srv))
+
+
+def csplat_server_add_scene(srv, scene) -> int:
+    sid = ctypes.c_int32()
+    _check(load_library().csplat_server_add_scene(srv, scene, ctypes.byref(sid)))
+    return sid.value
+
+
+def csplat_server_submit(srv, scene_id, kind, centers, radii, opts: ReduceOpts, n_sigma) -> int:
+    c = np.ascontiguousarray(centers, np.float32)
+    r = np.ascontiguousarray(radii, np.float32)
+    ns = np.ascontiguousarray(np.atleast_1d(n_sigma), np.float32)
+    t = ctypes.c_uint64()
+    _check(load_library().csplat_server_submit(srv, scene_id, kind, c.shape[0], _addr(c) if c.size else None,
+                                               _addr(r) if r.size else None, ctypes.byref(opts), _addr(ns),
+                                               ns.size, ctypes.byref(t)))
+    return t.value
+
+
+def _server_outputs(q, kind):
+    keys = ALL_OUTPUTS if kind == CSPLAT_SERVE_COST else ("label", "count")
+    shapes = dict(label=np.uint8, count=np.int32, min=np.float32, softmin=np.float32, cost=np.float32,
+                  nbr=np.int32)
+    out = {k: np.empty((q, 1) if k != "nbr" else (q,), shapes[k]) for k in keys}
+    return out, Outputs(*[_addr(out.get(k)) for k in ALL_OUTPUTS])
+
+
+def csplat_server_poll(srv, ticket, q, kind):
+    """Returns the outputs dict when done, None while pending."""
+    out, o = _server_outputs(q, kind)
+    st = load_library().csplat_server_poll(srv, ticket, ctypes.byref(o))
+    if st == CSPLAT_E_PENDING:
+        return None
+    _check(st)
+    return out
+
+
+def csplat_server_wait(srv, ticket, q, kind, timeout_ms=-1):
+    out, o = _server_outputs(q, kind)
+    st = load_library().csplat_server_wait(srv, ticket, ctypes.byref(o), int(timeout_ms))
+    if st == CSPLAT_E_PENDING:
+        return None
+    _check(st)
+    return out
+
+
+def csplat_server_cancel(srv, ticket):
+    _check(load_library().csplat_server_cancel(srv, ticket))
+
+
+def csplat_server_stats(srv) -> dict:
+    st = ServerStats()
+    _check(load_library().csplat_server_stats(srv, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
 
 # --- convenience ------------------------------------------------------------

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libcsplat.so")
 ARCH = os.environ.get("CSPLAT_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["abi.hip", "scene.hip", "pair_fp32.hip", "precision.hip"]
+SOURCES = ["abi.hip", "scene.hip", "pair_fp32.hip", "precision.hip", "serve.hip", "sched.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -54,6 +54,24 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     return out
 
 
+SCHED_TEST_LIB = os.path.join(HERE, "libcsplat_sched.so")
+
+
+def build_sched_test_lib(verbose: bool = False) -> str:
+    """The serving scheduler alone, host compiler only, for CPU tests."""
+    tmp = SCHED_TEST_LIB + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wextra",
+           os.path.join(CSRC, "sched.cpp"), os.path.join(CSRC, "sched_capi.cpp"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed on the scheduler:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SCHED_TEST_LIB)
+    if verbose:
+        print("built", SCHED_TEST_LIB)
+    return SCHED_TEST_LIB
+
+
 if __name__ == "__main__":
+    build_sched_test_lib(verbose=True)
     build(verbose=True)
     sys.exit(0)

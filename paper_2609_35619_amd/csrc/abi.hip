@@ -79,24 +79,7 @@ void DevBuf::release()
     bytes = 0;
 }
 
-namespace {
-
-// Set the context's device as current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) err = hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-// 0: host, 1: device, -1: unknown/invalid
+// 0: host, 1: device
 int pointer_kind(const void *p)
 {
     hipPointerAttribute_t a;
@@ -108,7 +91,7 @@ int pointer_kind(const void *p)
     return 0;
 }
 
-csplat_status build_params(const csplat_ctx *ctx, const csplat_reduce_opts &o, EvalParams &p)
+csplat_status build_params(const float *n_sigma, int m, const csplat_reduce_opts &o, EvalParams &p)
 {
     if (o.k < 0) return fail(CSPLAT_E_INVALID, "reduce opts: k must be >= 0");
     if (!(o.softmin_tau >= 0.f) || !std::isfinite(o.softmin_tau))
@@ -123,11 +106,11 @@ csplat_status build_params(const csplat_ctx *ctx, const csplat_reduce_opts &o, E
     if (o.precision < CSPLAT_PRECISION_FP32 || o.precision > CSPLAT_PRECISION_FP16_RECHECK)
         return fail(CSPLAT_E_INVALID, "reduce opts: unknown precision");
     std::memset(&p, 0, sizeof(p));
-    p.m = ctx->m;
+    p.m = m;
     p.k = o.k;
-    for (int v = 0; v < ctx->m; ++v) {
-        double n = ctx->n_sigma[v];
-        p.n_sigma[v] = ctx->n_sigma[v];
+    for (int v = 0; v < m; ++v) {
+        double n = n_sigma[v];
+        p.n_sigma[v] = n_sigma[v];
         p.two_n[v] = (float)(2.0 * n);
         p.four_n2[v] = (float)(4.0 * n * n);
     }
@@ -145,6 +128,8 @@ csplat_status build_params(const csplat_ctx *ctx, const csplat_reduce_opts &o, E
                                           : (float)((double)o.neighbor_radius * o.neighbor_radius);
     return CSPLAT_OK;
 }
+
+namespace {
 
 // Query spheres must have finite centres and finite radii > 0.  Host arrays
 // are checked here; device arrays by check_queries_kernel before any output
@@ -299,7 +284,7 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     if (q > (int64_t)0x7FFFFFFF / 8) return fail(CSPLAT_E_INVALID, "eval: q too large");
     if (sc->device != ctx->device) return fail(CSPLAT_E_INVALID, "eval: scene on another device");
     EvalParams p;
-    csplat_status s = build_params(ctx, *opts, p);
+    csplat_status s = build_params(ctx->n_sigma, ctx->m, *opts, p);
     if (s != CSPLAT_OK) return s;
     const bool want_dist = out->min || out->softmin || out->cost || out->nbr;
     if (!want_dist && !out->label && !out->count) return fail(CSPLAT_E_INVALID, "eval: no output requested");

@@ -26,6 +26,21 @@ csplat_status hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return ::csplat::hip_fail(e_, #call); \
     } while (0)
 
+// Set a device as current for the duration of a scope.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
 // A device buffer that grows on demand (never shrinks until freed).
 struct DevBuf {
     void *ptr = nullptr;
@@ -122,6 +137,12 @@ struct EvalOut {
     float *cost;
     int32_t *nbr;
 };
+
+// Evaluation parameters from conservatism values and reduction options
+// (validates the options; CSPLAT_E_INVALID with a message on error).
+csplat_status build_params(const float *n_sigma, int m, const csplat_reduce_opts &o, EvalParams &p);
+// 1 if p is a device (or managed) pointer, 0 for host memory.
+int pointer_kind(const void *p);
 
 // pair_fp32.hip: the float32 pair kernel and the split combine.
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,

@@ -1,0 +1,360 @@
+// Device code of the float32 pair path shared by the evaluation kernels and
+// the serving step kernels (one definition, identical arithmetic).
+//
+// Layout and mapping on gfx950:
+//  * 256 lanes (4 waves) per block, a few queries per lane; each query's
+//    centre, r^2 and accumulators live in VGPRs;
+//  * the Gaussian records are wave-uniform: every lane of a wave needs the
+//    same Gaussian at the same time, so they are fetched with scalar loads
+//    into SGPRs and used directly as VALU operands (no LDS round trip, no
+//    VGPRs spent on them, no bank conflicts);
+//  * the Gaussian list is cut into `splits` contiguous ranges so that small
+//    query batches still fill the 256 CUs; partial reductions are merged in a
+//    fixed order (bit-reproducible results).
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace csplat {
+namespace pair {
+
+constexpr int kBlock = 256;
+constexpr int kChunk = 512;  // Gaussians per first-level softmin/cost sum
+// Launch-shape constants (overridable at build time for tuning sweeps).
+#ifndef CSPLAT_UNROLL
+#define CSPLAT_UNROLL 4
+#endif
+#ifndef CSPLAT_QPL_FULL
+#define CSPLAT_QPL_FULL 2
+#endif
+#ifndef CSPLAT_QPL_LABELS
+#define CSPLAT_QPL_LABELS 4
+#endif
+#ifndef CSPLAT_PRETEST
+#define CSPLAT_PRETEST 0
+#endif
+constexpr int kUnroll = CSPLAT_UNROLL;       // Gaussians per group of scalar loads
+constexpr int kQplFull = CSPLAT_QPL_FULL;    // queries per lane, all outputs
+constexpr int kQplLabels = CSPLAT_QPL_LABELS;  // queries per lane, labels only
+// Expanded-form neighbourhood pre-test (4 operations instead of 6 per pair,
+// exact by a certified margin).  Off by default: on the MPPI workload the loop
+// is not VALU-issue bound and the extra work inside the branch costs more
+// than the pre-test saves (12.8 ms vs 13.7 ms per launch on MI355X).
+constexpr bool kPretest = CSPLAT_PRETEST != 0;
+
+__device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+struct Part {
+    int32_t *cnt;  // [split][v][q]
+    float *mt;     // running minimum of t = s~^2 * kt
+    float *sm;     // sum of 2^(mt - t)
+    float *cs;     // sum of the base-2 cost terms
+    int32_t *nb;   // [split][q] neighbourhood size
+};
+
+// Ball membership and the per-pair metric.  Terms in "r^2 units": with
+// d = mu - c, D = |d|^2 and V = |M d|^2 = d^T Sigma d,
+//   r^2 s^2 = D,  r^2 n sqrt(sigma^2) = 2 n sqrt(V),  r^2 s~^2 = max(0, D - 2 n sqrt(V)).
+//
+// Each lane holds QPL queries (slot u of block b is query b*kBlock*QPL + u*kBlock + tid),
+// so every scalar-loaded Gaussian feeds QPL pairs per lane; the Gaussian loop is
+// unrolled by kUnroll (the group's records in scalar loads).  In FULL mode a single branch per
+// Gaussian skips the metric when no query of the wave has it in its ball.
+template <int M, int QPL>
+struct Acc {
+    int cnt[QPL][M];
+    float mt[QPL][M], sm[QPL][M], cs[QPL][M];   // lane totals
+    float cmt[QPL][M], csm[QPL][M], ccs[QPL][M]; // current chunk
+    int nb[QPL];
+};
+
+template <int M, bool FULL, bool BALL, int QPL>
+__device__ __forceinline__ void pair_step(const float *__restrict__ gp, const float (&cx)[QPL],
+                                          const float (&cy)[QPL], const float (&cz)[QPL],
+                                          const float (&r2)[QPL], const float (&kq)[QPL],
+                                          const float (&cc)[QPL], const float (&rn2w)[QPL],
+                                          const EvalParams &p, Acc<M, QPL> &A)
+{
+    if constexpr (FULL) {
+        // neighbourhood pre-test on the expanded |d|^2 = |mu|^2 - 2 mu.c + |c|^2
+        // (4 operations) against r_nbr^2 widened by its certified rounding
+        // margin; the exact difference form decides inside the branch
+        bool any = !BALL;
+        if constexpr (BALL && kPretest) {
+#pragma unroll
+            for (int u = 0; u < QPL; ++u) {
+                const float De = fmaf(gp[12], cx[u], fmaf(gp[13], cy[u], fmaf(gp[14], cz[u], gp[15] + cc[u])));
+                any |= De <= rn2w[u];
+            }
+        } else if constexpr (BALL) {
+#pragma unroll
+            for (int u = 0; u < QPL; ++u) {
+                const float dx = gp[0] - cx[u], dy = gp[1] - cy[u], dz = gp[2] - cz[u];
+                any |= fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= p.rn2;
+            }
+        }
+        if (any) {
+#pragma unroll
+            for (int u = 0; u < QPL; ++u) {
+                const float dx = gp[0] - cx[u], dy = gp[1] - cy[u], dz = gp[2] - cz[u];
+                const float D = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (!BALL || D <= p.rn2) {
+                    ++A.nb[u];
+                    const float e0 = fmaf(gp[5], dz, fmaf(gp[4], dy, gp[3] * dx));
+                    const float e1 = fmaf(gp[8], dz, fmaf(gp[7], dy, gp[6] * dx));
+                    const float e2 = fmaf(gp[11], dz, fmaf(gp[10], dy, gp[9] * dx));
+                    const float sv = fast_sqrt(fmaf(e2, e2, fmaf(e1, e1, e0 * e0)));
+#pragma unroll
+                    for (int v = 0; v < M; ++v) {
+                        const float x = fmaf(-p.two_n[v], sv, D);  // r^2 (s^2 - n sqrt(sigma^2))
+                        A.cnt[u][v] += x < r2[u];                      // s~^2 < 1
+                        const float t = fmaxf(x, 0.f) * kq[u];
+                        // stable log-sum-exp about the running chunk minimum (one exp per pair)
+                        const float e = fast_exp2(-fabsf(t - A.cmt[u][v]));
+                        const bool lower = t < A.cmt[u][v];
+                        A.csm[u][v] = lower ? fmaf(A.csm[u][v], e, 1.f) : A.csm[u][v] + e;
+                        A.cmt[u][v] = lower ? t : A.cmt[u][v];
+                        A.ccs[u][v] += fast_exp2(fminf(fmaf(t, -p.g1, p.g0), 0.f));
+                    }
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < QPL; ++u) {
+            const float dx = gp[0] - cx[u], dy = gp[1] - cy[u], dz = gp[2] - cz[u];
+            // labels only: s~^2 < 1  <=>  a |a| < 4 n^2 V  with a = D - r^2 (exact rewrite)
+            const float a = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -r2[u])));
+            const float e0 = fmaf(gp[5], dz, fmaf(gp[4], dy, gp[3] * dx));
+            const float e1 = fmaf(gp[8], dz, fmaf(gp[7], dy, gp[6] * dx));
+            const float e2 = fmaf(gp[11], dz, fmaf(gp[10], dy, gp[9] * dx));
+            const float V = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
+            const float aa = a * fabsf(a);
+            bool in = true;
+            if constexpr (BALL) in = a + r2[u] <= p.rn2;
+#pragma unroll
+            for (int v = 0; v < M; ++v) A.cnt[u][v] += in && (aa < p.four_n2[v] * V);
+        }
+    }
+}
+
+// One work item: the queries of `tile` (kBlock x QPL of them) against the
+// Gaussian range of `split`, written to the split's partial records.  Shared
+// by the evaluation kernel and the serving step kernel, so a request gives
+// the same bits in either.
+template <int M, bool FULL, bool BALL, int QPL>
+__device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, int per_split, int split,
+                                          int tile, const float *__restrict__ centers,
+                                          const float *__restrict__ radii, int q, const EvalParams &p,
+                                          const Part &part, float mu_max)
+{
+    float cx[QPL], cy[QPL], cz[QPL], r2[QPL], kq[QPL], cc[QPL], rn2w[QPL];
+    int jq[QPL];
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+        jq[u] = (tile * QPL + u) * kBlock + (int)threadIdx.x;
+        const int jj = jq[u] < q ? jq[u] : q - 1;  // past the end: evaluate a real query, write nothing
+        cx[u] = centers[3 * jj];
+        cy[u] = centers[3 * jj + 1];
+        cz[u] = centers[3 * jj + 2];
+        const float r = radii[jj];
+        r2[u] = r * r;
+        kq[u] = p.kt / r2[u];  // t = max(0, r^2 s~^2) * kq = s~^2 * kt
+        cc[u] = fmaf(cz[u], cz[u], fmaf(cy[u], cy[u], cx[u] * cx[u]));
+        // the expanded |d|^2 is within 7 ulps of (|mu| + |c|)^2 of the exact value
+        // and the difference form within 3 ulps of it; 12 ulps of the widened
+        // threshold keep every pair the exact test accepts inside the branch
+        const float ext = mu_max + sqrtf(cc[u]);
+        rn2w[u] = p.rn2 + 12.f * 5.9604645e-08f * ext * ext;
+    }
+    Acc<M, QPL> A;
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+        A.nb[u] = 0;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            A.cnt[u][v] = 0;
+            A.mt[u][v] = INFINITY;
+            A.sm[u][v] = 0.f;
+            A.cs[u][v] = 0.f;
+        }
+    }
+
+    const int g0 = split * per_split;
+    const int g1 = min(n, g0 + per_split);
+    // The softmin and cost sums are accumulated per chunk of kChunk Gaussians
+    // and folded into the lane totals at the end of each chunk (two-level
+    // summation keeps the float32 rounding of long sums near sqrt(kChunk) ulps).
+    for (int c0 = g0; c0 < g1; c0 += kChunk) {
+        const int c1 = min(g1, c0 + kChunk);
+        if constexpr (FULL) {
+#pragma unroll
+            for (int u = 0; u < QPL; ++u)
+#pragma unroll
+                for (int v = 0; v < M; ++v) {
+                    A.cmt[u][v] = INFINITY;
+                    A.csm[u][v] = 0.f;
+                    A.ccs[u][v] = 0.f;
+                }
+        }
+        const float *gp = gs + (size_t)kGaussFloats * c0;
+        int g = c0;
+        for (; g + kUnroll <= c1; g += kUnroll, gp += kGaussFloats * kUnroll) {
+            float rec[kGaussFloats * kUnroll];  // wave-uniform (scalar) loads
+#pragma unroll
+            for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = gp[i];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k)
+                pair_step<M, FULL, BALL, QPL>(rec + kGaussFloats * k, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+        }
+        for (; g < c1; ++g, gp += kGaussFloats)
+            pair_step<M, FULL, BALL, QPL>(gp, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+        if constexpr (FULL) {
+#pragma unroll
+            for (int u = 0; u < QPL; ++u)
+#pragma unroll
+                for (int v = 0; v < M; ++v) {
+                    A.cs[u][v] += A.ccs[u][v];
+                    const float cm = A.cmt[u][v], tm = A.mt[u][v];
+                    if (cm < tm) {
+                        A.sm[u][v] = fmaf(A.sm[u][v], fast_exp2(tm == INFINITY ? -INFINITY : cm - tm), A.csm[u][v]);
+                        A.mt[u][v] = cm;
+                    } else if (cm < INFINITY) {
+                        A.sm[u][v] = fmaf(A.csm[u][v], fast_exp2(tm - cm), A.sm[u][v]);
+                    }
+                }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+        const int j = jq[u];
+        if (j >= q) continue;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            const size_t o = ((size_t)split * M + v) * q + j;
+            part.cnt[o] = A.cnt[u][v];
+            if constexpr (FULL) {
+                part.mt[o] = A.mt[u][v];
+                part.sm[o] = A.sm[u][v];
+                part.cs[o] = A.cs[u][v];
+            }
+        }
+        if constexpr (FULL) part.nb[(size_t)split * q + j] = A.nb[u];
+    }
+}
+
+template <int M, bool FULL, bool BALL, int QPL>
+__global__ void __launch_bounds__(kBlock)
+pair_kernel(const float *__restrict__ gs, int n, int per_split, int n_tiles,
+            const float *__restrict__ centers, const float *__restrict__ radii, int q,
+            const EvalParams p, Part part, float mu_max)
+{
+    int b = blockIdx.x;
+    const int B = gridDim.x;
+    if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few ranges
+    const int split = b / n_tiles;
+    const int tile = b - split * n_tiles;
+    eval_tile<M, FULL, BALL, QPL>(gs, n, per_split, split, tile, centers, radii, q, p, part, mu_max);
+}
+
+// Merge the split partials in split order and finalise every output.
+template <int M, bool FULL>
+__device__ __forceinline__ void combine_query(int j, int q, int S, const EvalParams &p, const Part &part,
+                                              const EvalOut &out)
+{
+    int nb = 0;
+    if constexpr (FULL)
+        for (int s = 0; s < S; ++s) nb += part.nb[(size_t)s * q + j];
+    if (out.nbr) out.nbr[j] = nb;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        int cnt = 0;
+        float mt = INFINITY, sm = 0.f, cs = 0.f;
+        for (int s = 0; s < S; ++s) {
+            const size_t o = ((size_t)s * M + v) * q + j;
+            cnt += part.cnt[o];
+            if constexpr (FULL) {
+                const float bm = part.mt[o], bs = part.sm[o];
+                cs += part.cs[o];
+                if (bm < INFINITY) {
+                    if (bm < mt) {
+                        sm = fmaf(sm, fast_exp2(mt == INFINITY ? -INFINITY : bm - mt), bs);
+                        mt = bm;
+                    } else {
+                        sm = fmaf(bs, fast_exp2(mt - bm), sm);
+                    }
+                }
+            }
+        }
+        const size_t o = (size_t)j * p.m + v;
+        if (out.count) out.count[o] = cnt;
+        if (out.label) out.label[o] = cnt > p.k ? 1 : 0;
+        if constexpr (FULL) {
+            const float mn = mt * p.inv_kt;
+            if (out.min) out.min[o] = mn;
+            if (out.softmin)
+                out.softmin[o] = (!p.soft || mt == INFINITY) ? mn : (mt - fast_log2(sm)) * p.inv_kt;
+            if (out.cost) out.cost[o] = nb > 0 ? p.d_max * (cs / (float)nb) : 0.f;
+        }
+    }
+}
+
+template <int M, bool FULL>
+__global__ void __launch_bounds__(256)
+combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < q) combine_query<M, FULL>(j, q, S, p, part, out);
+}
+
+// How an evaluation of q queries against n Gaussians is cut into work items:
+// query tiles of kBlock x QPL queries times `S` contiguous Gaussian ranges of
+// `per_split`, enough items to fill the device several times over and ranges
+// of at least 1024 Gaussians.  Depends only on (q, n, mode, device), so a
+// request gives the same partial reductions wherever it runs.
+struct SplitPlan {
+    int n_tiles, S, per_split, qpl;
+};
+
+inline SplitPlan split_plan(int target_blocks, int q, int n, bool full)
+{
+    SplitPlan sp;
+    sp.qpl = full ? kQplFull : kQplLabels;
+    sp.n_tiles = (q + kBlock * sp.qpl - 1) / (kBlock * sp.qpl);
+    int S = 1;
+    if (n > 0 && sp.n_tiles > 0) {
+        S = (target_blocks + sp.n_tiles - 1) / sp.n_tiles;
+        S = std::max(1, std::min(S, (n + 1023) / 1024));
+    }
+    sp.per_split = n > 0 ? (n + S - 1) / S : 0;
+    if (n > 0) S = (n + sp.per_split - 1) / sp.per_split;
+    sp.S = n > 0 ? S : 0;
+    return sp;
+}
+
+// Words of partial reductions per (split, query) for m conservatism values.
+inline size_t part_words(int m, bool full) { return (size_t)m * (full ? 4 : 1) + (full ? 1 : 0); }
+
+// Partial-record views over one buffer of S * q * part_words(m, full) words.
+inline Part part_views(void *base, int S, int q, int m, bool full)
+{
+    char *b = static_cast<char *>(base);
+    const size_t per = (size_t)(S > 0 ? S : 1) * q;
+    Part part{};
+    part.cnt = reinterpret_cast<int32_t *>(b);
+    if (full) {
+        part.mt = reinterpret_cast<float *>(b + per * m * 4);
+        part.sm = reinterpret_cast<float *>(b + per * m * 8);
+        part.cs = reinterpret_cast<float *>(b + per * m * 12);
+        part.nb = reinterpret_cast<int32_t *>(b + per * m * 16);
+    }
+    return part;
+}
+
+}  // namespace pair
+}  // namespace csplat

@@ -1,0 +1,619 @@
+// The serving form: resident scenes, admission by memory, continuous batching
+// of work items into steps that are replays of a captured HIP graph.
+//
+// Per step the graph copies a staging area from pinned host memory (the
+// descriptors of the active requests, the work items sorted by variant, the
+// requests completing in this step), runs four persistent step kernels (one
+// per (labels|full) x (ball|no ball) variant) that each walk their item
+// range with the same per-tile code as csplat_eval, and a combine kernel
+// that finalises the completing requests straight into pinned host memory.
+// Two graph instances with their own staging areas alternate, so the worker
+// thread prepares step k+1 while step k runs.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "pair_core.h"
+#include "sched.h"
+
+namespace csplat {
+namespace {
+
+using namespace pair;
+using serve::Item;
+using serve::ReqSpec;
+using serve::Scheduler;
+using serve::State;
+using serve::StepPlan;
+
+constexpr int kVariants = 4;        // 0 labels/no ball, 1 labels/ball, 2 full/no ball, 3 full/ball
+constexpr int kStepBlocks = 2048;   // persistent grid of each step kernel (8 blocks per CU)
+constexpr int kMaxItems = 16384;    // work items per step
+constexpr int kMaxSlots = 64;
+constexpr int64_t kStepPairs = 40000000000LL;  // ~10-20 ms of pair work per step
+
+struct ReqDesc {
+    const float *gs;
+    const float *centers;
+    const float *radii;
+    int32_t n, per_split, S, q;
+    int32_t full;
+    float mu_max;
+    EvalParams p;
+    Part part;
+    EvalOut out;  // device-visible pointers into pinned host memory
+};
+
+struct StepHeader {
+    int32_t begin[kVariants + 1];  // item range of each variant
+    int32_t n_done;
+    int32_t done[kMaxSlots];
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct StageLayout {
+    size_t desc, items, bytes;
+    explicit StageLayout(int slots)
+    {
+        desc = align256(sizeof(StepHeader));
+        items = desc + align256(sizeof(ReqDesc) * (size_t)slots);
+        bytes = items + align256(sizeof(Item) * (size_t)kMaxItems);
+    }
+};
+
+template <bool FULL, bool BALL>
+__global__ void __launch_bounds__(kBlock) step_kernel(const char *__restrict__ stage, int variant, size_t desc_off,
+                                                      size_t items_off)
+{
+    const StepHeader *h = reinterpret_cast<const StepHeader *>(stage);
+    const ReqDesc *reqs = reinterpret_cast<const ReqDesc *>(stage + desc_off);
+    const Item *items = reinterpret_cast<const Item *>(stage + items_off);
+    const int b1 = h->begin[variant + 1];
+    constexpr int QPL = FULL ? kQplFull : kQplLabels;
+    for (int it = h->begin[variant] + (int)blockIdx.x; it < b1; it += (int)gridDim.x) {
+        const Item w = items[it];
+        const ReqDesc &R = reqs[w.slot];
+        eval_tile<1, FULL, BALL, QPL>(R.gs, R.n, R.per_split, w.split, w.tile, R.centers, R.radii, R.q, R.p,
+                                      R.part, R.mu_max);
+    }
+}
+
+__global__ void __launch_bounds__(256) serve_combine_kernel(const char *__restrict__ stage, size_t desc_off)
+{
+    const StepHeader *h = reinterpret_cast<const StepHeader *>(stage);
+    const ReqDesc *reqs = reinterpret_cast<const ReqDesc *>(stage + desc_off);
+    for (int d = 0; d < h->n_done; ++d) {
+        const ReqDesc &R = reqs[h->done[d]];
+        for (int j = (int)(blockIdx.x * blockDim.x + threadIdx.x); j < R.q; j += (int)(gridDim.x * blockDim.x)) {
+            if (R.full) combine_query<1, true>(j, R.q, R.S, R.p, R.part, R.out);
+            else combine_query<1, false>(j, R.q, R.S, R.p, R.part, R.out);
+        }
+    }
+}
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Rec {
+    int32_t scene = 0, kind = 0;
+    int64_t q = 0;
+    std::vector<float> centers, radii;  // until admission
+    EvalParams p{};
+    SplitPlan sp{};
+    bool full = false, ball = false;
+    int64_t pairs = 0;
+    // arena layout of the request
+    size_t d_centers = 0, d_radii = 0, d_part = 0;
+    size_t h_in = 0, h_label = 0, h_count = 0, h_min = 0, h_soft = 0, h_cost = 0, h_nbr = 0;
+};
+
+}  // namespace
+}  // namespace csplat
+
+using namespace csplat;
+
+struct csplat_server {
+    int device = 0;
+    int slots = 0;
+    uint64_t budget = 0;
+    hipStream_t stream = nullptr, copy_stream = nullptr;
+    char *dev_arena = nullptr;
+    char *host_arena = nullptr;      // pinned, device-mapped
+    char *host_arena_dev = nullptr;  // its device address
+    StageLayout layout{1};
+    char *stage_host[2] = {nullptr, nullptr};
+    char *stage_dev[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
+    hipEvent_t copy_ev = nullptr;
+    bool copies_pending = false;
+    std::vector<const csplat_scene *> scenes;
+    Scheduler *sched = nullptr;
+    std::map<int64_t, Rec> recs;
+    std::vector<ReqDesc> desc;       // per slot
+    std::vector<int64_t> slot_ticket;
+    struct Inflight {
+        int64_t step;
+        int stage;
+    };
+    std::vector<Inflight> inflight;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    csplat_status fatal = CSPLAT_OK;
+    std::string fatal_msg;
+    // statistics
+    csplat_serving_stats st{};
+    std::vector<double> lat_ms;
+    double first_admit = -1, last_done = -1;
+    int64_t pairs_done = 0;
+};
+
+namespace csplat {
+namespace {
+
+void set_fatal(csplat_server *s, hipError_t e, const char *what)
+{
+    if (s->fatal == CSPLAT_OK) {
+        s->fatal = e == hipErrorOutOfMemory ? CSPLAT_E_OOM : CSPLAT_E_DEVICE;
+        s->fatal_msg = std::string("server: ") + what + ": " + hipGetErrorString(e);
+    }
+}
+
+// Admitted request: upload its inputs (pinned staging -> device arena, on the
+// copy stream) and write its descriptor.
+void setup_request(csplat_server *s, int64_t t)
+{
+    const serve::ReqInfo *ri = s->sched->info(t);
+    Rec &r = s->recs[t];
+    const size_t qn = (size_t)r.q;
+    char *hbase = s->host_arena + ri->host_off;
+    std::memcpy(hbase + r.h_in, r.centers.data(), qn * 12);
+    std::memcpy(hbase + r.h_in + qn * 12, r.radii.data(), qn * 4);
+    std::vector<float>().swap(r.centers);
+    std::vector<float>().swap(r.radii);
+    char *dbase = s->dev_arena + ri->dev_off;
+    if (qn) {
+        hipError_t e = hipMemcpyAsync(dbase + r.d_centers, hbase + r.h_in, qn * 16, hipMemcpyHostToDevice,
+                                      s->copy_stream);
+        if (e != hipSuccess) set_fatal(s, e, "input upload");
+        s->copies_pending = true;
+    }
+    const csplat_scene *sc = s->scenes[(size_t)r.scene];
+    ReqDesc d{};
+    d.gs = sc->gauss;
+    d.centers = reinterpret_cast<const float *>(dbase + r.d_centers);
+    d.radii = reinterpret_cast<const float *>(dbase + r.d_centers + qn * 12);
+    d.n = (int32_t)sc->n;
+    d.per_split = r.sp.per_split;
+    d.S = r.sp.S;
+    d.q = (int32_t)r.q;
+    d.full = r.full ? 1 : 0;
+    d.mu_max = sc->mu_max;
+    d.p = r.p;
+    d.part = part_views(dbase + r.d_part, r.sp.S, (int)r.q, 1, r.full);
+    char *hd = s->host_arena_dev + ri->host_off;
+    d.out.label = reinterpret_cast<uint8_t *>(hd + r.h_label);
+    d.out.count = reinterpret_cast<int32_t *>(hd + r.h_count);
+    if (r.full) {
+        d.out.min = reinterpret_cast<float *>(hd + r.h_min);
+        d.out.softmin = reinterpret_cast<float *>(hd + r.h_soft);
+        d.out.cost = reinterpret_cast<float *>(hd + r.h_cost);
+        d.out.nbr = reinterpret_cast<int32_t *>(hd + r.h_nbr);
+    }
+    s->desc[(size_t)ri->slot] = d;
+    s->slot_ticket[(size_t)ri->slot] = t;
+    if (s->first_admit < 0) s->first_admit = now_s();
+}
+
+void launch_step(csplat_server *s, const StepPlan &plan)
+{
+    const int k = (int)(plan.step & 1);
+    char *h = s->stage_host[k];
+    StepHeader *hd = reinterpret_cast<StepHeader *>(h);
+    std::memset(hd, 0, sizeof(StepHeader));
+    int n = 0;
+    for (int v = 0; v < kVariants; ++v) {
+        hd->begin[v] = n;
+        for (const Item &it : plan.items)
+            if (it.variant == v) reinterpret_cast<Item *>(h + s->layout.items)[n++] = it;
+    }
+    hd->begin[kVariants] = n;
+    hd->n_done = (int32_t)plan.completing.size();
+    for (size_t i = 0; i < plan.completing.size(); ++i) hd->done[i] = plan.completing[i];
+    std::memcpy(h + s->layout.desc, s->desc.data(), sizeof(ReqDesc) * (size_t)s->slots);
+    hipError_t e = hipSuccess;
+    if (s->copies_pending) {
+        e = hipEventRecord(s->copy_ev, s->copy_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->copy_ev, 0);
+        s->copies_pending = false;
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(s->graph[k], s->stream);
+    if (e == hipSuccess) e = hipEventRecord(s->step_ev[k], s->stream);
+    if (e != hipSuccess) {
+        set_fatal(s, e, "step launch");
+        return;
+    }
+    s->inflight.push_back({plan.step, k});
+    ++s->st.steps;
+}
+
+void worker_main(csplat_server *s)
+{
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        bool progressed = false;
+        // completed steps, oldest first
+        while (!s->inflight.empty()) {
+            hipError_t q = hipEventQuery(s->step_ev[s->inflight.front().stage]);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) {
+                set_fatal(s, q, "step execution");
+                (void)hipGetLastError();
+            }
+            const double t = now_s();
+            for (int64_t tk : s->sched->step_done(s->inflight.front().step, t)) {
+                const serve::ReqInfo *ri = s->sched->info(tk);
+                if (ri && ri->state == State::Done) {
+                    s->lat_ms.push_back((ri->t_done - ri->t_submit) * 1e3);
+                    s->pairs_done += s->recs[tk].pairs;
+                    s->last_done = t;
+                    ++s->st.completed;
+                } else if (ri && ri->state == State::Cancelled) {
+                    ++s->st.cancelled;
+                }
+            }
+            s->inflight.erase(s->inflight.begin());
+            s->cv_done.notify_all();
+            progressed = true;
+        }
+        if (s->fatal != CSPLAT_OK) {
+            s->cv_done.notify_all();
+            if (s->stop && s->inflight.empty()) break;
+        }
+        if (s->stop && s->inflight.empty()) break;
+        if (!s->stop && s->fatal == CSPLAT_OK) {
+            for (int64_t tk : s->sched->admit(now_s())) {
+                setup_request(s, tk);
+                progressed = true;
+            }
+            if (s->inflight.size() < 2) {
+                StepPlan plan;
+                if (s->sched->plan(&plan)) {
+                    launch_step(s, plan);
+                    progressed = true;
+                }
+            }
+        }
+        if (!progressed) {
+            // nothing to do right now: sleep briefly (woken early by submit/cancel/stop)
+            s->cv_work.wait_for(lk, std::chrono::microseconds(s->inflight.empty() ? 2000 : 50));
+        }
+    }
+}
+
+csplat_status capture_graphs(csplat_server *s)
+{
+    for (int k = 0; k < 2; ++k) {
+        hipGraph_t g = nullptr;
+        CSPLAT_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipMemcpyAsync(s->stage_dev[k], s->stage_host[k], s->layout.bytes, hipMemcpyHostToDevice,
+                                      s->stream);
+        const char *st = s->stage_dev[k];
+        const size_t dof = s->layout.desc, iof = s->layout.items;
+        if (e == hipSuccess) {
+            step_kernel<false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 0, dof, iof);
+            step_kernel<false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 1, dof, iof);
+            step_kernel<true, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 2, dof, iof);
+            step_kernel<true, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 3, dof, iof);
+            serve_combine_kernel<<<1024, 256, 0, s->stream>>>(st, dof);
+            e = hipGetLastError();
+        }
+        hipError_t e2 = hipStreamEndCapture(s->stream, &g);
+        if (e != hipSuccess) return hip_fail(e, "graph capture");
+        if (e2 != hipSuccess) return hip_fail(e2, "graph capture end");
+        e = hipGraphInstantiate(&s->graph[k], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    }
+    return CSPLAT_OK;
+}
+
+void server_release(csplat_server *s)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
+        if (s->step_ev[k]) (void)hipEventDestroy(s->step_ev[k]);
+        if (s->stage_host[k]) (void)hipHostFree(s->stage_host[k]);
+        if (s->stage_dev[k]) (void)hipFree(s->stage_dev[k]);
+    }
+    if (s->copy_ev) (void)hipEventDestroy(s->copy_ev);
+    if (s->dev_arena) (void)hipFree(s->dev_arena);
+    if (s->host_arena) (void)hipHostFree(s->host_arena);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+    delete s->sched;
+}
+
+}  // namespace
+}  // namespace csplat
+
+extern "C" {
+
+csplat_status csplat_server_create(int32_t device, uint64_t hbm_budget, int32_t slots, csplat_server **out)
+{
+    if (!out) return fail(CSPLAT_E_INVALID, "server_create: out is NULL");
+    *out = nullptr;
+    if (slots < 1 || slots > kMaxSlots) return fail(CSPLAT_E_INVALID, "server_create: slots must be in 1..64");
+    if (hbm_budget < (1u << 20)) return fail(CSPLAT_E_INVALID, "server_create: budget below 1 MiB");
+    int ndev = 0;
+    CSPLAT_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(CSPLAT_E_INVALID, "server_create: no such device");
+    DeviceGuard g(device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    csplat_server *s = new (std::nothrow) csplat_server();
+    if (!s) return fail(CSPLAT_E_OOM, "server_create: host allocation");
+    s->device = device;
+    s->slots = slots;
+    s->budget = hbm_budget;
+    s->layout = StageLayout(slots);
+    s->desc.assign((size_t)slots, ReqDesc{});
+    s->slot_ticket.assign((size_t)slots, 0);
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->dev_arena), hbm_budget);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&s->host_arena), hbm_budget, hipHostMallocMapped);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->host_arena_dev), s->host_arena, 0);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&s->stage_host[k]), s->layout.bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->stage_dev[k]), s->layout.bytes);
+        if (e == hipSuccess) {
+            std::memset(s->stage_host[k], 0, s->layout.bytes);
+            e = hipEventCreateWithFlags(&s->step_ev[k], hipEventDisableTiming);
+        }
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->copy_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        csplat_status st = hip_fail(e, "server_create");
+        server_release(s);
+        delete s;
+        return st;
+    }
+    csplat_status st = capture_graphs(s);
+    if (st != CSPLAT_OK) {
+        server_release(s);
+        delete s;
+        return st;
+    }
+    s->sched = new Scheduler(hbm_budget, hbm_budget, slots, kStepPairs, kMaxItems);
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_server_destroy(csplat_server *s)
+{
+    if (!s) return CSPLAT_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    DeviceGuard g(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->copy_stream);
+    server_release(s);
+    delete s;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_server_add_scene(csplat_server *s, const csplat_scene *sc, int32_t *scene_id)
+{
+    if (!s || !sc || !scene_id) return fail(CSPLAT_E_INVALID, "server_add_scene: NULL argument");
+    if (sc->device != s->device) return fail(CSPLAT_E_INVALID, "server_add_scene: scene on another device");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->scenes.push_back(sc);
+    *scene_id = (int32_t)s->scenes.size() - 1;
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t kind, int64_t q,
+                                   const float *centers, const float *radii, const csplat_reduce_opts *opts,
+                                   const float *n_sigma, int32_t m, uint64_t *ticket)
+{
+    if (!s || !opts || !n_sigma || !ticket) return fail(CSPLAT_E_INVALID, "server_submit: NULL argument");
+    *ticket = 0;
+    if (kind != CSPLAT_SERVE_COST && kind != CSPLAT_SERVE_LABELS)
+        return fail(CSPLAT_E_INVALID, "server_submit: unknown kind");
+    if (m != 1) return fail(CSPLAT_E_INVALID, "server_submit: one conservatism value per request (m = 1)");
+    if (!(n_sigma[0] >= 0.f) || !std::isfinite(n_sigma[0]))
+        return fail(CSPLAT_E_INVALID, "server_submit: n_sigma must be finite and >= 0");
+    if (opts->precision != CSPLAT_PRECISION_FP32)
+        return fail(CSPLAT_E_INVALID, "server_submit: the serving form evaluates in float32");
+    if (q < 0 || q > (int64_t)0x7FFFFFFF / 8) return fail(CSPLAT_E_INVALID, "server_submit: q out of range");
+    if (q > 0 && (!centers || !radii)) return fail(CSPLAT_E_INVALID, "server_submit: NULL centers or radii");
+    if (q > 0 && (pointer_kind(centers) || pointer_kind(radii)))
+        return fail(CSPLAT_E_INVALID, "server_submit: inputs must be host pointers");
+    for (int64_t j = 0; j < q; ++j) {
+        if (!std::isfinite(centers[3 * j]) || !std::isfinite(centers[3 * j + 1]) ||
+            !std::isfinite(centers[3 * j + 2]) || !(radii[j] > 0.f) || !std::isfinite(radii[j]))
+            return fail(CSPLAT_E_INVALID, "server_submit: query centres must be finite and radii finite and > 0");
+    }
+    Rec r;
+    csplat_status st = build_params(n_sigma, 1, *opts, r.p);
+    if (st != CSPLAT_OK) return st;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->fatal != CSPLAT_OK) return fail(s->fatal, s->fatal_msg);
+    if (scene_id < 0 || scene_id >= (int32_t)s->scenes.size())
+        return fail(CSPLAT_E_NOT_FOUND, "server_submit: unknown scene id");
+    const csplat_scene *sc = s->scenes[(size_t)scene_id];
+    r.scene = scene_id;
+    r.kind = kind;
+    r.q = q;
+    r.full = kind == CSPLAT_SERVE_COST;
+    r.ball = std::isfinite(r.p.rn2);
+    r.sp = split_plan(target_blocks(s->device), (int)q, (int)sc->n, r.full);
+    r.pairs = q * sc->n;
+    r.centers.assign(centers, centers + 3 * q);
+    r.radii.assign(radii, radii + q);
+    const size_t qn = (size_t)q;
+    const int S = std::max(r.sp.S, 1);
+    // device arena: inputs, then partial reductions
+    r.d_centers = 0;
+    r.d_part = align256(qn * 16);
+    const uint64_t dev_bytes = r.d_part + align256((size_t)S * qn * part_words(1, r.full) * 4);
+    // pinned host arena: input staging, then outputs
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += align256(b);
+        return o;
+    };
+    r.h_in = take(qn * 16);
+    r.h_label = take(qn);
+    r.h_count = take(qn * 4);
+    if (r.full) {
+        r.h_min = take(qn * 4);
+        r.h_soft = take(qn * 4);
+        r.h_cost = take(qn * 4);
+        r.h_nbr = take(qn * 4);
+    }
+    ReqSpec spec;
+    spec.tiles = r.sp.n_tiles;
+    spec.splits = r.sp.S;
+    spec.variant = (r.full ? 2 : 0) + (r.ball ? 1 : 0);
+    spec.item_pairs = (int64_t)kBlock * r.sp.qpl * r.sp.per_split;
+    spec.dev_bytes = dev_bytes;
+    spec.host_bytes = off;
+    const int64_t t = s->sched->submit(spec, now_s());
+    if (t < 0) {
+        ++s->st.refused;
+        return fail(CSPLAT_E_BUSY, "server_submit: the request can never fit the memory budget");
+    }
+    s->recs[t] = std::move(r);
+    ++s->st.submitted;
+    *ticket = (uint64_t)t;
+    lk.unlock();
+    s->cv_work.notify_all();
+    return CSPLAT_OK;
+}
+
+static csplat_status collect(csplat_server *s, int64_t t, const csplat_outputs *out)
+{
+    // caller holds the lock; the request is Done
+    const serve::ReqInfo *ri = s->sched->info(t);
+    const Rec &r = s->recs[t];
+    const char *h = s->host_arena + ri->host_off;
+    const size_t qn = (size_t)r.q;
+    if (out) {
+        if (out->label) std::memcpy(out->label, h + r.h_label, qn);
+        if (out->count) std::memcpy(out->count, h + r.h_count, qn * 4);
+        if (r.full) {
+            if (out->min) std::memcpy(out->min, h + r.h_min, qn * 4);
+            if (out->softmin) std::memcpy(out->softmin, h + r.h_soft, qn * 4);
+            if (out->cost) std::memcpy(out->cost, h + r.h_cost, qn * 4);
+            if (out->nbr) std::memcpy(out->nbr, h + r.h_nbr, qn * 4);
+        }
+    }
+    s->sched->finish(t);
+    s->recs.erase(t);
+    return CSPLAT_OK;
+}
+
+static csplat_status poll_locked(csplat_server *s, int64_t t, const csplat_outputs *out)
+{
+    const serve::ReqInfo *ri = s->sched->info(t);
+    if (!ri) return fail(CSPLAT_E_NOT_FOUND, "server: unknown ticket");
+    if (ri->state == State::Done) return collect(s, t, out);
+    if (ri->state == State::Cancelled) {
+        s->sched->finish(t);
+        s->recs.erase(t);
+        return fail(CSPLAT_E_CANCELLED, "server: the request was cancelled");
+    }
+    if (s->fatal != CSPLAT_OK) return fail(s->fatal, s->fatal_msg);
+    return CSPLAT_E_PENDING;
+}
+
+csplat_status csplat_server_poll(csplat_server *s, uint64_t ticket, const csplat_outputs *out)
+{
+    if (!s) return fail(CSPLAT_E_INVALID, "server_poll: NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    return poll_locked(s, (int64_t)ticket, out);
+}
+
+csplat_status csplat_server_wait(csplat_server *s, uint64_t ticket, const csplat_outputs *out, int64_t timeout_ms)
+{
+    if (!s) return fail(CSPLAT_E_INVALID, "server_wait: NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto t_end = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
+    for (;;) {
+        csplat_status st = poll_locked(s, (int64_t)ticket, out);
+        if (st != CSPLAT_E_PENDING) return st;
+        if (timeout_ms < 0) {
+            s->cv_done.wait_for(lk, std::chrono::milliseconds(100));
+        } else {
+            if (std::chrono::steady_clock::now() >= t_end) return CSPLAT_E_PENDING;
+            s->cv_done.wait_until(lk, std::min(t_end, std::chrono::steady_clock::now() + std::chrono::milliseconds(100)));
+        }
+    }
+}
+
+csplat_status csplat_server_cancel(csplat_server *s, uint64_t ticket)
+{
+    if (!s) return fail(CSPLAT_E_INVALID, "server_cancel: NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const serve::ReqInfo *ri = s->sched->info((int64_t)ticket);
+    if (!ri || (ri->state != State::Queued && ri->state != State::Active))
+        return fail(CSPLAT_E_NOT_FOUND, "server_cancel: unknown or finished ticket");
+    const bool was_queued = ri->state == State::Queued;
+    s->sched->cancel((int64_t)ticket, now_s());
+    if (was_queued) ++s->st.cancelled;
+    else if (s->sched->info((int64_t)ticket)->state == State::Cancelled) ++s->st.cancelled;
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_server_stats(csplat_server *s, csplat_serving_stats *out)
+{
+    if (!s || !out) return fail(CSPLAT_E_INVALID, "server_stats: NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    std::vector<double> v = s->lat_ms;
+    if (!v.empty()) {
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) {
+            double idx = p * (double)(v.size() - 1);
+            size_t lo = (size_t)idx;
+            size_t hi = std::min(lo + 1, v.size() - 1);
+            return v[lo] + (v[hi] - v[lo]) * (idx - (double)lo);
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double sum = 0;
+        for (double x : v) sum += x;
+        out->mean_ms = sum / (double)v.size();
+        out->max_ms = v.back();
+    }
+    if (s->first_admit >= 0 && s->last_done > s->first_admit) {
+        out->busy_s = s->last_done - s->first_admit;
+        out->pairs_per_s = (double)s->pairs_done / out->busy_s;
+    }
+    return CSPLAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+"""The serving form on the GPU: requests admitted while others run give the
+same bits as when run alone and as csplat_eval; memory refusal; cancel."""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from parity import compare
+from workloads import config, mppi_walk_queries, room_scene, serving_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2609_35619_amd as cs
+    cs.load_library()
+    return cs
+
+
+@pytest.fixture(scope="module")
+def env(cs):
+    """Two resident scenes (room law, 100k and 300k Gaussians) and a context."""
+    eng = cs.Engine(0)
+    scenes = [room_scene(100_000, seed=2), room_scene(300_000, seed=4)]
+    handles = [eng.load_scene(s, floater_opacity_max=0.05, floater_extent_min=0.1) for s in scenes]
+    yield eng, scenes, handles
+    for h in handles:
+        cs.csplat_scene_free(h)
+    eng.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _opts(cs, kind):
+    if kind == cs.CSPLAT_SERVE_COST:
+        return cs.reduce_opts(k=2, tau=0.1, r_nbr=1.0, d_max=1.0, gamma=1.0, s_min=1.0)
+    return cs.reduce_opts(k=2, r_nbr=math.inf)
+
+
+def _alone_eval(cs, eng, h, req, kind):
+    """The same request through csplat_eval (host pointers)."""
+    eng.set_conservatism([req["n_sigma"]])
+    want = ("label", "count", "min", "softmin", "cost", "nbr") if kind == cs.CSPLAT_SERVE_COST else ("label", "count")
+    return eng.evaluate(h, req["centers"], req["radii"], _opts(cs, kind), want)
+
+
+def _stream(n, seed, scale):
+    """A scaled serving stream (requests shrunk so the test runs in seconds)."""
+    reqs = serving_stream(n, seed=seed, rate_hz=200.0, max_mppi_k=256, max_rrt_points=2000, max_spheres=8)
+    out = []
+    for r in reqs:
+        q = r["centers"].shape[0]
+        keep = max(1, int(q * scale))
+        out.append(dict(r, centers=r["centers"][:keep], radii=r["radii"][:keep]))
+    return out
+
+
+def test_mix_equals_alone_and_eval(cs, env, oracle_mod):
+    eng, scenes, handles = env
+    _say("case: 24 requests in a Poisson mix vs alone vs csplat_eval")
+    srv = cs.csplat_server_create(0, 512 << 20, 8)
+    try:
+        ids = [cs.csplat_server_add_scene(srv, h) for h in handles]
+        reqs = _stream(24, seed=105, scale=0.5)
+        t0 = time.perf_counter()
+        tickets = []
+        for r in reqs:   # arrivals spread over time: later requests join running steps
+            while time.perf_counter() - t0 < r["t"]:
+                time.sleep(0.0005)
+            kind = cs.CSPLAT_SERVE_COST if r["kind"] == "mppi" else cs.CSPLAT_SERVE_LABELS
+            tickets.append((cs.csplat_server_submit(srv, ids[r["scene"]], kind, r["centers"], r["radii"],
+                                                    _opts(cs, kind), r["n_sigma"]), kind, r))
+        mixed = [cs.csplat_server_wait(srv, t, r["centers"].shape[0], kind) for t, kind, r in tickets]
+        st = cs.csplat_server_stats(srv)
+        _say(f"mix: {st}")
+        assert st["completed"] == len(reqs)
+        # each request alone on the server
+        for (t, kind, r), mix in zip(tickets[:6], mixed[:6]):
+            t2 = cs.csplat_server_submit(srv, ids[r["scene"]], kind, r["centers"], r["radii"], _opts(cs, kind),
+                                         r["n_sigma"])
+            alone = cs.csplat_server_wait(srv, t2, r["centers"].shape[0], kind)
+            for k in mix:
+                assert np.array_equal(mix[k].view(np.uint8), alone[k].view(np.uint8)), k
+    finally:
+        cs.csplat_server_destroy(srv)
+    # bit-identical to csplat_eval, and within parity of the oracle (sampled)
+    for i, ((t, kind, r), mix) in enumerate(zip(tickets, mixed)):
+        ev = _alone_eval(cs, eng, handles[r["scene"]], r, kind)
+        for k in mix:
+            a = mix[k].reshape(ev[k].shape)
+            assert np.array_equal(a.view(np.uint8), np.asarray(ev[k]).view(np.uint8)), (i, k)
+        if i % 6 == 0:
+            sub = np.arange(0, r["centers"].shape[0], max(1, r["centers"].shape[0] // 40))
+            from workloads import Queries
+            qs = Queries(r["centers"][sub], r["radii"][sub])
+            o = _opts(cs, kind)
+            ref = oracle_mod.evaluate_spheres(scenes[r["scene"]], qs, [r["n_sigma"]], alpha_f=0.05, extent_f=0.1,
+                                              k=2, tau=o.softmin_tau, r_nbr=o.neighbor_radius)
+            compare({k: v[sub] for k, v in mix.items()}, ref, tau=o.softmin_tau, gamma=1.0, where=f"serve-{i}")
+
+
+def test_admission_refusal_and_queueing(cs, env):
+    eng, scenes, handles = env
+    _say("case: budget refusal and queueing")
+    srv = cs.csplat_server_create(0, 8 << 20, 2)
+    try:
+        sid = cs.csplat_server_add_scene(srv, handles[0])
+        big = mppi_walk_queries(4096, 32, seed=1)       # 131k queries: ~2 MB inputs + 10 MB partials
+        with pytest.raises(cs.CsplatError) as ei:
+            cs.csplat_server_submit(srv, sid, cs.CSPLAT_SERVE_COST, big.centers, big.radii,
+                                    _opts(cs, cs.CSPLAT_SERVE_COST), 1.0)
+        assert ei.value.status == cs.CSPLAT_E_BUSY
+        small = mppi_walk_queries(16, 32, seed=2)
+        ts = [cs.csplat_server_submit(srv, sid, cs.CSPLAT_SERVE_LABELS, small.centers, small.radii,
+                                      _opts(cs, cs.CSPLAT_SERVE_LABELS), 1.0) for _ in range(6)]
+        outs = [cs.csplat_server_wait(srv, t, small.q, cs.CSPLAT_SERVE_LABELS) for t in ts]
+        for o in outs[1:]:
+            assert np.array_equal(o["label"], outs[0]["label"]) and np.array_equal(o["count"], outs[0]["count"])
+        st = cs.csplat_server_stats(srv)
+        assert st["refused"] == 1 and st["completed"] == 6
+    finally:
+        cs.csplat_server_destroy(srv)
+
+
+def test_cancel(cs, env):
+    eng, scenes, handles = env
+    _say("case: cancel a running and a queued request")
+    srv = cs.csplat_server_create(0, 256 << 20, 1)
+    try:
+        sid = cs.csplat_server_add_scene(srv, handles[1])
+        big = mppi_walk_queries(4096, 32, seed=3)
+        t_big = cs.csplat_server_submit(srv, sid, cs.CSPLAT_SERVE_LABELS, big.centers, big.radii,
+                                        _opts(cs, cs.CSPLAT_SERVE_LABELS), 2.0)
+        small = mppi_walk_queries(8, 32, seed=4)
+        t_q = cs.csplat_server_submit(srv, sid, cs.CSPLAT_SERVE_LABELS, small.centers, small.radii,
+                                      _opts(cs, cs.CSPLAT_SERVE_LABELS), 2.0)
+        t_after = cs.csplat_server_submit(srv, sid, cs.CSPLAT_SERVE_LABELS, small.centers, small.radii,
+                                          _opts(cs, cs.CSPLAT_SERVE_LABELS), 2.0)
+        cs.csplat_server_cancel(srv, t_q)     # queued behind the single slot
+        cs.csplat_server_cancel(srv, t_big)   # admitted (or about to be): stops after its in-flight step
+        for t, q in ((t_big, big.q), (t_q, small.q)):
+            with pytest.raises(cs.CsplatError) as ei:
+                cs.csplat_server_wait(srv, t, q, cs.CSPLAT_SERVE_LABELS)
+            assert ei.value.status == cs.CSPLAT_E_CANCELLED
+        out = cs.csplat_server_wait(srv, t_after, small.q, cs.CSPLAT_SERVE_LABELS)
+        assert out["label"].shape == (small.q, 1)
+        with pytest.raises(cs.CsplatError):
+            cs.csplat_server_cancel(srv, t_after)   # finished and collected
+    finally:
+        cs.csplat_server_destroy(srv)
+
+
+def test_edge_requests(cs, env):
+    import workloads
+    eng, scenes, handles = env
+    _say("case: empty request, empty scene, invalid submissions")
+    empty_scene = eng.load_scene(workloads.Scene(np.zeros((0, 3), np.float32), np.zeros((0, 4), np.float32),
+                                                 np.zeros((0, 3), np.float32), np.zeros(0, np.float32)))
+    srv = cs.csplat_server_create(0, 64 << 20, 4)
+    try:
+        sid = cs.csplat_server_add_scene(srv, handles[0])
+        eid = cs.csplat_server_add_scene(srv, empty_scene)
+        t0 = cs.csplat_server_submit(srv, sid, cs.CSPLAT_SERVE_COST, np.zeros((0, 3), np.float32),
+                                     np.zeros(0, np.float32), _opts(cs, cs.CSPLAT_SERVE_COST), 1.0)
+        assert cs.csplat_server_wait(srv, t0, 0, cs.CSPLAT_SERVE_COST)["label"].shape == (0, 1)
+        qs = mppi_walk_queries(4, 32, seed=9)
+        t1 = cs.csplat_server_submit(srv, eid, cs.CSPLAT_SERVE_COST, qs.centers, qs.radii,
+                                     _opts(cs, cs.CSPLAT_SERVE_COST), 1.0)
+        o = cs.csplat_server_wait(srv, t1, qs.q, cs.CSPLAT_SERVE_COST)
+        assert np.all(o["count"] == 0) and np.all(np.isinf(o["min"])) and np.all(o["cost"] == 0)
+        bad = qs.radii.copy()
+        bad[3] = -1
+        with pytest.raises(cs.CsplatError):
+            cs.csplat_server_submit(srv, sid, cs.CSPLAT_SERVE_COST, qs.centers, bad, _opts(cs, 0), 1.0)
+        with pytest.raises(cs.CsplatError):
+            cs.csplat_server_submit(srv, 99, cs.CSPLAT_SERVE_COST, qs.centers, qs.radii, _opts(cs, 0), 1.0)
+        with pytest.raises(cs.CsplatError):
+            cs.csplat_server_submit(srv, sid, cs.CSPLAT_SERVE_COST, qs.centers, qs.radii, _opts(cs, 0), [1.0, 2.0])
+    finally:
+        cs.csplat_server_destroy(srv)
+        cs.csplat_scene_free(empty_scene)
