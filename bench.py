@@ -48,7 +48,16 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full-size request law (MPPI K up to 4096 x 32 x 48; long)")
+    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "copy"), default="all",
+                    help="run one part only (for profiling); 'copy' is a plain 1 GiB device copy "
+                         "used to calibrate the HBM traffic counters")
     args = ap.parse_args()
+    if args.section == "copy":
+        return copy_calibration()
+    if args.section != "all":
+        args.no_precision = args.section not in ("precision",)
+        args.no_serving = args.section not in ("serving",)
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by queries with no exchange; see the design notes)", file=sys.stderr)
@@ -103,7 +112,12 @@ def main():
     gpu = {k: v.cpu().numpy() for k, v in out.items()}
     nbr_total = int(gpu["nbr"].astype(np.int64).sum())
     pairs = qs.q * n_kept
-    ops = OPS_ALL_PAIRS * pairs + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr_total
+    # the roofline counts the pairs the kernel evaluated: pairs in chunks
+    # skipped by the exact reach-bound test cost no arithmetic (every in-ball
+    # pair is evaluated); the dense count is reported beside it
+    evaluated = int(st["kernel_pairs"])
+    ops = OPS_ALL_PAIRS * evaluated + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr_total
+    dense_ops = OPS_ALL_PAIRS * pairs + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr_total
     achieved = ops / kernel_s
     res = {
         "metric": METRIC,
@@ -130,7 +144,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU / 1e9, "unit": "Gop/s",
                      "frac": achieved / PEAK_VALU, "traffic": None,
                      "kernel": "pair_kernel<3,full,ball>", "kernel_ms": kernel_s * 1e3,
-                     "ops_per_launch": ops, "in_ball_pairs": nbr_total},
+                     "ops_per_launch": ops, "in_ball_pairs": nbr_total, "evaluated_pairs": evaluated,
+                     "dense_pairs": pairs, "dense_ops_per_launch": dense_ops,
+                     "dense_equivalent_frac": dense_ops / kernel_s / PEAK_VALU},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"], res["label_accuracy"] = cpu_baseline(sc, qs, p, gpu, args.cpu_seconds, n_kept)
@@ -141,6 +157,19 @@ def main():
     cs.csplat_scene_free(h)
     eng.close()
     print(json.dumps(res), flush=True)
+
+
+def copy_calibration():
+    """One device-to-device copy of 1 GiB: the HBM bytes it moves are known
+    (1 GiB read, 1 GiB written), which calibrates FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4}), flush=True)
 
 
 def _time_eval(eng, h, c, r, opts, want, reps=3):

@@ -85,6 +85,12 @@ typedef struct {
     float gamma;           /* Eq. 11, >= 0 */
     float s_min;           /* Eq. 11, the paper uses 1 */
     int32_t precision;     /* CSPLAT_PRECISION_*; the MFMA forms compute labels/counts */
+    int32_t cull;          /* 1: sort the queries along a Morton curve and skip chunks of 64
+                              Gaussians that provably lie outside every query's neighbourhood
+                              ball (or, for labels, beyond the reach bound
+                              n s_max + sqrt(n^2 s_max^2 + r^2) of Eq. 8); the results are the
+                              same bits as with 0, which evaluates every pair.  Used by the
+                              float32 path; min/softmin/cost with an infinite ball never cull. */
 } csplat_reduce_opts;
 
 /* Outputs of one evaluation; every pointer is nullable (not computed/written). */

@@ -66,7 +66,8 @@ class SceneOpts(ctypes.Structure):
 class ReduceOpts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("softmin_tau", ctypes.c_float),
                 ("neighbor_radius", ctypes.c_float), ("d_max", ctypes.c_float),
-                ("gamma", ctypes.c_float), ("s_min", ctypes.c_float), ("precision", ctypes.c_int32)]
+                ("gamma", ctypes.c_float), ("s_min", ctypes.c_float), ("precision", ctypes.c_int32),
+                ("cull", ctypes.c_int32)]
 
 
 class Outputs(ctypes.Structure):
@@ -202,9 +203,9 @@ def csplat_set_conservatism(ctx, n_sigma):
 
 
 def reduce_opts(k=0, tau=0.0, r_nbr=math.inf, d_max=1.0, gamma=1.0, s_min=1.0,
-                precision=CSPLAT_PRECISION_FP32) -> ReduceOpts:
+                precision=CSPLAT_PRECISION_FP32, cull=1) -> ReduceOpts:
     return ReduceOpts(int(k), float(tau), float(r_nbr), float(d_max), float(gamma), float(s_min),
-                      int(precision))
+                      int(precision), int(cull))
 
 
 def csplat_eval(ctx, scene, centers, radii, opts: ReduceOpts, label=None, count=None, min=None,

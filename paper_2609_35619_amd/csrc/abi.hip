@@ -1,4 +1,5 @@
 // The C ABI of the library: argument validation, ownership and dispatch.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -126,6 +127,11 @@ csplat_status build_params(const float *n_sigma, int m, const csplat_reduce_opts
     p.d_max = o.d_max;
     p.rn2 = std::isinf(o.neighbor_radius) ? INFINITY
                                           : (float)((double)o.neighbor_radius * o.neighbor_radius);
+    p.r_nbr = o.neighbor_radius;
+    p.n_max = 0.f;
+    for (int v = 0; v < m; ++v) p.n_max = std::max(p.n_max, n_sigma[v]);
+    if (o.cull != 0 && o.cull != 1) return fail(CSPLAT_E_INVALID, "reduce opts: cull must be 0 or 1");
+    p.cull = o.cull;
     return CSPLAT_OK;
 }
 
@@ -200,6 +206,7 @@ csplat_status csplat_ctx_destroy(csplat_ctx *ctx)
     ctx->partial.release();
     ctx->staging.release();
     ctx->flags.release();
+    ctx->sortbuf.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -316,6 +323,7 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     ctx->timed = false;
     ctx->flag_counts = nullptr;
     ctx->flag_m = 0;
+    ctx->chunk_counter = nullptr;
     if (kind == 1) {
         // device inputs: check them on the device before any output is touched
         int *bad = nullptr;
@@ -414,6 +422,13 @@ csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats)
     if (!ctx || !stats) return fail(CSPLAT_E_INVALID, "last_stats: NULL argument");
     *stats = ctx->stats;
     stats->kernel_ms = -1.f;
+    if (ctx->chunk_counter) {  // culled evaluation: pairs the kernel actually evaluated
+        DeviceGuard g(ctx->device);
+        unsigned long long chunks = 0;
+        CSPLAT_HIP(hipMemcpyAsync(&chunks, ctx->chunk_counter, sizeof(chunks), hipMemcpyDeviceToHost, ctx->stream));
+        CSPLAT_HIP(hipStreamSynchronize(ctx->stream));
+        stats->kernel_pairs = (int64_t)chunks * ctx->pairs_per_chunk;
+    }
     if (ctx->flag_counts && ctx->flag_m > 0) {  // precision forms: rechecked queries
         DeviceGuard g(ctx->device);
         int32_t h[CSPLAT_MAX_M] = {0};

@@ -58,6 +58,8 @@ struct csplat_scene {
     int64_t n = 0;            // kept Gaussians
     float *gauss = nullptr;   // n x 16 float32 records, Morton order
     float mu_max = 0.f;       // max |mu| over the kept Gaussians
+    float *cull = nullptr;    // per chunk of 64: bounding sphere centre, radius, largest scale
+    float box_lo[3] = {0, 0, 0}, box_scale[3] = {0, 0, 0};  // Morton quantisation of the kept means
     // precision form (optional): per tile of 512 Gaussians the packed MFMA
     // operands (96 B per Gaussian) and 20 floats of metadata (origin, scale,
     // coefficient maxima), one set per dtype
@@ -78,9 +80,12 @@ struct csplat_ctx {
     csplat::DevBuf partial;    // split-N partial reductions
     csplat::DevBuf staging;    // host-pointer staging (inputs + outputs)
     csplat::DevBuf flags;      // validation flag; precision form: recheck counters
+    csplat::DevBuf sortbuf;    // spatial sort of the queries (codes, permutation, sorted copies)
     csplat_eval_stats stats{};
     int32_t *flag_counts = nullptr;  // device: rechecked queries per n_sigma (last eval)
     int32_t flag_m = 0;
+    unsigned long long *chunk_counter = nullptr;  // device: culling chunks evaluated (last eval)
+    int64_t pairs_per_chunk = 0;
     bool timing = false;
     bool timed = false;         // events of the last evaluation were recorded
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -127,6 +132,9 @@ struct EvalParams {
     float rn2;                    // neighbour radius squared (+inf: all)
     int32_t soft;                 // tau > 0
     float n_sigma[CSPLAT_MAX_M];  // the conservatism values as given
+    float r_nbr;                  // neighbour radius (+inf: all)
+    float n_max;                  // largest conservatism value
+    int32_t cull;                 // skip chunks outside every ball / beyond every reach
 };
 
 struct EvalOut {
@@ -143,6 +151,18 @@ struct EvalOut {
 csplat_status build_params(const float *n_sigma, int m, const csplat_reduce_opts &o, EvalParams &p);
 // 1 if p is a device (or managed) pointer, 0 for host memory.
 int pointer_kind(const void *p);
+
+// A copy of q query spheres sorted along the scene's Morton curve, with the
+// permutation (sorted index -> caller index) and a zeroed 64-bit counter,
+// all in the context's sort workspace (valid until the next evaluation).
+struct SortedQueries {
+    const float *c;
+    const float *r;
+    const int32_t *perm;
+    unsigned long long *counter;
+};
+csplat_status sort_queries(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *centers,
+                           const float *radii, SortedQueries *out);
 
 // pair_fp32.hip: the float32 pair kernel and the split combine.
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,

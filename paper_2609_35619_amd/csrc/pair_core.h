@@ -23,6 +23,11 @@ namespace pair {
 
 constexpr int kBlock = 256;
 constexpr int kChunk = 512;  // Gaussians per first-level softmin/cost sum
+constexpr int kCull = 64;    // Gaussians per culling chunk (Morton-consecutive)
+constexpr int kCullFloats = 8;  // per chunk: centre (3), radius, largest scale, 0 0 0
+// relative widening of the culling thresholds: far above float32 rounding, so
+// no pair the float32 test would accept is ever culled
+constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 // Launch-shape constants (overridable at build time for tuning sweeps).
 #ifndef CSPLAT_UNROLL
 #define CSPLAT_UNROLL 4
@@ -147,11 +152,19 @@ __device__ __forceinline__ void pair_step(const float *__restrict__ gp, const fl
 // Gaussian range of `split`, written to the split's partial records.  Shared
 // by the evaluation kernel and the serving step kernel, so a request gives
 // the same bits in either.
-template <int M, bool FULL, bool BALL, int QPL>
+// With CULL, Gaussians are visited in chunks of kCull (Morton-consecutive,
+// with a bounding sphere and largest scale per chunk); a wave skips a chunk
+// when it provably lies outside the neighbourhood ball of every query the
+// wave holds (FULL), or beyond the reach bound n s + sqrt(n^2 s^2 + r^2) of
+// every query (labels: no pair of it can have s~^2 < 1).  Skipped pairs
+// contribute nothing, and the order of every sum is unchanged: the results
+// are the same bits.
+template <int M, bool FULL, bool BALL, int QPL, bool CULL = false>
 __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, int per_split, int split,
                                           int tile, const float *__restrict__ centers,
                                           const float *__restrict__ radii, int q, const EvalParams &p,
-                                          const Part &part, float mu_max)
+                                          const Part &part, float mu_max,
+                                          const float *__restrict__ cull = nullptr, int *chunks_done = nullptr)
 {
     float cx[QPL], cy[QPL], cz[QPL], r2[QPL], kq[QPL], cc[QPL], rn2w[QPL];
     int jq[QPL];
@@ -202,18 +215,44 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                     A.ccs[u][v] = 0.f;
                 }
         }
-        const float *gp = gs + (size_t)kGaussFloats * c0;
-        int g = c0;
-        for (; g + kUnroll <= c1; g += kUnroll, gp += kGaussFloats * kUnroll) {
-            float rec[kGaussFloats * kUnroll];  // wave-uniform (scalar) loads
+        const int cstep = CULL ? kCull : kChunk;
+        for (int b0 = c0; b0 < c1; b0 += cstep) {
+            const int b1 = min(c1, b0 + cstep);
+            if constexpr (CULL) {
+                const float *ck = cull + (size_t)kCullFloats * (b0 / kCull);  // wave-uniform
+                bool pass = false;
 #pragma unroll
-            for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = gp[i];
+                for (int u = 0; u < QPL; ++u) {
+                    const float ex = ck[0] - cx[u], ey = ck[1] - cy[u], ez = ck[2] - cz[u];
+                    const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                    float thr;
+                    if constexpr (FULL) {
+                        thr = (p.r_nbr + ck[3]) * kCullMargin;
+                    } else {
+                        const float ns = p.n_max * ck[4];
+                        thr = (ns + sqrtf(fmaf(ns, ns, r2[u])) + ck[3]) * kCullMargin;
+                        if constexpr (BALL) thr = fminf(thr, (p.r_nbr + ck[3]) * kCullMargin);
+                    }
+                    pass |= d2 <= thr * thr;
+                }
+                // wave-level vote: lanes outside every ball evaluate the chunk with
+                // the wave, and their exact tests reject each of its pairs
+                if (!__any(pass)) continue;
+                if (chunks_done) ++*chunks_done;
+            }
+            const float *gp = gs + (size_t)kGaussFloats * b0;
+            int g = b0;
+            for (; g + kUnroll <= b1; g += kUnroll, gp += kGaussFloats * kUnroll) {
+                float rec[kGaussFloats * kUnroll];  // wave-uniform (scalar) loads
 #pragma unroll
-            for (int k = 0; k < kUnroll; ++k)
-                pair_step<M, FULL, BALL, QPL>(rec + kGaussFloats * k, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+                for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = gp[i];
+#pragma unroll
+                for (int k = 0; k < kUnroll; ++k)
+                    pair_step<M, FULL, BALL, QPL>(rec + kGaussFloats * k, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+            }
+            for (; g < b1; ++g, gp += kGaussFloats)
+                pair_step<M, FULL, BALL, QPL>(gp, cx, cy, cz, r2, kq, cc, rn2w, p, A);
         }
-        for (; g < c1; ++g, gp += kGaussFloats)
-            pair_step<M, FULL, BALL, QPL>(gp, cx, cy, cz, r2, kq, cc, rn2w, p, A);
         if constexpr (FULL) {
 #pragma unroll
             for (int u = 0; u < QPL; ++u)
@@ -248,29 +287,36 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
     }
 }
 
-template <int M, bool FULL, bool BALL, int QPL>
+template <int M, bool FULL, bool BALL, int QPL, bool CULL>
 __global__ void __launch_bounds__(kBlock)
 pair_kernel(const float *__restrict__ gs, int n, int per_split, int n_tiles,
             const float *__restrict__ centers, const float *__restrict__ radii, int q,
-            const EvalParams p, Part part, float mu_max)
+            const EvalParams p, Part part, float mu_max, const float *__restrict__ cull,
+            unsigned long long *__restrict__ chunk_count)
 {
     int b = blockIdx.x;
     const int B = gridDim.x;
     if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few ranges
     const int split = b / n_tiles;
     const int tile = b - split * n_tiles;
-    eval_tile<M, FULL, BALL, QPL>(gs, n, per_split, split, tile, centers, radii, q, p, part, mu_max);
+    int done = 0;
+    eval_tile<M, FULL, BALL, QPL, CULL>(gs, n, per_split, split, tile, centers, radii, q, p, part, mu_max, cull,
+                                        &done);
+    if (CULL && chunk_count && (threadIdx.x & 63) == 0) atomicAdd(chunk_count, (unsigned long long)done);
 }
 
 // Merge the split partials in split order and finalise every output.
+// Output row of query j: perm[j] when the queries were evaluated in a
+// permuted (spatially sorted) order, j otherwise.
 template <int M, bool FULL>
 __device__ __forceinline__ void combine_query(int j, int q, int S, const EvalParams &p, const Part &part,
-                                              const EvalOut &out)
+                                              const EvalOut &out, const int32_t *perm = nullptr)
 {
+    const int oj = perm ? perm[j] : j;
     int nb = 0;
     if constexpr (FULL)
         for (int s = 0; s < S; ++s) nb += part.nb[(size_t)s * q + j];
-    if (out.nbr) out.nbr[j] = nb;
+    if (out.nbr) out.nbr[oj] = nb;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
         int cnt = 0;
@@ -291,7 +337,7 @@ __device__ __forceinline__ void combine_query(int j, int q, int S, const EvalPar
                 }
             }
         }
-        const size_t o = (size_t)j * p.m + v;
+        const size_t o = (size_t)oj * p.m + v;
         if (out.count) out.count[o] = cnt;
         if (out.label) out.label[o] = cnt > p.k ? 1 : 0;
         if constexpr (FULL) {
@@ -306,10 +352,10 @@ __device__ __forceinline__ void combine_query(int j, int q, int S, const EvalPar
 
 template <int M, bool FULL>
 __global__ void __launch_bounds__(256)
-combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out)
+combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out, const int32_t *__restrict__ perm)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < q) combine_query<M, FULL>(j, q, S, p, part, out);
+    if (j < q) combine_query<M, FULL>(j, q, S, p, part, out, perm);
 }
 
 // How an evaluation of q queries against n Gaussians is cut into work items:
@@ -332,6 +378,7 @@ inline SplitPlan split_plan(int target_blocks, int q, int n, bool full)
         S = std::max(1, std::min(S, (n + 1023) / 1024));
     }
     sp.per_split = n > 0 ? (n + S - 1) / S : 0;
+    sp.per_split = (sp.per_split + kCull - 1) / kCull * kCull;  // ranges start on culling chunks
     if (n > 0) S = (n + sp.per_split - 1) / sp.per_split;
     sp.S = n > 0 ? S : 0;
     return sp;

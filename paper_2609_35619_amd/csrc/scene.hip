@@ -175,6 +175,49 @@ __global__ void gather_kernel(int64_t n_kept, const float *__restrict__ rec,
     out[t] = rec[(size_t)kGaussFloats * order[k] + c];
 }
 
+// Per chunk of kCullChunk Morton-consecutive Gaussians: the centre of the
+// bounding box of their means, the largest distance of a mean from it and the
+// largest scale (row norm of M), computed in double and rounded up.
+constexpr int kCullChunk = 64;
+
+__global__ void cull_meta_kernel(int64_t n, const float *__restrict__ g, float *__restrict__ meta)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = c * kCullChunk;
+    if (i0 >= n) return;
+    const int64_t i1 = i0 + kCullChunk < n ? i0 + kCullChunk : n;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double smax = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const float *r = g + (size_t)kGaussFloats * i;
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], (double)r[k]);
+            hi[k] = fmax(hi[k], (double)r[k]);
+            const double a = r[3 + 3 * k], b = r[4 + 3 * k], d = r[5 + 3 * k];
+            smax = fmax(smax, sqrt(a * a + b * b + d * d));
+        }
+    }
+    float ctr[3];
+    for (int k = 0; k < 3; ++k) ctr[k] = (float)(0.5 * (lo[k] + hi[k]));
+    double rad = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const float *r = g + (size_t)kGaussFloats * i;
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double d = (double)r[k] - (double)ctr[k];
+            d2 += d * d;
+        }
+        rad = fmax(rad, sqrt(d2));
+    }
+    float *m = meta + (size_t)8 * c;
+    m[0] = ctr[0];
+    m[1] = ctr[1];
+    m[2] = ctr[2];
+    m[3] = (float)(rad * (1.0 + 1e-6) + 1e-30);
+    m[4] = (float)(smax * (1.0 + 1e-6));
+    m[5] = m[6] = m[7] = 0.f;
+}
+
 struct Tmp {
     std::vector<void *> ptrs;
     ~Tmp()
@@ -276,6 +319,18 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
     int64_t tot = (int64_t)kept * kGaussFloats;
     gather_kernel<<<(int)((tot + 255) / 256), 256, 0, st>>>((int64_t)kept, d_rec, d_idx2, g);
     CSPLAT_HIP(hipGetLastError());
+    const int64_t n_chunks = ((int64_t)kept + kCullChunk - 1) / kCullChunk;
+    float *cm = nullptr;
+    if (hipMalloc(&cm, (size_t)n_chunks * 8 * sizeof(float)) != hipSuccess)
+        return fail(CSPLAT_E_OOM, "scene_load: culling metadata");
+    sc->cull = cm;
+    sc->device_bytes += (uint64_t)n_chunks * 8 * sizeof(float);
+    cull_meta_kernel<<<(unsigned)((n_chunks + 127) / 128), 128, 0, st>>>((int64_t)kept, g, cm);
+    CSPLAT_HIP(hipGetLastError());
+    for (int k = 0; k < 3; ++k) {
+        sc->box_lo[k] = lo[k];
+        sc->box_scale[k] = scl[k];
+    }
     CSPLAT_HIP(hipStreamSynchronize(st));
     return CSPLAT_OK;
 }
@@ -283,10 +338,11 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
 void scene_release(csplat_scene *sc)
 {
     if (!sc) return;
-    void *ptrs[] = {sc->gauss, sc->feat_bf16, sc->meta_bf16, sc->feat_fp16, sc->meta_fp16};
+    void *ptrs[] = {sc->gauss, sc->cull, sc->feat_bf16, sc->meta_bf16, sc->feat_fp16, sc->meta_fp16};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     sc->gauss = nullptr;
+    sc->cull = nullptr;
     sc->feat_bf16 = sc->feat_fp16 = nullptr;
     sc->meta_bf16 = sc->meta_fp16 = nullptr;
 }

@@ -45,6 +45,7 @@ struct ReqDesc {
     int32_t n, per_split, S, q;
     int32_t full;
     float mu_max;
+    const float *cull;  // the scene's culling chunks
     EvalParams p;
     Part part;
     EvalOut out;  // device-visible pointers into pinned host memory
@@ -77,11 +78,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const char *__restrict__ s
     const Item *items = reinterpret_cast<const Item *>(stage + items_off);
     const int b1 = h->begin[variant + 1];
     constexpr int QPL = FULL ? kQplFull : kQplLabels;
+    constexpr bool CULL = !FULL || BALL;  // same bits as without culling
     for (int it = h->begin[variant] + (int)blockIdx.x; it < b1; it += (int)gridDim.x) {
         const Item w = items[it];
         const ReqDesc &R = reqs[w.slot];
-        eval_tile<1, FULL, BALL, QPL>(R.gs, R.n, R.per_split, w.split, w.tile, R.centers, R.radii, R.q, R.p,
-                                      R.part, R.mu_max);
+        eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.per_split, w.split, w.tile, R.centers, R.radii, R.q,
+                                            R.p, R.part, R.mu_max, R.cull, nullptr);
     }
 }
 
@@ -201,6 +203,7 @@ void setup_request(csplat_server *s, int64_t t)
     d.q = (int32_t)r.q;
     d.full = r.full ? 1 : 0;
     d.mu_max = sc->mu_max;
+    d.cull = sc->cull;
     d.p = r.p;
     d.part = part_views(dbase + r.d_part, r.sp.S, (int)r.q, 1, r.full);
     char *hd = s->host_arena_dev + ri->host_off;

@@ -264,3 +264,33 @@ def test_full_size_sampled(cs, eng, oracle_mod, name, sample):
     if "min" in gpu and gpu["min"].shape[1] > 1:
         assert np.all(np.diff(gpu["min"], axis=1) <= 0)
     del torch
+
+
+# --- exact culling: the same bits as the dense evaluation ----------------------
+
+@pytest.mark.parametrize("name,scale,want", [("mppi_nav", 0.05, ALL), ("manip", 0.02, ALL),
+                                             ("tiny", 1.0, ("label", "count")),
+                                             ("precision", 0.01, ("label", "count")),
+                                             ("mppi_nav", 0.05, ("label", "count"))])
+def test_cull_is_bit_identical_to_dense(cs, eng, name, scale, want):
+    import torch
+    _say(f"case: cull vs dense, {name}@{scale} {want}")
+    sc, qs, p = config(name, scale)
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
+    eng.set_conservatism(p["n_sigma"])
+    c = torch.from_numpy(qs.centers).cuda()
+    r = torch.from_numpy(qs.radii).cuda()
+    res = {}
+    for cull in (0, 1):
+        opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"],
+                              s_min=p["s_min"], cull=cull)
+        out = eng.evaluate(h, c, r, opts, want)
+        torch.cuda.synchronize()
+        res[cull] = {k: v.cpu().numpy() for k, v in out.items()}
+        st = eng.stats()
+        _say(f"cull={cull}: kernel pairs {st['kernel_pairs']} of {qs.q * sc.n}")
+        if cull and (want != ALL or math.isfinite(p["r_nbr"])):
+            assert st["kernel_pairs"] < qs.q * sc.n
+    cs.csplat_scene_free(h)
+    for k in want:
+        assert np.array_equal(res[0][k].view(np.uint8), res[1][k].view(np.uint8)), k
