@@ -18,6 +18,8 @@
 // bound B decides every pair whose |w - a|a|| exceeds it; the counts of
 // certain and of possible collisions bracket the exact count, and only
 // queries whose label the bracket cannot decide are re-evaluated in fp64.
+#include <hipcub/hipcub.hpp>
+
 #include <cmath>
 
 #include "internal.h"
@@ -33,7 +35,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kPT = 512;             // Gaussians per tile (one origin)
 constexpr int kRB = kPT / 32;        // row blocks (MFMA rows) per tile
 constexpr int kOps = 3;              // operands per row block: a, w0, w1
-constexpr int kMeta = 20;            // floats per tile: o(3), 1/scale, M1[5], M2[10], 0
+constexpr int kMeta = 24;  // floats per tile: o(3), 1/scale, M1[5], M2[10], radius, largest scale, 0 0 0
+constexpr float kCullMarginP = 1.0000153f;  // 1 + 2^-16 widening of the reach test
 constexpr int kLanes = 64;
 constexpr float kU32 = 5.9604645e-08f;  // 2^-24
 
@@ -186,7 +189,19 @@ build_tiles_kernel(const float *__restrict__ gauss, int64_t n, float *__restrict
         feat[base + kLanes] = vw0;
         feat[base + 2 * kLanes] = vw1;
     }
-    // tile maxima of |hi| over the real rows, for the error bounds
+    // tile maxima of |hi| over the real rows, for the error bounds; the tile's
+    // radius about the origin and its largest scale, for the reach test
+    double rad = 0.0, smax = 0.0;
+    if (valid) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double dk = (double)mu[k] - (double)o[k];
+            d2 += dk * dk;
+            const double a = r[3 + 3 * k], b = r[4 + 3 * k], c = r[5 + 3 * k];
+            smax = fmax(smax, sqrt(a * a + b * b + c * c));
+        }
+        rad = sqrt(d2);
+    }
     __syncthreads();
     for (int k = 0; k < 5; ++k) red[k][i] = valid ? fabsf(h1[k]) : 0.f;
     for (int k = 0; k < 10; ++k) red[5 + k][i] = valid ? fabsf(h2[k]) : 0.f;
@@ -196,12 +211,21 @@ build_tiles_kernel(const float *__restrict__ gauss, int64_t n, float *__restrict
         for (int j = 0; j < kPT; ++j) v = fmaxf(v, red[i][j]);
         meta[t * kMeta + 4 + i] = v;
     }
+    __syncthreads();
+    red[0][i] = (float)(rad * (1.0 + 1e-6));
+    red[1][i] = (float)(smax * (1.0 + 1e-6));
+    __syncthreads();
+    if (i < 2) {
+        float v = 0.f;
+        for (int j = 0; j < kPT; ++j) v = fmaxf(v, red[i][j]);
+        meta[t * kMeta + 19 + i] = v;
+    }
     if (i == 0) {
         meta[t * kMeta + 0] = o[0];
         meta[t * kMeta + 1] = o[1];
         meta[t * kMeta + 2] = o[2];
         meta[t * kMeta + 3] = (float)(1.0 / scale);
-        meta[t * kMeta + 19] = 0.f;
+        meta[t * kMeta + 21] = meta[t * kMeta + 22] = meta[t * kMeta + 23] = 0.f;
     }
 }
 
@@ -281,12 +305,15 @@ __device__ __forceinline__ void build_query(float cx, float cy, float cz, float 
 // ---------------------------------------------------------------------------
 // Certification kernel: block = 4 waves x 64 queries (two 32-query column
 // blocks per wave); grid = query blocks x tile ranges.
-template <int P>
+// With CULL, a wave skips a tile when every query it holds is beyond the
+// reach bound n s_T + sqrt(n^2 s_T^2 + r^2) of the tile (largest scale s_T)
+// plus the tile's radius: no pair of it can collide, for certain.
+template <int P, bool CULL>
 __global__ void __launch_bounds__(256)
 mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *__restrict__ meta,
                   int n_tiles, int tiles_per_split, int n_qblocks, const float *__restrict__ centers,
-                  const float *__restrict__ radii, int q, float four_n2, int32_t *__restrict__ lo_out,
-                  int32_t *__restrict__ hi_out)
+                  const float *__restrict__ radii, int q, float four_n2, float n_sigma,
+                  int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out)
 {
     using T = Prec<P>;
     using vec = typename T::vec;
@@ -315,6 +342,18 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
     const f32x16 zero = {};
     for (int t = t0; t < t1; ++t) {
         const float *mt = meta + (size_t)t * kMeta;  // wave-uniform: scalar loads
+        if constexpr (CULL) {
+            bool pass = false;
+            const float ns = n_sigma * mt[20];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const float ex = mt[0] - cx[cb], ey = mt[1] - cy[cb], ez = mt[2] - cz[cb];
+                const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                const float thr = (ns + sqrtf(fmaf(ns, ns, r2[cb])) + mt[19]) * kCullMarginP;
+                pass |= d2 <= thr * thr;
+            }
+            if (!__any(pass)) continue;
+        }
         QFeat<P> Q[2];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
@@ -353,11 +392,12 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
     }
 }
 
-// Merge the splits, decide certified labels, list the rest for the recheck.
+// Merge the splits, decide certified labels (written to the caller's row
+// perm[j]) and flag the rest for the recheck.
 __global__ void __launch_bounds__(256)
 decide_kernel(int q, int S, int m, int v, int k, bool want_count, const int32_t *__restrict__ lo_in,
-              const int32_t *__restrict__ hi_in, uint8_t *label, int32_t *count,
-              int32_t *__restrict__ list, int32_t *__restrict__ n_list)
+              const int32_t *__restrict__ hi_in, const int32_t *__restrict__ perm, uint8_t *label, int32_t *count,
+              uint8_t *__restrict__ flag)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= q) return;
@@ -367,62 +407,73 @@ decide_kernel(int q, int S, int m, int v, int k, bool want_count, const int32_t 
         hi = min(hi + hi_in[(size_t)s * q + j], 1 << 29);
     }
     const bool certain = (lo > k || hi <= k) && (!want_count || lo == hi);
+    const int oj = perm ? perm[j] : j;
     if (certain) {
-        if (label) label[(size_t)j * m + v] = lo > k ? 1 : 0;
-        if (count) count[(size_t)j * m + v] = lo;
-    } else {
-        list[atomicAdd(n_list, 1)] = j;
+        if (label) label[(size_t)oj * m + v] = lo > k ? 1 : 0;
+        if (count) count[(size_t)oj * m + v] = lo;
     }
+    flag[j] = certain ? 0 : 1;
 }
 
-// fp64 recheck of the listed queries: work item = (listed query, chunk of
-// Gaussians); lanes walk the chunk's Gaussians, the block sums its count.
-constexpr int kRecheckChunk = 16384;
+// fp64 recheck of the listed queries.  One wave per work item (a tile of 64
+// listed queries on the lanes x a range of Gaussians read with wave-uniform
+// scalar loads); chunks of 64 Gaussians beyond every lane's reach bound are
+// skipped; the exact counts are summed with integer atomics (order-free).
+constexpr int kRecheckSplits = 256;
 
-__global__ void __launch_bounds__(256)
-recheck_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restrict__ centers,
-                    const float *__restrict__ radii, double four_n2, const int32_t *__restrict__ list,
-                    const int32_t *__restrict__ n_list, int32_t *__restrict__ exact)
+__global__ void __launch_bounds__(64)
+recheck_fp64_kernel(const float *__restrict__ gauss, int n, int per_split, const float *__restrict__ cull,
+                    const float *__restrict__ centers, const float *__restrict__ radii, float n_sigma,
+                    const int32_t *__restrict__ list, const int32_t *__restrict__ n_list, int32_t *__restrict__ exact)
 {
-    __shared__ int s_cnt[4];
     const int nl = *n_list;
-    const int chunks = (n + kRecheckChunk - 1) / kRecheckChunk;
-    const long total = (long)nl * chunks;
-    for (long item = blockIdx.x; item < total; item += gridDim.x) {
-        const int li = (int)(item / chunks), ch = (int)(item - (long)li * chunks);
-        const int j = list[li];
-        const double cx = centers[3 * j], cy = centers[3 * j + 1], cz = centers[3 * j + 2];
-        const double r = radii[j];
-        const double r2 = r * r;
-        const int g0 = ch * kRecheckChunk, g1 = min(n, g0 + kRecheckChunk);
+    const int tiles = (nl + 63) / 64;
+    const long items = (long)tiles * kRecheckSplits;
+    const double nd = n_sigma;
+    const double four_n2 = 4.0 * nd * nd;
+    for (long item = blockIdx.x; item < items; item += gridDim.x) {
+        const int tile = (int)(item / kRecheckSplits), split = (int)(item - (long)tile * kRecheckSplits);
+        const int li = tile * 64 + (int)threadIdx.x;
+        const bool valid = li < nl;
+        const int j = list[valid ? li : nl - 1];
+        const float fcx = centers[3 * j], fcy = centers[3 * j + 1], fcz = centers[3 * j + 2], fr = radii[j];
+        const double cx = fcx, cy = fcy, cz = fcz, r2 = (double)fr * fr;
+        const int g0 = split * per_split, g1 = min(n, g0 + per_split);
         int cnt = 0;
-        for (int g = g0 + (int)threadIdx.x; g < g1; g += blockDim.x) {
-            const float *p = gauss + (size_t)kGaussFloats * g;
-            const double dx = (double)p[0] - cx, dy = (double)p[1] - cy, dz = (double)p[2] - cz;
-            const double a = dx * dx + dy * dy + dz * dz - r2;
-            const double e0 = (double)p[3] * dx + (double)p[4] * dy + (double)p[5] * dz;
-            const double e1 = (double)p[6] * dx + (double)p[7] * dy + (double)p[8] * dz;
-            const double e2 = (double)p[9] * dx + (double)p[10] * dy + (double)p[11] * dz;
-            const double V = e0 * e0 + e1 * e1 + e2 * e2;
-            cnt += a * fabs(a) < four_n2 * V;
+        for (int b0 = g0; b0 < g1; b0 += 64) {
+            if (cull) {
+                const float *ck = cull + (size_t)8 * (b0 / 64);
+                const float ex = ck[0] - fcx, ey = ck[1] - fcy, ez = ck[2] - fcz;
+                const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                const float ns = n_sigma * ck[4];
+                const float thr = (ns + sqrtf(fmaf(ns, ns, fr * fr)) + ck[3]) * kCullMarginP;
+                if (!__any(d2 <= thr * thr)) continue;
+            }
+            const int b1 = min(g1, b0 + 64);
+            for (int g = b0; g < b1; ++g) {
+                const float *p = gauss + (size_t)kGaussFloats * g;  // wave-uniform
+                const double dx = (double)p[0] - cx, dy = (double)p[1] - cy, dz = (double)p[2] - cz;
+                const double a = dx * dx + dy * dy + dz * dz - r2;
+                const double e0 = (double)p[3] * dx + (double)p[4] * dy + (double)p[5] * dz;
+                const double e1 = (double)p[6] * dx + (double)p[7] * dy + (double)p[8] * dz;
+                const double e2 = (double)p[9] * dx + (double)p[10] * dy + (double)p[11] * dz;
+                cnt += a * fabs(a) < four_n2 * (e0 * e0 + e1 * e1 + e2 * e2);
+            }
         }
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
-        __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(exact + li, s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
-        __syncthreads();
+        if (valid && cnt) atomicAdd(exact + li, cnt);
     }
 }
 
 __global__ void finish_kernel(int m, int v, int k, const int32_t *__restrict__ list,
                               const int32_t *__restrict__ n_list, const int32_t *__restrict__ exact,
-                              uint8_t *label, int32_t *count)
+                              const int32_t *__restrict__ perm, uint8_t *label, int32_t *count)
 {
     const int li = blockIdx.x * blockDim.x + threadIdx.x;
     if (li >= *n_list) return;
     const int j = list[li];
-    if (label) label[(size_t)j * m + v] = exact[li] > k ? 1 : 0;
-    if (count) count[(size_t)j * m + v] = exact[li];
+    const int oj = perm ? perm[j] : j;
+    if (label) label[(size_t)oj * m + v] = exact[li] > k ? 1 : 0;
+    if (count) count[(size_t)oj * m + v] = exact[li];
 }
 
 template <int P>
@@ -493,15 +544,34 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
     }
     const int tps = n_tiles > 0 ? (n_tiles + S - 1) / S : 0;
     if (n_tiles > 0) S = (n_tiles + tps - 1) / tps;
-    // workspace: lo/hi partials, the recheck list, its length, exact counts
+    const bool cull = p.cull && n > 0 && sc->cull;
+    const float *c = centers, *r = radii;
+    const int32_t *perm = nullptr;
+    if (cull) {
+        SortedQueries sq;
+        csplat_status s = sort_queries(ctx, sc, q, centers, radii, &sq);
+        if (s != CSPLAT_OK) return s;
+        c = sq.c;
+        r = sq.r;
+        perm = sq.perm;
+    }
+    // workspace: lo/hi partials, the recheck list, exact counts, flags, compaction scratch
+    size_t sel_bytes = 0;
+    CSPLAT_HIP(hipcub::DeviceSelect::Flagged(nullptr, sel_bytes, hipcub::CountingInputIterator<int32_t>(0),
+                                             (const uint8_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, q,
+                                             st));
     const size_t part = (size_t)S * q;
-    const size_t words = 2 * part + 2 * (size_t)q + 64;
-    hipError_t e = ctx->partial.reserve(words * 4);
+    const size_t off_list = 2 * part * 4, off_exact = off_list + (size_t)q * 4, off_flag = off_exact + (size_t)q * 4,
+                 off_sel = (off_flag + (size_t)q + 255) & ~(size_t)255;
+    hipError_t e = ctx->partial.reserve(off_sel + sel_bytes + 256);
     if (e != hipSuccess) return hip_fail(e, "precision workspace");
-    int32_t *lo = ctx->partial.as<int32_t>();
+    char *base = ctx->partial.as<char>();
+    int32_t *lo = reinterpret_cast<int32_t *>(base);
     int32_t *hi = lo + part;
-    int32_t *list = hi + part;
-    int32_t *exact = list + q;
+    int32_t *list = reinterpret_cast<int32_t *>(base + off_list);
+    int32_t *exact = reinterpret_cast<int32_t *>(base + off_exact);
+    uint8_t *flag = reinterpret_cast<uint8_t *>(base + off_flag);
+    void *sel_tmp = base + off_sel;
     e = ctx->flags.reserve((size_t)CSPLAT_MAX_M * sizeof(int32_t) + 64);
     if (e != hipSuccess) return hip_fail(e, "flag counters");
     int32_t *n_list = ctx->flags.as<int32_t>();
@@ -512,32 +582,44 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
     ctx->flag_counts = n_list;
     ctx->flag_m = m;
     const bool want_count = out.count != nullptr;
-    const int rc_grid = 2048;
+    const int per_split_rc = n > 0 ? ((n + kRecheckSplits - 1) / kRecheckSplits + 63) / 64 * 64 : 0;
+    const unsigned qb = (unsigned)((q + 255) / 256);
     for (int v = 0; v < m; ++v) {
         if (n_tiles > 0) {
             if (v == 0) timing_begin(ctx);
             dim3 grid((unsigned)(n_qblocks * S));
-            if (precision == CSPLAT_PRECISION_BF16_RECHECK)
-                mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK><<<grid, 256, 0, st>>>(
-                    static_cast<const bf16x8 *>(sc->feat_bf16), sc->meta_bf16, n_tiles, tps, n_qblocks, centers,
-                    radii, q, p.four_n2[v], lo, hi);
-            else
-                mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK><<<grid, 256, 0, st>>>(
-                    static_cast<const f16x8 *>(sc->feat_fp16), sc->meta_fp16, n_tiles, tps, n_qblocks, centers,
-                    radii, q, p.four_n2[v], lo, hi);
+            const float nv = p.n_sigma[v];
+            if (precision == CSPLAT_PRECISION_BF16_RECHECK) {
+                const auto *f = static_cast<const bf16x8 *>(sc->feat_bf16);
+                if (cull)
+                    mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, true><<<grid, 256, 0, st>>>(
+                        f, sc->meta_bf16, n_tiles, tps, n_qblocks, c, r, q, p.four_n2[v], nv, lo, hi);
+                else
+                    mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, false><<<grid, 256, 0, st>>>(
+                        f, sc->meta_bf16, n_tiles, tps, n_qblocks, c, r, q, p.four_n2[v], nv, lo, hi);
+            } else {
+                const auto *f = static_cast<const f16x8 *>(sc->feat_fp16);
+                if (cull)
+                    mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, true><<<grid, 256, 0, st>>>(
+                        f, sc->meta_fp16, n_tiles, tps, n_qblocks, c, r, q, p.four_n2[v], nv, lo, hi);
+                else
+                    mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, false><<<grid, 256, 0, st>>>(
+                        f, sc->meta_fp16, n_tiles, tps, n_qblocks, c, r, q, p.four_n2[v], nv, lo, hi);
+            }
             if (v == 0) timing_end(ctx);
             CSPLAT_HIP(hipGetLastError());
         }
-        decide_kernel<<<(unsigned)((q + 255) / 256), 256, 0, st>>>(q, n_tiles > 0 ? S : 0, m, v, p.k, want_count,
-                                                                   lo, hi, out.label, out.count, list, n_list + v);
+        decide_kernel<<<qb, 256, 0, st>>>(q, n_tiles > 0 ? S : 0, m, v, p.k, want_count, lo, hi, perm, out.label,
+                                          out.count, flag);
         CSPLAT_HIP(hipGetLastError());
+        // the undecided queries, in (sorted) query order
+        CSPLAT_HIP(hipcub::DeviceSelect::Flagged(sel_tmp, sel_bytes, hipcub::CountingInputIterator<int32_t>(0), flag,
+                                                 list, n_list + v, q, st));
         CSPLAT_HIP(zero_words(exact, (size_t)q, st));
-        const double nv = p.n_sigma[v];
         if (n > 0)
-            recheck_fp64_kernel<<<rc_grid, 256, 0, st>>>(sc->gauss, n, centers, radii, 4.0 * nv * nv, list,
-                                                         n_list + v, exact);
-        finish_kernel<<<(unsigned)((q + 255) / 256), 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, out.label,
-                                                                  out.count);
+            recheck_fp64_kernel<<<2048, 64, 0, st>>>(sc->gauss, n, per_split_rc, cull ? sc->cull : nullptr, c, r,
+                                                     p.n_sigma[v], list, n_list + v, exact);
+        finish_kernel<<<qb, 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, perm, out.label, out.count);
         CSPLAT_HIP(hipGetLastError());
     }
     return CSPLAT_OK;

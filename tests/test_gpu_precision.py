@@ -45,10 +45,10 @@ def _load(cs, eng, scene, p):
                           precision_features=cs.CSPLAT_FEATURES_BF16 | cs.CSPLAT_FEATURES_FP16)
 
 
-def _eval(cs, eng, h, queries, p, precision, want=("label", "count")):
+def _eval(cs, eng, h, queries, p, precision, want=("label", "count"), cull=1):
     import torch
     eng.set_conservatism(p["n_sigma"])
-    opts = cs.reduce_opts(k=p.get("k", 0), r_nbr=math.inf, precision=precision)
+    opts = cs.reduce_opts(k=p.get("k", 0), r_nbr=math.inf, precision=precision, cull=cull)
     c = torch.from_numpy(queries.centers).cuda()
     r = torch.from_numpy(queries.radii).cuda()
     out = eng.evaluate(h, c, r, opts, want)
@@ -150,6 +150,22 @@ def test_precision_degenerate_gaussians(cs, eng, oracle_mod, prec):
     ref = _oracle(oracle_mod, sc, qs, p)
     s_ = compare(gpu, ref, tau=0.0, gamma=1.0, where=f"degenerate-{prec}")
     _say(f"{prec}: {s_} rechecked {st['flagged']}")
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_precision_cull_matches_dense(cs, eng, prec):
+    """Skipping tiles beyond the reach bound changes no label or count (both
+    are certified or rechecked exactly), only the work done."""
+    _say(f"case: precision {prec}, tile culling vs dense, room scene")
+    sc, qs, p = config("precision", 0.01)
+    p = dict(p, n_sigma=[0.0, 1.0, 2.0], k=2)
+    h = _load(cs, eng, sc, p)
+    dense, st0 = _eval(cs, eng, h, qs, p, _prec(cs, prec), cull=0)
+    culled, st1 = _eval(cs, eng, h, qs, p, _prec(cs, prec), cull=1)
+    cs.csplat_scene_free(h)
+    _say(f"{prec}: rechecked dense {st0['flagged']} culled {st1['flagged']} of {qs.q * 3}")
+    for k in dense:
+        assert np.array_equal(dense[k], culled[k]), k
 
 
 def test_precision_requires_features(cs, eng):
