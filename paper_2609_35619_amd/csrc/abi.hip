@@ -25,6 +25,11 @@ csplat_status hip_fail(hipError_t e, const char *what)
     return e == hipErrorOutOfMemory ? CSPLAT_E_OOM : CSPLAT_E_DEVICE;
 }
 
+#ifndef CSPLAT_BLOCKS_PER_CU
+#define CSPLAT_BLOCKS_PER_CU 32
+#endif
+
+// Work items per launch: a few resident blocks per compute unit.
 int target_blocks(int dev)
 {
     static int cache[64] = {0};
@@ -33,7 +38,7 @@ int target_blocks(int dev)
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
             v = 256;
-        cache[dev] = v * 8;
+        cache[dev] = v * CSPLAT_BLOCKS_PER_CU;
     }
     return cache[dev];
 }

@@ -24,6 +24,7 @@ namespace pair {
 constexpr int kBlock = 256;
 constexpr int kChunk = 512;  // Gaussians per first-level softmin/cost sum
 constexpr int kCull = 64;    // Gaussians per culling chunk (Morton-consecutive)
+constexpr int kPiece = kChunk / kCull;  // culling chunks per first-level sum
 constexpr int kCullFloats = 8;  // per chunk: centre (3), radius, largest scale, 0 0 0
 // relative widening of the culling thresholds: far above float32 rounding, so
 // no pair the float32 test would accept is ever culled
@@ -33,13 +34,22 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #define CSPLAT_UNROLL 4
 #endif
 #ifndef CSPLAT_QPL_FULL
-#define CSPLAT_QPL_FULL 2
+#define CSPLAT_QPL_FULL 1
 #endif
 #ifndef CSPLAT_QPL_LABELS
-#define CSPLAT_QPL_LABELS 4
+#define CSPLAT_QPL_LABELS 2
 #endif
 #ifndef CSPLAT_PRETEST
 #define CSPLAT_PRETEST 0
+#endif
+#ifndef CSPLAT_PIPELINE
+#define CSPLAT_PIPELINE 0
+#endif
+// Optional register cap: at least N waves of the pair kernels per SIMD.
+#ifdef CSPLAT_WAVES_PER_EU
+#define CSPLAT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(CSPLAT_WAVES_PER_EU)))
+#else
+#define CSPLAT_OCCUPANCY
 #endif
 constexpr int kUnroll = CSPLAT_UNROLL;       // Gaussians per group of scalar loads
 constexpr int kQplFull = CSPLAT_QPL_FULL;    // queries per lane, all outputs
@@ -49,6 +59,7 @@ constexpr int kQplLabels = CSPLAT_QPL_LABELS;  // queries per lane, labels only
 // is not VALU-issue bound and the extra work inside the branch costs more
 // than the pre-test saves (12.8 ms vs 13.7 ms per launch on MI355X).
 constexpr bool kPretest = CSPLAT_PRETEST != 0;
+constexpr bool kPipeline = CSPLAT_PIPELINE != 0;
 
 __device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -66,7 +77,9 @@ struct Part {
 // d = mu - c, D = |d|^2 and V = |M d|^2 = d^T Sigma d,
 //   r^2 s^2 = D,  r^2 n sqrt(sigma^2) = 2 n sqrt(V),  r^2 s~^2 = max(0, D - 2 n sqrt(V)).
 //
-// Each lane holds QPL queries (slot u of block b is query b*kBlock*QPL + u*kBlock + tid),
+// Each lane holds QPL queries (slot u of lane l in wave w of tile b is query
+// (b*kBlock + w*64)*QPL + u*64 + l: a wave holds 64*QPL consecutive queries,
+// which after the spatial sort are one compact region),
 // so every scalar-loaded Gaussian feeds QPL pairs per lane; the Gaussian loop is
 // unrolled by kUnroll (the group's records in scalar loads).  In FULL mode a single branch per
 // Gaussian skips the metric when no query of the wave has it in its ball.
@@ -160,7 +173,7 @@ __device__ __forceinline__ void pair_step(const float *__restrict__ gp, const fl
 // contribute nothing, and the order of every sum is unchanged: the results
 // are the same bits.
 template <int M, bool FULL, bool BALL, int QPL, bool CULL = false>
-__device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, int per_split, int split,
+__device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, int S, int split,
                                           int tile, const float *__restrict__ centers,
                                           const float *__restrict__ radii, int q, const EvalParams &p,
                                           const Part &part, float mu_max,
@@ -170,7 +183,7 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
     int jq[QPL];
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
-        jq[u] = (tile * QPL + u) * kBlock + (int)threadIdx.x;
+        jq[u] = (tile * kBlock + (int)(threadIdx.x & ~63u)) * QPL + u * 64 + (int)(threadIdx.x & 63u);
         const int jj = jq[u] < q ? jq[u] : q - 1;  // past the end: evaluate a real query, write nothing
         cx[u] = centers[3 * jj];
         cy[u] = centers[3 * jj + 1];
@@ -198,13 +211,16 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
         }
     }
 
-    const int g0 = split * per_split;
-    const int g1 = min(n, g0 + per_split);
-    // The softmin and cost sums are accumulated per chunk of kChunk Gaussians
-    // and folded into the lane totals at the end of each chunk (two-level
-    // summation keeps the float32 rounding of long sums near sqrt(kChunk) ulps).
-    for (int c0 = g0; c0 < g1; c0 += kChunk) {
-        const int c1 = min(g1, c0 + kChunk);
+    // The Gaussians are visited in chunks of kCull (Morton-consecutive); split
+    // `split` of S takes chunks split, split + S, split + 2S, ... so that every
+    // split samples the whole scene and the work of a query tile is spread
+    // evenly over its S work items.  The softmin and cost sums are accumulated
+    // per piece of kPiece consecutive chunks of the split and folded into the
+    // lane totals at the end of each piece (two-level summation keeps the
+    // float32 rounding of long sums near sqrt(kChunk) ulps).  Folding a piece
+    // that received no pair changes nothing.
+    const int n_chunks = (n + kCull - 1) / kCull;
+    auto reset_chunk = [&]() {
         if constexpr (FULL) {
 #pragma unroll
             for (int u = 0; u < QPL; ++u)
@@ -215,44 +231,8 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                     A.ccs[u][v] = 0.f;
                 }
         }
-        const int cstep = CULL ? kCull : kChunk;
-        for (int b0 = c0; b0 < c1; b0 += cstep) {
-            const int b1 = min(c1, b0 + cstep);
-            if constexpr (CULL) {
-                const float *ck = cull + (size_t)kCullFloats * (b0 / kCull);  // wave-uniform
-                bool pass = false;
-#pragma unroll
-                for (int u = 0; u < QPL; ++u) {
-                    const float ex = ck[0] - cx[u], ey = ck[1] - cy[u], ez = ck[2] - cz[u];
-                    const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-                    float thr;
-                    if constexpr (FULL) {
-                        thr = (p.r_nbr + ck[3]) * kCullMargin;
-                    } else {
-                        const float ns = p.n_max * ck[4];
-                        thr = (ns + sqrtf(fmaf(ns, ns, r2[u])) + ck[3]) * kCullMargin;
-                        if constexpr (BALL) thr = fminf(thr, (p.r_nbr + ck[3]) * kCullMargin);
-                    }
-                    pass |= d2 <= thr * thr;
-                }
-                // wave-level vote: lanes outside every ball evaluate the chunk with
-                // the wave, and their exact tests reject each of its pairs
-                if (!__any(pass)) continue;
-                if (chunks_done) ++*chunks_done;
-            }
-            const float *gp = gs + (size_t)kGaussFloats * b0;
-            int g = b0;
-            for (; g + kUnroll <= b1; g += kUnroll, gp += kGaussFloats * kUnroll) {
-                float rec[kGaussFloats * kUnroll];  // wave-uniform (scalar) loads
-#pragma unroll
-                for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = gp[i];
-#pragma unroll
-                for (int k = 0; k < kUnroll; ++k)
-                    pair_step<M, FULL, BALL, QPL>(rec + kGaussFloats * k, cx, cy, cz, r2, kq, cc, rn2w, p, A);
-            }
-            for (; g < b1; ++g, gp += kGaussFloats)
-                pair_step<M, FULL, BALL, QPL>(gp, cx, cy, cz, r2, kq, cc, rn2w, p, A);
-        }
+    };
+    auto fold_chunk = [&]() {
         if constexpr (FULL) {
 #pragma unroll
             for (int u = 0; u < QPL; ++u)
@@ -268,7 +248,148 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                     }
                 }
         }
+    };
+    // Gaussians [b0, b1): groups of kUnroll records in wave-uniform (scalar)
+    // loads; with kPipeline the next group's records are requested before the
+    // current group is evaluated, so their latency overlaps the arithmetic
+    auto run = [&](int b0, int b1) {
+        const float *gp = gs + (size_t)kGaussFloats * b0;
+        int g = b0;
+        if constexpr (kPipeline) {
+            if (g + kUnroll <= b1) {
+                float rec[kGaussFloats * kUnroll];
+#pragma unroll
+                for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = gp[i];
+                for (; g + kUnroll <= b1; g += kUnroll, gp += kGaussFloats * kUnroll) {
+                    // the last group re-reads itself: always an in-range address
+                    const float *np = g + 2 * kUnroll <= b1 ? gp + kGaussFloats * kUnroll : gp;
+                    float nxt[kGaussFloats * kUnroll];
+#pragma unroll
+                    for (int i = 0; i < kGaussFloats * kUnroll; ++i) nxt[i] = np[i];
+#pragma unroll
+                    for (int k = 0; k < kUnroll; ++k)
+                        pair_step<M, FULL, BALL, QPL>(rec + kGaussFloats * k, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+#pragma unroll
+                    for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = nxt[i];
+                }
+            }
+        } else {
+            for (; g + kUnroll <= b1; g += kUnroll, gp += kGaussFloats * kUnroll) {
+                float rec[kGaussFloats * kUnroll];
+#pragma unroll
+                for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = gp[i];
+#pragma unroll
+                for (int k = 0; k < kUnroll; ++k)
+                    pair_step<M, FULL, BALL, QPL>(rec + kGaussFloats * k, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+            }
+        }
+        for (; g < b1; ++g, gp += kGaussFloats)
+            pair_step<M, FULL, BALL, QPL>(gp, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+    };
+    int open = -1;  // piece holding the pending sums (wave-uniform)
+    auto visit = [&](int i) {  // i-th chunk of the split
+        const int piece = i / kPiece;
+        if (piece != open) {
+            if (open >= 0) fold_chunk();
+            reset_chunk();
+            open = piece;
+        }
+        const int b0 = (split + i * S) * kCull;
+        run(b0, min(n, b0 + kCull));
+    };
+    if constexpr (!CULL) {
+        for (int i = 0; split + i * S < n_chunks; ++i) visit(i);
+    } else {
+        // Two culling levels.  (1) A batch of 64 chunks of the split is tested
+        //     at once, one chunk per lane, against the bounding sphere of every
+        //     query the wave holds (centre w, radius `spread`): no pair of a
+        //     chunk farther than spread + chunk radius + reach can count.
+        // (2) Each surviving chunk is tested against every query separately
+        //     (wave vote).  Chunks are visited in the same order as without
+        //     culling, so every sum keeps its order: skipping changes no bit.
+        const int lane = (int)(threadIdx.x & 63u);
+        float lo[3] = {cx[0], cy[0], cz[0]}, hi[3] = {cx[0], cy[0], cz[0]};
+        float r2max = r2[0];
+#pragma unroll
+        for (int u = 1; u < QPL; ++u) {
+            lo[0] = fminf(lo[0], cx[u]), hi[0] = fmaxf(hi[0], cx[u]);
+            lo[1] = fminf(lo[1], cy[u]), hi[1] = fmaxf(hi[1], cy[u]);
+            lo[2] = fminf(lo[2], cz[u]), hi[2] = fmaxf(hi[2], cz[u]);
+            r2max = fmaxf(r2max, r2[u]);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+                hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+            }
+            r2max = fmaxf(r2max, __shfl_xor(r2max, off));
+        }
+        const float wx = 0.5f * (lo[0] + hi[0]), wy = 0.5f * (lo[1] + hi[1]), wz = 0.5f * (lo[2] + hi[2]);
+        float spread = 0.f;
+#pragma unroll
+        for (int u = 0; u < QPL; ++u) {
+            const float ex = cx[u] - wx, ey = cy[u] - wy, ez = cz[u] - wz;
+            spread = fmaxf(spread, sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))));
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) spread = fmaxf(spread, __shfl_xor(spread, off));
+        for (int ib = 0; split + ib * S < n_chunks; ib += 64) {
+            const int ci = split + (ib + lane) * S;
+            float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
+            bool pass = false;
+            if (ci < n_chunks) {
+                const float4 a = *reinterpret_cast<const float4 *>(cull + (size_t)kCullFloats * ci);
+                m0 = a.x, m1 = a.y, m2 = a.z, m3 = a.w;
+                m4 = cull[(size_t)kCullFloats * ci + 4];
+                const float ex = m0 - wx, ey = m1 - wy, ez = m2 - wz;
+                const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                float reach;
+                if constexpr (FULL) {
+                    reach = p.r_nbr;
+                } else {
+                    const float ns = p.n_max * m4;
+                    reach = ns + sqrtf(fmaf(ns, ns, r2max));
+                    if constexpr (BALL) reach = fminf(reach, p.r_nbr);
+                }
+                const float thr = (spread + m3 + reach) * kCullMargin;
+                pass = d2 <= thr * thr;
+            }
+            unsigned long long mask = __ballot(pass);
+            while (mask) {
+                const int bit = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                // chunk metadata of lane `bit`, as wave-uniform values
+                const float k0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m0), bit));
+                const float k1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m1), bit));
+                const float k2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m2), bit));
+                const float k3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m3), bit));
+                const float k4 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m4), bit));
+                bool near = false;
+#pragma unroll
+                for (int u = 0; u < QPL; ++u) {
+                    const float ex = k0 - cx[u], ey = k1 - cy[u], ez = k2 - cz[u];
+                    const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                    float thr;
+                    if constexpr (FULL) {
+                        thr = (p.r_nbr + k3) * kCullMargin;
+                    } else {
+                        const float ns = p.n_max * k4;
+                        thr = (ns + sqrtf(fmaf(ns, ns, r2[u])) + k3) * kCullMargin;
+                        if constexpr (BALL) thr = fminf(thr, (p.r_nbr + k3) * kCullMargin);
+                    }
+                    near |= d2 <= thr * thr;
+                }
+                // lanes outside every ball evaluate the chunk with the wave, and
+                // their exact tests reject each of its pairs
+                if (!__any(near)) continue;
+                if (chunks_done) ++*chunks_done;
+                visit(ib + bit);
+            }
+        }
     }
+    if (open >= 0) fold_chunk();
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
         const int j = jq[u];
@@ -288,8 +409,8 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
 }
 
 template <int M, bool FULL, bool BALL, int QPL, bool CULL>
-__global__ void __launch_bounds__(kBlock)
-pair_kernel(const float *__restrict__ gs, int n, int per_split, int n_tiles,
+__global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY
+pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
             const float *__restrict__ centers, const float *__restrict__ radii, int q,
             const EvalParams p, Part part, float mu_max, const float *__restrict__ cull,
             unsigned long long *__restrict__ chunk_count)
@@ -300,7 +421,7 @@ pair_kernel(const float *__restrict__ gs, int n, int per_split, int n_tiles,
     const int split = b / n_tiles;
     const int tile = b - split * n_tiles;
     int done = 0;
-    eval_tile<M, FULL, BALL, QPL, CULL>(gs, n, per_split, split, tile, centers, radii, q, p, part, mu_max, cull,
+    eval_tile<M, FULL, BALL, QPL, CULL>(gs, n, S, split, tile, centers, radii, q, p, part, mu_max, cull,
                                         &done);
     if (CULL && chunk_count && (threadIdx.x & 63) == 0) atomicAdd(chunk_count, (unsigned long long)done);
 }
@@ -359,10 +480,11 @@ combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out, const i
 }
 
 // How an evaluation of q queries against n Gaussians is cut into work items:
-// query tiles of kBlock x QPL queries times `S` contiguous Gaussian ranges of
-// `per_split`, enough items to fill the device several times over and ranges
-// of at least 1024 Gaussians.  Depends only on (q, n, mode, device), so a
-// request gives the same partial reductions wherever it runs.
+// query tiles of kBlock x QPL queries times S splits of the Gaussian chunks
+// (split s takes every S-th chunk from s), enough items to fill the device
+// several times over and at least 16 chunks per split.  Depends only on
+// (q, n, mode, device), so a request gives the same partial reductions
+// wherever it runs.  per_split: Gaussians of the largest split.
 struct SplitPlan {
     int n_tiles, S, per_split, qpl;
 };
@@ -372,15 +494,14 @@ inline SplitPlan split_plan(int target_blocks, int q, int n, bool full)
     SplitPlan sp;
     sp.qpl = full ? kQplFull : kQplLabels;
     sp.n_tiles = (q + kBlock * sp.qpl - 1) / (kBlock * sp.qpl);
-    int S = 1;
-    if (n > 0 && sp.n_tiles > 0) {
-        S = (target_blocks + sp.n_tiles - 1) / sp.n_tiles;
-        S = std::max(1, std::min(S, (n + 1023) / 1024));
+    const int n_chunks = (n + kCull - 1) / kCull;
+    int S = 0;
+    if (n > 0) {
+        S = sp.n_tiles > 0 ? (target_blocks + sp.n_tiles - 1) / sp.n_tiles : 1;
+        S = std::max(1, std::min(S, n_chunks / 16));
     }
-    sp.per_split = n > 0 ? (n + S - 1) / S : 0;
-    sp.per_split = (sp.per_split + kCull - 1) / kCull * kCull;  // ranges start on culling chunks
-    if (n > 0) S = (n + sp.per_split - 1) / sp.per_split;
-    sp.S = n > 0 ? S : 0;
+    sp.S = S;
+    sp.per_split = S > 0 ? (n_chunks + S - 1) / S * kCull : 0;
     return sp;
 }
 

@@ -30,7 +30,7 @@ struct Launch {
     dim3 grid;
     hipStream_t st;
     const float *gs;
-    int n, per_split, n_tiles;
+    int n, n_tiles;
     const float *c, *r;
     int q;
     EvalParams p;
@@ -47,7 +47,7 @@ template <int M, bool FULL, bool BALL, bool CULL>
 void launch_pair(const Launch &L)
 {
     constexpr int QPL = FULL ? kQplFull : kQplLabels;
-    pair_kernel<M, FULL, BALL, QPL, CULL><<<L.grid, kBlock, 0, L.st>>>(L.gs, L.n, L.per_split, L.n_tiles, L.c, L.r,
+    pair_kernel<M, FULL, BALL, QPL, CULL><<<L.grid, kBlock, 0, L.st>>>(L.gs, L.n, L.S, L.n_tiles, L.c, L.r,
                                                                        L.q, L.p, L.part, L.mu_max, L.cull,
                                                                        L.chunk_count);
 }
@@ -171,7 +171,6 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     L.st = st;
     L.gs = sc->gauss;
     L.n = n;
-    L.per_split = sp.per_split;
     L.n_tiles = sp.n_tiles;
     L.c = centers;
     L.r = radii;

@@ -70,7 +70,7 @@ struct StageLayout {
 };
 
 template <bool FULL, bool BALL>
-__global__ void __launch_bounds__(kBlock) step_kernel(const char *__restrict__ stage, int variant, size_t desc_off,
+__global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const char *__restrict__ stage, int variant, size_t desc_off,
                                                       size_t items_off)
 {
     const StepHeader *h = reinterpret_cast<const StepHeader *>(stage);
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const char *__restrict__ s
     for (int it = h->begin[variant] + (int)blockIdx.x; it < b1; it += (int)gridDim.x) {
         const Item w = items[it];
         const ReqDesc &R = reqs[w.slot];
-        eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.per_split, w.split, w.tile, R.centers, R.radii, R.q,
+        eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.S, w.split, w.tile, R.centers, R.radii, R.q,
                                             R.p, R.part, R.mu_max, R.cull, nullptr);
     }
 }
