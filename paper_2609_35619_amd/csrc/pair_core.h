@@ -161,6 +161,107 @@ __device__ __forceinline__ void pair_step(const float *__restrict__ gp, const fl
     }
 }
 
+// Culling metadata of one chunk of kCull Morton-consecutive Gaussians: the
+// centre of their bounding box, the largest distance of a mean from it and the
+// largest scale (all rounded up at load time).
+struct ChunkMeta {
+    float x, y, z, rad, smax;
+};
+
+__device__ __forceinline__ ChunkMeta load_chunk(const float *__restrict__ cull, int ci)
+{
+    const float4 a = *reinterpret_cast<const float4 *>(cull + (size_t)kCullFloats * ci);
+    return ChunkMeta{a.x, a.y, a.z, a.w, cull[(size_t)kCullFloats * ci + 4]};
+}
+
+__device__ __forceinline__ float lane_value(float v, int lane)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// The metadata held by lane `lane`, as wave-uniform values.
+__device__ __forceinline__ ChunkMeta lane_chunk(const ChunkMeta &m, int lane)
+{
+    return ChunkMeta{lane_value(m.x, lane), lane_value(m.y, lane), lane_value(m.z, lane), lane_value(m.rad, lane),
+                     lane_value(m.smax, lane)};
+}
+
+// Bounding sphere of every query the wave holds (centre w = middle of their
+// bounding box, radius `spread`) and their largest r^2.
+template <int QPL>
+__device__ __forceinline__ void wave_sphere(const float (&cx)[QPL], const float (&cy)[QPL], const float (&cz)[QPL],
+                                            const float (&r2)[QPL], float &wx, float &wy, float &wz, float &spread,
+                                            float &r2max)
+{
+    float lo[3] = {cx[0], cy[0], cz[0]}, hi[3] = {cx[0], cy[0], cz[0]};
+    r2max = r2[0];
+#pragma unroll
+    for (int u = 1; u < QPL; ++u) {
+        lo[0] = fminf(lo[0], cx[u]), hi[0] = fmaxf(hi[0], cx[u]);
+        lo[1] = fminf(lo[1], cy[u]), hi[1] = fmaxf(hi[1], cy[u]);
+        lo[2] = fminf(lo[2], cz[u]), hi[2] = fmaxf(hi[2], cz[u]);
+        r2max = fmaxf(r2max, r2[u]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+        }
+        r2max = fmaxf(r2max, __shfl_xor(r2max, off));
+    }
+    wx = 0.5f * (lo[0] + hi[0]), wy = 0.5f * (lo[1] + hi[1]), wz = 0.5f * (lo[2] + hi[2]);
+    spread = 0.f;
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+        const float ex = cx[u] - wx, ey = cy[u] - wy, ez = cz[u] - wz;
+        spread = fmaxf(spread, sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) spread = fmaxf(spread, __shfl_xor(spread, off));
+}
+
+// Squared distance of a chunk centre from a point, and the culling test
+// d <= (reach + extra) with the relative margin kCullMargin.
+__device__ __forceinline__ bool within(const ChunkMeta &m, float x, float y, float z, float reach)
+{
+    const float ex = m.x - x, ey = m.y - y, ez = m.z - z;
+    const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+    const float thr = reach * kCullMargin;
+    return d2 <= thr * thr;
+}
+
+// Walk the chunks split, split + S, split + 2S, ... (< n_chunks) in ascending
+// order with two culling levels: (1) a batch of 64 chunks at once, one per
+// lane, with `coarse(m)` (a test against the wave's bounding sphere); (2)
+// each survivor against every query of the wave with `near(m)` (a wave vote:
+// lanes outside every reach evaluate the chunk with the wave, and their own
+// exact tests reject each of its pairs).  visit(i) for the i-th chunk of the
+// split when some lane is near.
+template <class Coarse, class Near, class Visit>
+__device__ __forceinline__ void cull_walk(const float *__restrict__ cull, int n_chunks, int split, int S,
+                                          Coarse coarse, Near near, Visit visit)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    for (int ib = 0; split + ib * S < n_chunks; ib += 64) {
+        const int ci = split + (ib + lane) * S;
+        ChunkMeta m{0.f, 0.f, 0.f, 0.f, 0.f};
+        bool pass = false;
+        if (ci < n_chunks) {
+            m = load_chunk(cull, ci);
+            pass = coarse(m);
+        }
+        unsigned long long mask = __ballot(pass);
+        while (mask) {
+            const int bit = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            if (!__any(near(lane_chunk(m, bit)))) continue;
+            visit(ib + bit);
+        }
+    }
+}
+
 // One work item: the queries of `tile` (kBlock x QPL of them) against the
 // Gaussian range of `split`, written to the split's partial records.  Shared
 // by the evaluation kernel and the serving step kernel, so a request gives
@@ -300,94 +401,33 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
     if constexpr (!CULL) {
         for (int i = 0; split + i * S < n_chunks; ++i) visit(i);
     } else {
-        // Two culling levels.  (1) A batch of 64 chunks of the split is tested
-        //     at once, one chunk per lane, against the bounding sphere of every
-        //     query the wave holds (centre w, radius `spread`): no pair of a
-        //     chunk farther than spread + chunk radius + reach can count.
-        // (2) Each surviving chunk is tested against every query separately
-        //     (wave vote).  Chunks are visited in the same order as without
-        //     culling, so every sum keeps its order: skipping changes no bit.
-        const int lane = (int)(threadIdx.x & 63u);
-        float lo[3] = {cx[0], cy[0], cz[0]}, hi[3] = {cx[0], cy[0], cz[0]};
-        float r2max = r2[0];
-#pragma unroll
-        for (int u = 1; u < QPL; ++u) {
-            lo[0] = fminf(lo[0], cx[u]), hi[0] = fmaxf(hi[0], cx[u]);
-            lo[1] = fminf(lo[1], cy[u]), hi[1] = fmaxf(hi[1], cy[u]);
-            lo[2] = fminf(lo[2], cz[u]), hi[2] = fmaxf(hi[2], cz[u]);
-            r2max = fmaxf(r2max, r2[u]);
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
-                hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+        // Chunks are visited in the same order as without culling, so every
+        // sum keeps its order: skipping changes no bit.
+        float wx, wy, wz, spread, r2max;
+        wave_sphere<QPL>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
+        auto reach_of = [&](const ChunkMeta &m, float rr2) {  // reach of a chunk for r^2 = rr2
+            if constexpr (FULL) {
+                return p.r_nbr;
+            } else {
+                const float ns = p.n_max * m.smax;
+                float reach = ns + sqrtf(fmaf(ns, ns, rr2));
+                if constexpr (BALL) reach = fminf(reach, p.r_nbr);
+                return reach;
             }
-            r2max = fmaxf(r2max, __shfl_xor(r2max, off));
-        }
-        const float wx = 0.5f * (lo[0] + hi[0]), wy = 0.5f * (lo[1] + hi[1]), wz = 0.5f * (lo[2] + hi[2]);
-        float spread = 0.f;
-#pragma unroll
-        for (int u = 0; u < QPL; ++u) {
-            const float ex = cx[u] - wx, ey = cy[u] - wy, ez = cz[u] - wz;
-            spread = fmaxf(spread, sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))));
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) spread = fmaxf(spread, __shfl_xor(spread, off));
-        for (int ib = 0; split + ib * S < n_chunks; ib += 64) {
-            const int ci = split + (ib + lane) * S;
-            float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
-            bool pass = false;
-            if (ci < n_chunks) {
-                const float4 a = *reinterpret_cast<const float4 *>(cull + (size_t)kCullFloats * ci);
-                m0 = a.x, m1 = a.y, m2 = a.z, m3 = a.w;
-                m4 = cull[(size_t)kCullFloats * ci + 4];
-                const float ex = m0 - wx, ey = m1 - wy, ez = m2 - wz;
-                const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-                float reach;
-                if constexpr (FULL) {
-                    reach = p.r_nbr;
-                } else {
-                    const float ns = p.n_max * m4;
-                    reach = ns + sqrtf(fmaf(ns, ns, r2max));
-                    if constexpr (BALL) reach = fminf(reach, p.r_nbr);
-                }
-                const float thr = (spread + m3 + reach) * kCullMargin;
-                pass = d2 <= thr * thr;
-            }
-            unsigned long long mask = __ballot(pass);
-            while (mask) {
-                const int bit = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                // chunk metadata of lane `bit`, as wave-uniform values
-                const float k0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m0), bit));
-                const float k1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m1), bit));
-                const float k2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m2), bit));
-                const float k3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m3), bit));
-                const float k4 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m4), bit));
+        };
+        cull_walk(
+            cull, n_chunks, split, S,
+            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m, r2max)); },
+            [&](const ChunkMeta &m) {
                 bool near = false;
 #pragma unroll
-                for (int u = 0; u < QPL; ++u) {
-                    const float ex = k0 - cx[u], ey = k1 - cy[u], ez = k2 - cz[u];
-                    const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-                    float thr;
-                    if constexpr (FULL) {
-                        thr = (p.r_nbr + k3) * kCullMargin;
-                    } else {
-                        const float ns = p.n_max * k4;
-                        thr = (ns + sqrtf(fmaf(ns, ns, r2[u])) + k3) * kCullMargin;
-                        if constexpr (BALL) thr = fminf(thr, (p.r_nbr + k3) * kCullMargin);
-                    }
-                    near |= d2 <= thr * thr;
-                }
-                // lanes outside every ball evaluate the chunk with the wave, and
-                // their exact tests reject each of its pairs
-                if (!__any(near)) continue;
+                for (int u = 0; u < QPL; ++u) near |= within(m, cx[u], cy[u], cz[u], m.rad + reach_of(m, r2[u]));
+                return near;
+            },
+            [&](int i) {
                 if (chunks_done) ++*chunks_done;
-                visit(ib + bit);
-            }
-        }
+                visit(i);
+            });
     }
     if (open >= 0) fold_chunk();
 #pragma unroll

@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "pair_core.h"
 
 namespace csplat {
 
@@ -36,7 +37,7 @@ constexpr int kPT = 512;             // Gaussians per tile (one origin)
 constexpr int kRB = kPT / 32;        // row blocks (MFMA rows) per tile
 constexpr int kOps = 3;              // operands per row block: a, w0, w1
 constexpr int kMeta = 24;  // floats per tile: o(3), 1/scale, M1[5], M2[10], radius, largest scale, 0 0 0
-constexpr float kCullMarginP = 1.0000153f;  // 1 + 2^-16 widening of the reach test
+constexpr int kChunksPerTile = kPT / pair::kCull;  // culling chunks per tile (two row blocks each)
 constexpr int kLanes = 64;
 constexpr float kU32 = 5.9604645e-08f;  // 2^-24
 
@@ -304,22 +305,26 @@ __device__ __forceinline__ void build_query(float cx, float cy, float cz, float 
 
 // ---------------------------------------------------------------------------
 // Certification kernel: block = 4 waves x 64 queries (two 32-query column
-// blocks per wave); grid = query blocks x tile ranges.
-// With CULL, a wave skips a tile when every query it holds is beyond the
-// reach bound n s_T + sqrt(n^2 s_T^2 + r^2) of the tile (largest scale s_T)
-// plus the tile's radius: no pair of it can collide, for certain.
+// blocks per wave); grid = query blocks x S splits, split s taking the tiles
+// s, s + S, s + 2S, ... (every split samples the whole scene, so the work of
+// a query block is spread evenly over its S items).
+// With CULL, row blocks are skipped in pairs (one culling chunk of 64
+// Gaussians) when every query the wave holds is beyond the chunk's reach
+// bound n s_c + sqrt(n^2 s_c^2 + r^2) plus its radius: no pair of it can
+// collide.  Chunks are tested 64 at a time (8 tiles x 8 chunks, one per lane)
+// against the wave's bounding sphere, then each survivor against every query.
 template <int P, bool CULL>
 __global__ void __launch_bounds__(256)
 mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *__restrict__ meta,
-                  int n_tiles, int tiles_per_split, int n_qblocks, const float *__restrict__ centers,
-                  const float *__restrict__ radii, int q, float four_n2, float n_sigma,
-                  int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out)
+                  int n_tiles, int S, int n_qblocks, const float *__restrict__ cull, int n_chunks,
+                  const float *__restrict__ centers, const float *__restrict__ radii, int q, float four_n2,
+                  float n_sigma, int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out)
 {
     using T = Prec<P>;
     using vec = typename T::vec;
     int b = blockIdx.x;
     const int B = gridDim.x;
-    if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few tile ranges
+    if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few splits
     const int split = b / n_qblocks;
     const int qb = b - split * n_qblocks;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
@@ -337,31 +342,21 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
     }
     int lo[2] = {0, 0}, hi[2] = {0, 0};
     bool bad[2] = {false, false};
-    const int t0 = split * tiles_per_split;
-    const int t1 = min(n_tiles, t0 + tiles_per_split);
     const f32x16 zero = {};
-    for (int t = t0; t < t1; ++t) {
+    // the row blocks of tile t selected by the 16-bit mask rbm (wave-uniform)
+    auto do_tile = [&](int t, unsigned rbm) {
         const float *mt = meta + (size_t)t * kMeta;  // wave-uniform: scalar loads
-        if constexpr (CULL) {
-            bool pass = false;
-            const float ns = n_sigma * mt[20];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                const float ex = mt[0] - cx[cb], ey = mt[1] - cy[cb], ez = mt[2] - cz[cb];
-                const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-                const float thr = (ns + sqrtf(fmaf(ns, ns, r2[cb])) + mt[19]) * kCullMarginP;
-                pass |= d2 <= thr * thr;
-            }
-            if (!__any(pass)) continue;
-        }
         QFeat<P> Q[2];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             build_query<P>(cx[cb], cy[cb], cz[cb], r2[cb], four_n2, mt, h, Q[cb]);
             bad[cb] |= Q[cb].bad;
         }
-        const vec *fp = feat + (size_t)t * kRB * kOps * kLanes + lane;
-        for (int rb = 0; rb < kRB; ++rb, fp += kOps * kLanes) {
+        const vec *ft = feat + (size_t)t * kRB * kOps * kLanes + lane;
+        while (rbm) {
+            const int rb = __builtin_ctz(rbm);
+            rbm &= rbm - 1;
+            const vec *fp = ft + (size_t)rb * kOps * kLanes;
             const vec Aa = fp[0], Aw0 = fp[kLanes], Aw1 = fp[2 * kLanes];
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
@@ -377,6 +372,44 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
                     lo[cb] += f > bnd;                    // certainly in collision
                     hi[cb] += f > -bnd;                   // possibly in collision
                 }
+            }
+        }
+    };
+    if constexpr (!CULL) {
+        for (int t = split; t < n_tiles; t += S) do_tile(t, 0xffffu);
+    } else {
+        float wx, wy, wz, spread, r2max;
+        pair::wave_sphere<2>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
+        auto reach_of = [&](const pair::ChunkMeta &m, float rr2) {
+            const float ns = n_sigma * m.smax;
+            return ns + sqrtf(fmaf(ns, ns, rr2));
+        };
+        for (int ib = 0; split + ib * S < n_tiles; ib += 64 / kChunksPerTile) {
+            const int t = split + (ib + lane / kChunksPerTile) * S;
+            const int ci = t * kChunksPerTile + lane % kChunksPerTile;
+            pair::ChunkMeta m{0.f, 0.f, 0.f, 0.f, 0.f};
+            bool pass = false;
+            if (t < n_tiles && ci < n_chunks) {
+                m = pair::load_chunk(cull, ci);
+                pass = pair::within(m, wx, wy, wz, spread + m.rad + reach_of(m, r2max));
+            }
+            unsigned long long mask = __ballot(pass);
+            while (mask) {
+                const int g = __builtin_ctzll(mask) / kChunksPerTile;  // tile of the batch
+                unsigned tm = (unsigned)(mask >> (kChunksPerTile * g)) & ((1u << kChunksPerTile) - 1u);
+                mask &= ~((((unsigned long long)1 << kChunksPerTile) - 1ull) << (kChunksPerTile * g));
+                unsigned rbm = 0;
+                while (tm) {
+                    const int k = __builtin_ctz(tm);
+                    tm &= tm - 1;
+                    const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
+                    bool near = false;
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        near |= pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, r2[cb]));
+                    if (__any(near)) rbm |= 3u << (2 * k);
+                }
+                if (rbm) do_tile(split + (ib + g) * S, rbm);
             }
         }
     }
@@ -415,20 +448,24 @@ decide_kernel(int q, int S, int m, int v, int k, bool want_count, const int32_t 
     flag[j] = certain ? 0 : 1;
 }
 
-// fp64 recheck of the listed queries.  One wave per work item (a tile of 64
-// listed queries on the lanes x a range of Gaussians read with wave-uniform
-// scalar loads); chunks of 64 Gaussians beyond every lane's reach bound are
-// skipped; the exact counts are summed with integer atomics (order-free).
+// fp64 recheck of the listed queries.  One wave per work item: a tile of 64
+// listed queries on the lanes x split s of kRecheckSplits (the culling chunks
+// s, s + kRecheckSplits, ...), Gaussians read with wave-uniform scalar loads;
+// chunks beyond every lane's reach bound are skipped (batch test against the
+// wave's bounding sphere, then a vote); the exact counts are summed with
+// integer atomics (order-free).
 constexpr int kRecheckSplits = 256;
+constexpr int kRecheckGrid = 8192;
 
 __global__ void __launch_bounds__(64)
-recheck_fp64_kernel(const float *__restrict__ gauss, int n, int per_split, const float *__restrict__ cull,
+recheck_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restrict__ cull,
                     const float *__restrict__ centers, const float *__restrict__ radii, float n_sigma,
                     const int32_t *__restrict__ list, const int32_t *__restrict__ n_list, int32_t *__restrict__ exact)
 {
     const int nl = *n_list;
     const int tiles = (nl + 63) / 64;
     const long items = (long)tiles * kRecheckSplits;
+    const int n_chunks = (n + pair::kCull - 1) / pair::kCull;
     const double nd = n_sigma;
     const double four_n2 = 4.0 * nd * nd;
     for (long item = blockIdx.x; item < items; item += gridDim.x) {
@@ -436,20 +473,13 @@ recheck_fp64_kernel(const float *__restrict__ gauss, int n, int per_split, const
         const int li = tile * 64 + (int)threadIdx.x;
         const bool valid = li < nl;
         const int j = list[valid ? li : nl - 1];
-        const float fcx = centers[3 * j], fcy = centers[3 * j + 1], fcz = centers[3 * j + 2], fr = radii[j];
-        const double cx = fcx, cy = fcy, cz = fcz, r2 = (double)fr * fr;
-        const int g0 = split * per_split, g1 = min(n, g0 + per_split);
+        float fc[3][1] = {{centers[3 * j]}, {centers[3 * j + 1]}, {centers[3 * j + 2]}};
+        const float fr = radii[j];
+        float fr2[1] = {fr * fr};
+        const double cx = fc[0][0], cy = fc[1][0], cz = fc[2][0], r2 = (double)fr * fr;
         int cnt = 0;
-        for (int b0 = g0; b0 < g1; b0 += 64) {
-            if (cull) {
-                const float *ck = cull + (size_t)8 * (b0 / 64);
-                const float ex = ck[0] - fcx, ey = ck[1] - fcy, ez = ck[2] - fcz;
-                const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-                const float ns = n_sigma * ck[4];
-                const float thr = (ns + sqrtf(fmaf(ns, ns, fr * fr)) + ck[3]) * kCullMarginP;
-                if (!__any(d2 <= thr * thr)) continue;
-            }
-            const int b1 = min(g1, b0 + 64);
+        auto chunk = [&](int ci) {
+            const int b0 = ci * pair::kCull, b1 = min(n, b0 + pair::kCull);
             for (int g = b0; g < b1; ++g) {
                 const float *p = gauss + (size_t)kGaussFloats * g;  // wave-uniform
                 const double dx = (double)p[0] - cx, dy = (double)p[1] - cy, dz = (double)p[2] - cz;
@@ -459,6 +489,25 @@ recheck_fp64_kernel(const float *__restrict__ gauss, int n, int per_split, const
                 const double e2 = (double)p[9] * dx + (double)p[10] * dy + (double)p[11] * dz;
                 cnt += a * fabs(a) < four_n2 * (e0 * e0 + e1 * e1 + e2 * e2);
             }
+        };
+        if (cull) {
+            float wx, wy, wz, spread, r2max;
+            pair::wave_sphere<1>(fc[0], fc[1], fc[2], fr2, wx, wy, wz, spread, r2max);
+            auto reach_of = [&](const pair::ChunkMeta &m, float rr2) {
+                const float ns = n_sigma * m.smax;
+                return ns + sqrtf(fmaf(ns, ns, rr2));
+            };
+            pair::cull_walk(
+                cull, n_chunks, split, kRecheckSplits,
+                [&](const pair::ChunkMeta &m) {
+                    return pair::within(m, wx, wy, wz, spread + m.rad + reach_of(m, r2max));
+                },
+                [&](const pair::ChunkMeta &m) {
+                    return pair::within(m, fc[0][0], fc[1][0], fc[2][0], m.rad + reach_of(m, fr2[0]));
+                },
+                [&](int i) { chunk(split + i * kRecheckSplits); });
+        } else {
+            for (int ci = split; ci < n_chunks; ci += kRecheckSplits) chunk(ci);
         }
         if (valid && cnt) atomicAdd(exact + li, cnt);
     }
@@ -542,8 +591,7 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
         S = (ctx_target_blocks(ctx) + n_qblocks - 1) / n_qblocks;
         S = std::max(1, std::min(S, n_tiles));
     }
-    const int tps = n_tiles > 0 ? (n_tiles + S - 1) / S : 0;
-    if (n_tiles > 0) S = (n_tiles + tps - 1) / tps;
+    const int n_chunks = (n + pair::kCull - 1) / pair::kCull;
     const bool cull = p.cull && n > 0 && sc->cull;
     const float *c = centers, *r = radii;
     const int32_t *perm = nullptr;
@@ -582,7 +630,6 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
     ctx->flag_counts = n_list;
     ctx->flag_m = m;
     const bool want_count = out.count != nullptr;
-    const int per_split_rc = n > 0 ? ((n + kRecheckSplits - 1) / kRecheckSplits + 63) / 64 * 64 : 0;
     const unsigned qb = (unsigned)((q + 255) / 256);
     for (int v = 0; v < m; ++v) {
         if (n_tiles > 0) {
@@ -593,18 +640,18 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
                 const auto *f = static_cast<const bf16x8 *>(sc->feat_bf16);
                 if (cull)
                     mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, true><<<grid, 256, 0, st>>>(
-                        f, sc->meta_bf16, n_tiles, tps, n_qblocks, c, r, q, p.four_n2[v], nv, lo, hi);
+                        f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, p.four_n2[v], nv, lo, hi);
                 else
                     mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, false><<<grid, 256, 0, st>>>(
-                        f, sc->meta_bf16, n_tiles, tps, n_qblocks, c, r, q, p.four_n2[v], nv, lo, hi);
+                        f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, p.four_n2[v], nv, lo, hi);
             } else {
                 const auto *f = static_cast<const f16x8 *>(sc->feat_fp16);
                 if (cull)
                     mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, true><<<grid, 256, 0, st>>>(
-                        f, sc->meta_fp16, n_tiles, tps, n_qblocks, c, r, q, p.four_n2[v], nv, lo, hi);
+                        f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, p.four_n2[v], nv, lo, hi);
                 else
                     mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, false><<<grid, 256, 0, st>>>(
-                        f, sc->meta_fp16, n_tiles, tps, n_qblocks, c, r, q, p.four_n2[v], nv, lo, hi);
+                        f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, p.four_n2[v], nv, lo, hi);
             }
             if (v == 0) timing_end(ctx);
             CSPLAT_HIP(hipGetLastError());
@@ -617,8 +664,8 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
                                                  list, n_list + v, q, st));
         CSPLAT_HIP(zero_words(exact, (size_t)q, st));
         if (n > 0)
-            recheck_fp64_kernel<<<2048, 64, 0, st>>>(sc->gauss, n, per_split_rc, cull ? sc->cull : nullptr, c, r,
-                                                     p.n_sigma[v], list, n_list + v, exact);
+            recheck_fp64_kernel<<<kRecheckGrid, 64, 0, st>>>(sc->gauss, n, cull ? sc->cull : nullptr, c, r,
+                                                             p.n_sigma[v], list, n_list + v, exact);
         finish_kernel<<<qb, 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, perm, out.label, out.count);
         CSPLAT_HIP(hipGetLastError());
     }
