@@ -31,8 +31,44 @@ OPS_IN_BALL_SHARED = 17            # M d (9), V (3), sqrt (4 slots), ball count 
 OPS_IN_BALL_PER_NSIGMA = 19        # s~^2 (2), label (2), min (1), softmin (exp 4 + 2), cost (exp 4 + 4)
 
 
+# The pair kernel's HBM traffic comes from the rocprofv3 counter summary under
+# profiles/ (FETCH_SIZE and WRITE_SIZE of the same command, scaled by what the
+# counters read for a plain copy of known size).  It is reported only while
+# the kernel sources still hash to the digest recorded with the counters.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernel_mppi_nav.md")
+KERNEL_SOURCES = ("paper_2609_35619_amd/csrc/pair_core.h", "paper_2609_35619_amd/csrc/pair_fp32.hip",
+                  "paper_2609_35619_amd/csrc/internal.h")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per pair-kernel launch from the committed counter summary, or
+    None when the summary is missing or was taken on other kernel sources."""
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    rec = {}
+    for ln in lines:
+        if ln.startswith("traffic-record:"):
+            for kv in ln.split(":", 1)[1].split():
+                k, v = kv.split("=")
+                rec[k] = v
+    if rec.get("digest") != kernel_digest():
+        return None
+    return float(rec["fetch_bytes"]) + float(rec["write_bytes"])
 
 
 def main():
@@ -48,12 +84,15 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full-size request law (MPPI K up to 4096 x 32 x 48; long)")
-    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "copy"), default="all",
+    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "copy", "digest"), default="all",
                     help="run one part only (for profiling); 'copy' is a plain 1 GiB device copy "
                          "used to calibrate the HBM traffic counters")
     args = ap.parse_args()
     if args.section == "copy":
         return copy_calibration()
+    if args.section == "digest":
+        print(kernel_digest())
+        return None
     if args.section != "all":
         args.no_precision = args.section not in ("precision",)
         args.no_serving = args.section not in ("serving",)
@@ -142,7 +181,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "vram_bytes": {"scene": int(scene_bytes)},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU / 1e9, "unit": "Gop/s",
-                     "frac": achieved / PEAK_VALU, "traffic": None,
+                     "frac": achieved / PEAK_VALU, "traffic": traffic_from_profile(), "traffic_unit": "bytes",
                      "kernel": "pair_kernel<3,full,ball>", "kernel_ms": kernel_s * 1e3,
                      "ops_per_launch": ops, "in_ball_pairs": nbr_total, "evaluated_pairs": evaluated,
                      "dense_pairs": pairs, "dense_ops_per_launch": dense_ops,

@@ -25,15 +25,11 @@ csplat_status hip_fail(hipError_t e, const char *what)
     return e == hipErrorOutOfMemory ? CSPLAT_E_OOM : CSPLAT_E_DEVICE;
 }
 
-#ifndef CSPLAT_BLOCKS_PER_CU
-#define CSPLAT_BLOCKS_PER_CU 32
-#endif
-
-// Work items per launch: a few resident blocks per compute unit.
+// Work items per launch: CSPLAT_BLOCKS_PER_CU blocks per compute unit.
 int target_blocks(int dev)
 {
     static int cache[64] = {0};
-    if (dev < 0 || dev >= 64) return 2048;
+    if (dev < 0 || dev >= 64) return 256 * CSPLAT_BLOCKS_PER_CU;
     if (!cache[dev]) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)

@@ -107,6 +107,12 @@ inline void timing_end(csplat_ctx *ctx)
 }
 
 // Blocks that fill the device several times over (8 per compute unit).
+// Blocks per compute unit that a launch aims for: several rounds of resident
+// blocks, so that uneven work items even out (measured on MI355X: 32 beats
+// 8 and 16 on the navigation and label workloads).
+#ifndef CSPLAT_BLOCKS_PER_CU
+#define CSPLAT_BLOCKS_PER_CU 32
+#endif
 int target_blocks(int device);
 inline int ctx_target_blocks(const csplat_ctx *ctx) { return target_blocks(ctx->device); }
 

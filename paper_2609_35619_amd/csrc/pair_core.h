@@ -466,57 +466,83 @@ pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
     if (CULL && chunk_count && (threadIdx.x & 63) == 0) atomicAdd(chunk_count, (unsigned long long)done);
 }
 
-// Merge the split partials in split order and finalise every output.
-// Output row of query j: perm[j] when the queries were evaluated in a
-// permuted (spatially sorted) order, j otherwise.
+// Merge the split partials of query j, conservatism value v, in split order
+// and finalise its outputs.  Output row of query j: perm[j] when the queries
+// were evaluated in a permuted (spatially sorted) order, j otherwise.  The
+// partials are read eight splits at a time ahead of the (sequential) merge.
 template <int M, bool FULL>
-__device__ __forceinline__ void combine_query(int j, int q, int S, const EvalParams &p, const Part &part,
-                                              const EvalOut &out, const int32_t *perm = nullptr)
+__device__ __forceinline__ void combine_one(int j, int v, int q, int S, const EvalParams &p, const Part &part,
+                                            const EvalOut &out, const int32_t *perm)
 {
+    constexpr int kAhead = 8;
     const int oj = perm ? perm[j] : j;
     int nb = 0;
-    if constexpr (FULL)
-        for (int s = 0; s < S; ++s) nb += part.nb[(size_t)s * q + j];
-    if (out.nbr) out.nbr[oj] = nb;
+    if constexpr (FULL) {
+        if (out.cost || (v == 0 && out.nbr))
+            for (int s = 0; s < S; ++s) nb += part.nb[(size_t)s * q + j];
+    }
+    if (v == 0 && out.nbr) out.nbr[oj] = nb;
+    int cnt = 0;
+    float mt = INFINITY, sm = 0.f, cs = 0.f;
+    for (int s0 = 0; s0 < S; s0 += kAhead) {
+        int c[kAhead];
+        float bm[kAhead], bs[kAhead], bc[kAhead];
 #pragma unroll
-    for (int v = 0; v < M; ++v) {
-        int cnt = 0;
-        float mt = INFINITY, sm = 0.f, cs = 0.f;
-        for (int s = 0; s < S; ++s) {
+        for (int k = 0; k < kAhead; ++k) {
+            const int s = min(s0 + k, S - 1);
             const size_t o = ((size_t)s * M + v) * q + j;
-            cnt += part.cnt[o];
+            c[k] = part.cnt[o];
             if constexpr (FULL) {
-                const float bm = part.mt[o], bs = part.sm[o];
-                cs += part.cs[o];
-                if (bm < INFINITY) {
-                    if (bm < mt) {
-                        sm = fmaf(sm, fast_exp2(mt == INFINITY ? -INFINITY : bm - mt), bs);
-                        mt = bm;
+                bm[k] = part.mt[o];
+                bs[k] = part.sm[o];
+                bc[k] = part.cs[o];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            if (s0 + k >= S) break;
+            cnt += c[k];
+            if constexpr (FULL) {
+                cs += bc[k];
+                if (bm[k] < INFINITY) {
+                    if (bm[k] < mt) {
+                        sm = fmaf(sm, fast_exp2(mt == INFINITY ? -INFINITY : bm[k] - mt), bs[k]);
+                        mt = bm[k];
                     } else {
-                        sm = fmaf(bs, fast_exp2(mt - bm), sm);
+                        sm = fmaf(bs[k], fast_exp2(mt - bm[k]), sm);
                     }
                 }
             }
         }
-        const size_t o = (size_t)oj * p.m + v;
-        if (out.count) out.count[o] = cnt;
-        if (out.label) out.label[o] = cnt > p.k ? 1 : 0;
-        if constexpr (FULL) {
-            const float mn = mt * p.inv_kt;
-            if (out.min) out.min[o] = mn;
-            if (out.softmin)
-                out.softmin[o] = (!p.soft || mt == INFINITY) ? mn : (mt - fast_log2(sm)) * p.inv_kt;
-            if (out.cost) out.cost[o] = nb > 0 ? p.d_max * (cs / (float)nb) : 0.f;
-        }
+    }
+    const size_t o = (size_t)oj * p.m + v;
+    if (out.count) out.count[o] = cnt;
+    if (out.label) out.label[o] = cnt > p.k ? 1 : 0;
+    if constexpr (FULL) {
+        const float mn = mt * p.inv_kt;
+        if (out.min) out.min[o] = mn;
+        if (out.softmin) out.softmin[o] = (!p.soft || mt == INFINITY) ? mn : (mt - fast_log2(sm)) * p.inv_kt;
+        if (out.cost) out.cost[o] = nb > 0 ? p.d_max * (cs / (float)nb) : 0.f;
     }
 }
 
 template <int M, bool FULL>
+__device__ __forceinline__ void combine_query(int j, int q, int S, const EvalParams &p, const Part &part,
+                                              const EvalOut &out, const int32_t *perm = nullptr)
+{
+#pragma unroll
+    for (int v = 0; v < M; ++v) combine_one<M, FULL>(j, v, q, S, p, part, out, perm);
+}
+
+// One thread per (query, conservatism value), queries fastest.
+template <int M, bool FULL>
 __global__ void __launch_bounds__(256)
 combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out, const int32_t *__restrict__ perm)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < q) combine_query<M, FULL>(j, q, S, p, part, out, perm);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)q * M) return;
+    const int v = (int)(idx / q), j = (int)(idx - (int64_t)v * q);
+    combine_one<M, FULL>(j, v, q, S, p, part, out, perm);
 }
 
 // How an evaluation of q queries against n Gaussians is cut into work items:

@@ -71,7 +71,7 @@ void launch_m(csplat_ctx *ctx, bool full, bool ball, bool cull, const Launch &L)
         }
         timing_end(ctx);
     }
-    const int cb = (L.q + 255) / 256;
+    const unsigned cb = (unsigned)(((int64_t)L.q * M + 255) / 256);
     if (full) combine_kernel<M, true><<<cb, 256, 0, L.st>>>(L.q, L.S, L.p, L.part, L.out, L.perm);
     else combine_kernel<M, false><<<cb, 256, 0, L.st>>>(L.q, L.S, L.p, L.part, L.out, L.perm);
 }
