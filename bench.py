@@ -148,6 +148,15 @@ def main():
         kms.append(st["kernel_ms"])
     cs.csplat_ctx_set_timing(eng.ctx, False)
     kernel_s = float(np.mean(kms)) / 1e3
+    # the same step from host arrays (inputs copied in, outputs copied back
+    # over PCIe inside the call): reported beside the resident-input value
+    host_out = eng.alloc_outputs(qs.q, like="host")
+    eng.evaluate(h, qs.centers, qs.radii, opts, out=host_out)
+    host_t = []
+    for _ in range(max(3, args.steps // 4)):
+        s0 = time.perf_counter()
+        eng.evaluate(h, qs.centers, qs.radii, opts, out=host_out)
+        host_t.append(time.perf_counter() - s0)
     gpu = {k: v.cpu().numpy() for k, v in out.items()}
     nbr_total = int(gpu["nbr"].astype(np.int64).sum())
     pairs = qs.q * n_kept
@@ -178,7 +187,11 @@ def main():
                    "n_gaussians": int(sc.n), "n_kept": int(n_kept), "queries": int(qs.q), "m": m,
                    "global_batch": int(qs.q), "parallelism": "single GPU"},
         "queries_per_s": qs.q / step_s,
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                       "mean": float(np.mean(lat) * 1e3), "std": float(np.std(lat) * 1e3)},
+        "host_arrays": {"ms_per_step_median": float(np.median(host_t) * 1e3),
+                        "pair_evals_per_s": pairs / float(np.median(host_t)),
+                        "note": "inputs from and outputs to host memory, PCIe copies inside the call"},
         "vram_bytes": {"scene": int(scene_bytes)},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU / 1e9, "unit": "Gop/s",
                      "frac": achieved / PEAK_VALU, "traffic": traffic_from_profile(), "traffic_unit": "bytes",
