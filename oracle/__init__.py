@@ -107,6 +107,28 @@ def ellipsoid_bodies(rot, semi_axes):
     return rot @ P @ np.swapaxes(rot, -1, -2)
 
 
+def quat_to_rot(quats):
+    """Rotation matrices of (w, x, y, z) quaternions of any nonzero norm
+    (normalised first), the Hamilton convention of 3DGS (Sec. II-A), in double
+    precision."""
+    qv = np.asarray(quats, np.float64).reshape(-1, 4)
+    nrm = np.linalg.norm(qv, axis=1)
+    if np.any(~np.isfinite(nrm)) or np.any(nrm == 0):
+        raise OracleError("quaternions must be finite and nonzero")
+    w, x, y, z = (qv / nrm[:, None]).T
+    R = np.empty((qv.shape[0], 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - w * z)
+    R[:, 0, 2] = 2 * (x * z + w * y)
+    R[:, 1, 0] = 2 * (x * y + w * z)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - w * x)
+    R[:, 2, 0] = 2 * (x * z - w * y)
+    R[:, 2, 1] = 2 * (y * z + w * x)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
 def evaluate(mu, sigma, centers, A, n_sigma, k=0, tau=0.0, r_nbr=math.inf, d_max=1.0,
              gamma=1.0, s_min=1.0, eps=1e-5, eps_ball=1e-6, nthreads=0):
     """Evaluate all outputs.  Returns a dict of (q, m) arrays plus `nbr` (q,)."""
@@ -137,6 +159,16 @@ def evaluate(mu, sigma, centers, A, n_sigma, k=0, tau=0.0, r_nbr=math.inf, d_max
     if rc != 0:
         raise OracleError(f"oracle_eval failed ({rc})")
     return out
+
+
+def evaluate_ellipsoids(scene, bodies, n_sigma, raw_mode=False, alpha_f=0.0, extent_f=0.0, **reduce):
+    """Convenience: float32 scene against ellipsoidal bodies (centre, (w,x,y,z)
+    quaternion of the body frame, semi-axes along its local x, y, z), with
+    A_j = R_j diag(1/a^2, 1/b^2, 1/c^2) R_j^T (Eq. 5-6)."""
+    _, mu, sig = prepare_scene(scene.means, scene.quats, scene.scales, scene.opacity,
+                               raw_mode=raw_mode, alpha_f=alpha_f, extent_f=extent_f)
+    A = ellipsoid_bodies(quat_to_rot(bodies.quats), bodies.axes)
+    return evaluate(mu, sig, bodies.centers.astype(np.float64), A, n_sigma, **reduce)
 
 
 def evaluate_spheres(scene, queries, n_sigma, raw_mode=False, alpha_f=0.0, extent_f=0.0,

@@ -401,6 +401,62 @@ def test_ellipsoid_point_membership(oracle_mod):
     assert np.allclose(sph["min"], ref["min"], rtol=1e-12)
 
 
+def test_body_quaternion_matches_library_rotation(oracle_mod):
+    """Body frames: (w, x, y, z) of any nonzero norm, against scipy's rotation
+    (scalar-last convention)."""
+    rng = np.random.default_rng(84)
+    q = rng.normal(size=(40, 4)) * rng.uniform(0.1, 5.0, (40, 1))
+    R = oracle_mod.quat_to_rot(q)
+    ref = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+    assert np.allclose(R, ref, atol=1e-14)
+    assert np.allclose(oracle_mod.quat_to_rot(-q), R, atol=1e-14)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.quat_to_rot([[0.0, 0.0, 0.0, 0.0]])
+
+
+def test_ellipsoid_bodies_from_quaternions_membership(oracle_mod):
+    """n_sigma = 0: the count is the number of means strictly inside the body,
+    tested in the body frame built by scipy from the same quaternion."""
+    from workloads import random_ellipsoids
+    sc = _random_scene(3000, seed=85)
+    bodies = random_ellipsoids(40, seed=86, box=(1, 1, 1), axis_range=(0.03, 0.25))
+    out = oracle_mod.evaluate_ellipsoids(sc, bodies, [0.0])
+    mu = sc.means.astype(np.float64)
+    for j in range(bodies.q):
+        w, x, y, z = bodies.quats[j].astype(np.float64)
+        Rj = Rotation.from_quat([x, y, z, w]).as_matrix()
+        local = (mu - bodies.centers[j].astype(np.float64)) @ Rj   # body-frame coordinates
+        inside = ((local / bodies.axes[j].astype(np.float64)) ** 2).sum(1) < 1.0
+        assert out["count"][j, 0] == inside.sum()
+
+
+def test_ellipsoid_principal_axis_closed_form(oracle_mod):
+    """Sigma = s^2 I and d along the body's local axis k at distance rho:
+    s^2 = rho^2 / a_k^2, sqrt(sigma^2) = 2 s rho / a_k^2, so collision iff
+    rho < n s + sqrt(n^2 s^2 + a_k^2)."""
+    from workloads import Bodies
+    rng = np.random.default_rng(87)
+    s = float(np.float32(0.02))
+    for trial in range(4):
+        quat = rng.normal(size=4)
+        axes = rng.uniform(0.05, 0.3, 3)
+        w, x, y, z = quat
+        Rb = Rotation.from_quat([x, y, z, w]).as_matrix()
+        for k in range(3):
+            for n in (0.0, 1.0, 2.5):
+                rho = n * s + math.sqrt(n * n * s * s + axes[k] ** 2)
+                for fac, want in ((1 - 1e-7, 1), (1 + 1e-7, 0)):
+                    c = -Rb[:, k] * rho * fac      # the mean sits at +rho along local axis k
+                    sc = _scene([[0, 0, 0]], [[1, 0, 0, 0]], [[s, s, s]])
+                    b = Bodies(c[None].astype(np.float64), quat[None], axes[None])
+                    out = oracle_mod.evaluate_ellipsoids(sc, b, [n])
+                    assert out["count"][0, 0] == want, (trial, k, n, fac)
+                b = Bodies(-Rb[:, k][None] * 0.03, quat[None], axes[None])
+                out = oracle_mod.evaluate_ellipsoids(sc, b, [n])
+                ref = max(0.0, (0.03 ** 2 - 2 * n * s * 0.03) / axes[k] ** 2)
+                assert abs(out["min"][0, 0] - ref) <= 1e-12 * max(1.0, ref)
+
+
 # --- Brute force on tiny isotropic scenes, per-pair closed form --------------
 
 def test_isotropic_scene_brute_force(oracle_mod):

@@ -6,6 +6,7 @@ metric's arithmetic (no covariance, no distance, no reduction).
 from .generators import (  # noqa: F401
     Scene,
     Queries,
+    Bodies,
     common_attrs,
     uniform_box_scene,
     room_scene,
@@ -13,6 +14,8 @@ from .generators import (  # noqa: F401
     uniform_queries,
     mppi_walk_queries,
     chain_queries,
+    chain_ellipsoids,
+    random_ellipsoids,
     grid_queries,
     serving_stream,
     config,

@@ -54,6 +54,22 @@ class Queries:
         return Queries(self.centers[idx].copy(), self.radii[idx].copy())
 
 
+@dataclasses.dataclass
+class Bodies:
+    """Ellipsoidal robot bodies: centre, orientation quaternion (w, x, y, z;
+    not necessarily unit) and semi-axes along the body's local x, y, z."""
+    centers: np.ndarray
+    quats: np.ndarray
+    axes: np.ndarray
+
+    @property
+    def q(self) -> int:
+        return int(self.centers.shape[0])
+
+    def subset(self, idx) -> "Bodies":
+        return Bodies(self.centers[idx].copy(), self.quats[idx].copy(), self.axes[idx].copy())
+
+
 def _rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
@@ -267,6 +283,63 @@ def chain_queries(configs: int, steps: int, seed: int, base=(0.75, 0.1, 0.1)) ->
     return Queries(c, r)
 
 
+def _qmul(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Hamilton product of (w, x, y, z) quaternions, broadcast over leading axes."""
+    aw, ax, ay, az = np.moveaxis(a, -1, 0)
+    bw, bx, by, bz = np.moveaxis(b, -1, 0)
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw], -1)
+
+
+def _axis_quat(axis: str, ang: np.ndarray) -> np.ndarray:
+    c, s = np.cos(ang / 2), np.sin(ang / 2)
+    z = np.zeros_like(ang)
+    return np.stack([c, z, z, s] if axis == "z" else [c, z, s, z], -1)
+
+
+def chain_ellipsoids(configs: int, steps: int, seed: int, base=(0.75, 0.1, 0.1)) -> Bodies:
+    """The 7-link chain of chain_queries with one ellipsoid per link: centred on
+    the link, local z along it, semi-axes (r_l, r_l, L_l / 2 + r_l) with link
+    radii r_l ~ U[0.04, 0.08].  Index = (config * steps + step) * 7 + link."""
+    rng = _rng(seed)
+    lengths = rng.uniform(0.1, 0.2, 7)
+    link_r = rng.uniform(0.04, 0.08, 7)
+    q = np.empty((configs, steps, 7))
+    q[:, 0] = rng.uniform(-math.pi / 2, math.pi / 2, (configs, 7))
+    for t in range(1, steps):
+        q[:, t] = q[:, t - 1] + rng.normal(0, 0.05, (configs, 7))
+    qf = q.reshape(-1, 7)
+    B = qf.shape[0]
+    Rw = np.tile(np.eye(3), (B, 1, 1))
+    qw = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), (B, 1))
+    pw = np.tile(np.asarray(base, float), (B, 1))
+    centers = np.empty((B, 7, 3))
+    quats = np.empty((B, 7, 4))
+    axes = np.empty((B, 7, 3))
+    for l in range(7):
+        Rw = Rw @ _axis_rot(_AXES[l], qf[:, l])
+        qw = _qmul(qw, _axis_quat(_AXES[l], qf[:, l]))
+        seg = Rw[:, :, 2] * lengths[l]
+        centers[:, l] = pw + 0.5 * seg
+        quats[:, l] = qw
+        axes[:, l] = (link_r[l], link_r[l], 0.5 * lengths[l] + link_r[l])
+        pw = pw + seg
+    return Bodies(centers.reshape(-1, 3).astype(np.float32), quats.reshape(-1, 4).astype(np.float32),
+                  axes.reshape(-1, 3).astype(np.float32))
+
+
+def random_ellipsoids(q: int, seed: int, box=(4.0, 4.0, 2.0), axis_range=(0.02, 0.2)) -> Bodies:
+    """Centres uniform in the box, orientations from 4 iid normals (left
+    unnormalised), semi-axes uniform in axis_range."""
+    rng = _rng(seed)
+    c = rng.uniform(0, 1, (q, 3)) * np.asarray(box)
+    quat = rng.normal(size=(q, 4))
+    ax = rng.uniform(axis_range[0], axis_range[1], (q, 3))
+    return Bodies(c.astype(np.float32), quat.astype(np.float32), ax.astype(np.float32))
+
+
 def grid_queries(res: int, size=(10.0, 10.0, 3.0), radius_classes=(0.05, 0.10, 0.20, 0.40),
                  stress_scene: Scene | None = None, seed: int = 0, stress_frac=0.5) -> Queries:
     """Cell centres of a res^3 grid over the box (x fastest); radius class =
@@ -329,7 +402,7 @@ def serving_stream(n_requests: int, seed: int, rate_hz: float, scene_ids=(0, 1),
 
 # Named workloads.  Reduction defaults: k=2, tau=0.1, d_max=1, gamma=1, s_min=1;
 # floater filter alpha_f=0.05, extent_f=0.1 m.
-CONFIG_NAMES = ("tiny", "mppi_nav", "manip", "precision")
+CONFIG_NAMES = ("tiny", "mppi_nav", "manip", "precision", "manip_ell")
 
 REDUCE_DEFAULTS = dict(k=2, tau=0.1, d_max=1.0, gamma=1.0, s_min=1.0)
 FLOATER = dict(alpha_f=0.05, extent_f=0.1)
@@ -352,6 +425,10 @@ def config(name: str, scale: float = 1.0):
         sc = tabletop_scene(sz(500_000), seed=3)
         qs = chain_queries(sz(256), 32, seed=103)
         par = dict(n_sigma=[1.0], r_nbr=0.3)
+    elif name == "manip_ell":
+        sc = tabletop_scene(sz(500_000), seed=3)
+        qs = chain_ellipsoids(sz(256), 32, seed=106)
+        par = dict(n_sigma=[1.0], r_nbr=0.4)
     elif name == "precision":
         sc = room_scene(sz(4_000_000), seed=4)
         res = max(4, int(round(64 * scale ** (1 / 3))))
