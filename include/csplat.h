@@ -161,6 +161,20 @@ csplat_status csplat_eval_distance(csplat_ctx *ctx, const csplat_scene *scene, i
                                    const csplat_reduce_opts *opts, float *min,
                                    float *softmin, float *cost);
 
+/* Ellipsoidal robot bodies (Eq. 5-6 with a general A_j, Sec. II-B): body j
+ * has centre c_j (q x 3), orientation quaternion (q x 4, (w, x, y, z), any
+ * nonzero norm; normalised here) and semi-axes (a, b, c) > 0 along its local
+ * x, y, z axes (q x 3), so A_j = R_j diag(1/a^2, 1/b^2, 1/c^2) R_j^T and
+ * s~^2 = max(0, s^2 - n sqrt(sigma^2)) with s^2 = d^T A d and
+ * sigma^2 = 4 d^T A Sigma A d (Eq. 7-8).  A sphere is a = b = c = r.
+ * Outputs, options, pointer rules and the neighbourhood ball (about c_j) are
+ * those of csplat_eval; only opts->precision = CSPLAT_PRECISION_FP32 is
+ * accepted.  Errors: CSPLAT_E_INVALID (as csplat_eval, or a non-finite
+ * centre, a zero or non-finite quaternion, a semi-axis not finite and > 0). */
+csplat_status csplat_eval_ellipsoids(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
+                                     const float *centers, const float *quats, const float *axes,
+                                     const csplat_reduce_opts *opts, const csplat_outputs *out);
+
 /* Timing mode (off by default): when on, every evaluation records HIP events
  * around its dominant kernel and csplat_last_stats waits for the second one. */
 csplat_status csplat_ctx_set_timing(csplat_ctx *ctx, int32_t enable);

@@ -43,7 +43,7 @@ CSPLAT_FEATURES_FP16 = 2
 EXPORTS = (
     "csplat_ctx_create", "csplat_ctx_destroy", "csplat_scene_load", "csplat_scene_info",
     "csplat_scene_free", "csplat_set_conservatism", "csplat_eval", "csplat_eval_labels",
-    "csplat_eval_distance", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
+    "csplat_eval_distance", "csplat_eval_ellipsoids", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
     "csplat_last_error", "csplat_server_create", "csplat_server_destroy", "csplat_server_add_scene",
     "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
     "csplat_server_stats",
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "csplat_eval": [P, P, I64, P, P, P, P],
         "csplat_eval_labels": [P, P, I64, P, P, P, P, P],
         "csplat_eval_distance": [P, P, I64, P, P, P, P, P, P],
+        "csplat_eval_ellipsoids": [P, P, I64, P, P, P, P, P],
         "csplat_ctx_set_timing": [P, I32],
         "csplat_last_stats": [P, P],
         "csplat_synchronize": [P],
@@ -229,6 +230,16 @@ def csplat_eval_distance(ctx, scene, centers, radii, opts: ReduceOpts, min, soft
     _check(load_library().csplat_eval_distance(ctx, scene, q, _addr(centers), _addr(radii),
                                                ctypes.byref(opts), _addr(min), _addr(softmin),
                                                _addr(cost)))
+
+
+def csplat_eval_ellipsoids(ctx, scene, centers, quats, axes, opts: ReduceOpts, label=None, count=None,
+                           min=None, softmin=None, cost=None, nbr=None):
+    """Ellipsoidal bodies: centres (q x 3), (w, x, y, z) quaternions (q x 4),
+    semi-axes (q x 3); outputs as csplat_eval."""
+    q = int(centers.shape[0])
+    o = Outputs(*[_addr(x) for x in (label, count, min, softmin, cost, nbr)])
+    _check(load_library().csplat_eval_ellipsoids(ctx, scene, q, _addr(centers), _addr(quats), _addr(axes),
+                                                 ctypes.byref(opts), ctypes.byref(o)))
 
 
 def csplat_ctx_set_timing(ctx, enable: bool):
@@ -380,6 +391,21 @@ class Engine:
             for t in (centers, radii, *out.values()):
                 t.record_stream(self.stream)
         csplat_eval(self.ctx, scene, centers, radii, opts, **out)
+        if like == "cuda":
+            self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def evaluate_ellipsoids(self, scene, centers, quats, axes, opts: ReduceOpts, want=ALL_OUTPUTS, out=None):
+        """Ellipsoidal bodies (arrays all torch CUDA tensors or all numpy)."""
+        like = "cuda" if _is_torch_cuda(centers) else "host"
+        if out is None:
+            out = self.alloc_outputs(int(centers.shape[0]), want, like)
+        if like == "cuda":
+            cur = self.torch.cuda.current_stream(self.device)
+            self.stream.wait_stream(cur)
+            for t in (centers, quats, axes, *out.values()):
+                t.record_stream(self.stream)
+        csplat_eval_ellipsoids(self.ctx, scene, centers, quats, axes, opts, **out)
         if like == "cuda":
             self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return out

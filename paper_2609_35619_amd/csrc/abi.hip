@@ -2,8 +2,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -161,6 +163,143 @@ __global__ void check_queries_kernel(int64_t q, const float *__restrict__ c, con
     if (!ok) atomicOr(bad, 1);
 }
 
+// Ellipsoidal bodies: finite centres, finite nonzero quaternions, finite
+// semi-axes > 0.
+bool bodies_valid_host(int64_t q, const float *c, const float *quat, const float *ax)
+{
+    for (int64_t j = 0; j < q; ++j) {
+        float qq = 0.f;
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(c[3 * j + k]) || !(ax[3 * j + k] > 0.f) || !std::isfinite(ax[3 * j + k])) return false;
+        for (int k = 0; k < 4; ++k) {
+            if (!std::isfinite(quat[4 * j + k])) return false;
+            qq += quat[4 * j + k] * quat[4 * j + k];
+        }
+        if (!(qq > 0.f)) return false;
+    }
+    return true;
+}
+
+__global__ void check_bodies_kernel(int64_t q, const float *__restrict__ c, const float *__restrict__ quat,
+                                    const float *__restrict__ ax, int *bad)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    bool ok = true;
+    float qq = 0.f;
+    for (int k = 0; k < 3; ++k) ok = ok && isfinite(c[3 * j + k]) && ax[3 * j + k] > 0.f && isfinite(ax[3 * j + k]);
+    for (int k = 0; k < 4; ++k) {
+        ok = ok && isfinite(quat[4 * j + k]);
+        qq += quat[4 * j + k] * quat[4 * j + k];
+    }
+    if (!(ok && qq > 0.f)) atomicOr(bad, 1);
+}
+
+// Checks common to the evaluation calls; fills p.
+csplat_status eval_checks(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const csplat_reduce_opts *opts,
+                          const csplat_outputs *out, const char *who, EvalParams &p, bool &want_dist)
+{
+    if (!ctx || !sc || !opts || !out) return fail(CSPLAT_E_INVALID, std::string(who) + ": NULL argument");
+    if (q < 0) return fail(CSPLAT_E_INVALID, std::string(who) + ": q < 0");
+    if (q > (int64_t)0x7FFFFFFF / 8) return fail(CSPLAT_E_INVALID, std::string(who) + ": q too large");
+    if (sc->device != ctx->device) return fail(CSPLAT_E_INVALID, std::string(who) + ": scene on another device");
+    csplat_status s = build_params(ctx->n_sigma, ctx->m, *opts, p);
+    if (s != CSPLAT_OK) return s;
+    want_dist = out->min || out->softmin || out->cost || out->nbr;
+    if (!want_dist && !out->label && !out->count)
+        return fail(CSPLAT_E_INVALID, std::string(who) + ": no output requested");
+    return CSPLAT_OK;
+}
+
+// One kind (1 device, 0 host) for every non-NULL pointer, or -1 for a mix.
+int common_kind(std::initializer_list<const void *> ptrs)
+{
+    int kind = -2;
+    for (const void *ptr : ptrs) {
+        if (!ptr) continue;
+        int k = pointer_kind(ptr);
+        if (kind == -2) kind = k;
+        else if (kind != k) return -1;
+    }
+    return kind == -2 ? 0 : kind;
+}
+
+// Device-side validation: `launch(bad)` queues a check kernel that sets *bad.
+template <class Launch>
+csplat_status device_check(csplat_ctx *ctx, Launch launch, const char *msg)
+{
+    hipError_t e = ctx->flags.reserve(64);
+    if (e != hipSuccess) return hip_fail(e, "flag workspace");
+    int *bad = ctx->flags.as<int>();
+    CSPLAT_HIP(zero_words(bad, 1, ctx->stream));
+    launch(bad);
+    CSPLAT_HIP(hipGetLastError());
+    int hbad = 0;
+    CSPLAT_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    CSPLAT_HIP(hipStreamSynchronize(ctx->stream));
+    if (hbad) return fail(CSPLAT_E_INVALID, msg);
+    return CSPLAT_OK;
+}
+
+// Runs run(dev_inputs, eo) with every input and output on the device: device
+// pointers as given (asynchronous); host inputs staged through the context's
+// staging buffer and host outputs copied back (synchronous).
+template <class Run>
+csplat_status on_device(csplat_ctx *ctx, int kind, int64_t q, int m, std::initializer_list<const void *> in,
+                        std::initializer_list<size_t> in_bytes, const csplat_outputs *out, Run run)
+{
+    std::vector<const void *> dev_in(in);
+    if (kind == 1) {
+        EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr};
+        return run(dev_in, eo);
+    }
+    const size_t qm = (size_t)q * m;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    std::vector<size_t> o_in;
+    for (size_t b : in_bytes) o_in.push_back(take(b));
+    const size_t o_lab = out->label ? take(qm) : 0, o_cnt = out->count ? take(qm * 4) : 0;
+    const size_t o_min = out->min ? take(qm * 4) : 0, o_sm = out->softmin ? take(qm * 4) : 0;
+    const size_t o_cs = out->cost ? take(qm * 4) : 0, o_nb = out->nbr ? take((size_t)q * 4) : 0;
+    hipError_t e = ctx->staging.reserve(off);
+    if (e != hipSuccess) return hip_fail(e, "staging workspace");
+    char *b = ctx->staging.as<char>();
+    hipStream_t st = ctx->stream;
+    size_t i = 0;
+    for (size_t bytes : in_bytes) {
+        CSPLAT_HIP(hipMemcpyAsync(b + o_in[i], dev_in[i], bytes, hipMemcpyHostToDevice, st));
+        dev_in[i] = b + o_in[i];
+        ++i;
+    }
+    EvalOut eo{out->label ? (uint8_t *)(b + o_lab) : nullptr, out->count ? (int32_t *)(b + o_cnt) : nullptr,
+               out->min ? (float *)(b + o_min) : nullptr, out->softmin ? (float *)(b + o_sm) : nullptr,
+               out->cost ? (float *)(b + o_cs) : nullptr, out->nbr ? (int32_t *)(b + o_nb) : nullptr};
+    csplat_status s = run(dev_in, eo);
+    if (s != CSPLAT_OK) return s;
+    if (out->label) CSPLAT_HIP(hipMemcpyAsync(out->label, eo.label, qm, hipMemcpyDeviceToHost, st));
+    if (out->count) CSPLAT_HIP(hipMemcpyAsync(out->count, eo.count, qm * 4, hipMemcpyDeviceToHost, st));
+    if (out->min) CSPLAT_HIP(hipMemcpyAsync(out->min, eo.min, qm * 4, hipMemcpyDeviceToHost, st));
+    if (out->softmin) CSPLAT_HIP(hipMemcpyAsync(out->softmin, eo.softmin, qm * 4, hipMemcpyDeviceToHost, st));
+    if (out->cost) CSPLAT_HIP(hipMemcpyAsync(out->cost, eo.cost, qm * 4, hipMemcpyDeviceToHost, st));
+    if (out->nbr) CSPLAT_HIP(hipMemcpyAsync(out->nbr, eo.nbr, (size_t)q * 4, hipMemcpyDeviceToHost, st));
+    CSPLAT_HIP(hipStreamSynchronize(st));
+    return CSPLAT_OK;
+}
+
+void reset_stats(csplat_ctx *ctx, int64_t q, const csplat_scene *sc)
+{
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    ctx->stats.pairs = q * sc->n;
+    ctx->timed = false;
+    ctx->flag_counts = nullptr;
+    ctx->flag_m = 0;
+    ctx->chunk_counter = nullptr;
+}
+
 }  // namespace
 }  // namespace csplat
 
@@ -208,6 +347,7 @@ csplat_status csplat_ctx_destroy(csplat_ctx *ctx)
     ctx->staging.release();
     ctx->flags.release();
     ctx->sortbuf.release();
+    ctx->bodies.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -287,15 +427,10 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
                           const float *radii, const csplat_reduce_opts *opts,
                           const csplat_outputs *out)
 {
-    if (!ctx || !sc || !opts || !out) return fail(CSPLAT_E_INVALID, "eval: NULL argument");
-    if (q < 0) return fail(CSPLAT_E_INVALID, "eval: q < 0");
-    if (q > (int64_t)0x7FFFFFFF / 8) return fail(CSPLAT_E_INVALID, "eval: q too large");
-    if (sc->device != ctx->device) return fail(CSPLAT_E_INVALID, "eval: scene on another device");
     EvalParams p;
-    csplat_status s = build_params(ctx->n_sigma, ctx->m, *opts, p);
+    bool want_dist = false;
+    csplat_status s = eval_checks(ctx, sc, q, opts, out, "eval", p, want_dist);
     if (s != CSPLAT_OK) return s;
-    const bool want_dist = out->min || out->softmin || out->cost || out->nbr;
-    if (!want_dist && !out->label && !out->count) return fail(CSPLAT_E_INVALID, "eval: no output requested");
     if (opts->precision != CSPLAT_PRECISION_FP32) {
         if (want_dist)
             return fail(CSPLAT_E_INVALID, "eval: the MFMA precision forms compute labels and counts only");
@@ -307,79 +442,76 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     }
     if (q == 0) return CSPLAT_OK;
     if (!centers || !radii) return fail(CSPLAT_E_INVALID, "eval: NULL centers or radii");
-    const void *ptrs[] = {centers, radii, out->label, out->count, out->min, out->softmin, out->cost, out->nbr};
-    int kind = -2;
-    for (const void *ptr : ptrs) {
-        if (!ptr) continue;
-        int k = pointer_kind(ptr);
-        if (kind == -2) kind = k;
-        else if (kind != k)
-            return fail(CSPLAT_E_INVALID, "eval: mix of host and device pointers");
-    }
+    const int kind = common_kind({centers, radii, out->label, out->count, out->min, out->softmin, out->cost,
+                                  out->nbr});
+    if (kind < 0) return fail(CSPLAT_E_INVALID, "eval: mix of host and device pointers");
+    const char *bad_msg = "eval: query centres must be finite and radii finite and > 0";
+    if (kind == 0 && !queries_valid_host(q, centers, radii)) return fail(CSPLAT_E_INVALID, bad_msg);
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-    const int m = ctx->m;
-    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
-    ctx->stats.pairs = q * sc->n;
-    ctx->timed = false;
-    ctx->flag_counts = nullptr;
-    ctx->flag_m = 0;
-    ctx->chunk_counter = nullptr;
+    reset_stats(ctx, q, sc);
     if (kind == 1) {
         // device inputs: check them on the device before any output is touched
-        int *bad = nullptr;
-        hipError_t e = ctx->flags.reserve(64);
-        if (e != hipSuccess) return hip_fail(e, "flag workspace");
-        bad = ctx->flags.as<int>();
-        CSPLAT_HIP(zero_words(bad, 1, ctx->stream));
-        check_queries_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, radii, bad);
-        CSPLAT_HIP(hipGetLastError());
-        int hbad = 0;
-        CSPLAT_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-        CSPLAT_HIP(hipStreamSynchronize(ctx->stream));
-        if (hbad) return fail(CSPLAT_E_INVALID, "eval: query centres must be finite and radii finite and > 0");
-        EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr};
-        if (opts->precision != CSPLAT_PRECISION_FP32)
-            return precision_eval(ctx, sc, q, centers, radii, p, eo, opts->precision);
-        return fp32_eval(ctx, sc, q, centers, radii, p, eo, !want_dist);
+        s = device_check(
+            ctx,
+            [&](int *bad) {
+                check_queries_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, radii, bad);
+            },
+            bad_msg);
+        if (s != CSPLAT_OK) return s;
     }
-    // host pointers: validate, stage, run, copy back, synchronise
-    if (!queries_valid_host(q, centers, radii))
-        return fail(CSPLAT_E_INVALID, "eval: query centres must be finite and radii finite and > 0");
-    const size_t qm = (size_t)q * m;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off += (bytes + 255) & ~(size_t)255;
-        return o;
-    };
-    const size_t o_c = take((size_t)q * 12), o_r = take((size_t)q * 4);
-    const size_t o_lab = out->label ? take(qm) : 0, o_cnt = out->count ? take(qm * 4) : 0;
-    const size_t o_min = out->min ? take(qm * 4) : 0, o_sm = out->softmin ? take(qm * 4) : 0;
-    const size_t o_cs = out->cost ? take(qm * 4) : 0, o_nb = out->nbr ? take((size_t)q * 4) : 0;
-    hipError_t e = ctx->staging.reserve(off);
-    if (e != hipSuccess) return hip_fail(e, "staging workspace");
-    char *b = ctx->staging.as<char>();
-    hipStream_t st = ctx->stream;
-    CSPLAT_HIP(hipMemcpyAsync(b + o_c, centers, (size_t)q * 12, hipMemcpyHostToDevice, st));
-    CSPLAT_HIP(hipMemcpyAsync(b + o_r, radii, (size_t)q * 4, hipMemcpyHostToDevice, st));
-    EvalOut eo{out->label ? (uint8_t *)(b + o_lab) : nullptr, out->count ? (int32_t *)(b + o_cnt) : nullptr,
-               out->min ? (float *)(b + o_min) : nullptr, out->softmin ? (float *)(b + o_sm) : nullptr,
-               out->cost ? (float *)(b + o_cs) : nullptr, out->nbr ? (int32_t *)(b + o_nb) : nullptr};
-    if (opts->precision != CSPLAT_PRECISION_FP32)
-        s = precision_eval(ctx, sc, q, (const float *)(b + o_c), (const float *)(b + o_r), p, eo,
-                           opts->precision);
-    else
-        s = fp32_eval(ctx, sc, q, (const float *)(b + o_c), (const float *)(b + o_r), p, eo, !want_dist);
+    return on_device(ctx, kind, q, ctx->m, {centers, radii}, {(size_t)q * 12, (size_t)q * 4}, out,
+                     [&](const std::vector<const void *> &in, const EvalOut &eo) {
+                         const float *c = static_cast<const float *>(in[0]), *r = static_cast<const float *>(in[1]);
+                         if (opts->precision != CSPLAT_PRECISION_FP32)
+                             return precision_eval(ctx, sc, q, c, r, p, eo, opts->precision);
+                         return fp32_eval(ctx, sc, q, c, r, p, eo, !want_dist);
+                     });
+}
+
+csplat_status csplat_eval_ellipsoids(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const float *centers,
+                                     const float *quats, const float *axes, const csplat_reduce_opts *opts,
+                                     const csplat_outputs *out)
+{
+    EvalParams p;
+    bool want_dist = false;
+    csplat_status s = eval_checks(ctx, sc, q, opts, out, "eval_ellipsoids", p, want_dist);
     if (s != CSPLAT_OK) return s;
-    if (out->label) CSPLAT_HIP(hipMemcpyAsync(out->label, eo.label, qm, hipMemcpyDeviceToHost, st));
-    if (out->count) CSPLAT_HIP(hipMemcpyAsync(out->count, eo.count, qm * 4, hipMemcpyDeviceToHost, st));
-    if (out->min) CSPLAT_HIP(hipMemcpyAsync(out->min, eo.min, qm * 4, hipMemcpyDeviceToHost, st));
-    if (out->softmin) CSPLAT_HIP(hipMemcpyAsync(out->softmin, eo.softmin, qm * 4, hipMemcpyDeviceToHost, st));
-    if (out->cost) CSPLAT_HIP(hipMemcpyAsync(out->cost, eo.cost, qm * 4, hipMemcpyDeviceToHost, st));
-    if (out->nbr) CSPLAT_HIP(hipMemcpyAsync(out->nbr, eo.nbr, (size_t)q * 4, hipMemcpyDeviceToHost, st));
-    CSPLAT_HIP(hipStreamSynchronize(st));
-    return CSPLAT_OK;
+    if (opts->precision != CSPLAT_PRECISION_FP32)
+        return fail(CSPLAT_E_INVALID, "eval_ellipsoids: ellipsoidal bodies use the float32 path only");
+    if (q == 0) return CSPLAT_OK;
+    if (!centers || !quats || !axes) return fail(CSPLAT_E_INVALID, "eval_ellipsoids: NULL body array");
+    const int kind = common_kind({centers, quats, axes, out->label, out->count, out->min, out->softmin,
+                                  out->cost, out->nbr});
+    if (kind < 0) return fail(CSPLAT_E_INVALID, "eval_ellipsoids: mix of host and device pointers");
+    const char *bad_msg =
+        "eval_ellipsoids: centres must be finite, quaternions finite and nonzero, semi-axes finite and > 0";
+    if (kind == 0 && !bodies_valid_host(q, centers, quats, axes)) return fail(CSPLAT_E_INVALID, bad_msg);
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    reset_stats(ctx, q, sc);
+    if (kind == 1) {
+        s = device_check(
+            ctx,
+            [&](int *bad) {
+                check_bodies_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, quats, axes,
+                                                                                       bad);
+            },
+            bad_msg);
+        if (s != CSPLAT_OK) return s;
+    }
+    hipError_t e = ctx->bodies.reserve((size_t)q * kBodyFloats * 4);
+    if (e != hipSuccess) return hip_fail(e, "body workspace");
+    return on_device(ctx, kind, q, ctx->m, {centers, quats, axes},
+                     {(size_t)q * 12, (size_t)q * 16, (size_t)q * 12}, out,
+                     [&](const std::vector<const void *> &in, const EvalOut &eo) {
+                         float *rec = ctx->bodies.as<float>();
+                         csplat_status st = prepare_bodies(ctx, (int)q, static_cast<const float *>(in[0]),
+                                                           static_cast<const float *>(in[1]),
+                                                           static_cast<const float *>(in[2]), rec);
+                         if (st != CSPLAT_OK) return st;
+                         return fp32_eval(ctx, sc, q, rec, nullptr, p, eo, !want_dist, true);
+                     });
 }
 
 csplat_status csplat_eval_labels(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const float *centers,

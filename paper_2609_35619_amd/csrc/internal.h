@@ -13,8 +13,12 @@ namespace csplat {
 // Per-Gaussian record of the float32 pair kernel: 16 floats (64 B), read by
 // scalar (wave-uniform) loads.  M = diag(s) R^T, so that for d = mu - c the
 // linearised variance term V = d^T Sigma d = |M d|^2 is a sum of squares;
-// -2 mu and |mu|^2 serve the neighbourhood pre-test |mu|^2 - 2 mu.c + |c|^2.
+// -2 mu and |mu|^2 complete the record to 16 floats (the expanded form
+// |mu|^2 - 2 mu.c + |c|^2 of |d|^2; unused by the current kernels).
 constexpr int kGaussFloats = 16;  // mx my mz | M00..M22 (row-major) | -2mx -2my -2mz | |mu|^2
+// Prepared ellipsoidal body: centre (3), L = diag(1/a) R^T row-major (9), the
+// reach constants qa = (smallest semi-axis)^2 and qk = largest / smallest, 0, 0.
+constexpr int kBodyFloats = 16;
 
 void set_error(const std::string &msg);
 csplat_status fail(csplat_status code, const std::string &msg);
@@ -81,6 +85,7 @@ struct csplat_ctx {
     csplat::DevBuf staging;    // host-pointer staging (inputs + outputs)
     csplat::DevBuf flags;      // validation flag; precision form: recheck counters
     csplat::DevBuf sortbuf;    // spatial sort of the queries (codes, permutation, sorted copies)
+    csplat::DevBuf bodies;     // prepared ellipsoid records
     csplat_eval_stats stats{};
     int32_t *flag_counts = nullptr;  // device: rechecked queries per n_sigma (last eval)
     int32_t flag_m = 0;
@@ -169,11 +174,19 @@ struct SortedQueries {
 };
 csplat_status sort_queries(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *centers,
                            const float *radii, SortedQueries *out);
+// The same for ellipsoid records (ell: `centers` holds kBodyFloats-float
+// records, which are gathered into out->c; out->r is NULL).
+csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *centers,
+                          const float *radii, bool ell, SortedQueries *out);
+// Ellipsoid records from centres (q x 3), (w, x, y, z) quaternions (q x 4) and
+// semi-axes (q x 3), all device pointers, on the context stream.
+csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const float *quats, const float *axes,
+                             float *rec);
 
 // pair_fp32.hip: the float32 pair kernel and the split combine.
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
                         const float *centers, const float *radii, const EvalParams &p,
-                        const EvalOut &out, bool labels_only);
+                        const EvalOut &out, bool labels_only, bool ell = false);
 
 // precision.hip: MFMA form with certified recheck (labels and counts).
 csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,

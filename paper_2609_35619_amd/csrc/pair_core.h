@@ -39,9 +39,6 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #ifndef CSPLAT_QPL_LABELS
 #define CSPLAT_QPL_LABELS 2
 #endif
-#ifndef CSPLAT_PRETEST
-#define CSPLAT_PRETEST 0
-#endif
 #ifndef CSPLAT_PIPELINE
 #define CSPLAT_PIPELINE 0
 #endif
@@ -54,11 +51,6 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 constexpr int kUnroll = CSPLAT_UNROLL;       // Gaussians per group of scalar loads
 constexpr int kQplFull = CSPLAT_QPL_FULL;    // queries per lane, all outputs
 constexpr int kQplLabels = CSPLAT_QPL_LABELS;  // queries per lane, labels only
-// Expanded-form neighbourhood pre-test (4 operations instead of 6 per pair,
-// exact by a certified margin).  Off by default: on the MPPI workload the loop
-// is not VALU-issue bound and the extra work inside the branch costs more
-// than the pre-test saves (12.8 ms vs 13.7 ms per launch on MI355X).
-constexpr bool kPretest = CSPLAT_PRETEST != 0;
 constexpr bool kPipeline = CSPLAT_PIPELINE != 0;
 
 __device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -73,9 +65,14 @@ struct Part {
     int32_t *nb;   // [split][q] neighbourhood size
 };
 
-// Ball membership and the per-pair metric.  Terms in "r^2 units": with
-// d = mu - c, D = |d|^2 and V = |M d|^2 = d^T Sigma d,
-//   r^2 s^2 = D,  r^2 n sqrt(sigma^2) = 2 n sqrt(V),  r^2 s~^2 = max(0, D - 2 n sqrt(V)).
+// Ball membership and the per-pair metric, with d = mu - c.
+//  * Sphere of radius r (Eq. 6 with a = b = c = r): terms in "r^2 units", with
+//    D = |d|^2 and V = |M d|^2 = d^T Sigma d,
+//      r^2 s^2 = D,  r^2 n sqrt(sigma^2) = 2 n sqrt(V),  r^2 s~^2 = max(0, D - 2 n sqrt(V)).
+//  * Ellipsoid A = L^T L with L = diag(1/a, 1/b, 1/c) R^T (Eq. 5-6): e = L d,
+//    s^2 = |e|^2 and the gradient of s^2 is 2 A d = 2 L^T e (Eq. 7), so
+//    sqrt(sigma^2) = 2 |M L^T e| and s~^2 = max(0, s^2 - 2 n |M L^T e|)
+//    (dimensionless: threshold 1).
 //
 // Each lane holds QPL queries (slot u of lane l in wave w of tile b is query
 // (b*kBlock + w*64)*QPL + u*64 + l: a wave holds 64*QPL consecutive queries,
@@ -91,47 +88,72 @@ struct Acc {
     int nb[QPL];
 };
 
-template <int M, bool FULL, bool BALL, int QPL>
-__device__ __forceinline__ void pair_step(const float *__restrict__ gp, const float (&cx)[QPL],
-                                          const float (&cy)[QPL], const float (&cz)[QPL],
-                                          const float (&r2)[QPL], const float (&kq)[QPL],
-                                          const float (&cc)[QPL], const float (&rn2w)[QPL],
+// Per-lane query state.  r2, kq: the collision threshold and the factor that
+// turns the metric into t = s~^2 * kt (sphere: r^2 and kt / r^2; ellipsoid: 1
+// and kt).  qa, qk: the reach-bound constants, the smallest semi-axis squared
+// and largest / smallest semi-axis (sphere: r^2 and 1).  L: the ellipsoid's
+// matrix diag(1/a) R^T, row-major.
+template <int QPL, bool ELL>
+struct QState {
+    float cx[QPL], cy[QPL], cz[QPL], r2[QPL], kq[QPL], qa[QPL], qk[QPL];
+    float L[ELL ? QPL : 1][9];
+};
+
+// D: the metric's squared term, W: its variance term (see above), from d.
+template <bool ELL, int QPL>
+__device__ __forceinline__ void metric_terms(const float *__restrict__ gp, const QState<QPL, ELL> &Q, int u,
+                                             float dx, float dy, float dz, float D_sphere, float &D, float &W)
+{
+    if constexpr (ELL) {
+        const float *L = Q.L[u];
+        const float e0 = fmaf(L[2], dz, fmaf(L[1], dy, L[0] * dx));
+        const float e1 = fmaf(L[5], dz, fmaf(L[4], dy, L[3] * dx));
+        const float e2 = fmaf(L[8], dz, fmaf(L[7], dy, L[6] * dx));
+        D = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
+        const float hx = fmaf(L[6], e2, fmaf(L[3], e1, L[0] * e0));  // L^T e = A d
+        const float hy = fmaf(L[7], e2, fmaf(L[4], e1, L[1] * e0));
+        const float hz = fmaf(L[8], e2, fmaf(L[5], e1, L[2] * e0));
+        const float g0 = fmaf(gp[5], hz, fmaf(gp[4], hy, gp[3] * hx));
+        const float g1 = fmaf(gp[8], hz, fmaf(gp[7], hy, gp[6] * hx));
+        const float g2 = fmaf(gp[11], hz, fmaf(gp[10], hy, gp[9] * hx));
+        W = fmaf(g2, g2, fmaf(g1, g1, g0 * g0));
+    } else {
+        D = D_sphere;
+        const float e0 = fmaf(gp[5], dz, fmaf(gp[4], dy, gp[3] * dx));
+        const float e1 = fmaf(gp[8], dz, fmaf(gp[7], dy, gp[6] * dx));
+        const float e2 = fmaf(gp[11], dz, fmaf(gp[10], dy, gp[9] * dx));
+        W = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
+    }
+}
+
+template <int M, bool FULL, bool BALL, int QPL, bool ELL>
+__device__ __forceinline__ void pair_step(const float *__restrict__ gp, const QState<QPL, ELL> &Q,
                                           const EvalParams &p, Acc<M, QPL> &A)
 {
     if constexpr (FULL) {
-        // neighbourhood pre-test on the expanded |d|^2 = |mu|^2 - 2 mu.c + |c|^2
-        // (4 operations) against r_nbr^2 widened by its certified rounding
-        // margin; the exact difference form decides inside the branch
         bool any = !BALL;
-        if constexpr (BALL && kPretest) {
+        if constexpr (BALL) {
 #pragma unroll
             for (int u = 0; u < QPL; ++u) {
-                const float De = fmaf(gp[12], cx[u], fmaf(gp[13], cy[u], fmaf(gp[14], cz[u], gp[15] + cc[u])));
-                any |= De <= rn2w[u];
-            }
-        } else if constexpr (BALL) {
-#pragma unroll
-            for (int u = 0; u < QPL; ++u) {
-                const float dx = gp[0] - cx[u], dy = gp[1] - cy[u], dz = gp[2] - cz[u];
+                const float dx = gp[0] - Q.cx[u], dy = gp[1] - Q.cy[u], dz = gp[2] - Q.cz[u];
                 any |= fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= p.rn2;
             }
         }
         if (any) {
 #pragma unroll
             for (int u = 0; u < QPL; ++u) {
-                const float dx = gp[0] - cx[u], dy = gp[1] - cy[u], dz = gp[2] - cz[u];
-                const float D = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                if (!BALL || D <= p.rn2) {
+                const float dx = gp[0] - Q.cx[u], dy = gp[1] - Q.cy[u], dz = gp[2] - Q.cz[u];
+                const float Db = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                if (!BALL || Db <= p.rn2) {
                     ++A.nb[u];
-                    const float e0 = fmaf(gp[5], dz, fmaf(gp[4], dy, gp[3] * dx));
-                    const float e1 = fmaf(gp[8], dz, fmaf(gp[7], dy, gp[6] * dx));
-                    const float e2 = fmaf(gp[11], dz, fmaf(gp[10], dy, gp[9] * dx));
-                    const float sv = fast_sqrt(fmaf(e2, e2, fmaf(e1, e1, e0 * e0)));
+                    float D, W;
+                    metric_terms<ELL, QPL>(gp, Q, u, dx, dy, dz, Db, D, W);
+                    const float sv = fast_sqrt(W);
 #pragma unroll
                     for (int v = 0; v < M; ++v) {
-                        const float x = fmaf(-p.two_n[v], sv, D);  // r^2 (s^2 - n sqrt(sigma^2))
-                        A.cnt[u][v] += x < r2[u];                      // s~^2 < 1
-                        const float t = fmaxf(x, 0.f) * kq[u];
+                        const float x = fmaf(-p.two_n[v], sv, D);  // (r^2) (s^2 - n sqrt(sigma^2))
+                        A.cnt[u][v] += x < Q.r2[u];                  // s~^2 < 1
+                        const float t = fmaxf(x, 0.f) * Q.kq[u];
                         // stable log-sum-exp about the running chunk minimum (one exp per pair)
                         const float e = fast_exp2(-fabsf(t - A.cmt[u][v]));
                         const bool lower = t < A.cmt[u][v];
@@ -145,18 +167,24 @@ __device__ __forceinline__ void pair_step(const float *__restrict__ gp, const fl
     } else {
 #pragma unroll
         for (int u = 0; u < QPL; ++u) {
-            const float dx = gp[0] - cx[u], dy = gp[1] - cy[u], dz = gp[2] - cz[u];
-            // labels only: s~^2 < 1  <=>  a |a| < 4 n^2 V  with a = D - r^2 (exact rewrite)
-            const float a = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -r2[u])));
-            const float e0 = fmaf(gp[5], dz, fmaf(gp[4], dy, gp[3] * dx));
-            const float e1 = fmaf(gp[8], dz, fmaf(gp[7], dy, gp[6] * dx));
-            const float e2 = fmaf(gp[11], dz, fmaf(gp[10], dy, gp[9] * dx));
-            const float V = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
-            const float aa = a * fabsf(a);
+            const float dx = gp[0] - Q.cx[u], dy = gp[1] - Q.cy[u], dz = gp[2] - Q.cz[u];
+            // labels only: s~^2 < 1  <=>  a |a| < 4 n^2 W  with a = (r^2)(s^2 - 1) (exact rewrite)
+            float a, W;
             bool in = true;
-            if constexpr (BALL) in = a + r2[u] <= p.rn2;
+            if constexpr (ELL) {
+                float D;
+                metric_terms<ELL, QPL>(gp, Q, u, dx, dy, dz, 0.f, D, W);
+                a = D - 1.f;
+                if constexpr (BALL) in = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= p.rn2;
+            } else {
+                a = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -Q.r2[u])));
+                float D;
+                metric_terms<ELL, QPL>(gp, Q, u, dx, dy, dz, 0.f, D, W);
+                if constexpr (BALL) in = a + Q.r2[u] <= p.rn2;
+            }
+            const float aa = a * fabsf(a);
 #pragma unroll
-            for (int v = 0; v < M; ++v) A.cnt[u][v] += in && (aa < p.four_n2[v] * V);
+            for (int v = 0; v < M; ++v) A.cnt[u][v] += in && (aa < p.four_n2[v] * W);
         }
     }
 }
@@ -273,31 +301,40 @@ __device__ __forceinline__ void cull_walk(const float *__restrict__ cull, int n_
 // every query (labels: no pair of it can have s~^2 < 1).  Skipped pairs
 // contribute nothing, and the order of every sum is unchanged: the results
 // are the same bits.
-template <int M, bool FULL, bool BALL, int QPL, bool CULL = false>
+template <int M, bool FULL, bool BALL, int QPL, bool CULL = false, bool ELL = false>
 __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, int S, int split,
                                           int tile, const float *__restrict__ centers,
                                           const float *__restrict__ radii, int q, const EvalParams &p,
-                                          const Part &part, float mu_max,
-                                          const float *__restrict__ cull = nullptr, int *chunks_done = nullptr)
+                                          const Part &part, const float *__restrict__ cull = nullptr,
+                                          int *chunks_done = nullptr)
 {
-    float cx[QPL], cy[QPL], cz[QPL], r2[QPL], kq[QPL], cc[QPL], rn2w[QPL];
+    // Spheres: centers (q x 3) and radii (q).  Ellipsoids (ELL): `centers`
+    // holds the prepared records of kBodyFloats floats, `radii` is unused.
+    QState<QPL, ELL> Q;
     int jq[QPL];
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
         jq[u] = (tile * kBlock + (int)(threadIdx.x & ~63u)) * QPL + u * 64 + (int)(threadIdx.x & 63u);
         const int jj = jq[u] < q ? jq[u] : q - 1;  // past the end: evaluate a real query, write nothing
-        cx[u] = centers[3 * jj];
-        cy[u] = centers[3 * jj + 1];
-        cz[u] = centers[3 * jj + 2];
-        const float r = radii[jj];
-        r2[u] = r * r;
-        kq[u] = p.kt / r2[u];  // t = max(0, r^2 s~^2) * kq = s~^2 * kt
-        cc[u] = fmaf(cz[u], cz[u], fmaf(cy[u], cy[u], cx[u] * cx[u]));
-        // the expanded |d|^2 is within 7 ulps of (|mu| + |c|)^2 of the exact value
-        // and the difference form within 3 ulps of it; 12 ulps of the widened
-        // threshold keep every pair the exact test accepts inside the branch
-        const float ext = mu_max + sqrtf(cc[u]);
-        rn2w[u] = p.rn2 + 12.f * 5.9604645e-08f * ext * ext;
+        if constexpr (ELL) {
+            const float4 *b = reinterpret_cast<const float4 *>(centers + (size_t)kBodyFloats * jj);
+            const float4 b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3];
+            Q.cx[u] = b0.x, Q.cy[u] = b0.y, Q.cz[u] = b0.z;
+            Q.L[u][0] = b0.w, Q.L[u][1] = b1.x, Q.L[u][2] = b1.y, Q.L[u][3] = b1.z, Q.L[u][4] = b1.w;
+            Q.L[u][5] = b2.x, Q.L[u][6] = b2.y, Q.L[u][7] = b2.z, Q.L[u][8] = b2.w;
+            Q.qa[u] = b3.x, Q.qk[u] = b3.y;
+            Q.r2[u] = 1.f;
+            Q.kq[u] = p.kt;
+        } else {
+            Q.cx[u] = centers[3 * jj];
+            Q.cy[u] = centers[3 * jj + 1];
+            Q.cz[u] = centers[3 * jj + 2];
+            const float r = radii[jj];
+            Q.r2[u] = r * r;
+            Q.kq[u] = p.kt / Q.r2[u];  // t = max(0, r^2 s~^2) * kq = s~^2 * kt
+            Q.qa[u] = Q.r2[u];
+            Q.qk[u] = 1.f;
+        }
     }
     Acc<M, QPL> A;
 #pragma unroll
@@ -369,7 +406,7 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                     for (int i = 0; i < kGaussFloats * kUnroll; ++i) nxt[i] = np[i];
 #pragma unroll
                     for (int k = 0; k < kUnroll; ++k)
-                        pair_step<M, FULL, BALL, QPL>(rec + kGaussFloats * k, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+                        pair_step<M, FULL, BALL, QPL, ELL>(rec + kGaussFloats * k, Q, p, A);
 #pragma unroll
                     for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = nxt[i];
                 }
@@ -381,11 +418,11 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                 for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = gp[i];
 #pragma unroll
                 for (int k = 0; k < kUnroll; ++k)
-                    pair_step<M, FULL, BALL, QPL>(rec + kGaussFloats * k, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+                    pair_step<M, FULL, BALL, QPL, ELL>(rec + kGaussFloats * k, Q, p, A);
             }
         }
         for (; g < b1; ++g, gp += kGaussFloats)
-            pair_step<M, FULL, BALL, QPL>(gp, cx, cy, cz, r2, kq, cc, rn2w, p, A);
+            pair_step<M, FULL, BALL, QPL, ELL>(gp, Q, p, A);
     };
     int open = -1;  // piece holding the pending sums (wave-uniform)
     auto visit = [&](int i) {  // i-th chunk of the split
@@ -403,25 +440,38 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
     } else {
         // Chunks are visited in the same order as without culling, so every
         // sum keeps its order: skipping changes no bit.
-        float wx, wy, wz, spread, r2max;
-        wave_sphere<QPL>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
-        auto reach_of = [&](const ChunkMeta &m, float rr2) {  // reach of a chunk for r^2 = rr2
+        float wx, wy, wz, spread, qamax;
+        wave_sphere<QPL>(Q.cx, Q.cy, Q.cz, Q.qa, wx, wy, wz, spread, qamax);
+        float qkmax = 1.f;
+        if constexpr (ELL) {
+            qkmax = Q.qk[0];
+#pragma unroll
+            for (int u = 1; u < QPL; ++u) qkmax = fmaxf(qkmax, Q.qk[u]);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) qkmax = fmaxf(qkmax, __shfl_xor(qkmax, off));
+        }
+        // reach of a chunk for a body with constants (qa, qk): no pair farther
+        // than qk (n s + sqrt(n^2 s^2 + qa)) from the body's centre can collide
+        // (s: the chunk's largest scale); full outputs reduce over the ball
+        auto reach_of = [&](const ChunkMeta &m, float qa, float qk) {
             if constexpr (FULL) {
                 return p.r_nbr;
             } else {
                 const float ns = p.n_max * m.smax;
-                float reach = ns + sqrtf(fmaf(ns, ns, rr2));
+                float reach = ns + sqrtf(fmaf(ns, ns, qa));
+                if constexpr (ELL) reach *= qk;
                 if constexpr (BALL) reach = fminf(reach, p.r_nbr);
                 return reach;
             }
         };
         cull_walk(
             cull, n_chunks, split, S,
-            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m, r2max)); },
+            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m, qamax, qkmax)); },
             [&](const ChunkMeta &m) {
                 bool near = false;
 #pragma unroll
-                for (int u = 0; u < QPL; ++u) near |= within(m, cx[u], cy[u], cz[u], m.rad + reach_of(m, r2[u]));
+                for (int u = 0; u < QPL; ++u)
+                    near |= within(m, Q.cx[u], Q.cy[u], Q.cz[u], m.rad + reach_of(m, Q.qa[u], Q.qk[u]));
                 return near;
             },
             [&](int i) {
@@ -448,11 +498,11 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
     }
 }
 
-template <int M, bool FULL, bool BALL, int QPL, bool CULL>
+template <int M, bool FULL, bool BALL, int QPL, bool CULL, bool ELL>
 __global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY
 pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
             const float *__restrict__ centers, const float *__restrict__ radii, int q,
-            const EvalParams p, Part part, float mu_max, const float *__restrict__ cull,
+            const EvalParams p, Part part, const float *__restrict__ cull,
             unsigned long long *__restrict__ chunk_count)
 {
     int b = blockIdx.x;
@@ -461,7 +511,7 @@ pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
     const int split = b / n_tiles;
     const int tile = b - split * n_tiles;
     int done = 0;
-    eval_tile<M, FULL, BALL, QPL, CULL>(gs, n, S, split, tile, centers, radii, q, p, part, mu_max, cull,
+    eval_tile<M, FULL, BALL, QPL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
                                         &done);
     if (CULL && chunk_count && (threadIdx.x & 63) == 0) atomicAdd(chunk_count, (unsigned long long)done);
 }

@@ -10,10 +10,12 @@
 //    same Gaussian at the same time, so they are fetched with scalar loads
 //    into SGPRs and used directly as VALU operands (no LDS round trip, no
 //    VGPRs spent on them, no bank conflicts);
-//  * the Gaussian list is cut into `splits` contiguous ranges so that small
-//    query batches still fill the 256 CUs; blocks are mapped XCD-major so the
-//    blocks of one XCD share a range in their L2; partial reductions are
-//    merged in a fixed order by combine_kernel (bit-reproducible results).
+//  * the Gaussian chunks are dealt to S splits (split s takes every S-th
+//    chunk) so that small query batches still fill the 256 CUs and every work
+//    item gets an even share; partial reductions are merged in a fixed order
+//    by combine_kernel (bit-reproducible results).
+// Robot bodies are spheres (centre, radius) or ellipsoids (centre, orientation
+// quaternion, semi-axes; Eq. 5-6), prepared into records of kBodyFloats.
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
@@ -35,7 +37,7 @@ struct Launch {
     int q;
     EvalParams p;
     Part part;
-    float mu_max;
+    bool ell;
     const float *cull;
     unsigned long long *chunk_count;
     int S;
@@ -47,9 +49,12 @@ template <int M, bool FULL, bool BALL, bool CULL>
 void launch_pair(const Launch &L)
 {
     constexpr int QPL = FULL ? kQplFull : kQplLabels;
-    pair_kernel<M, FULL, BALL, QPL, CULL><<<L.grid, kBlock, 0, L.st>>>(L.gs, L.n, L.S, L.n_tiles, L.c, L.r,
-                                                                       L.q, L.p, L.part, L.mu_max, L.cull,
-                                                                       L.chunk_count);
+    if (L.ell)
+        pair_kernel<M, FULL, BALL, QPL, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
+            L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
+    else
+        pair_kernel<M, FULL, BALL, QPL, CULL, false><<<L.grid, kBlock, 0, L.st>>>(
+            L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
 }
 
 template <int M>
@@ -87,13 +92,13 @@ __device__ inline uint32_t spread3(uint32_t v)  // 10 bits -> every third bit
 }
 
 // Morton code of each query centre on the scene's quantisation grid.
-__global__ void query_code_kernel(int q, const float *__restrict__ c, float3 lo, float3 scale,
+__global__ void query_code_kernel(int q, const float *__restrict__ c, int stride, float3 lo, float3 scale,
                                   uint32_t *__restrict__ code, int32_t *__restrict__ idx)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= q) return;
-    const float fx = (c[3 * j] - lo.x) * scale.x, fy = (c[3 * j + 1] - lo.y) * scale.y,
-                fz = (c[3 * j + 2] - lo.z) * scale.z;
+    const float *cj = c + (size_t)stride * j;
+    const float fx = (cj[0] - lo.x) * scale.x, fy = (cj[1] - lo.y) * scale.y, fz = (cj[2] - lo.z) * scale.z;
     const uint32_t ix = (uint32_t)fminf(fmaxf(fx, 0.f), 1023.f), iy = (uint32_t)fminf(fmaxf(fy, 0.f), 1023.f),
                    iz = (uint32_t)fminf(fmaxf(fz, 0.f), 1023.f);
     code[j] = spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2);
@@ -112,18 +117,66 @@ __global__ void query_gather_kernel(int q, const int32_t *__restrict__ perm, con
     sr[j] = r[i];
 }
 
+// Ellipsoid records in sorted order: one float4 of a record per thread.
+__global__ void body_gather_kernel(int q, const int32_t *__restrict__ perm, const float4 *__restrict__ rec,
+                                   float4 *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)q * 4) return;
+    const int j = (int)(t >> 2), k = (int)(t & 3);
+    out[t] = rec[(size_t)perm[j] * 4 + k];
+}
+
+// Ellipsoid records (Eq. 5-6): centre, L = diag(1/a, 1/b, 1/c) R^T with R the
+// rotation of the normalised (w, x, y, z) quaternion, so that A = L^T L =
+// R diag(1/a^2, 1/b^2, 1/c^2) R^T; qa = (smallest semi-axis)^2 and qk =
+// largest / smallest semi-axis for the reach bound, both rounded up.
+// Computed in double, stored in float32.
+__global__ void body_prep_kernel(int q, const float *__restrict__ centers, const float *__restrict__ quats,
+                                 const float *__restrict__ axes, float *__restrict__ rec)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    double w = quats[4 * j], x = quats[4 * j + 1], y = quats[4 * j + 2], z = quats[4 * j + 3];
+    const double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+    w *= inv, x *= inv, y *= inv, z *= inv;
+    const double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                            {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                            {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    const double a[3] = {axes[3 * j], axes[3 * j + 1], axes[3 * j + 2]};
+    float *o = rec + (size_t)kBodyFloats * j;
+    o[0] = centers[3 * j];
+    o[1] = centers[3 * j + 1];
+    o[2] = centers[3 * j + 2];
+    for (int k = 0; k < 3; ++k)      // row k of L: column k of R over a_k
+        for (int c = 0; c < 3; ++c) o[3 + 3 * k + c] = (float)(R[c][k] / a[k]);
+    const double amin = fmin(a[0], fmin(a[1], a[2])), amax = fmax(a[0], fmax(a[1], a[2]));
+    o[12] = (float)(amin * amin * (1.0 + 1e-6));
+    o[13] = (float)(amax / amin * (1.0 + 1e-6));
+    o[14] = 0.f;
+    o[15] = 0.f;
+}
+
 }  // namespace
 
 csplat_status sort_queries(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *centers,
                            const float *radii, SortedQueries *out)
+{
+    return sort_bodies(ctx, sc, q, centers, radii, false, out);
+}
+
+csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *centers,
+                          const float *radii, bool ell, SortedQueries *out)
 {
     hipStream_t st = ctx->stream;
     size_t tbytes = 0;
     CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                   (int32_t *)nullptr, (int32_t *)nullptr, q, 0, 30, st));
     const size_t qn = (size_t)q;
-    const size_t off_code2 = qn * 4, off_idx = qn * 8, off_perm = qn * 12, off_c = qn * 16, off_r = qn * 28,
-                 off_cnt = (qn * 32 + 255) & ~(size_t)255, off_tmp = off_cnt + 256;
+    const size_t rec_bytes = ell ? qn * kBodyFloats * 4 : qn * 16;  // sorted records, or centres + radii
+    const size_t off_code2 = qn * 4, off_idx = qn * 8, off_perm = qn * 12, off_c = (qn * 16 + 255) & ~(size_t)255,
+                 off_r = off_c + qn * 12, off_cnt = (off_c + rec_bytes + 255) & ~(size_t)255,
+                 off_tmp = off_cnt + 256;
     hipError_t e = ctx->sortbuf.reserve(off_tmp + tbytes);
     if (e != hipSuccess) return hip_fail(e, "sort workspace");
     char *b = ctx->sortbuf.as<char>();
@@ -132,24 +185,37 @@ csplat_status sort_queries(csplat_ctx *ctx, const csplat_scene *sc, int q, const
     float *sc_c = reinterpret_cast<float *>(b + off_c), *sc_r = reinterpret_cast<float *>(b + off_r);
     auto *counter = reinterpret_cast<unsigned long long *>(b + off_cnt);
     const unsigned qb = (unsigned)((q + 255) / 256);
-    query_code_kernel<<<qb, 256, 0, st>>>(q, centers, make_float3(sc->box_lo[0], sc->box_lo[1], sc->box_lo[2]),
+    query_code_kernel<<<qb, 256, 0, st>>>(q, centers, ell ? kBodyFloats : 3,
+                                          make_float3(sc->box_lo[0], sc->box_lo[1], sc->box_lo[2]),
                                           make_float3(sc->box_scale[0], sc->box_scale[1], sc->box_scale[2]), code,
                                           idx);
     CSPLAT_HIP(hipGetLastError());
     CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(b + off_tmp, tbytes, code, code2, idx, perm, q, 0, 30, st));
-    query_gather_kernel<<<qb, 256, 0, st>>>(q, perm, centers, radii, sc_c, sc_r);
+    if (ell)
+        body_gather_kernel<<<(unsigned)((qn * 4 + 255) / 256), 256, 0, st>>>(
+            q, perm, reinterpret_cast<const float4 *>(centers), reinterpret_cast<float4 *>(sc_c));
+    else
+        query_gather_kernel<<<qb, 256, 0, st>>>(q, perm, centers, radii, sc_c, sc_r);
     CSPLAT_HIP(hipGetLastError());
     CSPLAT_HIP(zero_words(reinterpret_cast<int32_t *>(counter), 2, st));
     out->c = sc_c;
-    out->r = sc_r;
+    out->r = ell ? nullptr : sc_r;
     out->perm = perm;
     out->counter = counter;
     return CSPLAT_OK;
 }
 
+csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const float *quats, const float *axes,
+                             float *rec)
+{
+    body_prep_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, quats, axes, rec);
+    CSPLAT_HIP(hipGetLastError());
+    return CSPLAT_OK;
+}
+
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
                         const float *radii, const EvalParams &p, const EvalOut &out,
-                        bool labels_only)
+                        bool labels_only, bool ell)
 {
     const int q = (int)q64;
     const int n = (int)sc->n;
@@ -177,7 +243,7 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     L.q = q;
     L.p = p;
     L.part = part_views(ctx->partial.ptr, S, q, M, full);
-    L.mu_max = sc->mu_max;
+    L.ell = ell;
     L.S = sp.S;
     L.out = out;
     ctx->stats.splits = S;
@@ -188,7 +254,7 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
         // evaluate a copy of the queries sorted along the scene's Morton curve
         // (the lanes of a wave then hold nearby queries), scatter the outputs
         SortedQueries sq;
-        csplat_status s = sort_queries(ctx, sc, q, centers, radii, &sq);
+        csplat_status s = sort_bodies(ctx, sc, q, centers, radii, ell, &sq);
         if (s != CSPLAT_OK) return s;
         L.c = sq.c;
         L.r = sq.r;

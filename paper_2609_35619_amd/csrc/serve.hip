@@ -44,7 +44,6 @@ struct ReqDesc {
     const float *radii;
     int32_t n, per_split, S, q;
     int32_t full;
-    float mu_max;
     const float *cull;  // the scene's culling chunks
     EvalParams p;
     Part part;
@@ -83,7 +82,7 @@ __global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const cha
         const Item w = items[it];
         const ReqDesc &R = reqs[w.slot];
         eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.S, w.split, w.tile, R.centers, R.radii, R.q,
-                                            R.p, R.part, R.mu_max, R.cull, nullptr);
+                                            R.p, R.part, R.cull, nullptr);
     }
 }
 
@@ -202,7 +201,6 @@ void setup_request(csplat_server *s, int64_t t)
     d.S = r.sp.S;
     d.q = (int32_t)r.q;
     d.full = r.full ? 1 : 0;
-    d.mu_max = sc->mu_max;
     d.cull = sc->cull;
     d.p = r.p;
     d.part = part_views(dbase + r.d_part, r.sp.S, (int)r.q, 1, r.full);
