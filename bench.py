@@ -2,7 +2,9 @@
 
 One step = one evaluation of the whole hot path (query preparation, the
 float32 pair kernel with every per-query reduction for the m conservatism
-values, and the split combine) over the MPPI-shaped navigation workload:
+values, the split combine, and the per-rollout epilogue: any collision and
+summed cost over each rollout's 32 steps) over the MPPI-shaped navigation
+workload:
 1M Gaussians (room scene) x 32,768 robot spheres (1,024 rollouts x 32 steps,
 r = 0.2 m), n_sigma in {0, 1, 2}, neighbourhood ball 1 m, k = 2, tau = 0.1.
 Inputs are resident in HBM before the timed region.
@@ -81,10 +83,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-ellipsoids", action="store_true", help="skip the ellipsoidal-body workload")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full-size request law (MPPI K up to 4096 x 32 x 48; long)")
-    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "copy", "digest"), default="all",
+    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "ellipsoids", "copy", "digest"), default="all",
                     help="run one part only (for profiling); 'copy' is a plain 1 GiB device copy "
                          "used to calibrate the HBM traffic counters")
     args = ap.parse_args()
@@ -96,6 +99,7 @@ def main():
     if args.section != "all":
         args.no_precision = args.section not in ("precision",)
         args.no_serving = args.section not in ("serving",)
+        args.no_ellipsoids = args.section not in ("ellipsoids",)
         args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -121,16 +125,28 @@ def main():
     c = torch.from_numpy(qs.centers).to(f"cuda:{dev}")
     r = torch.from_numpy(qs.radii).to(f"cuda:{dev}")
     out = eng.alloc_outputs(qs.q)
+    # planner epilogue of the step: per rollout (32 steps x 1 sphere), any
+    # collision and the summed cost (Sec. II-D Eq. 11, Sec. II-E)
+    n_roll = qs.q // 32
+    seg_any = torch.empty((n_roll, m), dtype=torch.uint8, device=f"cuda:{dev}")
+    seg_cost = torch.empty((n_roll, m), dtype=torch.float32, device=f"cuda:{dev}")
     torch.cuda.synchronize()
+
+    def epilogue():
+        cs.csplat_segment_reduce(eng.ctx, n_roll, label=out["label"], cost=out["cost"], seg_any=seg_any,
+                                 seg_cost=seg_cost)
+
     log(f"bench: {n_kept} kept Gaussians, {qs.q} queries, m={m}; warmup {args.warmup}")
     for _ in range(args.warmup):
         eng.evaluate(h, c, r, opts, out=out)
+        epilogue()
     torch.cuda.synchronize()
 
     # timed region: K steps bracketed by synchronisations
     t0 = time.perf_counter()
     for _ in range(args.steps):
         eng.evaluate(h, c, r, opts, out=out)
+        epilogue()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
@@ -143,6 +159,7 @@ def main():
         s0 = time.perf_counter()
         eng.evaluate(h, c, r, opts, out=out)
         st = cs.csplat_last_stats(eng.ctx)
+        epilogue()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - s0)
         kms.append(st["kernel_ms"])
@@ -187,6 +204,7 @@ def main():
                    "n_gaussians": int(sc.n), "n_kept": int(n_kept), "queries": int(qs.q), "m": m,
                    "global_batch": int(qs.q), "parallelism": "single GPU"},
         "queries_per_s": qs.q / step_s,
+        "rollout_epilogue": {"rollouts": n_roll, "in_collision_per_n_sigma": seg_any.sum(0).tolist()},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "mean": float(np.mean(lat) * 1e3), "std": float(np.std(lat) * 1e3)},
         "host_arrays": {"ms_per_step_median": float(np.median(host_t) * 1e3),
@@ -204,6 +222,8 @@ def main():
         res["cpu_baseline"], res["label_accuracy"] = cpu_baseline(sc, qs, p, gpu, args.cpu_seconds, n_kept)
     if not args.no_precision:
         res["precision_form"] = precision_form(cs, eng)
+    if not args.no_ellipsoids:
+        res["ellipsoids"] = ellipsoids(cs, eng, args.steps)
     if not args.no_serving:
         res["serving"] = serving(cs, eng, sc, h, args.serving_requests, args.serving_full)
     cs.csplat_scene_free(h)
@@ -234,6 +254,54 @@ def _time_eval(eng, h, c, r, opts, want, reps=3):
         eng.evaluate(h, c, r, opts, out=out)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+OPS_ELL_SHARED = 38   # L d (9), s^2 (3), L^T e (9), M h (9), W (3), sqrt (4), ball count (1)
+
+
+def ellipsoids(cs, eng, steps):
+    """Ellipsoidal links: the tabletop scene (500k Gaussians) against 256
+    configurations x 32 steps x 7 chain links as ellipsoids, all outputs,
+    n_sigma = 1, neighbourhood ball 0.4 m."""
+    import torch
+    from workloads import config
+    log("bench: ellipsoidal links (500k Gaussians x 57,344 link ellipsoids)")
+    sc, b, p = config("manip_ell")
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
+    n_kept, _ = cs.csplat_scene_info(h)
+    eng.set_conservatism(p["n_sigma"])
+    m = len(p["n_sigma"])
+    opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"],
+                          s_min=p["s_min"])
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (b.centers, b.quats, b.axes)]
+    out = eng.alloc_outputs(b.q)
+    for _ in range(2):
+        eng.evaluate_ellipsoids(h, *t, opts, out=out)
+    torch.cuda.synchronize()
+    reps = max(5, steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        eng.evaluate_ellipsoids(h, *t, opts, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    cs.csplat_ctx_set_timing(eng.ctx, True)
+    kms = []
+    for _ in range(3):
+        eng.evaluate_ellipsoids(h, *t, opts, out=out)
+        st = cs.csplat_last_stats(eng.ctx)
+        kms.append(st["kernel_ms"])
+    cs.csplat_ctx_set_timing(eng.ctx, False)
+    nbr = int(out["nbr"].cpu().numpy().astype(np.int64).sum())
+    cs.csplat_scene_free(h)
+    ops = OPS_ALL_PAIRS * int(st["kernel_pairs"]) + (OPS_ELL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr
+    kernel_s = float(np.mean(kms)) / 1e3
+    return {"workload": "manip_ell: 500k-Gaussian tabletop, 256 configurations x 32 steps x 7 link ellipsoids "
+                        "(semi-axes r, r, L/2 + r), n_sigma 1, ball 0.4 m, all outputs",
+            "n_kept": int(n_kept), "bodies": int(b.q), "ms_per_step": dt * 1e3,
+            "pair_evals_per_s": b.q * n_kept / dt, "queries_per_s": b.q / dt,
+            "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e9, "peak": PEAK_VALU / 1e9,
+                         "unit": "Gop/s", "frac": ops / kernel_s / PEAK_VALU, "kernel_ms": kernel_s * 1e3,
+                         "evaluated_pairs": int(st["kernel_pairs"]), "in_ball_pairs": nbr}}
 
 
 def precision_form(cs, eng):

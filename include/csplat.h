@@ -175,6 +175,26 @@ csplat_status csplat_eval_ellipsoids(csplat_ctx *ctx, const csplat_scene *scene,
                                      const float *centers, const float *quats, const float *axes,
                                      const csplat_reduce_opts *opts, const csplat_outputs *out);
 
+/* Planner epilogues: reductions of per-query outputs over segments of
+ * consecutive queries -- the links of a robot state or the points x links of
+ * an RRT edge ("in collision if any link ...", Sec. II-E), the steps x links
+ * of an MPPI rollout (the rollout's collision cost sums the per-body costs
+ * over links and horizon, Sec. II-D, Eq. 11).  Segment s covers queries
+ * [offsets[s], offsets[s+1]) (n_seg + 1 values rising from 0 to q); with
+ * offsets NULL every segment has q / n_seg queries (q a multiple of n_seg).
+ *   label (q x m) -> seg_any (n_seg x m): 1 iff some query of the segment has
+ *                    label 1, else 0 (an empty segment gives 0);
+ *   cost  (q x m) -> seg_cost (n_seg x m): the sum over the segment, in a
+ *                    fixed order (bit-reproducible; 0 for an empty segment).
+ * Either output may be NULL (not both); an output needs its input.  All
+ * pointers host or all device, as for csplat_eval (device: asynchronous on
+ * the context stream; device offsets are checked by a kernel and one stream
+ * synchronisation first).  Errors: CSPLAT_E_INVALID (bad sizes or offsets,
+ * mixed pointer kinds); nothing is written on error. */
+csplat_status csplat_segment_reduce(csplat_ctx *ctx, int64_t q, int32_t m, int64_t n_seg,
+                                    const int64_t *offsets, const uint8_t *label, const float *cost,
+                                    uint8_t *seg_any, float *seg_cost);
+
 /* Timing mode (off by default): when on, every evaluation records HIP events
  * around its dominant kernel and csplat_last_stats waits for the second one. */
 csplat_status csplat_ctx_set_timing(csplat_ctx *ctx, int32_t enable);

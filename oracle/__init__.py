@@ -161,6 +161,35 @@ def evaluate(mu, sigma, centers, A, n_sigma, k=0, tau=0.0, r_nbr=math.inf, d_max
     return out
 
 
+def segment_reduce(label=None, cost=None, offsets=None, n_seg=None):
+    """Planner epilogues over segments of consecutive queries: an RRT state or
+    edge is in collision when any of its bodies is (Sec. II-E); an MPPI
+    rollout's collision cost sums its per-body costs over links and horizon
+    (Sec. II-D, Eq. 11).  Segment s is queries offsets[s]:offsets[s+1]
+    (offsets None: n_seg equal segments).  Returns (seg_any uint8 (n_seg, m),
+    seg_sum float64 (n_seg, m)), exactly rounded sums (math.fsum)."""
+    src = label if label is not None else cost
+    q, m = np.asarray(src).shape
+    if offsets is None:
+        if n_seg is None or (n_seg > 0 and q % n_seg) or (n_seg == 0 and q):
+            raise OracleError("equal segments need q to be a multiple of n_seg")
+        offsets = np.arange(n_seg + 1, dtype=np.int64) * (q // n_seg if n_seg else 0)
+    offsets = np.asarray(offsets, np.int64)
+    if offsets[0] != 0 or offsets[-1] != q or np.any(np.diff(offsets) < 0):
+        raise OracleError("offsets must rise from 0 to q")
+    ns = offsets.size - 1
+    seg_any = np.zeros((ns, m), np.uint8)
+    seg_sum = np.zeros((ns, m), np.float64)
+    for s_ in range(ns):
+        a, b = int(offsets[s_]), int(offsets[s_ + 1])
+        for v in range(m):
+            if label is not None:
+                seg_any[s_, v] = 1 if any(int(x) != 0 for x in np.asarray(label)[a:b, v]) else 0
+            if cost is not None:
+                seg_sum[s_, v] = math.fsum(float(x) for x in np.asarray(cost)[a:b, v])
+    return seg_any, seg_sum
+
+
 def evaluate_ellipsoids(scene, bodies, n_sigma, raw_mode=False, alpha_f=0.0, extent_f=0.0, **reduce):
     """Convenience: float32 scene against ellipsoidal bodies (centre, (w,x,y,z)
     quaternion of the body frame, semi-axes along its local x, y, z), with

@@ -43,7 +43,7 @@ CSPLAT_FEATURES_FP16 = 2
 EXPORTS = (
     "csplat_ctx_create", "csplat_ctx_destroy", "csplat_scene_load", "csplat_scene_info",
     "csplat_scene_free", "csplat_set_conservatism", "csplat_eval", "csplat_eval_labels",
-    "csplat_eval_distance", "csplat_eval_ellipsoids", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
+    "csplat_eval_distance", "csplat_eval_ellipsoids", "csplat_segment_reduce", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
     "csplat_last_error", "csplat_server_create", "csplat_server_destroy", "csplat_server_add_scene",
     "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
     "csplat_server_stats",
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH):
         "csplat_eval_labels": [P, P, I64, P, P, P, P, P],
         "csplat_eval_distance": [P, P, I64, P, P, P, P, P, P],
         "csplat_eval_ellipsoids": [P, P, I64, P, P, P, P, P],
+        "csplat_segment_reduce": [P, I64, I32, I64, P, P, P, P, P],
         "csplat_ctx_set_timing": [P, I32],
         "csplat_last_stats": [P, P],
         "csplat_synchronize": [P],
@@ -240,6 +241,15 @@ def csplat_eval_ellipsoids(ctx, scene, centers, quats, axes, opts: ReduceOpts, l
     o = Outputs(*[_addr(x) for x in (label, count, min, softmin, cost, nbr)])
     _check(load_library().csplat_eval_ellipsoids(ctx, scene, q, _addr(centers), _addr(quats), _addr(axes),
                                                  ctypes.byref(opts), ctypes.byref(o)))
+
+
+def csplat_segment_reduce(ctx, n_seg, label=None, cost=None, seg_any=None, seg_cost=None, offsets=None):
+    """Segment OR of labels and segment sums of costs (arrays of shape (q, m);
+    outputs (n_seg, m)); offsets (n_seg + 1, int64) or None for equal segments."""
+    src = label if label is not None else cost
+    q, m = int(src.shape[0]), int(src.shape[1])
+    _check(load_library().csplat_segment_reduce(ctx, q, m, int(n_seg), _addr(offsets), _addr(label), _addr(cost),
+                                                _addr(seg_any), _addr(seg_cost)))
 
 
 def csplat_ctx_set_timing(ctx, enable: bool):

@@ -547,3 +547,39 @@ def test_ball_band_brackets_ball(oracle_mod):
     assert np.array_equal(out["nbr"], (d2 <= 0.09).sum(1))
     assert np.array_equal(out["nbr_lo"], (d2 <= 0.09 * (1 - 1e-2)).sum(1))
     assert np.array_equal(out["nbr_hi"], (d2 <= 0.09 * (1 + 1e-2)).sum(1))
+
+
+# --- Planner epilogues (Sec. II-D Eq. 11, Sec. II-E) ---------------------------
+
+def test_segment_reduce_against_membership_matrix(oracle_mod):
+    """Segment OR and sums equal a 0/1 membership matrix applied with a matrix
+    product (a library routine), including empty segments."""
+    rng = np.random.default_rng(90)
+    q, m = 300, 3
+    cuts = np.sort(rng.integers(0, q + 1, 40))
+    offsets = np.concatenate([[0], cuts, [q]]).astype(np.int64)
+    label = (rng.uniform(size=(q, m)) < 0.05).astype(np.uint8)
+    cost = rng.uniform(0, 1, (q, m)).astype(np.float32)
+    seg_any, seg_sum = oracle_mod.segment_reduce(label, cost, offsets)
+    S = np.zeros((offsets.size - 1, q))
+    for s_ in range(offsets.size - 1):
+        S[s_, offsets[s_]:offsets[s_ + 1]] = 1.0
+    assert np.array_equal(seg_any, (S @ label.astype(np.float64) > 0).astype(np.uint8))
+    assert np.allclose(seg_sum, S @ cost.astype(np.float64), rtol=1e-14, atol=0)
+    # invariants: the segment sums add up to the total; empty segments give 0 and no collision
+    assert math.isclose(seg_sum.sum(), cost.astype(np.float64).sum(), rel_tol=1e-13)
+    empty = np.diff(offsets) == 0
+    assert np.all(seg_sum[empty] == 0) and np.all(seg_any[empty] == 0)
+
+
+def test_segment_reduce_equal_segments_and_errors(oracle_mod):
+    rng = np.random.default_rng(91)
+    cost = rng.uniform(size=(64, 2))
+    a, s1 = oracle_mod.segment_reduce(cost=cost, n_seg=64)       # one query per segment: identity
+    assert np.array_equal(s1, cost)
+    _, s8 = oracle_mod.segment_reduce(cost=cost, n_seg=8)
+    assert np.allclose(s8, cost.reshape(8, 8, 2).sum(1), rtol=1e-14)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.segment_reduce(cost=cost, n_seg=7)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.segment_reduce(cost=cost, offsets=[0, 40, 30, 64])
