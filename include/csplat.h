@@ -134,6 +134,26 @@ csplat_status csplat_scene_load(csplat_ctx *ctx, int64_t n, const float *means,
                                 const float *quats, const float *scales,
                                 const float *opacity, const csplat_scene_opts *opts,
                                 csplat_scene **out);
+/* Scene files (Sec. II-A): the binary little-endian PLY layout written by the
+ * 3DGS and 2DGS trainers.  Per vertex: x, y, z, opacity (logit), scale_0,
+ * scale_1 and, for 3DGS, scale_2 (log; 2DGS files have two scales: the third
+ * axis is flat, scale 0), rot_0..rot_3 ((w, x, y, z)); every other vertex
+ * property (normals, spherical-harmonic colours) is skipped, as are other
+ * elements after the vertices.  Property types: any PLY scalar type.
+ *
+ * csplat_ply_read parses the file on the host into activated parameters
+ * (linear scales exp(s), opacity sigmoid(o), computed in double; quaternions
+ * as stored): with capacity 0 it only sets *n; otherwise the arrays (n x 3,
+ * n x 4, n x 3, n, caller-owned) must hold capacity >= n Gaussians.  No GPU
+ * is needed.  csplat_scene_load_ply reads the file and loads it as
+ * csplat_scene_load would (opts as there; param_mode is ignored).
+ * Errors: CSPLAT_E_INVALID (cannot open, not binary little-endian PLY, a
+ * missing property, list properties in the vertex element, truncated data,
+ * capacity below n), then those of csplat_scene_load. */
+csplat_status csplat_ply_read(const char *path, int64_t capacity, int64_t *n, float *means,
+                              float *quats, float *scales, float *opacity);
+csplat_status csplat_scene_load_ply(csplat_ctx *ctx, const char *path,
+                                    const csplat_scene_opts *opts, csplat_scene **out);
 /* Kept Gaussians and device bytes held by the scene (the VRAM figure). */
 csplat_status csplat_scene_info(const csplat_scene *scene, int64_t *n_kept,
                                 uint64_t *device_bytes);

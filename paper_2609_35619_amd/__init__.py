@@ -43,7 +43,7 @@ CSPLAT_FEATURES_FP16 = 2
 EXPORTS = (
     "csplat_ctx_create", "csplat_ctx_destroy", "csplat_scene_load", "csplat_scene_info",
     "csplat_scene_free", "csplat_set_conservatism", "csplat_eval", "csplat_eval_labels",
-    "csplat_eval_distance", "csplat_eval_ellipsoids", "csplat_segment_reduce", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
+    "csplat_eval_distance", "csplat_eval_ellipsoids", "csplat_ply_read", "csplat_scene_load_ply", "csplat_segment_reduce", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
     "csplat_last_error", "csplat_server_create", "csplat_server_destroy", "csplat_server_add_scene",
     "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
     "csplat_server_stats",
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH):
         "csplat_ctx_create": [I32, P, P],
         "csplat_ctx_destroy": [P],
         "csplat_scene_load": [P, I64, P, P, P, P, P, P],
+        "csplat_ply_read": [ctypes.c_char_p, I64, P, P, P, P, P],
+        "csplat_scene_load_ply": [P, ctypes.c_char_p, P, P],
         "csplat_scene_info": [P, P, P],
         "csplat_scene_free": [P],
         "csplat_set_conservatism": [P, P, I32],
@@ -185,6 +187,27 @@ def csplat_scene_load(ctx, means, quats, scales, opacity, param_mode=CSPLAT_PARA
     out = ctypes.c_void_p()
     _check(lib.csplat_scene_load(ctx, n, *[_addr(a) if n else None for a in arrs], ctypes.byref(opts),
                                  ctypes.byref(out)))
+    return out
+
+
+def csplat_ply_read(path):
+    """Parse a 3DGS/2DGS PLY file on the host: (means, quats, scales, opacity),
+    activated (linear scales, opacity in [0, 1])."""
+    lib = load_library()
+    n = ctypes.c_int64()
+    p = os.fsencode(path)
+    _check(lib.csplat_ply_read(p, 0, ctypes.byref(n), None, None, None, None))
+    k = n.value
+    arrs = [np.empty((k, 3), np.float32), np.empty((k, 4), np.float32), np.empty((k, 3), np.float32),
+            np.empty(k, np.float32)]
+    _check(lib.csplat_ply_read(p, k, ctypes.byref(n), *[_addr(a) for a in arrs]))
+    return tuple(arrs)
+
+
+def csplat_scene_load_ply(ctx, path, floater_opacity_max=0.0, floater_extent_min=0.0, precision_features=0):
+    opts = SceneOpts(CSPLAT_PARAM_ACTIVATED, floater_opacity_max, floater_extent_min, precision_features)
+    out = ctypes.c_void_p()
+    _check(load_library().csplat_scene_load_ply(ctx, os.fsencode(path), ctypes.byref(opts), ctypes.byref(out)))
     return out
 
 
