@@ -85,7 +85,7 @@ typedef struct {
     float gamma;           /* Eq. 11, >= 0 */
     float s_min;           /* Eq. 11, the paper uses 1 */
     int32_t precision;     /* CSPLAT_PRECISION_*; the MFMA forms compute labels/counts */
-    int32_t cull;          /* 1: sort the queries along a Morton curve and skip chunks of 64
+    int32_t cull;          /* 1: sort the queries along a Hilbert curve and skip chunks of 64
                               Gaussians that provably lie outside every query's neighbourhood
                               ball (or, for labels, beyond the reach bound
                               n s_max + sqrt(n^2 s_max^2 + r^2) of Eq. 8); the results are the
@@ -126,7 +126,7 @@ csplat_status csplat_ctx_destroy(csplat_ctx *ctx);
  * opacity (n).  Host pointers only; the inputs are copied and may be freed
  * after return.  On the device the parameters are validated and activated,
  * the floater filter applied, Sigma_i factored as M_i = diag(s_i) R_i^T and
- * the survivors sorted along a Morton curve.  n = 0 is allowed.
+ * the survivors sorted along a Hilbert curve.  n = 0 is allowed.
  * Errors: CSPLAT_E_INVALID (n < 0, NULL pointer with n > 0, a non-finite
  * value, a zero quaternion, a negative linear scale), CSPLAT_E_OOM,
  * CSPLAT_E_DEVICE.  opts may be NULL (activated, no filter, no features). */

@@ -16,6 +16,41 @@ namespace csplat {
 // -2 mu and |mu|^2 complete the record to 16 floats (the expanded form
 // |mu|^2 - 2 mu.c + |c|^2 of |d|^2; unused by the current kernels).
 constexpr int kGaussFloats = 16;  // mx my mz | M00..M22 (row-major) | -2mx -2my -2mz | |mu|^2
+// Position of an integer cell (10 bits per axis) along a 3-D Hilbert curve
+// (30-bit key), by Skilling's transform of the axes to the transposed index
+// ("Programming the Hilbert curve", 2004) followed by bit interleaving.
+// Consecutive keys are face-adjacent cells, so runs of the sorted order are
+// compact in space (the culling chunks of the scene, the query groups of a
+// wave).
+__host__ __device__ inline uint32_t hilbert_key(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint32_t X[3] = {x & 1023u, y & 1023u, z & 1023u};
+    for (uint32_t Q = 512u; Q > 1u; Q >>= 1) {
+        const uint32_t P = Q - 1u;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;  // invert
+            } else {       // exchange the low bits of X[0] and X[i]
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];  // Gray encode
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = 512u; Q > 1u; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1u;
+    X[0] ^= t;
+    X[1] ^= t;
+    X[2] ^= t;
+    uint32_t key = 0;
+    for (int b = 9; b >= 0; --b)
+        key = (key << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) | ((X[2] >> b) & 1u);
+    return key;
+}
+
 // Prepared ellipsoidal body: centre (3), L = diag(1/a) R^T row-major (9), the
 // reach constants qa = (smallest semi-axis)^2 and qk = largest / smallest, 0, 0.
 constexpr int kBodyFloats = 16;
@@ -60,10 +95,10 @@ struct csplat_scene {
     int device = 0;
     int64_t n_input = 0;
     int64_t n = 0;            // kept Gaussians
-    float *gauss = nullptr;   // n x 16 float32 records, Morton order
+    float *gauss = nullptr;   // n x 16 float32 records, Hilbert order of the means
     float mu_max = 0.f;       // max |mu| over the kept Gaussians
     float *cull = nullptr;    // per chunk of 64: bounding sphere centre, radius, largest scale
-    float box_lo[3] = {0, 0, 0}, box_scale[3] = {0, 0, 0};  // Morton quantisation of the kept means
+    float box_lo[3] = {0, 0, 0}, box_scale[3] = {0, 0, 0};  // grid of the kept means (one cell size)
     // precision form (optional): per tile of 512 Gaussians the packed MFMA
     // operands (96 B per Gaussian) and 20 floats of metadata (origin, scale,
     // coefficient maxima), one set per dtype
@@ -163,7 +198,7 @@ csplat_status build_params(const float *n_sigma, int m, const csplat_reduce_opts
 // 1 if p is a device (or managed) pointer, 0 for host memory.
 int pointer_kind(const void *p);
 
-// A copy of q query spheres sorted along the scene's Morton curve, with the
+// A copy of q query spheres sorted along the scene's Hilbert curve, with the
 // permutation (sorted index -> caller index) and a zeroed 64-bit counter,
 // all in the context's sort workspace (valid until the next evaluation).
 struct SortedQueries {

@@ -23,7 +23,7 @@ namespace pair {
 
 constexpr int kBlock = 256;
 constexpr int kChunk = 512;  // Gaussians per first-level softmin/cost sum
-constexpr int kCull = 64;    // Gaussians per culling chunk (Morton-consecutive)
+constexpr int kCull = 64;    // Gaussians per culling chunk (consecutive on the curve)
 constexpr int kPiece = kChunk / kCull;  // culling chunks per first-level sum
 constexpr int kCullFloats = 8;  // per chunk: centre (3), radius, largest scale, 0 0 0
 // relative widening of the culling thresholds: far above float32 rounding, so
@@ -189,7 +189,7 @@ __device__ __forceinline__ void pair_step(const float *__restrict__ gp, const QS
     }
 }
 
-// Culling metadata of one chunk of kCull Morton-consecutive Gaussians: the
+// Culling metadata of one chunk of kCull Gaussians consecutive on the curve: the
 // centre of their bounding box, the largest distance of a mean from it and the
 // largest scale (all rounded up at load time).
 struct ChunkMeta {
@@ -294,7 +294,7 @@ __device__ __forceinline__ void cull_walk(const float *__restrict__ cull, int n_
 // Gaussian range of `split`, written to the split's partial records.  Shared
 // by the evaluation kernel and the serving step kernel, so a request gives
 // the same bits in either.
-// With CULL, Gaussians are visited in chunks of kCull (Morton-consecutive,
+// With CULL, Gaussians are visited in chunks of kCull (consecutive on the curve,
 // with a bounding sphere and largest scale per chunk); a wave skips a chunk
 // when it provably lies outside the neighbourhood ball of every query the
 // wave holds (FULL), or beyond the reach bound n s + sqrt(n^2 s^2 + r^2) of
@@ -349,7 +349,7 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
         }
     }
 
-    // The Gaussians are visited in chunks of kCull (Morton-consecutive); split
+    // The Gaussians are visited in chunks of kCull (consecutive on the curve); split
     // `split` of S takes chunks split, split + S, split + 2S, ... so that every
     // split samples the whole scene and the work of a query tile is spread
     // evenly over its S work items.  The softmin and cost sums are accumulated

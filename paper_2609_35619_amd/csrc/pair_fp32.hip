@@ -81,17 +81,7 @@ void launch_m(csplat_ctx *ctx, bool full, bool ball, bool cull, const Launch &L)
     else combine_kernel<M, false><<<cb, 256, 0, L.st>>>(L.q, L.S, L.p, L.part, L.out, L.perm);
 }
 
-__device__ inline uint32_t spread3(uint32_t v)  // 10 bits -> every third bit
-{
-    v &= 0x3FF;
-    v = (v | (v << 16)) & 0x030000FF;
-    v = (v | (v << 8)) & 0x0300F00F;
-    v = (v | (v << 4)) & 0x030C30C3;
-    v = (v | (v << 2)) & 0x09249249;
-    return v;
-}
-
-// Morton code of each query centre on the scene's quantisation grid.
+// Hilbert key of each query centre on the scene's grid (the scene's curve).
 __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride, float3 lo, float3 scale,
                                   uint32_t *__restrict__ code, int32_t *__restrict__ idx)
 {
@@ -101,7 +91,7 @@ __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride
     const float fx = (cj[0] - lo.x) * scale.x, fy = (cj[1] - lo.y) * scale.y, fz = (cj[2] - lo.z) * scale.z;
     const uint32_t ix = (uint32_t)fminf(fmaxf(fx, 0.f), 1023.f), iy = (uint32_t)fminf(fmaxf(fy, 0.f), 1023.f),
                    iz = (uint32_t)fminf(fmaxf(fz, 0.f), 1023.f);
-    code[j] = spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2);
+    code[j] = hilbert_key(ix, iy, iz);
     idx[j] = j;
 }
 
@@ -251,7 +241,7 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     ctx->stats.kernel_pairs = (int64_t)q * n;
     ctx->chunk_counter = nullptr;
     if (cull) {
-        // evaluate a copy of the queries sorted along the scene's Morton curve
+        // evaluate a copy of the queries sorted along the scene's Hilbert curve
         // (the lanes of a wave then hold nearby queries), scatter the outputs
         SortedQueries sq;
         csplat_status s = sort_bodies(ctx, sc, q, centers, radii, ell, &sq);
