@@ -391,7 +391,12 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
     // loads; with kPipeline the next group's records are requested before the
     // current group is evaluated, so their latency overlaps the arithmetic
     auto run = [&](int b0, int b1) {
-        const float *gp = gs + (size_t)kGaussFloats * b0;
+        // the scene records are read-only during every kernel that calls this:
+        // reading them through the constant address space makes the
+        // wave-uniform loads scalar whatever else the kernel writes
+        using CFloat = const __attribute__((address_space(4))) float;
+        const CFloat *gp = reinterpret_cast<const CFloat *>(reinterpret_cast<uintptr_t>(gs)) +
+                           (size_t)kGaussFloats * b0;
         int g = b0;
         if constexpr (kPipeline) {
             if (g + kUnroll <= b1) {
@@ -400,7 +405,7 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                 for (int i = 0; i < kGaussFloats * kUnroll; ++i) rec[i] = gp[i];
                 for (; g + kUnroll <= b1; g += kUnroll, gp += kGaussFloats * kUnroll) {
                     // the last group re-reads itself: always an in-range address
-                    const float *np = g + 2 * kUnroll <= b1 ? gp + kGaussFloats * kUnroll : gp;
+                    const CFloat *np = g + 2 * kUnroll <= b1 ? gp + kGaussFloats * kUnroll : gp;
                     float nxt[kGaussFloats * kUnroll];
 #pragma unroll
                     for (int i = 0; i < kGaussFloats * kUnroll; ++i) nxt[i] = np[i];
@@ -421,8 +426,12 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                     pair_step<M, FULL, BALL, QPL, ELL>(rec + kGaussFloats * k, Q, p, A);
             }
         }
-        for (; g < b1; ++g, gp += kGaussFloats)
-            pair_step<M, FULL, BALL, QPL, ELL>(gp, Q, p, A);
+        for (; g < b1; ++g, gp += kGaussFloats) {
+            float rec[kGaussFloats];
+#pragma unroll
+            for (int i = 0; i < kGaussFloats; ++i) rec[i] = gp[i];
+            pair_step<M, FULL, BALL, QPL, ELL>(rec, Q, p, A);
+        }
     };
     int open = -1;  // piece holding the pending sums (wave-uniform)
     auto visit = [&](int i) {  // i-th chunk of the split

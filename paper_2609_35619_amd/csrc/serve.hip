@@ -54,6 +54,7 @@ struct StepHeader {
     int32_t begin[kVariants + 1];  // item range of each variant
     int32_t n_done;
     int32_t done[kMaxSlots];
+    int32_t next[kVariants];       // work counters of the step kernels (zero in the staged copy)
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -69,20 +70,33 @@ struct StageLayout {
 };
 
 template <bool FULL, bool BALL>
-__global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const char *__restrict__ stage, int variant, size_t desc_off,
-                                                      size_t items_off)
+__global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const char *__restrict__ stage, int variant,
+                                                                          size_t desc_off, size_t items_off,
+                                                                          int32_t *__restrict__ next)
 {
+    // the staged step is read-only here (scalar loads); the work counter is
+    // the header's next[variant], written only through `next`
     const StepHeader *h = reinterpret_cast<const StepHeader *>(stage);
     const ReqDesc *reqs = reinterpret_cast<const ReqDesc *>(stage + desc_off);
     const Item *items = reinterpret_cast<const Item *>(stage + items_off);
-    const int b1 = h->begin[variant + 1];
+    const int b0 = h->begin[variant], b1 = h->begin[variant + 1];
     constexpr int QPL = FULL ? kQplFull : kQplLabels;
     constexpr bool CULL = !FULL || BALL;  // same bits as without culling
-    for (int it = h->begin[variant] + (int)blockIdx.x; it < b1; it += (int)gridDim.x) {
+    // blocks take the variant's items in order from a shared counter, so a
+    // block that drew cheap items goes on to the next one (items differ
+    // widely in cost once culled)
+    __shared__ int s_it;
+    for (;;) {
+        if (threadIdx.x == 0) s_it = b0 + atomicAdd(next, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_it);
+        __syncthreads();
+        if (it >= b1) break;
         const Item w = items[it];
-        const ReqDesc &R = reqs[w.slot];
-        eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.S, w.split, w.tile, R.centers, R.radii, R.q,
-                                            R.p, R.part, R.cull, nullptr);
+        const ReqDesc &R = reqs[__builtin_amdgcn_readfirstlane(w.slot)];
+        eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.S, __builtin_amdgcn_readfirstlane(w.split),
+                                            __builtin_amdgcn_readfirstlane(w.tile), R.centers, R.radii, R.q, R.p,
+                                            R.part, R.cull, nullptr);
     }
 }
 
@@ -108,7 +122,8 @@ double now_s()
 struct Rec {
     int32_t scene = 0, kind = 0;
     int64_t q = 0;
-    std::vector<float> centers, radii;  // until admission
+    std::vector<float> centers, radii;  // until admission, in curve order
+    std::vector<int32_t> perm;          // curve position -> the caller's query index
     EvalParams p{};
     SplitPlan sp{};
     bool full = false, ball = false;
@@ -313,12 +328,13 @@ csplat_status capture_graphs(csplat_server *s)
         hipError_t e = hipMemcpyAsync(s->stage_dev[k], s->stage_host[k], s->layout.bytes, hipMemcpyHostToDevice,
                                       s->stream);
         const char *st = s->stage_dev[k];
+        int32_t *ctr = reinterpret_cast<StepHeader *>(s->stage_dev[k])->next;
         const size_t dof = s->layout.desc, iof = s->layout.items;
         if (e == hipSuccess) {
-            step_kernel<false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 0, dof, iof);
-            step_kernel<false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 1, dof, iof);
-            step_kernel<true, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 2, dof, iof);
-            step_kernel<true, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 3, dof, iof);
+            step_kernel<false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 0, dof, iof, ctr + 0);
+            step_kernel<false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 1, dof, iof, ctr + 1);
+            step_kernel<true, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 2, dof, iof, ctr + 2);
+            step_kernel<true, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 3, dof, iof, ctr + 3);
             serve_combine_kernel<<<1024, 256, 0, s->stream>>>(st, dof);
             e = hipGetLastError();
         }
@@ -469,8 +485,30 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     r.ball = std::isfinite(r.p.rn2);
     r.sp = split_plan(target_blocks(s->device), (int)q, (int)sc->n, r.full);
     r.pairs = q * sc->n;
-    r.centers.assign(centers, centers + 3 * q);
-    r.radii.assign(radii, radii + q);
+    // the queries in the scene's Hilbert order (as csplat_eval evaluates
+    // them): waves hold nearby spheres and the culling skips more; results
+    // go back to the caller's order when collected
+    {
+        std::vector<std::pair<uint32_t, int32_t>> key((size_t)q);
+        for (int64_t j = 0; j < q; ++j) {
+            uint32_t ix[3];
+            for (int k = 0; k < 3; ++k) {
+                const float f = (centers[3 * j + k] - sc->box_lo[k]) * sc->box_scale[k];
+                ix[k] = (uint32_t)std::min(std::max(f, 0.f), 1023.f);
+            }
+            key[(size_t)j] = {hilbert_key(ix[0], ix[1], ix[2]), (int32_t)j};
+        }
+        std::sort(key.begin(), key.end());
+        r.perm.resize((size_t)q);
+        r.centers.resize((size_t)q * 3);
+        r.radii.resize((size_t)q);
+        for (int64_t j = 0; j < q; ++j) {
+            const int32_t i = key[(size_t)j].second;
+            r.perm[(size_t)j] = i;
+            for (int k = 0; k < 3; ++k) r.centers[(size_t)(3 * j + k)] = centers[3 * i + k];
+            r.radii[(size_t)j] = radii[i];
+        }
+    }
     const size_t qn = (size_t)q;
     const int S = std::max(r.sp.S, 1);
     // device arena: inputs, then partial reductions
@@ -521,13 +559,20 @@ static csplat_status collect(csplat_server *s, int64_t t, const csplat_outputs *
     const char *h = s->host_arena + ri->host_off;
     const size_t qn = (size_t)r.q;
     if (out) {
-        if (out->label) std::memcpy(out->label, h + r.h_label, qn);
-        if (out->count) std::memcpy(out->count, h + r.h_count, qn * 4);
+        // back to the caller's query order
+        auto scatter = [&](void *dst, size_t off, size_t elem) {
+            if (!dst) return;
+            char *d = static_cast<char *>(dst);
+            const char *src = h + off;
+            for (size_t j = 0; j < qn; ++j) std::memcpy(d + (size_t)r.perm[j] * elem, src + j * elem, elem);
+        };
+        scatter(out->label, r.h_label, 1);
+        scatter(out->count, r.h_count, 4);
         if (r.full) {
-            if (out->min) std::memcpy(out->min, h + r.h_min, qn * 4);
-            if (out->softmin) std::memcpy(out->softmin, h + r.h_soft, qn * 4);
-            if (out->cost) std::memcpy(out->cost, h + r.h_cost, qn * 4);
-            if (out->nbr) std::memcpy(out->nbr, h + r.h_nbr, qn * 4);
+            scatter(out->min, r.h_min, 4);
+            scatter(out->softmin, r.h_soft, 4);
+            scatter(out->cost, r.h_cost, 4);
+            scatter(out->nbr, r.h_nbr, 4);
         }
     }
     s->sched->finish(t);
