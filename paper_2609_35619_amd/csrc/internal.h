@@ -146,12 +146,11 @@ inline void timing_end(csplat_ctx *ctx)
     }
 }
 
-// Blocks that fill the device several times over (8 per compute unit).
 // Blocks per compute unit that a launch aims for: several rounds of resident
-// blocks, so that uneven work items even out (measured on MI355X: 32 beats
-// 8 and 16 on the navigation and label workloads).
+// blocks, so that uneven work items even out (measured on MI355X: 64 beats
+// 16 and 32, and 96-128 on the navigation workload, whose partials grow).
 #ifndef CSPLAT_BLOCKS_PER_CU
-#define CSPLAT_BLOCKS_PER_CU 32
+#define CSPLAT_BLOCKS_PER_CU 64
 #endif
 int target_blocks(int device);
 inline int ctx_target_blocks(const csplat_ctx *ctx) { return target_blocks(ctx->device); }
