@@ -28,9 +28,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sphere-Gaussian pair evals/s + queries/s at stated label accuracy; p50/p99 latency"
 PEAK_VALU = 256 * 4 * 16 * 2.4e9   # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz (one VALU slot per lane-cycle)
+# Transcendentals (v_sqrt, v_exp) issue at half the FMA rate on gfx950
+# (measured: 0.5 against 0.9-1.0 wave instructions per CU per cycle), so each
+# counts 2 VALU slots.
 OPS_ALL_PAIRS = 7                  # d (3), |d|^2 (3), ball test (1)
-OPS_IN_BALL_SHARED = 17            # M d (9), V (3), sqrt (4 slots), ball count (1)
-OPS_IN_BALL_PER_NSIGMA = 19        # s~^2 (2), label (2), min (1), softmin (exp 4 + 2), cost (exp 4 + 4)
+OPS_IN_BALL_SHARED = 15            # M d (9), V (3), sqrt (2 slots), ball count (1)
+OPS_IN_BALL_PER_NSIGMA = 15        # s~^2 (2), label (2), min (1), softmin (exp 2 + 2), cost (exp 2 + 4)
 
 
 # The pair kernel's HBM traffic comes from the rocprofv3 counter summary under
@@ -256,7 +259,7 @@ def _time_eval(eng, h, c, r, opts, want, reps=3):
     return (time.perf_counter() - t0) / reps, {k: v.cpu().numpy() for k, v in out.items()}
 
 
-OPS_ELL_SHARED = 38   # L d (9), s^2 (3), L^T e (9), M h (9), W (3), sqrt (4), ball count (1)
+OPS_ELL_SHARED = 36   # L d (9), s^2 (3), L^T e (9), M h (9), W (3), sqrt (2), ball count (1)
 
 
 def ellipsoids(cs, eng, steps):
