@@ -121,6 +121,11 @@ def main():
     eng = cs.Engine(dev)
     h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
     n_kept, scene_bytes = cs.csplat_scene_info(h)
+    import hashlib
+    dig = hashlib.sha256()
+    for a in (sc.means, sc.quats, sc.scales, sc.opacity, qs.centers, qs.radii):
+        dig.update(np.ascontiguousarray(a).tobytes())
+    inputs_sha256 = dig.hexdigest()[:16]
     eng.set_conservatism(p["n_sigma"])
     m = len(p["n_sigma"])
     opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"],
@@ -205,7 +210,7 @@ def main():
                                "neighbourhood ball 1 m, k=2, tau=0.1, d_max=1, gamma=1, s_min=1; "
                                "outputs label, count, min, softmin, cost, nbr",
                    "n_gaussians": int(sc.n), "n_kept": int(n_kept), "queries": int(qs.q), "m": m,
-                   "global_batch": int(qs.q), "parallelism": "single GPU"},
+                   "global_batch": int(qs.q), "parallelism": "single GPU", "inputs_sha256": inputs_sha256},
         "queries_per_s": qs.q / step_s,
         "rollout_epilogue": {"rollouts": n_roll, "in_collision_per_n_sigma": seg_any.sum(0).tolist()},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
@@ -213,7 +218,7 @@ def main():
         "host_arrays": {"ms_per_step_median": float(np.median(host_t) * 1e3),
                         "pair_evals_per_s": pairs / float(np.median(host_t)),
                         "note": "inputs from and outputs to host memory, PCIe copies inside the call"},
-        "vram_bytes": {"scene": int(scene_bytes)},
+        "vram_bytes": {"scene": int(scene_bytes), "workspace": int(st["workspace_bytes"])},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU / 1e9, "unit": "Gop/s",
                      "frac": achieved / PEAK_VALU, "traffic": traffic_from_profile(), "traffic_unit": "bytes",
                      "kernel": "pair_kernel<3,full,ball>", "kernel_ms": kernel_s * 1e3,
@@ -441,7 +446,16 @@ def cpu_baseline(sc, qs, p, gpu, target_s, n_kept):
                  where="bench")
     amb = ref["ambiguous"].astype(bool)
     agree = float(((gpu["label"][idx] == ref["label"]) | amb).mean())
+    cpu_model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu_model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     base = {"value": n_s * n_kept / dt, "unit": "pair evals/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model,
             "sample": f"{n_s} of {qs.q} queries (seeded) against all {n_kept} kept Gaussians, all outputs, FP64",
             "seconds": dt, "queries_per_s": n_s / dt}
     acc = {"labels_equal_outside_eps_band": agree, "ambiguous_queries": int(amb.sum()),

@@ -113,6 +113,8 @@ typedef struct {
     int64_t kernel_pairs;   /* pairs the dominant kernel evaluated (after any culling) */
     float kernel_ms;        /* with timing on: duration of the dominant (pair) kernel,
                                measured with HIP events on the context stream; else -1 */
+    uint64_t workspace_bytes; /* device bytes the context holds (partials, sorted queries,
+                                 staging, body records, counters) */
 } csplat_eval_stats;
 
 /* Context: a device, a stream (its own if hip_stream is NULL, else the given

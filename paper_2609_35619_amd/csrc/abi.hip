@@ -555,6 +555,8 @@ csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats)
     if (!ctx || !stats) return fail(CSPLAT_E_INVALID, "last_stats: NULL argument");
     *stats = ctx->stats;
     stats->kernel_ms = -1.f;
+    stats->workspace_bytes = ctx->partial.bytes + ctx->staging.bytes + ctx->flags.bytes + ctx->sortbuf.bytes +
+                             ctx->bodies.bytes;
     if (ctx->chunk_counter) {  // culled evaluation: pairs the kernel actually evaluated
         DeviceGuard g(ctx->device);
         unsigned long long chunks = 0;
