@@ -392,13 +392,18 @@ def serving(cs, eng, sc_nav, h_nav, n_requests, full):
             tickets.append((cs.csplat_server_submit(srv, ids[rq["scene"]], kind, rq["centers"], rq["radii"],
                                                     mppi_opts if kind == 0 else rrt_opts, rq["n_sigma"]),
                             kind, rq["centers"].shape[0]))
-        for t, kind, q in tickets:
+        last = time.perf_counter()
+        for i, (t, kind, q) in enumerate(tickets):
             cs.csplat_server_wait(srv, t, q, kind)
+            if time.perf_counter() - last > 10.0:
+                last = time.perf_counter()
+                log(f"bench: serving: {i + 1} of {len(tickets)} requests collected")
         wall = time.perf_counter() - t0
         st = cs.csplat_server_stats(srv)
         cs.csplat_server_destroy(srv)
         return st, wall
 
+    log(f"bench: serving: generating {n_requests} requests")
     reqs = serving_stream(n_requests, seed=105, rate_hz=1.0, **kw)
     pairs = sum(rq["centers"].shape[0] * n_scene[rq["scene"]] for rq in reqs)
     sat, wall = run(reqs, 0)           # saturated: every request at t = 0

@@ -131,7 +131,11 @@ bool Scheduler::plan(StepPlan *out)
     std::map<int32_t, int64_t> per_slot;
     const size_t ns = slot_owner_.size();
     bool progress = true;
-    while (progress && out->pairs < step_pairs_ && (int64_t)out->items.size() < max_items_) {
+    auto room = [&]() {
+        const int64_t n = (int64_t)out->items.size();
+        return n < max_items_ && (out->pairs < step_pairs_ || n < min_items_);
+    };
+    while (progress && room()) {
         progress = false;
         for (size_t k = 0; k < ns; ++k) {
             const size_t s = (rr_ + k) % ns;
@@ -153,7 +157,7 @@ bool Scheduler::plan(StepPlan *out)
                 continue;
             }
             if (r.next_item >= total) continue;
-            if (out->pairs >= step_pairs_ || (int64_t)out->items.size() >= max_items_) break;
+            if (!room()) break;
             const int64_t idx = r.next_item++;
             Item it;
             it.slot = (int32_t)s;

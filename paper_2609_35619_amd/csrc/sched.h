@@ -92,6 +92,15 @@ class Scheduler {
     // The caller collected a Done/Cancelled request: free its host memory.
     bool finish(int64_t ticket);
 
+    // The pair budget of a step (dense pairs, Q x N per item); the executor
+    // steers it toward a target step duration.
+    void set_step_pairs(int64_t pairs) { step_pairs_ = pairs; }
+    int64_t step_pairs() const { return step_pairs_; }
+    // A step takes at least this many items when that many are waiting,
+    // whatever the pair budget (a step of a few long items would leave the
+    // device idle while they run).
+    void set_min_items(int64_t n) { min_items_ = n; }
+
     const ReqInfo *info(int64_t ticket) const;
     int active() const;
     int queued() const { return (int)queue_.size(); }
@@ -105,6 +114,7 @@ class Scheduler {
     Arena dev_, host_;
     int slots_;
     int64_t step_pairs_, max_items_;
+    int64_t min_items_ = 0;
     int64_t next_ticket_ = 1, next_step_ = 1;
     std::map<int64_t, ReqInfo> reqs_;
     std::deque<int64_t> queue_;

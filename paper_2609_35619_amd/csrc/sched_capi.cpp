@@ -18,6 +18,8 @@ void *sched_new(uint64_t dev, uint64_t host, int32_t slots, int64_t step_pairs, 
     return new Scheduler(dev, host, slots, step_pairs, max_items);
 }
 
+void sched_set_min_items(void *s, int64_t n) { static_cast<Scheduler *>(s)->set_min_items(n); }
+
 void sched_free(void *s) { delete static_cast<Scheduler *>(s); }
 
 int64_t sched_submit(void *s, int32_t tiles, int32_t splits, int32_t variant, int64_t item_pairs,

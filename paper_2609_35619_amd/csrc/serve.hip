@@ -36,7 +36,14 @@ constexpr int kVariants = 4;        // 0 labels/no ball, 1 labels/ball, 2 full/n
 constexpr int kStepBlocks = 2048;   // persistent grid of each step kernel (8 blocks per CU)
 constexpr int kMaxItems = 16384;    // work items per step
 constexpr int kMaxSlots = 64;
-constexpr int64_t kStepPairs = 40000000000LL;  // ~10-20 ms of pair work per step
+constexpr int64_t kStepPairs = 40000000000LL;  // first step budget (dense pairs)
+// The budget is steered toward kStepTargetMs of GPU time per step: culling
+// makes a dense pair cost very different amounts of work from one request
+// mix to the next, and steps much shorter than that are dominated by their
+// fixed costs (staging, launch, host planning); much longer ones delay the
+// small requests that share them.
+constexpr double kStepTargetMs = 4.0;
+constexpr int64_t kStepPairsMin = 1000000000LL, kStepPairsMax = 1000000000000000LL;
 
 struct ReqDesc {
     const float *gs;
@@ -151,6 +158,7 @@ struct csplat_server {
     char *stage_dev[2] = {nullptr, nullptr};
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipEvent_t step_ev[2] = {nullptr, nullptr};
+    hipEvent_t step_ev0[2] = {nullptr, nullptr};  // step starts (timing)
     hipEvent_t copy_ev = nullptr;
     bool copies_pending = false;
     std::vector<const csplat_scene *> scenes;
@@ -161,6 +169,7 @@ struct csplat_server {
     struct Inflight {
         int64_t step;
         int stage;
+        bool full;  // the plan stopped at the budget (more work was waiting)
     };
     std::vector<Inflight> inflight;
     std::mutex mu;
@@ -255,13 +264,14 @@ void launch_step(csplat_server *s, const StepPlan &plan)
         if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->copy_ev, 0);
         s->copies_pending = false;
     }
+    if (e == hipSuccess) e = hipEventRecord(s->step_ev0[k], s->stream);
     if (e == hipSuccess) e = hipGraphLaunch(s->graph[k], s->stream);
     if (e == hipSuccess) e = hipEventRecord(s->step_ev[k], s->stream);
     if (e != hipSuccess) {
         set_fatal(s, e, "step launch");
         return;
     }
-    s->inflight.push_back({plan.step, k});
+    s->inflight.push_back({plan.step, k, plan.pairs >= s->sched->step_pairs()});
     ++s->st.steps;
 }
 
@@ -280,6 +290,18 @@ void worker_main(csplat_server *s)
                 (void)hipGetLastError();
             }
             const double t = now_s();
+            {
+                // steer the step budget toward kStepTargetMs (full steps only)
+                const auto &f = s->inflight.front();
+                float ms = 0.f;
+                if (f.full && hipEventElapsedTime(&ms, s->step_ev0[f.stage], s->step_ev[f.stage]) == hipSuccess &&
+                    ms > 0.f) {
+                    const double scale = std::min(2.0, std::max(0.5, kStepTargetMs / ms));
+                    const double b = (double)s->sched->step_pairs() * scale;
+                    s->sched->set_step_pairs(
+                        (int64_t)std::min((double)kStepPairsMax, std::max((double)kStepPairsMin, b)));
+                }
+            }
             for (int64_t tk : s->sched->step_done(s->inflight.front().step, t)) {
                 const serve::ReqInfo *ri = s->sched->info(tk);
                 if (ri && ri->state == State::Done) {
@@ -353,6 +375,7 @@ void server_release(csplat_server *s)
     for (int k = 0; k < 2; ++k) {
         if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
         if (s->step_ev[k]) (void)hipEventDestroy(s->step_ev[k]);
+        if (s->step_ev0[k]) (void)hipEventDestroy(s->step_ev0[k]);
         if (s->stage_host[k]) (void)hipHostFree(s->stage_host[k]);
         if (s->stage_dev[k]) (void)hipFree(s->stage_dev[k]);
     }
@@ -399,7 +422,8 @@ csplat_status csplat_server_create(int32_t device, uint64_t hbm_budget, int32_t 
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->stage_dev[k]), s->layout.bytes);
         if (e == hipSuccess) {
             std::memset(s->stage_host[k], 0, s->layout.bytes);
-            e = hipEventCreateWithFlags(&s->step_ev[k], hipEventDisableTiming);
+            e = hipEventCreate(&s->step_ev[k]);
+            if (e == hipSuccess) e = hipEventCreate(&s->step_ev0[k]);
         }
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->copy_ev, hipEventDisableTiming);
@@ -416,6 +440,7 @@ csplat_status csplat_server_create(int32_t device, uint64_t hbm_budget, int32_t 
         return st;
     }
     s->sched = new Scheduler(hbm_budget, hbm_budget, slots, kStepPairs, kMaxItems);
+    s->sched->set_min_items(kStepBlocks);
     s->worker = std::thread(worker_main, s);
     *out = s;
     return CSPLAT_OK;

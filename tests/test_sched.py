@@ -20,6 +20,7 @@ def lib():
     L.sched_new.restype = P
     L.sched_new.argtypes = [U64, U64, I32, I64, I64]
     L.sched_free.argtypes = [P]
+    L.sched_set_min_items.argtypes = [P, I64]
     L.sched_submit.restype = I64
     L.sched_submit.argtypes = [P, I32, I32, I32, I64, U64, U64, D]
     L.sched_admit.restype = I32
@@ -203,4 +204,16 @@ def test_arena_coalesces(lib):
     for t in ts:
         lib.sched_finish(f.s, t)
     assert lib.sched_dev_largest(f.s) == 1 << 20
+    f.close()
+
+
+def test_min_items_overrides_a_small_budget(lib):
+    """A step of a few long items would leave the device idle: with a minimum,
+    the step takes that many items even past the pair budget."""
+    f = Fake(lib, slots=2, step_pairs=10, max_items=100)
+    lib.sched_set_min_items(f.s, 6)
+    t = f.submit(tiles=20, splits=1, pairs=1000)
+    f.admit()
+    step, items, comp, pairs = f.plan()
+    assert len(items) == 6 and pairs == 6000
     f.close()
