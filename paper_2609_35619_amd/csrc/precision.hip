@@ -449,15 +449,19 @@ decide_kernel(int q, int S, int m, int v, int k, bool want_count, const int32_t 
 }
 
 // fp64 recheck of the listed queries.  One wave per work item: a tile of 64
-// listed queries on the lanes x split s of kRecheckSplits (the culling chunks
-// s, s + kRecheckSplits, ...), Gaussians read with wave-uniform scalar loads;
-// chunks beyond every lane's reach bound are skipped (batch test against the
-// wave's bounding sphere, then a vote); the exact counts are summed with
-// integer atomics (order-free).
+// listed queries (one per lane) x split s of kRecheckSplits (the culling
+// chunks s, s + kRecheckSplits, ...).  Chunks are tested 64 at a time
+// against the bounding sphere of the tile's queries, then each survivor
+// against every query (ballot); a surviving chunk is evaluated with one
+// Gaussian per lane (coalesced record loads) for each query that needs it,
+// the per-query hit count taken with a ballot.  Exact counts are summed in
+// integers (order-free).  Without culling metadata every chunk is evaluated
+// for every query.
 constexpr int kRecheckSplits = 256;
-constexpr int kRecheckGrid = 8192;
+constexpr int kRecheckWaves = 4;      // waves per block
+constexpr int kRecheckGrid = 2048;    // blocks (persistent)
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64 * kRecheckWaves)
 recheck_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restrict__ cull,
                     const float *__restrict__ centers, const float *__restrict__ radii, float n_sigma,
                     const int32_t *__restrict__ list, const int32_t *__restrict__ n_list, int32_t *__restrict__ exact)
@@ -466,30 +470,44 @@ recheck_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restr
     const int tiles = (nl + 63) / 64;
     const long items = (long)tiles * kRecheckSplits;
     const int n_chunks = (n + pair::kCull - 1) / pair::kCull;
-    const double nd = n_sigma;
-    const double four_n2 = 4.0 * nd * nd;
-    for (long item = blockIdx.x; item < items; item += gridDim.x) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const double four_n2 = 4.0 * (double)n_sigma * (double)n_sigma;
+    const long wave0 = (long)blockIdx.x * kRecheckWaves + (long)(threadIdx.x >> 6);
+    const long waves = (long)gridDim.x * kRecheckWaves;
+    for (long item = wave0; item < items; item += waves) {
         const int tile = (int)(item / kRecheckSplits), split = (int)(item - (long)tile * kRecheckSplits);
-        const int li = tile * 64 + (int)threadIdx.x;
+        const int li = tile * 64 + lane;
         const bool valid = li < nl;
         const int j = list[valid ? li : nl - 1];
         float fc[3][1] = {{centers[3 * j]}, {centers[3 * j + 1]}, {centers[3 * j + 2]}};
         const float fr = radii[j];
         float fr2[1] = {fr * fr};
-        const double cx = fc[0][0], cy = fc[1][0], cz = fc[2][0], r2 = (double)fr * fr;
-        int cnt = 0;
-        auto chunk = [&](int ci) {
-            const int b0 = ci * pair::kCull, b1 = min(n, b0 + pair::kCull);
-            for (int g = b0; g < b1; ++g) {
-                const float *p = gauss + (size_t)kGaussFloats * g;  // wave-uniform
-                const double dx = (double)p[0] - cx, dy = (double)p[1] - cy, dz = (double)p[2] - cz;
-                const double a = dx * dx + dy * dy + dz * dz - r2;
-                const double e0 = (double)p[3] * dx + (double)p[4] * dy + (double)p[5] * dz;
-                const double e1 = (double)p[6] * dx + (double)p[7] * dy + (double)p[8] * dz;
-                const double e2 = (double)p[9] * dx + (double)p[10] * dy + (double)p[11] * dz;
-                cnt += a * fabs(a) < four_n2 * (e0 * e0 + e1 * e1 + e2 * e2);
+        int cnt = 0;  // exact count of this lane's query
+        // chunk ci against the queries of qmask: lanes hold the chunk's Gaussians
+        auto chunk = [&](int ci, unsigned long long qmask) {
+            const int g = ci * pair::kCull + lane;
+            const bool real = g < n;
+            const float *p = gauss + (size_t)kGaussFloats * (real ? g : n - 1);
+            double mu[3], M[9];
+            for (int k = 0; k < 3; ++k) mu[k] = p[k];
+            for (int k = 0; k < 9; ++k) M[k] = p[3 + k];
+            while (qmask) {
+                const int b = __builtin_ctzll(qmask);
+                qmask &= qmask - 1;
+                const double cx = pair::lane_value(fc[0][0], b), cy = pair::lane_value(fc[1][0], b),
+                             cz = pair::lane_value(fc[2][0], b);
+                const double rb = pair::lane_value(fr, b);
+                const double dx = mu[0] - cx, dy = mu[1] - cy, dz = mu[2] - cz;
+                const double a = dx * dx + dy * dy + dz * dz - rb * rb;
+                const double e0 = M[0] * dx + M[1] * dy + M[2] * dz;
+                const double e1 = M[3] * dx + M[4] * dy + M[5] * dz;
+                const double e2 = M[6] * dx + M[7] * dy + M[8] * dz;
+                const bool hit = real && a * fabs(a) < four_n2 * (e0 * e0 + e1 * e1 + e2 * e2);
+                const int h = __popcll(__ballot(hit));
+                if (lane == b) cnt += h;
             }
         };
+        const unsigned long long vmask = __ballot(valid);
         if (cull) {
             float wx, wy, wz, spread, r2max;
             pair::wave_sphere<1>(fc[0], fc[1], fc[2], fr2, wx, wy, wz, spread, r2max);
@@ -497,17 +515,26 @@ recheck_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restr
                 const float ns = n_sigma * m.smax;
                 return ns + sqrtf(fmaf(ns, ns, rr2));
             };
-            pair::cull_walk(
-                cull, n_chunks, split, kRecheckSplits,
-                [&](const pair::ChunkMeta &m) {
-                    return pair::within(m, wx, wy, wz, spread + m.rad + reach_of(m, r2max));
-                },
-                [&](const pair::ChunkMeta &m) {
-                    return pair::within(m, fc[0][0], fc[1][0], fc[2][0], m.rad + reach_of(m, fr2[0]));
-                },
-                [&](int i) { chunk(split + i * kRecheckSplits); });
+            for (int ib = 0; split + ib * kRecheckSplits < n_chunks; ib += 64) {
+                const int ci = split + (ib + lane) * kRecheckSplits;
+                pair::ChunkMeta m{0.f, 0.f, 0.f, 0.f, 0.f};
+                bool pass = false;
+                if (ci < n_chunks) {
+                    m = pair::load_chunk(cull, ci);
+                    pass = pair::within(m, wx, wy, wz, spread + m.rad + reach_of(m, r2max));
+                }
+                unsigned long long mask = __ballot(pass);
+                while (mask) {
+                    const int bit = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    const pair::ChunkMeta k = pair::lane_chunk(m, bit);
+                    const bool near = pair::within(k, fc[0][0], fc[1][0], fc[2][0], k.rad + reach_of(k, fr2[0]));
+                    const unsigned long long qmask = __ballot(near) & vmask;
+                    if (qmask) chunk(split + (ib + bit) * kRecheckSplits, qmask);
+                }
+            }
         } else {
-            for (int ci = split; ci < n_chunks; ci += kRecheckSplits) chunk(ci);
+            for (int ci = split; ci < n_chunks; ci += kRecheckSplits) chunk(ci, vmask);
         }
         if (valid && cnt) atomicAdd(exact + li, cnt);
     }
@@ -664,7 +691,7 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
                                                  list, n_list + v, q, st));
         CSPLAT_HIP(zero_words(exact, (size_t)q, st));
         if (n > 0)
-            recheck_fp64_kernel<<<kRecheckGrid, 64, 0, st>>>(sc->gauss, n, cull ? sc->cull : nullptr, c, r,
+            recheck_fp64_kernel<<<kRecheckGrid, 64 * kRecheckWaves, 0, st>>>(sc->gauss, n, cull ? sc->cull : nullptr, c, r,
                                                              p.n_sigma[v], list, n_list + v, exact);
         finish_kernel<<<qb, 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, perm, out.label, out.count);
         CSPLAT_HIP(hipGetLastError());
