@@ -87,10 +87,11 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-ellipsoids", action="store_true", help="skip the ellipsoidal-body workload")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped context workload")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full-size request law (MPPI K up to 4096 x 32 x 48; long)")
-    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "ellipsoids", "copy", "digest"), default="all",
+    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "ellipsoids", "paper", "copy", "digest"), default="all",
                     help="run one part only (for profiling); 'copy' is a plain 1 GiB device copy "
                          "used to calibrate the HBM traffic counters")
     args = ap.parse_args()
@@ -103,6 +104,7 @@ def main():
         args.no_precision = args.section not in ("precision",)
         args.no_serving = args.section not in ("serving",)
         args.no_ellipsoids = args.section not in ("ellipsoids",)
+        args.no_paper = args.section not in ("paper",)
         args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -232,6 +234,8 @@ def main():
         res["precision_form"] = precision_form(cs, eng)
     if not args.no_ellipsoids:
         res["ellipsoids"] = ellipsoids(cs, eng, args.steps)
+    if not args.no_paper:
+        res["paper_context"] = paper_context(cs, eng)
     if not args.no_serving:
         res["serving"] = serving(cs, eng, sc, h, args.serving_requests, args.serving_full)
     cs.csplat_scene_free(h)
@@ -310,6 +314,33 @@ def ellipsoids(cs, eng, steps):
             "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e9, "peak": PEAK_VALU / 1e9,
                          "unit": "Gop/s", "frac": ops / kernel_s / PEAK_VALU, "kernel_ms": kernel_s * 1e3,
                          "evaluated_pairs": int(st["kernel_pairs"]), "in_ball_pairs": nbr}}
+
+
+def paper_context(cs, eng):
+    """Shaped like the paper's own measurement (Table I): a 200k-Gaussian unit
+    scene, grid points as spheres of radius 0.015, collision labels for
+    batches of 4,096 and 32,768, n_sigma = 1.  The paper's numbers were taken on
+    other hardware with its own scene: context only."""
+    import torch
+    from workloads import config, grid_queries
+    log("bench: paper-shaped context (200k Gaussians, batches 4,096 and 32,768)")
+    sc, _, p = config("paper_p0")
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
+    n_kept, nbytes = cs.csplat_scene_info(h)
+    eng.set_conservatism(p["n_sigma"])
+    opts = cs.reduce_opts(k=p["k"], r_nbr=math.inf)
+    out = {"workload": "paper_p0: 200k-Gaussian unit scene (ring of columns and lintels, 20% clutter), "
+                       "grid points r = 0.015, n_sigma 1, k = 2, labels",
+           "n_kept": int(n_kept), "scene_bytes": int(nbytes),
+           "paper_table_I_context": {"hardware": "RTX 6000 Pro (Warp)", "checks_per_s_4096": 215578.9,
+                                     "checks_per_s_32768": 1638400.0, "vram_gb": 0.166}}
+    for res_, name in ((16, "batch_4096"), (32, "batch_32768")):
+        qs = grid_queries(res_, size=(1.0, 1.0, 0.6), radius_classes=(0.015,))
+        c, r = torch.from_numpy(qs.centers).cuda(), torch.from_numpy(qs.radii).cuda()
+        dt, _ = _time_eval(eng, h, c, r, opts, ("label",), reps=20)
+        out[name] = {"ms": dt * 1e3, "checks_per_s": qs.q / dt, "pair_evals_per_s": qs.q * n_kept / dt}
+    cs.csplat_scene_free(h)
+    return out
 
 
 def precision_form(cs, eng):

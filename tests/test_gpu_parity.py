@@ -83,7 +83,8 @@ def test_tiny_every_output(cs, eng, oracle_mod):
     _check(gpu, ref, p, "tiny")
 
 
-@pytest.mark.parametrize("name,scale", [("mppi_nav", 0.02), ("manip", 0.004), ("precision", 0.002)])
+@pytest.mark.parametrize("name,scale", [("mppi_nav", 0.02), ("manip", 0.004), ("precision", 0.002),
+                                        ("paper_p0", 0.05)])
 def test_scaled_configs(cs, eng, oracle_mod, name, scale):
     _say(f"case: {name} at scale {scale}")
     sc, qs, p = config(name, scale)

@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     uniform_box_scene,
     room_scene,
     tabletop_scene,
+    stone_circle_scene,
     uniform_queries,
     mppi_walk_queries,
     chain_queries,

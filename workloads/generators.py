@@ -209,6 +209,49 @@ def tabletop_scene(n: int, seed: int, n_boxes=15, n_cyl=15, normal_sigma=0.01) -
     return _finish(rng, means)
 
 
+def stone_circle_scene(n: int, seed: int, n_columns=12, clutter_frac=0.2, normal_sigma=0.003) -> Scene:
+    """A scene shaped like the paper's normalised ring of standing stones, in
+    the unit cube: a ground slab (z = 0), a ring of upright columns (radius
+    U[0.02, 0.05], height U[0.25, 0.45]) with lintel slabs on pairs of them;
+    (1 - clutter_frac) of the splats on the surfaces in proportion to area,
+    offset along the normal by N(0, normal_sigma^2), the rest uniform clutter."""
+    rng = _rng(seed)
+    n_surf = int(round(n * (1 - clutter_frac)))
+    ang = np.linspace(0, 2 * math.pi, n_columns, endpoint=False) + rng.uniform(0, 0.2, n_columns)
+    cx, cy = 0.5 + 0.35 * np.cos(ang), 0.5 + 0.35 * np.sin(ang)
+    rad = rng.uniform(0.02, 0.05, n_columns)
+    hgt = rng.uniform(0.25, 0.45, n_columns)
+    # surfaces: ground, column mantles, lintels (boxes between neighbours, every other pair)
+    areas = [1.0] + list(2 * math.pi * rad * hgt)
+    lintels = []
+    for i in range(0, n_columns, 2):
+        k = (i + 1) % n_columns
+        p0 = np.array([cx[i], cy[i]]); p1 = np.array([cx[k], cy[k]])
+        z = min(hgt[i], hgt[k])
+        lintels.append((p0, p1, z))
+        areas.append(2 * np.linalg.norm(p1 - p0) * 0.06)
+    areas = np.asarray(areas)
+    which = rng.choice(areas.size, n_surf, p=areas / areas.sum())
+    pts = np.empty((n_surf, 3))
+    u = rng.uniform(size=(n_surf, 2))
+    off = rng.normal(0.0, normal_sigma, n_surf)
+    g = which == 0
+    pts[g] = np.stack([u[g, 0], u[g, 1], off[g]], 1)
+    for c in range(n_columns):
+        sel = which == 1 + c
+        th = 2 * math.pi * u[sel, 0]
+        rr = rad[c] + off[sel]
+        pts[sel] = np.stack([cx[c] + rr * np.cos(th), cy[c] + rr * np.sin(th), u[sel, 1] * hgt[c]], 1)
+    for li, (p0, p1, z) in enumerate(lintels):
+        sel = which == 1 + n_columns + li
+        t = u[sel, 0]
+        side = np.where(u[sel, 1] < 0.5, 0.0, 0.06)
+        xy = p0[None] + (p1 - p0)[None] * t[:, None]
+        pts[sel] = np.stack([xy[:, 0], xy[:, 1], z + side + off[sel]], 1)
+    clutter = rng.uniform(0, 1, (n - n_surf, 3)) * np.array([1.0, 1.0, 0.6])
+    return _finish(rng, np.concatenate([pts, clutter], 0))
+
+
 def uniform_queries(q: int, seed: int, box=(4.0, 4.0, 2.0), radius=0.1) -> Queries:
     rng = _rng(seed)
     c = rng.uniform(0.0, 1.0, size=(q, 3)) * np.asarray(box)
@@ -402,7 +445,7 @@ def serving_stream(n_requests: int, seed: int, rate_hz: float, scene_ids=(0, 1),
 
 # Named workloads.  Reduction defaults: k=2, tau=0.1, d_max=1, gamma=1, s_min=1;
 # floater filter alpha_f=0.05, extent_f=0.1 m.
-CONFIG_NAMES = ("tiny", "mppi_nav", "manip", "precision", "manip_ell")
+CONFIG_NAMES = ("tiny", "mppi_nav", "manip", "precision", "manip_ell", "paper_p0")
 
 REDUCE_DEFAULTS = dict(k=2, tau=0.1, d_max=1.0, gamma=1.0, s_min=1.0)
 FLOATER = dict(alpha_f=0.05, extent_f=0.1)
@@ -429,6 +472,13 @@ def config(name: str, scale: float = 1.0):
         sc = tabletop_scene(sz(500_000), seed=3)
         qs = chain_ellipsoids(sz(256), 32, seed=106)
         par = dict(n_sigma=[1.0], r_nbr=0.4)
+    elif name == "paper_p0":
+        # shaped like the paper's own measurement: ~200k Gaussians in a unit
+        # scene, grid points as robot spheres of radius 0.015, labels
+        sc = stone_circle_scene(sz(200_000), seed=6)
+        res = max(4, int(round(32 * scale ** (1 / 3))))
+        qs = grid_queries(res, size=(1.0, 1.0, 0.6), radius_classes=(0.015,))
+        par = dict(n_sigma=[1.0], r_nbr=math.inf)
     elif name == "precision":
         sc = room_scene(sz(4_000_000), seed=4)
         res = max(4, int(round(64 * scale ** (1 / 3))))
