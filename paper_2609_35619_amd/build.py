@@ -26,10 +26,16 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-result",
          "-I", os.path.join(ROOT, "include")]
 
+# Per-source extra flags.  The MFMA label kernel reads every accumulator
+# element right after its product; with the accumulators in ordinary VGPRs
+# (the backend otherwise picks the AccVGPR file) no v_accvgpr_read copies
+# are needed, and the kernel needs fewer registers.
+SOURCE_FLAGS = {"precision.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 
 def _compile(src: str, build_dir: str = BUILD, defines=()) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

@@ -231,17 +231,47 @@ build_tiles_kernel(const float *__restrict__ gauss, int64_t n, float *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Query features of one lane (query column, K half h) relative to a tile.
+// Query features relative to a tile.  A wave holds two 32-query column
+// blocks; the B operand of column block cb at lane col + 32 h is K half h of
+// query (cb, col).  Lane col + 32 h builds both K halves of query (h, col)
+// once, and one exchange of the upper 32 lanes of the first half with the
+// lower 32 lanes of the second (v_permlane32_swap) hands every lane the two
+// operands it needs: the first register then holds column block 0, the
+// second column block 1.
 template <int P>
 struct QFeat {
     typename Prec<P>::vec a, w0, w1;
     float two_ea, c0;
-    bool bad;
 };
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <class V>
+__device__ __forceinline__ void swap_halves(V &x, V &y)
+{
+    u32x4 bx = __builtin_bit_cast(u32x4, x), by = __builtin_bit_cast(u32x4, y);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(bx[i], by[i], false, false);
+        bx[i] = r[0];
+        by[i] = r[1];
+    }
+    x = __builtin_bit_cast(V, bx);
+    y = __builtin_bit_cast(V, by);
+}
+
+__device__ __forceinline__ void swap_halves(float &x, float &y)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+}
+
+// Features of the lane's own query (cx, cy, cz, r2) about tile origin mt,
+// exchanged into Q[0], Q[1]; returns false when a bound is not finite.
 template <int P>
-__device__ __forceinline__ void build_query(float cx, float cy, float cz, float r2, float four_n2,
-                                            const float *__restrict__ mt, int h, QFeat<P> &Q)
+__device__ __forceinline__ bool build_query(float cx, float cy, float cz, float r2, float four_n2,
+                                            const float *__restrict__ mt, QFeat<P> (&Q)[2])
 {
     using T = Prec<P>;
     using elem = typename T::elem;
@@ -262,22 +292,20 @@ __device__ __forceinline__ void build_query(float cx, float cy, float cz, float 
         h2[k] = (float)(elem)ch[k];
         l2[k] = (float)(elem)(ch[k] - h2[k]);
     }
+    // K halves 0 (slots 0-7) and 1 (slots 8-15) of a, of w's first and second
+    // operand (slots 0-15, 16-31)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        // both halves' slot values, then the lane's half
         const int sa0 = j, sa1 = 8 + j;
         const int fa0 = slot_feat_a(sa0), fa1 = slot_feat_a(sa1);
-        const float va0 = fa0 < 0 ? 0.f : (slot_part_q_a(sa0) ? l1[fa0] : h1[fa0]);
-        const float va1 = fa1 < 0 ? 0.f : (slot_part_q_a(sa1) ? l1[fa1] : h1[fa1]);
-        Q.a[j] = (elem)(h ? va1 : va0);
+        Q[0].a[j] = (elem)(fa0 < 0 ? 0.f : (slot_part_q_a(sa0) ? l1[fa0] : h1[fa0]));
+        Q[1].a[j] = (elem)(fa1 < 0 ? 0.f : (slot_part_q_a(sa1) ? l1[fa1] : h1[fa1]));
         const int s00 = j, s01 = 8 + j, s10 = 16 + j, s11 = 24 + j;
         const int f00 = slot_feat_w(s00), f01 = slot_feat_w(s01), f10 = slot_feat_w(s10), f11 = slot_feat_w(s11);
-        const float w00 = f00 < 0 ? 0.f : (slot_part_q_w(s00) ? l2[f00] : h2[f00]);
-        const float w01 = f01 < 0 ? 0.f : (slot_part_q_w(s01) ? l2[f01] : h2[f01]);
-        const float w10 = f10 < 0 ? 0.f : (slot_part_q_w(s10) ? l2[f10] : h2[f10]);
-        const float w11 = f11 < 0 ? 0.f : (slot_part_q_w(s11) ? l2[f11] : h2[f11]);
-        Q.w0[j] = (elem)(h ? w01 : w00);
-        Q.w1[j] = (elem)(h ? w11 : w10);
+        Q[0].w0[j] = (elem)(f00 < 0 ? 0.f : (slot_part_q_w(s00) ? l2[f00] : h2[f00]));
+        Q[1].w0[j] = (elem)(f01 < 0 ? 0.f : (slot_part_q_w(s01) ? l2[f01] : h2[f01]));
+        Q[0].w1[j] = (elem)(f10 < 0 ? 0.f : (slot_part_q_w(s10) ? l2[f10] : h2[f10]));
+        Q[1].w1[j] = (elem)(f11 < 0 ? 0.f : (slot_part_q_w(s11) ? l2[f11] : h2[f11]));
     }
     // certified error bounds of the computed a and w for this (query, tile):
     // per feature 3.1 u^2 |phi||psi| (split residuals and the dropped lo*lo),
@@ -298,9 +326,18 @@ __device__ __forceinline__ void build_query(float cx, float cy, float cz, float 
     }
     const float ea = 1.1f * (ue * sa + T::eta * sa_abs + 4.f * kU32 * (c2 + r2));
     const float ew = 1.1f * (ue * sw + T::eta * sw_abs);
-    Q.two_ea = 2.f * ea;
-    Q.c0 = fmaf(ea, ea, ew) * 1.0001f;
-    Q.bad = !(isfinite(Q.two_ea) && isfinite(Q.c0) && isfinite(sa) && isfinite(sw));
+    const float two_ea = 2.f * ea, c0 = fmaf(ea, ea, ew) * 1.0001f;
+    swap_halves(Q[0].a, Q[1].a);
+    swap_halves(Q[0].w0, Q[1].w0);
+    swap_halves(Q[0].w1, Q[1].w1);
+    // the query's own scalars, then the same exchange of a register with
+    // itself, which broadcasts column block 0's value to the first and
+    // column block 1's to the second
+    Q[0].two_ea = Q[1].two_ea = two_ea;
+    Q[0].c0 = Q[1].c0 = c0;
+    swap_halves(Q[0].two_ea, Q[1].two_ea);
+    swap_halves(Q[0].c0, Q[1].c0);
+    return isfinite(two_ea) && isfinite(c0) && isfinite(sa) && isfinite(sw);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,17 +378,14 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         r2[cb] = r * r;
     }
     int lo[2] = {0, 0}, hi[2] = {0, 0};
-    bool bad[2] = {false, false};
+    bool bad = false;  // a non-finite bound for the lane's own query (column block h)
+    const float ox = h ? cx[1] : cx[0], oy = h ? cy[1] : cy[0], oz = h ? cz[1] : cz[0], or2 = h ? r2[1] : r2[0];
     const f32x16 zero = {};
     // the row blocks of tile t selected by the 16-bit mask rbm (wave-uniform)
     auto do_tile = [&](int t, unsigned rbm) {
         const float *mt = meta + (size_t)t * kMeta;  // wave-uniform: scalar loads
         QFeat<P> Q[2];
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-            build_query<P>(cx[cb], cy[cb], cz[cb], r2[cb], four_n2, mt, h, Q[cb]);
-            bad[cb] |= Q[cb].bad;
-        }
+        bad |= !build_query<P>(ox, oy, oz, or2, four_n2, mt, Q);
         const vec *ft = feat + (size_t)t * kRB * kOps * kLanes + lane;
         while (rbm) {
             const int rb = __builtin_ctz(rbm);
@@ -364,13 +398,23 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
                 f32x16 W = T::mfma(Aw0, Q[cb].w0, zero);
                 W = T::mfma(Aw1, Q[cb].w1, W);
                 const float te = Q[cb].two_ea, c0 = Q[cb].c0;
+                float f[16], bnd[16];
+                bool poss = false;
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const float a = A[i], aa = fabsf(a);
-                    const float f = fmaf(-a, aa, W[i]);   // w - a|a|: > 0 iff collision
-                    const float bnd = fmaf(aa, te, c0);   // certified |f - f_exact| bound
-                    lo[cb] += f > bnd;                    // certainly in collision
-                    hi[cb] += f > -bnd;                   // possibly in collision
+                    f[i] = fmaf(-a, aa, W[i]);      // w - a|a|: > 0 iff collision
+                    bnd[i] = fmaf(aa, te, c0);      // certified |f - f_exact| bound
+                    poss |= f[i] > -bnd[i];
+                }
+                // most blocks hold no possible collision (and so no certain
+                // one): count only where some lane has one
+                if (__any(poss)) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        lo[cb] += f[i] > bnd[i];    // certainly in collision
+                        hi[cb] += f[i] > -bnd[i];   // possibly in collision
+                    }
                 }
             }
         }
@@ -417,7 +461,8 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
     for (int cb = 0; cb < 2; ++cb) {
         lo[cb] += __shfl_xor(lo[cb], 32);
         hi[cb] += __shfl_xor(hi[cb], 32);
-        const bool anybad = bad[cb] || __shfl_xor((int)bad[cb], 32) != 0;
+        const bool other = __shfl_xor((int)bad, 32) != 0;
+        const bool anybad = (h == cb) ? bad : other;
         if (h == 0 && jq[cb] < q) {
             lo_out[(size_t)split * q + jq[cb]] = lo[cb];
             hi_out[(size_t)split * q + jq[cb]] = anybad ? (1 << 29) : hi[cb];
