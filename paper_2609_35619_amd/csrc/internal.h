@@ -95,9 +95,11 @@ struct csplat_scene {
     int device = 0;
     int64_t n_input = 0;
     int64_t n = 0;            // kept Gaussians
-    float *gauss = nullptr;   // n x 16 float32 records, Hilbert order of the means
+    float *gauss = nullptr;   // 16-float records in Hilbert order of the means, padded to whole
+                              // culling chunks of 64 (pad records: mean at +inf, zero covariance)
     float mu_max = 0.f;       // max |mu| over the kept Gaussians
-    float *cull = nullptr;    // per chunk of 64: bounding sphere centre, radius, largest scale
+    float *cull = nullptr;    // per chunk of 64, then per sub-chunk of 16 (from record ceil(n / 64)):
+                              // bounding sphere centre, radius, largest scale (8 floats each)
     float box_lo[3] = {0, 0, 0}, box_scale[3] = {0, 0, 0};  // grid of the kept means (one cell size)
     // precision form (optional): per tile of 512 Gaussians the packed MFMA
     // operands (96 B per Gaussian) and 20 floats of metadata (origin, scale,

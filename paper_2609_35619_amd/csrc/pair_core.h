@@ -48,6 +48,17 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #else
 #define CSPLAT_OCCUPANCY
 #endif
+// The task walk (full outputs over a ball) at 4 waves per SIMD: its vector
+// loads want the latency hiding, and the cap costs it a few spilled bytes
+// (measured on MI355X: 1.25 -> 1.10 ms on the navigation workload).
+#ifndef CSPLAT_TASK_WAVES_PER_EU
+#define CSPLAT_TASK_WAVES_PER_EU 4
+#endif
+// Work items of the task walk per compute unit (fewer, longer splits keep
+// its task queues full; measured: 32 beats 16 and 64).
+#ifndef CSPLAT_TASK_BLOCKS_PER_CU
+#define CSPLAT_TASK_BLOCKS_PER_CU 32
+#endif
 constexpr int kUnroll = CSPLAT_UNROLL;       // Gaussians per group of scalar loads
 constexpr int kQplFull = CSPLAT_QPL_FULL;    // queries per lane, all outputs
 constexpr int kQplLabels = CSPLAT_QPL_LABELS;  // queries per lane, labels only
@@ -99,13 +110,13 @@ struct QState {
     float L[ELL ? QPL : 1][9];
 };
 
-// D: the metric's squared term, W: its variance term (see above), from d.
-template <bool ELL, int QPL>
-__device__ __forceinline__ void metric_terms(const float *__restrict__ gp, const QState<QPL, ELL> &Q, int u,
-                                             float dx, float dy, float dz, float D_sphere, float &D, float &W)
+// D: the metric's squared term, W: its variance term (see above), from d
+// (L: the body's matrix, ellipsoids only).
+template <bool ELL>
+__device__ __forceinline__ void metric_dw(const float *__restrict__ gp, const float *L, float dx, float dy,
+                                          float dz, float D_sphere, float &D, float &W)
 {
     if constexpr (ELL) {
-        const float *L = Q.L[u];
         const float e0 = fmaf(L[2], dz, fmaf(L[1], dy, L[0] * dx));
         const float e1 = fmaf(L[5], dz, fmaf(L[4], dy, L[3] * dx));
         const float e2 = fmaf(L[8], dz, fmaf(L[7], dy, L[6] * dx));
@@ -124,6 +135,13 @@ __device__ __forceinline__ void metric_terms(const float *__restrict__ gp, const
         const float e2 = fmaf(gp[11], dz, fmaf(gp[10], dy, gp[9] * dx));
         W = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
     }
+}
+
+template <bool ELL, int QPL>
+__device__ __forceinline__ void metric_terms(const float *__restrict__ gp, const QState<QPL, ELL> &Q, int u,
+                                             float dx, float dy, float dz, float D_sphere, float &D, float &W)
+{
+    metric_dw<ELL>(gp, Q.L[ELL ? u : 0], dx, dy, dz, D_sphere, D, W);
 }
 
 template <int M, bool FULL, bool BALL, int QPL, bool ELL>
@@ -263,10 +281,9 @@ __device__ __forceinline__ bool within(const ChunkMeta &m, float x, float y, flo
 // Walk the chunks split, split + S, split + 2S, ... (< n_chunks) in ascending
 // order with two culling levels: (1) a batch of 64 chunks at once, one per
 // lane, with `coarse(m)` (a test against the wave's bounding sphere); (2)
-// each survivor against every query of the wave with `near(m)` (a wave vote:
-// lanes outside every reach evaluate the chunk with the wave, and their own
-// exact tests reject each of its pairs).  visit(i) for the i-th chunk of the
-// split when some lane is near.
+// each survivor against every query of the wave with `near(m)`.
+// visit(i, lanes) for the i-th chunk of the split when some lane is near,
+// with the wave mask of the near lanes.
 template <class Coarse, class Near, class Visit>
 __device__ __forceinline__ void cull_walk(const float *__restrict__ cull, int n_chunks, int split, int S,
                                           Coarse coarse, Near near, Visit visit)
@@ -284,9 +301,306 @@ __device__ __forceinline__ void cull_walk(const float *__restrict__ cull, int n_
         while (mask) {
             const int bit = __builtin_ctzll(mask);
             mask &= mask - 1;
-            if (!__any(near(lane_chunk(m, bit)))) continue;
-            visit(ib + bit);
+            const unsigned long long lanes = __ballot(near(lane_chunk(m, bit)));
+            if (!lanes) continue;
+            visit(ib + bit, lanes);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Full outputs over the neighbourhood ball, one query per lane, as tasks.
+//
+// The 64 queries of a wave spread over a region comparable to the ball, so a
+// chunk that some lane needs lies in the ball of only part of the wave: a
+// walk that steps every lane through every such chunk leaves most lanes
+// masked in the per-pair work.  Here the wave's work is cut into tasks
+// (query, sub-chunk of kFine Gaussians), one for each sub-chunk whose
+// bounding sphere reaches the query's ball, queued in curve order and run 64
+// at a time, one per lane: lane i takes the i-th task, fetches that query's
+// state from the lane that owns it and the sub-chunk's records with vector
+// loads, and reduces the task's pairs into a partial (the first level of the
+// two-level softmin and cost sums).  Each query then folds its tasks'
+// partials into its totals in queue order.  Without culling every lane
+// queues every sub-chunk of the split for itself: the sub-chunks outside a
+// query's ball give empty partials, whose fold changes no bit, so culled and
+// dense walks give the same bits.
+constexpr int kFine = 16;                // Gaussians per task
+constexpr int kFinePer = kCull / kFine;  // sub-chunks per culling chunk
+
+template <int M>
+struct TaskAcc {
+    int cnt[M];
+    float mt[M], sm[M], cs[M];
+    int nb;
+};
+
+template <bool ELL>
+struct TaskQuery {
+    float cx, cy, cz, r2, kq;
+    float L[ELL ? 9 : 1];
+};
+
+template <int M>
+__device__ __forceinline__ void task_reset(TaskAcc<M> &T)
+{
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        T.cnt[v] = 0;
+        T.mt[v] = INFINITY;
+        T.sm[v] = 0.f;
+        T.cs[v] = 0.f;
+    }
+    T.nb = 0;
+}
+
+// One pair: Gaussian record (mean, M row-major) in r0..r2, query Q.
+// g0: the cost constant p.g0 held in a VGPR (the cost's fma would otherwise
+// name two scalar operands and copy one of them for every pair).
+template <int M, bool ELL>
+__device__ __forceinline__ void task_pair(const float4 &r0, const float4 &r1, const float4 &r2,
+                                          const TaskQuery<ELL> &Q, const EvalParams &p, float g0, TaskAcc<M> &T)
+{
+    const float dx = r0.x - Q.cx, dy = r0.y - Q.cy, dz = r0.z - Q.cz;
+    const float Db = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    if (Db <= p.rn2) {
+        ++T.nb;
+        const float gp[12] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
+        float D, W;
+        metric_dw<ELL>(gp, Q.L, dx, dy, dz, Db, D, W);
+        const float sv = fast_sqrt(W);
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            const float x = fmaf(-p.two_n[v], sv, D);  // (r^2) (s^2 - n sqrt(sigma^2))
+            T.cnt[v] += x < Q.r2;                       // s~^2 < 1
+            const float t = fmaxf(x, 0.f) * Q.kq;
+            // stable log-sum-exp about the task's running minimum (one exp per pair)
+            const float e = fast_exp2(-fabsf(t - T.mt[v]));
+            const bool lower = t < T.mt[v];
+            T.sm[v] = lower ? fmaf(T.sm[v], e, 1.f) : T.sm[v] + e;
+            T.mt[v] = lower ? t : T.mt[v];
+            // 2^min(y, 0) = min(2^y, 1): the clamp folds into the exp
+            T.cs[v] += __builtin_amdgcn_fmed3f(fast_exp2(fmaf(t, -p.g1, g0)), 0.f, 1.f);
+        }
+    }
+}
+
+// Fold a task partial X into the totals A (first-level sums into the second).
+template <int M>
+__device__ __forceinline__ void task_fold(TaskAcc<M> &A, const TaskAcc<M> &X)
+{
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        A.cnt[v] += X.cnt[v];
+        A.cs[v] += X.cs[v];
+        const float cm = X.mt[v], tm = A.mt[v];
+        if (cm < tm) {
+            A.sm[v] = fmaf(A.sm[v], fast_exp2(tm == INFINITY ? -INFINITY : cm - tm), X.sm[v]);
+            A.mt[v] = cm;
+        } else if (cm < INFINITY) {
+            A.sm[v] = fmaf(X.sm[v], fast_exp2(tm - cm), A.sm[v]);
+        }
+    }
+    A.nb += X.nb;
+}
+
+// Words of a task partial in LDS: 4M + 1 rounded up to whole float4s, and
+// kept off a multiple of 8 words so that the lanes' rows spread over banks.
+template <int M>
+constexpr int task_words()
+{
+    return ((4 * M + 1 + 3) / 4) * 4 % 8 == 0 ? ((4 * M + 1 + 3) / 4) * 4 + 4 : ((4 * M + 1 + 3) / 4) * 4;
+}
+
+__device__ __forceinline__ float lane_shfl(float v, int src) { return __shfl(v, src); }
+
+template <int M, bool CULL, bool ELL>
+__device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, int n, int S, int split, int tile,
+                                                const float *__restrict__ centers, const float *__restrict__ radii,
+                                                int q, const EvalParams &p, const Part &part,
+                                                const float *__restrict__ cull, int *tasks_done)
+{
+    constexpr int kRing = 128;  // queued tasks per wave: at most 63 waiting + 64 of one sub-chunk
+    constexpr int PW = task_words<M>();
+    constexpr int kWaves = kBlock / 64;
+    __shared__ int s_task[kWaves][kRing];              // sub-chunk of each queued task
+    __shared__ unsigned char s_owner[kWaves][kRing];   // lane of its query
+    __shared__ float4 s_part[kWaves][64 * PW / 4];     // partials of a round, PW words per task
+    const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+    const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
+    const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
+    TaskQuery<ELL> own;
+    float qa;
+    if constexpr (ELL) {
+        const float4 *b = reinterpret_cast<const float4 *>(centers + (size_t)kBodyFloats * jj);
+        const float4 b0 = b[0], b1 = b[1], b2 = b[2];
+        own.cx = b0.x, own.cy = b0.y, own.cz = b0.z;
+        own.L[0] = b0.w, own.L[1] = b1.x, own.L[2] = b1.y, own.L[3] = b1.z, own.L[4] = b1.w;
+        own.L[5] = b2.x, own.L[6] = b2.y, own.L[7] = b2.z, own.L[8] = b2.w;
+        own.r2 = 1.f;
+        own.kq = p.kt;
+        qa = 0.f;
+    } else {
+        own.cx = centers[3 * jj];
+        own.cy = centers[3 * jj + 1];
+        own.cz = centers[3 * jj + 2];
+        const float r = radii[jj];
+        own.r2 = r * r;
+        own.kq = p.kt / own.r2;
+        qa = own.r2;
+    }
+    TaskAcc<M> A;
+    task_reset(A);
+    // ring positions of the lane's own queued tasks (bit k of lo: position k,
+    // of hi: position 64 + k); head, tail: wave-uniform, counting up
+    unsigned long long own_lo = 0, own_hi = 0;
+    int head = 0, tail = 0;
+    float g0v = p.g0;
+    asm volatile("" : "+v"(g0v));
+
+    auto run_round = [&](int n_t) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const bool valid = lane < n_t;
+        const int pos = (head + lane) & (kRing - 1);
+        const int f = valid ? s_task[wv][pos] : 0;
+        const int qi = valid ? (int)s_owner[wv][pos] : 0;
+        // the lane permutes run with every lane active (a permute reads
+        // nothing useful from an inactive source lane), the selects after
+        TaskQuery<ELL> tq;
+        tq.cx = lane_shfl(own.cx, qi);
+        // a lane without a task walks sub-chunk 0 for a query at infinity,
+        // which has no Gaussian in its ball (its partial is never folded)
+        if (!valid) tq.cx = INFINITY;
+        tq.cy = lane_shfl(own.cy, qi);
+        tq.cz = lane_shfl(own.cz, qi);
+        tq.r2 = lane_shfl(own.r2, qi);
+        tq.kq = lane_shfl(own.kq, qi);
+        if constexpr (ELL) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) tq.L[k] = lane_shfl(own.L[k], qi);
+        }
+        TaskAcc<M> T;
+        task_reset(T);
+        // the scene's records are padded to whole chunks (pad means at +inf)
+        const float4 *rp = reinterpret_cast<const float4 *>(gs) + (size_t)f * (kFine * kGaussFloats / 4);
+#pragma unroll 1
+        for (int k = 0; k < kFine; k += kUnroll, rp += kUnroll * (kGaussFloats / 4)) {
+            float4 r[kUnroll][3];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                r[u][0] = rp[u * (kGaussFloats / 4)];
+                r[u][1] = rp[u * (kGaussFloats / 4) + 1];
+                r[u][2] = rp[u * (kGaussFloats / 4) + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, p, g0v, T);
+        }
+        // the round's partials to LDS (slot = lane), words: cnt | mt | sm | cs | nb
+        {
+            float w[PW];
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                w[v] = __int_as_float(T.cnt[v]);
+                w[M + v] = T.mt[v];
+                w[2 * M + v] = T.sm[v];
+                w[3 * M + v] = T.cs[v];
+            }
+            w[4 * M] = __int_as_float(T.nb);
+#pragma unroll
+            for (int k = 4 * M + 1; k < PW; ++k) w[k] = 0.f;
+            float4 *dst = &s_part[wv][lane * (PW / 4)];
+#pragma unroll
+            for (int k = 0; k < PW / 4; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // each query folds its tasks of this round, in queue order; the
+        // round's slot i is ring position head + i, head a multiple of 64
+        for (unsigned long long mine = (head & 64) ? own_hi : own_lo; mine; mine &= mine - 1) {
+            const float4 *src = &s_part[wv][__builtin_ctzll(mine) * (PW / 4)];
+            float w[PW];
+#pragma unroll
+            for (int k = 0; k < PW / 4; ++k) {
+                const float4 x = src[k];
+                w[4 * k] = x.x, w[4 * k + 1] = x.y, w[4 * k + 2] = x.z, w[4 * k + 3] = x.w;
+            }
+            TaskAcc<M> X;
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                X.cnt[v] = __float_as_int(w[v]);
+                X.mt[v] = w[M + v];
+                X.sm[v] = w[2 * M + v];
+                X.cs[v] = w[3 * M + v];
+            }
+            X.nb = __float_as_int(w[4 * M]);
+            task_fold(A, X);
+        }
+        if (head & 64) own_hi = 0;
+        else own_lo = 0;
+        head += n_t;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // queue the tasks of sub-chunk fi for the lanes in `lanes` (every lane is active)
+    auto enqueue = [&](int fi, unsigned long long lanes) {
+        const int k = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(lanes >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)lanes, 0u));
+        if ((lanes >> lane) & 1ull) {
+            const int pos = (tail + k) & (kRing - 1);
+            s_task[wv][pos] = fi;
+            s_owner[wv][pos] = (unsigned char)lane;
+            if (pos < 64) own_lo |= 1ull << pos;
+            else own_hi |= 1ull << (pos - 64);
+        }
+        const int cnt = __popcll(lanes);
+        tail += cnt;
+        if (tasks_done) *tasks_done += cnt;
+        if (tail - head >= 64) run_round(64);
+    };
+
+    const int n_chunks = (n + kCull - 1) / kCull;
+    const int n_fine = (n + kFine - 1) / kFine;
+    if constexpr (!CULL) {
+        for (int i = 0; split + i * S < n_chunks; ++i)
+            for (int k = 0; k < kFinePer; ++k) {
+                const int fi = (split + i * S) * kFinePer + k;
+                if (fi < n_fine) enqueue(fi, ~0ull);
+            }
+    } else {
+        const float *fine = cull + (size_t)n_chunks * kCullFloats;  // the sub-chunk level
+        float cx[1] = {own.cx}, cy[1] = {own.cy}, cz[1] = {own.cz}, qv[1] = {qa};
+        float wx, wy, wz, spread, qamax;
+        wave_sphere<1>(cx, cy, cz, qv, wx, wy, wz, spread, qamax);
+        cull_walk(
+            cull, n_chunks, split, S,
+            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + p.r_nbr); },
+            [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + p.r_nbr); },
+            [&](int i, unsigned long long lanes) {
+                for (int k = 0; k < kFinePer; ++k) {
+                    const int fi = (split + i * S) * kFinePer + k;
+                    if (fi >= n_fine) break;
+                    const ChunkMeta fm = load_chunk(fine, fi);
+                    const unsigned long long fl =
+                        lanes & __ballot(within(fm, own.cx, own.cy, own.cz, fm.rad + p.r_nbr));
+                    if (fl) enqueue(fi, fl);
+                }
+            });
+    }
+    if (tail > head) run_round(tail - head);
+    if (jq < q) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            const size_t o = ((size_t)split * M + v) * q + jq;
+            part.cnt[o] = A.cnt[v];
+            part.mt[o] = A.mt[v];
+            part.sm[o] = A.sm[v];
+            part.cs[o] = A.cs[v];
+        }
+        part.nb[(size_t)split * q + jq] = A.nb;
     }
 }
 
@@ -308,6 +622,10 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                                           const Part &part, const float *__restrict__ cull = nullptr,
                                           int *chunks_done = nullptr)
 {
+    if constexpr (FULL && BALL && QPL == 1) {
+        eval_tile_tasks<M, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, chunks_done);
+        return;
+    }
     // Spheres: centers (q x 3) and radii (q).  Ellipsoids (ELL): `centers`
     // holds the prepared records of kBodyFloats floats, `radii` is unused.
     QState<QPL, ELL> Q;
@@ -483,7 +801,9 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                     near |= within(m, Q.cx[u], Q.cy[u], Q.cz[u], m.rad + reach_of(m, Q.qa[u], Q.qk[u]));
                 return near;
             },
-            [&](int i) {
+            [&](int i, unsigned long long) {
+                // lanes outside every reach evaluate the chunk with the
+                // wave; their own exact tests reject each of its pairs
                 if (chunks_done) ++*chunks_done;
                 visit(i);
             });
@@ -523,6 +843,24 @@ pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
     eval_tile<M, FULL, BALL, QPL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
                                         &done);
     if (CULL && chunk_count && (threadIdx.x & 63) == 0) atomicAdd(chunk_count, (unsigned long long)done);
+}
+
+// The task walk as its own kernel (full outputs over a ball, one query per
+// lane), with its occupancy target.
+template <int M, bool CULL, bool ELL>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CSPLAT_TASK_WAVES_PER_EU)))
+pair_task_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const float *__restrict__ centers,
+                 const float *__restrict__ radii, int q, const EvalParams p, Part part,
+                 const float *__restrict__ cull, unsigned long long *__restrict__ task_count)
+{
+    int b = blockIdx.x;
+    const int B = gridDim.x;
+    if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few ranges
+    const int split = b / n_tiles;
+    const int tile = b - split * n_tiles;
+    int done = 0;
+    eval_tile_tasks<M, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
+    if (CULL && task_count && (threadIdx.x & 63) == 0) atomicAdd(task_count, (unsigned long long)done);
 }
 
 // Merge the split partials of query j, conservatism value v, in split order
@@ -614,10 +952,12 @@ struct SplitPlan {
     int n_tiles, S, per_split, qpl;
 };
 
-inline SplitPlan split_plan(int target_blocks, int q, int n, bool full)
+inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool ball)
 {
     SplitPlan sp;
     sp.qpl = full ? kQplFull : kQplLabels;
+    if (full && ball && sp.qpl == 1)  // the task walk
+        target_blocks = (int)((int64_t)target_blocks * CSPLAT_TASK_BLOCKS_PER_CU / CSPLAT_BLOCKS_PER_CU);
     sp.n_tiles = (q + kBlock * sp.qpl - 1) / (kBlock * sp.qpl);
     const int n_chunks = (n + kCull - 1) / kCull;
     int S = 0;

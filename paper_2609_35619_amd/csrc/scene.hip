@@ -155,27 +155,32 @@ __global__ void curve_key_kernel(int64_t n, const float *__restrict__ rec, const
     idx[i] = (uint32_t)i;
 }
 
-__global__ void gather_kernel(int64_t n_kept, const float *__restrict__ rec,
+// Records n_kept .. n_pad - 1 complete the last chunk: a mean at +infinity
+// (never inside a finite ball, and d = +-inf or NaN for every query) and zero
+// covariance, so a kernel can always read whole chunks.
+__global__ void gather_kernel(int64_t n_kept, int64_t n_pad, const float *__restrict__ rec,
                               const uint32_t *__restrict__ order, float *__restrict__ out)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one float per thread
-    if (t >= n_kept * kGaussFloats) return;
+    if (t >= n_pad * kGaussFloats) return;
     int64_t k = t / kGaussFloats;
     int c = (int)(t - k * kGaussFloats);
-    out[t] = rec[(size_t)kGaussFloats * order[k] + c];
+    out[t] = k < n_kept ? rec[(size_t)kGaussFloats * order[k] + c] : (c < 3 ? INFINITY : 0.f);
 }
 
-// Per chunk of kCullChunk Gaussians consecutive on the curve: the centre of the
+// Per chunk of `csz` Gaussians consecutive on the curve: the centre of the
 // bounding box of their means, the largest distance of a mean from it and the
-// largest scale (row norm of M), computed in double and rounded up.
+// largest scale (row norm of M), computed in double and rounded up.  Two
+// levels: chunks of kCullChunk, then sub-chunks of kFineChunk.
 constexpr int kCullChunk = 64;
+constexpr int kFineChunk = 16;
 
-__global__ void cull_meta_kernel(int64_t n, const float *__restrict__ g, float *__restrict__ meta)
+__global__ void cull_meta_kernel(int64_t n, int csz, const float *__restrict__ g, float *__restrict__ meta)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i0 = c * kCullChunk;
+    const int64_t i0 = c * csz;
     if (i0 >= n) return;
-    const int64_t i1 = i0 + kCullChunk < n ? i0 + kCullChunk : n;
+    const int64_t i1 = i0 + csz < n ? i0 + csz : n;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double smax = 0.0;
     for (int64_t i = i0; i < i1; ++i) {
@@ -305,22 +310,34 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
         return fail(CSPLAT_E_OOM, "scene_load: sort workspace");
     CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(d_tmp, tbytes, d_code, d_code2, d_idx, d_idx2,
                                                   (int)n, 0, 32, st));
+    // records in Hilbert order, padded to whole chunks of kCullChunk
+    const int64_t n_chunks = ((int64_t)kept + kCullChunk - 1) / kCullChunk;
+    const int64_t n_pad = n_chunks * kCullChunk;
     float *g = nullptr;
-    if (hipMalloc(&g, (size_t)kept * kGaussFloats * sizeof(float)) != hipSuccess)
+    if (hipMalloc(&g, (size_t)n_pad * kGaussFloats * sizeof(float)) != hipSuccess)
         return fail(CSPLAT_E_OOM, "scene_load: scene allocation");
     sc->gauss = g;
-    sc->device_bytes += (uint64_t)kept * kGaussFloats * sizeof(float);
-    int64_t tot = (int64_t)kept * kGaussFloats;
-    gather_kernel<<<(int)((tot + 255) / 256), 256, 0, st>>>((int64_t)kept, d_rec, d_idx2, g);
-    CSPLAT_HIP(hipGetLastError());
-    const int64_t n_chunks = ((int64_t)kept + kCullChunk - 1) / kCullChunk;
+    sc->device_bytes += (uint64_t)n_pad * kGaussFloats * sizeof(float);
+    int64_t tot = n_pad * kGaussFloats;
+    if (tot > 0) {
+        gather_kernel<<<(int)((tot + 255) / 256), 256, 0, st>>>((int64_t)kept, n_pad, d_rec, d_idx2, g);
+        CSPLAT_HIP(hipGetLastError());
+    }
+    // culling metadata: n_chunks records for the chunks, then one per
+    // sub-chunk (the sub-chunk level starts at record n_chunks)
+    const int64_t n_fine = ((int64_t)kept + kFineChunk - 1) / kFineChunk;
     float *cm = nullptr;
-    if (hipMalloc(&cm, (size_t)n_chunks * 8 * sizeof(float)) != hipSuccess)
+    if (hipMalloc(&cm, (size_t)(n_chunks + n_fine) * 8 * sizeof(float)) != hipSuccess)
         return fail(CSPLAT_E_OOM, "scene_load: culling metadata");
     sc->cull = cm;
-    sc->device_bytes += (uint64_t)n_chunks * 8 * sizeof(float);
-    cull_meta_kernel<<<(unsigned)((n_chunks + 127) / 128), 128, 0, st>>>((int64_t)kept, g, cm);
-    CSPLAT_HIP(hipGetLastError());
+    sc->device_bytes += (uint64_t)(n_chunks + n_fine) * 8 * sizeof(float);
+    if (n_chunks > 0) {
+        cull_meta_kernel<<<(unsigned)((n_chunks + 127) / 128), 128, 0, st>>>((int64_t)kept, kCullChunk, g, cm);
+        CSPLAT_HIP(hipGetLastError());
+        cull_meta_kernel<<<(unsigned)((n_fine + 127) / 128), 128, 0, st>>>((int64_t)kept, kFineChunk, g,
+                                                                          cm + (size_t)n_chunks * 8);
+        CSPLAT_HIP(hipGetLastError());
+    }
     for (int k = 0; k < 3; ++k) {
         sc->box_lo[k] = lo[k];
         sc->box_scale[k] = scl[k];

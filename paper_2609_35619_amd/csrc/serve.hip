@@ -77,9 +77,8 @@ struct StageLayout {
 };
 
 template <bool FULL, bool BALL>
-__global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const char *__restrict__ stage, int variant,
-                                                                          size_t desc_off, size_t items_off,
-                                                                          int32_t *__restrict__ next)
+__device__ __forceinline__ void step_body(const char *__restrict__ stage, int variant, size_t desc_off,
+                                          size_t items_off, int32_t *__restrict__ next)
 {
     // the staged step is read-only here (scalar loads); the work counter is
     // the header's next[variant], written only through `next`
@@ -105,6 +104,22 @@ __global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const cha
                                             __builtin_amdgcn_readfirstlane(w.tile), R.centers, R.radii, R.q, R.p,
                                             R.part, R.cull, nullptr);
     }
+}
+
+template <bool FULL, bool BALL>
+__global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const char *__restrict__ stage, int variant,
+                                                                          size_t desc_off, size_t items_off,
+                                                                          int32_t *__restrict__ next)
+{
+    step_body<FULL, BALL>(stage, variant, desc_off, items_off, next);
+}
+
+// Full outputs over a ball (the task walk), at its own occupancy target.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CSPLAT_TASK_WAVES_PER_EU)))
+step_task_kernel(const char *__restrict__ stage, int variant, size_t desc_off, size_t items_off,
+                 int32_t *__restrict__ next)
+{
+    step_body<true, true>(stage, variant, desc_off, items_off, next);
 }
 
 __global__ void __launch_bounds__(256) serve_combine_kernel(const char *__restrict__ stage, size_t desc_off)
@@ -356,7 +371,7 @@ csplat_status capture_graphs(csplat_server *s)
             step_kernel<false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 0, dof, iof, ctr + 0);
             step_kernel<false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 1, dof, iof, ctr + 1);
             step_kernel<true, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 2, dof, iof, ctr + 2);
-            step_kernel<true, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 3, dof, iof, ctr + 3);
+            step_task_kernel<<<kStepBlocks, kBlock, 0, s->stream>>>(st, 3, dof, iof, ctr + 3);
             serve_combine_kernel<<<1024, 256, 0, s->stream>>>(st, dof);
             e = hipGetLastError();
         }
@@ -508,7 +523,7 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     r.q = q;
     r.full = kind == CSPLAT_SERVE_COST;
     r.ball = std::isfinite(r.p.rn2);
-    r.sp = split_plan(target_blocks(s->device), (int)q, (int)sc->n, r.full);
+    r.sp = split_plan(target_blocks(s->device), (int)q, (int)sc->n, r.full, r.ball);
     r.pairs = q * sc->n;
     // the queries in the scene's Hilbert order (as csplat_eval evaluates
     // them): waves hold nearby spheres and the culling skips more; results
