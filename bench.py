@@ -40,7 +40,7 @@ OPS_IN_BALL_PER_NSIGMA = 15        # s~^2 (2), label (2), min (1), softmin (exp 
 # profiles/ (FETCH_SIZE and WRITE_SIZE of the same command, scaled by what the
 # counters read for a plain copy of known size).  It is reported only while
 # the kernel sources still hash to the digest recorded with the counters.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernel_mppi_nav.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_task_kernel_mppi_nav.md")
 KERNEL_SOURCES = ("paper_2609_35619_amd/csrc/pair_core.h", "paper_2609_35619_amd/csrc/pair_fp32.hip",
                   "paper_2609_35619_amd/csrc/internal.h")
 
@@ -223,7 +223,7 @@ def main():
         "vram_bytes": {"scene": int(scene_bytes), "workspace": int(st["workspace_bytes"])},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU / 1e9, "unit": "Gop/s",
                      "frac": achieved / PEAK_VALU, "traffic": traffic_from_profile(), "traffic_unit": "bytes",
-                     "kernel": "pair_kernel<3,full,ball>", "kernel_ms": kernel_s * 1e3,
+                     "kernel": "pair_task_kernel<3,cull,sphere>", "kernel_ms": kernel_s * 1e3,
                      "ops_per_launch": ops, "in_ball_pairs": nbr_total, "evaluated_pairs": evaluated,
                      "dense_pairs": pairs, "dense_ops_per_launch": dense_ops,
                      "dense_equivalent_frac": dense_ops / kernel_s / PEAK_VALU},
@@ -373,6 +373,8 @@ def precision_form(cs, eng):
         per_class = {}
         if prec != cs.CSPLAT_PRECISION_FP32:
             per_class = {"rechecked_fraction": flagged / qs.q}
+        if prec == cs.CSPLAT_PRECISION_FP32:
+            per_class = {"evaluated_pairs": int(st["kernel_pairs"])}
         out[name] = {"ms": dt * 1e3, "pair_evals_per_s": qs.q * n_kept / dt, "kernel_ms": st["kernel_ms"],
                      "rechecked_queries": flagged, **per_class}
         log(f"bench: precision {name}: {dt*1e3:.1f} ms")

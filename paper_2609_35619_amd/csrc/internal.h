@@ -98,7 +98,8 @@ struct csplat_scene {
     float *gauss = nullptr;   // 16-float records in Hilbert order of the means, padded to whole
                               // culling chunks of 64 (pad records: mean at +inf, zero covariance)
     float mu_max = 0.f;       // max |mu| over the kept Gaussians
-    float *cull = nullptr;    // per chunk of 64, then per sub-chunk of 16 (from record ceil(n / 64)):
+    float *cull = nullptr;    // per chunk of 64, then per sub-chunk of 16 (from record ceil(n / 64)),
+                              // then per group of 1024 (from record ceil(n / 64) + ceil(n / 16)):
                               // bounding sphere centre, radius, largest scale (8 floats each)
     float box_lo[3] = {0, 0, 0}, box_scale[3] = {0, 0, 0};  // grid of the kept means (one cell size)
     // precision form (optional): per tile of 512 Gaussians the packed MFMA

@@ -37,7 +37,7 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #define CSPLAT_QPL_FULL 1
 #endif
 #ifndef CSPLAT_QPL_LABELS
-#define CSPLAT_QPL_LABELS 2
+#define CSPLAT_QPL_LABELS 1  // 1: the task walk; 2: the wave walk with two queries per lane
 #endif
 #ifndef CSPLAT_PIPELINE
 #define CSPLAT_PIPELINE 0
@@ -53,6 +53,15 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 // (measured on MI355X: 1.25 -> 1.10 ms on the navigation workload).
 #ifndef CSPLAT_TASK_WAVES_PER_EU
 #define CSPLAT_TASK_WAVES_PER_EU 4
+#endif
+// Full outputs for ellipsoids over a ball: task walk (1) or wave walk (0).
+// The tabletop workload puts 88% of the pairs the task walk evaluates inside
+// the ball, so the wave walk's masked lanes cost little there, while the
+// task walk's per-lane record loads (48 B per pair against ~50 operations)
+// approach the vector-memory return rate (measured: 5.2 ms wave walk, 5.95
+// ms task walk).
+#ifndef CSPLAT_ELL_FULL_TASKS
+#define CSPLAT_ELL_FULL_TASKS 0
 #endif
 // Work items of the task walk per compute unit (fewer, longer splits keep
 // its task queues full; measured: 32 beats 16 and 64).
@@ -292,11 +301,12 @@ __device__ __forceinline__ void cull_walk(const float *__restrict__ cull, int n_
     for (int ib = 0; split + ib * S < n_chunks; ib += 64) {
         const int ci = split + (ib + lane) * S;
         ChunkMeta m{0.f, 0.f, 0.f, 0.f, 0.f};
-        bool pass = false;
+        bool ok = false;
         if (ci < n_chunks) {
             m = load_chunk(cull, ci);
-            pass = coarse(m);
+            ok = true;
         }
+        const bool pass = ok && coarse(m);
         unsigned long long mask = __ballot(pass);
         while (mask) {
             const int bit = __builtin_ctzll(mask);
@@ -327,6 +337,92 @@ __device__ __forceinline__ void cull_walk(const float *__restrict__ cull, int n_
 // dense walks give the same bits.
 constexpr int kFine = 16;                // Gaussians per task
 constexpr int kFinePer = kCull / kFine;  // sub-chunks per culling chunk
+constexpr int kGroup = 16;               // culling chunks per group (the task walk's coarsest level)
+
+// The task walk's culling.  Split `split` of S takes the chunks split,
+// split + S, ... (< n_chunks) as in cull_walk, visited in ascending order:
+// visit(c, lanes) for chunk c with the mask of its near lanes.  When S <= 16
+// every group of 16 chunks holds chunks of every split, and the walk goes
+// through the groups instead: 64 groups at a time against the wave
+// (`coarse`), then the split's chunks of a surviving group (`coarse` again),
+// then each surviving chunk against every query of the wave (`near`).  A
+// walk with a short reach (labels) culls nearly every batch, and the group
+// level cuts its batches by up to 16/S.  With AHEAD the next batch is
+// requested before the current one is tested (for walks that are mostly
+// culled; it holds five more registers).  The group level and AHEAD are
+// compiled in with LABELS only (full outputs over a 1 m ball rarely cull a
+// group, and the registers they hold would spill the full-output kernel).
+template <bool LABELS, class Coarse, class Near, class Visit>
+__device__ __forceinline__ void split_walk(const float *__restrict__ groups, const float *__restrict__ chunks,
+                                           int n_groups, int n_chunks, int split, int S, Coarse coarse, Near near,
+                                           Visit visit)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    constexpr bool AHEAD = LABELS;
+    const bool by_group = LABELS && S <= kGroup;
+    const int n_units = by_group ? n_groups : n_chunks;
+    const int stride = by_group ? 1 : S;
+    const int first = by_group ? 0 : split;
+    const float *meta = by_group ? groups : chunks;
+    auto fetch = [&](int ib, ChunkMeta &m) {
+        const int u = first + (ib + lane) * stride;
+        m = u < n_units ? load_chunk(meta, u) : ChunkMeta{0.f, 0.f, 0.f, 0.f, 0.f};
+        return u < n_units;
+    };
+    ChunkMeta next{0.f, 0.f, 0.f, 0.f, 0.f};
+    bool next_ok = false;
+    if constexpr (AHEAD) next_ok = fetch(0, next);
+    for (int ib = 0; first + ib * stride < n_units; ib += 64) {
+        ChunkMeta m;
+        bool ok;
+        if constexpr (AHEAD) {
+            m = next;
+            ok = next_ok;
+            next_ok = fetch(ib + 64, next);
+        } else {
+            ok = fetch(ib, m);
+        }
+        const unsigned long long mask = __ballot(ok && coarse(m));
+        // the surviving groups to open, or the batch itself as one (one
+        // visit site, so the caller's visit is inlined once)
+        unsigned long long gmask = by_group ? mask : 1ull;
+        while (gmask) {
+            ChunkMeta cm = m;
+            unsigned long long cmask = mask;
+            int c0 = first + ib * stride, cs = stride;
+            if (by_group) {
+                // the split's chunks of group gi: gi*16 <= c < gi*16 + 16, c = split (mod S)
+                const int gi = ib + __builtin_ctzll(gmask);
+                const int base = gi * kGroup;
+                c0 = base + ((split - base) % S + S) % S;
+                cs = S;
+                const int c = c0 + lane * S;
+                bool cok = false;
+                cm = ChunkMeta{0.f, 0.f, 0.f, 0.f, 0.f};
+                if (c < base + kGroup && c < n_chunks) {
+                    cm = load_chunk(chunks, c);
+                    cok = coarse(cm);
+                }
+                cmask = __ballot(cok);
+            }
+            gmask &= gmask - 1;
+            while (cmask) {
+                const int cb = __builtin_ctzll(cmask);
+                cmask &= cmask - 1;
+                const unsigned long long lanes = __ballot(near(lane_chunk(cm, cb)));
+                if (lanes) visit(c0 + cb * cs, lanes);
+            }
+        }
+    }
+}
+
+// Which evaluations run as tasks: labels, and full outputs over a ball, with
+// one query per lane.
+template <bool FULL, bool BALL, int QPL, bool ELL>
+constexpr bool uses_tasks()
+{
+    return QPL == 1 && (!FULL || (BALL && (!ELL || CSPLAT_ELL_FULL_TASKS)));
+}
 
 template <int M>
 struct TaskAcc {
@@ -385,6 +481,30 @@ __device__ __forceinline__ void task_pair(const float4 &r0, const float4 &r1, co
     }
 }
 
+// One pair for labels only: the sqrt-free test a |a| < 4 n^2 W with
+// a = (r^2)(s^2 - 1) (an exact rewrite of s~^2 < 1), inside the ball if any.
+template <int M, bool BALL, bool ELL>
+__device__ __forceinline__ void task_pair_label(const float4 &r0, const float4 &r1, const float4 &r2,
+                                                const TaskQuery<ELL> &Q, const EvalParams &p, TaskAcc<M> &T)
+{
+    const float dx = r0.x - Q.cx, dy = r0.y - Q.cy, dz = r0.z - Q.cz;
+    const float gp[12] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
+    float a, D, W;
+    bool in = true;
+    if constexpr (ELL) {
+        metric_dw<ELL>(gp, Q.L, dx, dy, dz, 0.f, D, W);
+        a = D - 1.f;
+        if constexpr (BALL) in = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= p.rn2;
+    } else {
+        a = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -Q.r2)));
+        metric_dw<ELL>(gp, Q.L, dx, dy, dz, 0.f, D, W);
+        if constexpr (BALL) in = a + Q.r2 <= p.rn2;
+    }
+    const float aa = a * fabsf(a);
+#pragma unroll
+    for (int v = 0; v < M; ++v) T.cnt[v] += in && (aa < p.four_n2[v] * W);
+}
+
 // Fold a task partial X into the totals A (first-level sums into the second).
 template <int M>
 __device__ __forceinline__ void task_fold(TaskAcc<M> &A, const TaskAcc<M> &X)
@@ -404,24 +524,26 @@ __device__ __forceinline__ void task_fold(TaskAcc<M> &A, const TaskAcc<M> &X)
     A.nb += X.nb;
 }
 
-// Words of a task partial in LDS: 4M + 1 rounded up to whole float4s, and
-// kept off a multiple of 8 words so that the lanes' rows spread over banks.
-template <int M>
+// Words of a task partial in LDS (4M + 1 for full outputs, M for labels)
+// rounded up to whole float4s, and kept off a multiple of 8 words so that the
+// lanes' rows spread over banks.
+constexpr int task_words_of(int w) { return ((w + 3) / 4) * 4 % 8 == 0 ? ((w + 3) / 4) * 4 + 4 : ((w + 3) / 4) * 4; }
+template <int M, bool FULL>
 constexpr int task_words()
 {
-    return ((4 * M + 1 + 3) / 4) * 4 % 8 == 0 ? ((4 * M + 1 + 3) / 4) * 4 + 4 : ((4 * M + 1 + 3) / 4) * 4;
+    return task_words_of(FULL ? 4 * M + 1 : M);
 }
 
 __device__ __forceinline__ float lane_shfl(float v, int src) { return __shfl(v, src); }
 
-template <int M, bool CULL, bool ELL>
+template <int M, bool FULL, bool BALL, bool CULL, bool ELL>
 __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, int n, int S, int split, int tile,
                                                 const float *__restrict__ centers, const float *__restrict__ radii,
                                                 int q, const EvalParams &p, const Part &part,
                                                 const float *__restrict__ cull, int *tasks_done)
 {
     constexpr int kRing = 128;  // queued tasks per wave: at most 63 waiting + 64 of one sub-chunk
-    constexpr int PW = task_words<M>();
+    constexpr int PW = task_words<M, FULL>();
     constexpr int kWaves = kBlock / 64;
     __shared__ int s_task[kWaves][kRing];              // sub-chunk of each queued task
     __shared__ unsigned char s_owner[kWaves][kRing];   // lane of its query
@@ -430,16 +552,17 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
     const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
     TaskQuery<ELL> own;
-    float qa;
+    float qa, qk;  // reach constants: smallest semi-axis squared, largest / smallest
     if constexpr (ELL) {
         const float4 *b = reinterpret_cast<const float4 *>(centers + (size_t)kBodyFloats * jj);
-        const float4 b0 = b[0], b1 = b[1], b2 = b[2];
+        const float4 b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3];
         own.cx = b0.x, own.cy = b0.y, own.cz = b0.z;
         own.L[0] = b0.w, own.L[1] = b1.x, own.L[2] = b1.y, own.L[3] = b1.z, own.L[4] = b1.w;
         own.L[5] = b2.x, own.L[6] = b2.y, own.L[7] = b2.z, own.L[8] = b2.w;
         own.r2 = 1.f;
         own.kq = p.kt;
-        qa = 0.f;
+        qa = b3.x;
+        qk = b3.y;
     } else {
         own.cx = centers[3 * jj];
         own.cy = centers[3 * jj + 1];
@@ -448,6 +571,7 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         own.r2 = r * r;
         own.kq = p.kt / own.r2;
         qa = own.r2;
+        qk = 1.f;
     }
     TaskAcc<M> A;
     task_reset(A);
@@ -476,7 +600,7 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         tq.cy = lane_shfl(own.cy, qi);
         tq.cz = lane_shfl(own.cz, qi);
         tq.r2 = lane_shfl(own.r2, qi);
-        tq.kq = lane_shfl(own.kq, qi);
+        if constexpr (FULL) tq.kq = lane_shfl(own.kq, qi);
         if constexpr (ELL) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) tq.L[k] = lane_shfl(own.L[k], qi);
@@ -495,21 +619,27 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
                 r[u][2] = rp[u * (kGaussFloats / 4) + 2];
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, p, g0v, T);
+            for (int u = 0; u < kUnroll; ++u) {
+                if constexpr (FULL) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, p, g0v, T);
+                else task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tq, p, T);
+            }
         }
         // the round's partials to LDS (slot = lane), words: cnt | mt | sm | cs | nb
         {
+            constexpr int used = FULL ? 4 * M + 1 : M;
             float w[PW];
 #pragma unroll
             for (int v = 0; v < M; ++v) {
                 w[v] = __int_as_float(T.cnt[v]);
-                w[M + v] = T.mt[v];
-                w[2 * M + v] = T.sm[v];
-                w[3 * M + v] = T.cs[v];
+                if constexpr (FULL) {
+                    w[M + v] = T.mt[v];
+                    w[2 * M + v] = T.sm[v];
+                    w[3 * M + v] = T.cs[v];
+                }
             }
-            w[4 * M] = __int_as_float(T.nb);
+            if constexpr (FULL) w[4 * M] = __int_as_float(T.nb);
 #pragma unroll
-            for (int k = 4 * M + 1; k < PW; ++k) w[k] = 0.f;
+            for (int k = used; k < PW; ++k) w[k] = 0.f;
             float4 *dst = &s_part[wv][lane * (PW / 4)];
 #pragma unroll
             for (int k = 0; k < PW / 4; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
@@ -527,16 +657,21 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
                 const float4 x = src[k];
                 w[4 * k] = x.x, w[4 * k + 1] = x.y, w[4 * k + 2] = x.z, w[4 * k + 3] = x.w;
             }
-            TaskAcc<M> X;
+            if constexpr (FULL) {
+                TaskAcc<M> X;
 #pragma unroll
-            for (int v = 0; v < M; ++v) {
-                X.cnt[v] = __float_as_int(w[v]);
-                X.mt[v] = w[M + v];
-                X.sm[v] = w[2 * M + v];
-                X.cs[v] = w[3 * M + v];
+                for (int v = 0; v < M; ++v) {
+                    X.cnt[v] = __float_as_int(w[v]);
+                    X.mt[v] = w[M + v];
+                    X.sm[v] = w[2 * M + v];
+                    X.cs[v] = w[3 * M + v];
+                }
+                X.nb = __float_as_int(w[4 * M]);
+                task_fold(A, X);
+            } else {
+#pragma unroll
+                for (int v = 0; v < M; ++v) A.cnt[v] += __float_as_int(w[v]);
             }
-            X.nb = __float_as_int(w[4 * M]);
-            task_fold(A, X);
         }
         if (head & 64) own_hi = 0;
         else own_lo = 0;
@@ -564,29 +699,63 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
 
     const int n_chunks = (n + kCull - 1) / kCull;
     const int n_fine = (n + kFine - 1) / kFine;
+    const int n_groups = (n_chunks + kGroup - 1) / kGroup;
     if constexpr (!CULL) {
-        for (int i = 0; split + i * S < n_chunks; ++i)
+        for (int c = split; c < n_chunks; c += S)
             for (int k = 0; k < kFinePer; ++k) {
-                const int fi = (split + i * S) * kFinePer + k;
+                const int fi = c * kFinePer + k;
                 if (fi < n_fine) enqueue(fi, ~0ull);
             }
     } else {
-        const float *fine = cull + (size_t)n_chunks * kCullFloats;  // the sub-chunk level
+        const float *fine = cull + (size_t)n_chunks * kCullFloats;     // the sub-chunk level
+        const float *groups = fine + (size_t)n_fine * kCullFloats;     // the group level
         float cx[1] = {own.cx}, cy[1] = {own.cy}, cz[1] = {own.cz}, qv[1] = {qa};
         float wx, wy, wz, spread, qamax;
         wave_sphere<1>(cx, cy, cz, qv, wx, wy, wz, spread, qamax);
-        cull_walk(
-            cull, n_chunks, split, S,
-            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + p.r_nbr); },
-            [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + p.r_nbr); },
-            [&](int i, unsigned long long lanes) {
+        float qkmax = qk;
+        if constexpr (ELL) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) qkmax = fmaxf(qkmax, __shfl_xor(qkmax, off));
+        }
+        // how far from a body's centre a chunk can hold a counted pair: the
+        // ball for full outputs; for labels the collision bound
+        // qk (n s + sqrt(n^2 s^2 + qa)) (s: the chunk's largest scale),
+        // capped by the ball when one is given
+        auto reach_of = [&](const ChunkMeta &m, float a2, float k) {
+            if constexpr (FULL) {
+                return p.r_nbr;
+            } else {
+                const float ns = p.n_max * m.smax;
+                float reach = ns + fast_sqrt(fmaf(ns, ns, a2));  // v_sqrt: ~1 ulp, far inside kCullMargin
+                if constexpr (ELL) reach *= k;
+                if constexpr (BALL) reach = fminf(reach, p.r_nbr);
+                return reach;
+            }
+        };
+        split_walk<!FULL>(
+            groups, cull, n_groups, n_chunks, split, S,
+            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m, qamax, qkmax)); },
+            [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + reach_of(m, qa, qk)); },
+            [&](int ci, unsigned long long lanes) {
+                // the sub-chunks' records are read together (one latency),
+                // tested, and their lanes rotated through one enqueue site
+                static_assert(kFinePer == 4, "sub-chunk rotation below assumes four");
+                const int f0 = ci * kFinePer;
+                ChunkMeta fm[kFinePer];
+#pragma unroll
+                for (int k = 0; k < kFinePer; ++k) fm[k] = load_chunk(fine, min(f0 + k, n_fine - 1));
+                unsigned long long fl[kFinePer];
+#pragma unroll
                 for (int k = 0; k < kFinePer; ++k) {
-                    const int fi = (split + i * S) * kFinePer + k;
-                    if (fi >= n_fine) break;
-                    const ChunkMeta fm = load_chunk(fine, fi);
-                    const unsigned long long fl =
-                        lanes & __ballot(within(fm, own.cx, own.cy, own.cz, fm.rad + p.r_nbr));
-                    if (fl) enqueue(fi, fl);
+                    const unsigned long long exists = f0 + k < n_fine ? ~0ull : 0ull;
+                    fl[k] = lanes & exists &
+                            __ballot(within(fm[k], own.cx, own.cy, own.cz, fm[k].rad + reach_of(fm[k], qa, qk)));
+                }
+                unsigned long long l0 = fl[0], l1 = fl[1], l2 = fl[2], l3 = fl[3];
+#pragma unroll 1
+                for (int k = 0; k < kFinePer; ++k) {
+                    if (l0) enqueue(f0 + k, l0);
+                    l0 = l1, l1 = l2, l2 = l3, l3 = 0;
                 }
             });
     }
@@ -596,11 +765,13 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         for (int v = 0; v < M; ++v) {
             const size_t o = ((size_t)split * M + v) * q + jq;
             part.cnt[o] = A.cnt[v];
-            part.mt[o] = A.mt[v];
-            part.sm[o] = A.sm[v];
-            part.cs[o] = A.cs[v];
+            if constexpr (FULL) {
+                part.mt[o] = A.mt[v];
+                part.sm[o] = A.sm[v];
+                part.cs[o] = A.cs[v];
+            }
         }
-        part.nb[(size_t)split * q + jq] = A.nb;
+        if constexpr (FULL) part.nb[(size_t)split * q + jq] = A.nb;
     }
 }
 
@@ -622,8 +793,9 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                                           const Part &part, const float *__restrict__ cull = nullptr,
                                           int *chunks_done = nullptr)
 {
-    if constexpr (FULL && BALL && QPL == 1) {
-        eval_tile_tasks<M, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, chunks_done);
+    if constexpr (uses_tasks<FULL, BALL, QPL, ELL>()) {
+        eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
+                                                  chunks_done);
         return;
     }
     // Spheres: centers (q x 3) and radii (q).  Ellipsoids (ELL): `centers`
@@ -785,7 +957,7 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                 return p.r_nbr;
             } else {
                 const float ns = p.n_max * m.smax;
-                float reach = ns + sqrtf(fmaf(ns, ns, qa));
+                float reach = ns + fast_sqrt(fmaf(ns, ns, qa));  // v_sqrt: ~1 ulp, far inside kCullMargin
                 if constexpr (ELL) reach *= qk;
                 if constexpr (BALL) reach = fminf(reach, p.r_nbr);
                 return reach;
@@ -845,10 +1017,18 @@ pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
     if (CULL && chunk_count && (threadIdx.x & 63) == 0) atomicAdd(chunk_count, (unsigned long long)done);
 }
 
-// The task walk as its own kernel (full outputs over a ball, one query per
-// lane), with its occupancy target.
-template <int M, bool CULL, bool ELL>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CSPLAT_TASK_WAVES_PER_EU)))
+// The task walk as its own kernel (labels, or full outputs over a ball; one
+// query per lane), with its occupancy target.
+// Instances whose state outgrows the cap (ellipsoids with several
+// conservatism values) keep 3 waves per SIMD rather than spill.
+template <int M, bool FULL, bool ELL>
+constexpr int task_waves_per_eu()
+{
+    return (ELL && !(FULL && M == 1)) || (FULL && M > 3) ? 3 : CSPLAT_TASK_WAVES_PER_EU;
+}
+
+template <int M, bool FULL, bool BALL, bool CULL, bool ELL>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(task_waves_per_eu<M, FULL, ELL>())))
 pair_task_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const float *__restrict__ centers,
                  const float *__restrict__ radii, int q, const EvalParams p, Part part,
                  const float *__restrict__ cull, unsigned long long *__restrict__ task_count)
@@ -859,7 +1039,7 @@ pair_task_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const 
     const int split = b / n_tiles;
     const int tile = b - split * n_tiles;
     int done = 0;
-    eval_tile_tasks<M, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
+    eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
     if (CULL && task_count && (threadIdx.x & 63) == 0) atomicAdd(task_count, (unsigned long long)done);
 }
 
@@ -945,18 +1125,19 @@ combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out, const i
 // How an evaluation of q queries against n Gaussians is cut into work items:
 // query tiles of kBlock x QPL queries times S splits of the Gaussian chunks
 // (split s takes every S-th chunk from s), enough items to fill the device
-// several times over and at least 16 chunks per split.  Depends only on
-// (q, n, mode, device), so a request gives the same partial reductions
-// wherever it runs.  per_split: Gaussians of the largest split.
+// several times over and at least 16 chunks per split.  Depends only on (q, n, mode, device), so a
+// request gives the same partial reductions wherever it runs.  per_split:
+// Gaussians of the largest split.
 struct SplitPlan {
     int n_tiles, S, per_split, qpl;
 };
 
-inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool ball)
+inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool ball, bool ell = false)
 {
     SplitPlan sp;
     sp.qpl = full ? kQplFull : kQplLabels;
-    if (full && ball && sp.qpl == 1)  // the task walk
+    const bool tasks = sp.qpl == 1 && (!full || (ball && (!ell || CSPLAT_ELL_FULL_TASKS)));
+    if (tasks)
         target_blocks = (int)((int64_t)target_blocks * CSPLAT_TASK_BLOCKS_PER_CU / CSPLAT_BLOCKS_PER_CU);
     sp.n_tiles = (q + kBlock * sp.qpl - 1) / (kBlock * sp.qpl);
     const int n_chunks = (n + kCull - 1) / kCull;

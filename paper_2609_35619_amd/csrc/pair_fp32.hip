@@ -49,12 +49,15 @@ template <int M, bool FULL, bool BALL, bool CULL>
 void launch_pair(const Launch &L)
 {
     constexpr int QPL = FULL ? kQplFull : kQplLabels;
-    if constexpr (FULL && BALL && QPL == 1) {
-        if (L.ell)
-            pair_task_kernel<M, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
+    if constexpr (QPL == 1 && (BALL || !FULL)) {
+        if (L.ell && !uses_tasks<FULL, BALL, QPL, true>())
+            pair_kernel<M, FULL, BALL, QPL, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
+                L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
+        else if (L.ell)
+            pair_task_kernel<M, FULL, BALL, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
                 L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
         else
-            pair_task_kernel<M, CULL, false><<<L.grid, kBlock, 0, L.st>>>(
+            pair_task_kernel<M, FULL, BALL, CULL, false><<<L.grid, kBlock, 0, L.st>>>(
                 L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
     } else {
         if (L.ell)
@@ -222,7 +225,7 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     const bool ball = std::isfinite(p.rn2);
     // culling applies to labels, and to full outputs over a finite ball
     const bool cull = p.cull && n > 0 && sc->cull && (!full || ball);
-    const SplitPlan sp = split_plan(ctx_target_blocks(ctx), q, n, full, ball);
+    const SplitPlan sp = split_plan(ctx_target_blocks(ctx), q, n, full, ball, ell);
     const int S = std::max(sp.S, 1);
     const int M = p.m;
     const size_t words = (size_t)S * q * part_words(M, full);
@@ -261,9 +264,10 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
         L.cull = sc->cull;
         L.chunk_count = sq.counter;
         ctx->chunk_counter = sq.counter;
-        // the counter counts visited (wave, chunk) steps, or for full outputs
-        // over a ball with one query per lane (query, chunk) tasks
-        ctx->pairs_per_chunk = (full && ball && sp.qpl == 1) ? (int64_t)kFine : (int64_t)kCull * 64 * sp.qpl;
+        // the counter counts visited (wave, chunk) steps, or in the task
+        // walk (query, sub-chunk) tasks
+        const bool tasks = sp.qpl == 1 && (!full || (ball && (!ell || CSPLAT_ELL_FULL_TASKS)));
+        ctx->pairs_per_chunk = tasks ? (int64_t)kFine : (int64_t)kCull * 64 * sp.qpl;
     }
     switch (M) {
     case 1: launch_m<1>(ctx, full, ball, cull, L); break;

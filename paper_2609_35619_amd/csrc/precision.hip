@@ -426,7 +426,7 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         pair::wave_sphere<2>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
         auto reach_of = [&](const pair::ChunkMeta &m, float rr2) {
             const float ns = n_sigma * m.smax;
-            return ns + sqrtf(fmaf(ns, ns, rr2));
+            return ns + pair::fast_sqrt(fmaf(ns, ns, rr2));  // ~1 ulp, far inside the culling margin
         };
         for (int ib = 0; split + ib * S < n_tiles; ib += 64 / kChunksPerTile) {
             const int t = split + (ib + lane / kChunksPerTile) * S;
@@ -558,7 +558,7 @@ recheck_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restr
             pair::wave_sphere<1>(fc[0], fc[1], fc[2], fr2, wx, wy, wz, spread, r2max);
             auto reach_of = [&](const pair::ChunkMeta &m, float rr2) {
                 const float ns = n_sigma * m.smax;
-                return ns + sqrtf(fmaf(ns, ns, rr2));
+                return ns + pair::fast_sqrt(fmaf(ns, ns, rr2));  // ~1 ulp, far inside the culling margin
             };
             for (int ib = 0; split + ib * kRecheckSplits < n_chunks; ib += 64) {
                 const int ci = split + (ib + lane) * kRecheckSplits;

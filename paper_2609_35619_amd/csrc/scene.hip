@@ -174,6 +174,7 @@ __global__ void gather_kernel(int64_t n_kept, int64_t n_pad, const float *__rest
 // levels: chunks of kCullChunk, then sub-chunks of kFineChunk.
 constexpr int kCullChunk = 64;
 constexpr int kFineChunk = 16;
+constexpr int kGroupChunk = 1024;  // 16 chunks
 
 __global__ void cull_meta_kernel(int64_t n, int csz, const float *__restrict__ g, float *__restrict__ meta)
 {
@@ -324,18 +325,24 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
         CSPLAT_HIP(hipGetLastError());
     }
     // culling metadata: n_chunks records for the chunks, then one per
-    // sub-chunk (the sub-chunk level starts at record n_chunks)
+    // sub-chunk (from record n_chunks), then one per group of 16 chunks
+    // (from record n_chunks + n_fine)
     const int64_t n_fine = ((int64_t)kept + kFineChunk - 1) / kFineChunk;
+    const int64_t n_group = ((int64_t)kept + kGroupChunk - 1) / kGroupChunk;
+    const int64_t n_meta = n_chunks + n_fine + n_group;
     float *cm = nullptr;
-    if (hipMalloc(&cm, (size_t)(n_chunks + n_fine) * 8 * sizeof(float)) != hipSuccess)
+    if (hipMalloc(&cm, (size_t)n_meta * 8 * sizeof(float)) != hipSuccess)
         return fail(CSPLAT_E_OOM, "scene_load: culling metadata");
     sc->cull = cm;
-    sc->device_bytes += (uint64_t)(n_chunks + n_fine) * 8 * sizeof(float);
+    sc->device_bytes += (uint64_t)n_meta * 8 * sizeof(float);
     if (n_chunks > 0) {
         cull_meta_kernel<<<(unsigned)((n_chunks + 127) / 128), 128, 0, st>>>((int64_t)kept, kCullChunk, g, cm);
         CSPLAT_HIP(hipGetLastError());
         cull_meta_kernel<<<(unsigned)((n_fine + 127) / 128), 128, 0, st>>>((int64_t)kept, kFineChunk, g,
                                                                           cm + (size_t)n_chunks * 8);
+        CSPLAT_HIP(hipGetLastError());
+        cull_meta_kernel<<<(unsigned)((n_group + 127) / 128), 128, 0, st>>>(
+            (int64_t)kept, kGroupChunk, g, cm + (size_t)(n_chunks + n_fine) * 8);
         CSPLAT_HIP(hipGetLastError());
     }
     for (int k = 0; k < 3; ++k) {

@@ -194,6 +194,45 @@ def test_parameter_variants(cs, eng, oracle_mod, variant):
     _check(gpu, ref, p, variant)
 
 
+def test_task_walk_queue_edges(cs, eng, oracle_mod):
+    """Full outputs over a ball run as (query, sub-chunk) tasks queued per
+    wave: a cluster inside every query's ball queues up to 64 tasks per
+    sub-chunk (the ring wraps many times), n = 1037 leaves a last sub-chunk
+    of 13 Gaussians plus padding, q = 197 a partial last wave, and far
+    queries have no task at all.  Parity with the oracle on every output and
+    the same bits with culling off."""
+    import torch
+    _say("case: task walk, clustered 1037 Gaussians x 197 queries, ball 0.5")
+    rng = np.random.default_rng(11)
+    q, s, o = common_attrs(rng, 1037)
+    m = (0.5 + 0.1 * rng.standard_normal((1037, 3))).astype(np.float32)
+    sc = Scene(m, q, s * 0.3, o)
+    near = (0.5 + 0.15 * rng.standard_normal((190, 3))).astype(np.float32)
+    near[:4] = near[0]                                    # coincident queries
+    far = np.array([[5.0, 5.0, 5.0], [-4.0, 0.5, 0.5], [0.5, 9.0, 0.5]], np.float32)
+    centers = np.concatenate([near[:100], far, near[100:], far[:1], m[:3]]).astype(np.float32)
+    assert centers.shape[0] == 197
+    qs = Queries(centers, rng.uniform(0.02, 0.08, 197).astype(np.float32))
+    p = dict(n_sigma=[0.0, 1.0, 3.0], tau=0.05, k=1, r_nbr=0.5, gamma=1.5, d_max=2.0)
+    gpu = _run(cs, eng, sc, qs, p)
+    _check(gpu, _oracle(oracle_mod, sc, qs, p), p, "task-walk")
+    h = eng.load_scene(sc)
+    eng.set_conservatism(p["n_sigma"])
+    c = torch.from_numpy(qs.centers).cuda()
+    r = torch.from_numpy(qs.radii).cuda()
+    res = {}
+    for cull in (0, 1):
+        opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"],
+                              s_min=1.0, cull=cull)
+        out = eng.evaluate(h, c, r, opts, ALL)
+        torch.cuda.synchronize()
+        res[cull] = {k: v.cpu().numpy() for k, v in out.items()}
+    cs.csplat_scene_free(h)
+    for k in ALL:
+        assert np.array_equal(res[0][k].view(np.uint8), res[1][k].view(np.uint8)), k
+    assert np.all(res[1]["nbr"][[100, 101, 102, 193]] == 0)  # far queries: empty ball
+
+
 def test_invalid_inputs_are_rejected_without_writing(cs, eng):
     import torch
     _say("case: invalid inputs")
