@@ -51,6 +51,42 @@ __host__ __device__ inline uint32_t hilbert_key(uint32_t x, uint32_t y, uint32_t
     return key;
 }
 
+// The same key without data-dependent branches (host side: the serving form
+// sorts each request's spheres on the host, millions at a time).
+inline uint32_t spread3_10(uint32_t v)  // bit i of v to bit 3i
+{
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+inline uint32_t hilbert_key_branchless(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint32_t X[3] = {x & 1023u, y & 1023u, z & 1023u};
+    for (uint32_t Q = 512u; Q > 1u; Q >>= 1) {
+        const uint32_t P = Q - 1u;
+        for (int i = 0; i < 3; ++i) {
+            const uint32_t set = 0u - ((X[i] & Q) != 0u);        // all ones when bit Q of X[i] is set
+            const uint32_t t = (X[0] ^ X[i]) & P & ~set;         // exchange otherwise
+            X[0] ^= (P & set) ^ t;
+            X[i] ^= t;
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    // t = XOR of (Q - 1) over the set bits Q > 1 of X[2]: bit j of t is the
+    // parity of X[2]'s bits above j
+    uint32_t t = 0;
+    for (int b = 9; b >= 1; --b) t ^= (0u - ((X[2] >> b) & 1u)) & ((1u << b) - 1u);
+    X[0] ^= t;
+    X[1] ^= t;
+    X[2] ^= t;
+    return (spread3_10(X[0]) << 2) | (spread3_10(X[1]) << 1) | spread3_10(X[2]);
+}
+
 // Prepared ellipsoidal body: centre (3), L = diag(1/a) R^T row-major (9), the
 // reach constants qa = (smallest semi-axis)^2 and qk = largest / smallest, 0, 0.
 constexpr int kBodyFloats = 16;

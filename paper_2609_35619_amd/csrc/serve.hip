@@ -141,6 +141,28 @@ double now_s()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// f(begin, end) over [0, n) on up to 16 host threads (one for small n).
+template <class F>
+void parallel_rows(size_t n, F f)
+{
+    const size_t kMinRows = 1 << 17;
+    unsigned t = std::thread::hardware_concurrency();
+    t = std::max(1u, std::min(t, 16u));
+    if (n < 2 * kMinRows || t == 1) {
+        f(0, n);
+        return;
+    }
+    t = (unsigned)std::min<size_t>(t, n / kMinRows);
+    std::vector<std::thread> pool;
+    const size_t per = (n + t - 1) / t;
+    for (unsigned k = 1; k < t; ++k) {
+        const size_t b = k * per, e = std::min(n, b + per);
+        if (b < e) pool.emplace_back([=, &f] { f(b, e); });
+    }
+    f(0, std::min(n, per));
+    for (auto &th : pool) th.join();
+}
+
 struct Rec {
     int32_t scene = 0, kind = 0;
     int64_t q = 0;
@@ -513,11 +535,16 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     Rec r;
     csplat_status st = build_params(n_sigma, 1, *opts, r.p);
     if (st != CSPLAT_OK) return st;
-    std::unique_lock<std::mutex> lk(s->mu);
-    if (s->fatal != CSPLAT_OK) return fail(s->fatal, s->fatal_msg);
-    if (scene_id < 0 || scene_id >= (int32_t)s->scenes.size())
-        return fail(CSPLAT_E_NOT_FOUND, "server_submit: unknown scene id");
-    const csplat_scene *sc = s->scenes[(size_t)scene_id];
+    const csplat_scene *sc = nullptr;
+    {
+        // resident scenes stay until the server is destroyed: the pointer
+        // and the scene's grid are read without the lock below
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->fatal != CSPLAT_OK) return fail(s->fatal, s->fatal_msg);
+        if (scene_id < 0 || scene_id >= (int32_t)s->scenes.size())
+            return fail(CSPLAT_E_NOT_FOUND, "server_submit: unknown scene id");
+        sc = s->scenes[(size_t)scene_id];
+    }
     r.scene = scene_id;
     r.kind = kind;
     r.q = q;
@@ -528,26 +555,41 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     // the queries in the scene's Hilbert order (as csplat_eval evaluates
     // them): waves hold nearby spheres and the culling skips more; results
     // go back to the caller's order when collected
+    // (key << 32 | index) words: keys and the gather on several host threads
+    // for large requests, a stable LSD radix sort on the 30 key bits (the
+    // same order as sorting (key, index) pairs)
     {
-        std::vector<std::pair<uint32_t, int32_t>> key((size_t)q);
-        for (int64_t j = 0; j < q; ++j) {
-            uint32_t ix[3];
-            for (int k = 0; k < 3; ++k) {
-                const float f = (centers[3 * j + k] - sc->box_lo[k]) * sc->box_scale[k];
-                ix[k] = (uint32_t)std::min(std::max(f, 0.f), 1023.f);
+        const size_t qn = (size_t)q;
+        std::vector<uint64_t> a(qn), b(qn);
+        parallel_rows(qn, [&](size_t j0, size_t j1) {
+            for (size_t j = j0; j < j1; ++j) {
+                uint32_t ix[3];
+                for (int k = 0; k < 3; ++k) {
+                    const float f = (centers[3 * j + k] - sc->box_lo[k]) * sc->box_scale[k];
+                    ix[k] = (uint32_t)std::min(std::max(f, 0.f), 1023.f);
+                }
+                a[j] = ((uint64_t)hilbert_key_branchless(ix[0], ix[1], ix[2]) << 32) | (uint64_t)j;
             }
-            key[(size_t)j] = {hilbert_key(ix[0], ix[1], ix[2]), (int32_t)j};
+        });
+        for (int pass = 0; pass < 3; ++pass) {
+            const int sh = 32 + 10 * pass;
+            std::vector<size_t> pos(1025, 0);
+            for (size_t j = 0; j < qn; ++j) ++pos[((a[j] >> sh) & 1023u) + 1];
+            for (int d = 0; d < 1024; ++d) pos[d + 1] += pos[d];
+            for (size_t j = 0; j < qn; ++j) b[pos[(a[j] >> sh) & 1023u]++] = a[j];
+            a.swap(b);
         }
-        std::sort(key.begin(), key.end());
-        r.perm.resize((size_t)q);
-        r.centers.resize((size_t)q * 3);
-        r.radii.resize((size_t)q);
-        for (int64_t j = 0; j < q; ++j) {
-            const int32_t i = key[(size_t)j].second;
-            r.perm[(size_t)j] = i;
-            for (int k = 0; k < 3; ++k) r.centers[(size_t)(3 * j + k)] = centers[3 * i + k];
-            r.radii[(size_t)j] = radii[i];
-        }
+        r.perm.resize(qn);
+        r.centers.resize(qn * 3);
+        r.radii.resize(qn);
+        parallel_rows(qn, [&](size_t j0, size_t j1) {
+            for (size_t j = j0; j < j1; ++j) {
+                const int32_t i = (int32_t)(a[j] & 0xffffffffu);
+                r.perm[j] = i;
+                for (int k = 0; k < 3; ++k) r.centers[3 * j + k] = centers[3 * (size_t)i + k];
+                r.radii[j] = radii[i];
+            }
+        });
     }
     const size_t qn = (size_t)q;
     const int S = std::max(r.sp.S, 1);
@@ -578,6 +620,9 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     spec.item_pairs = (int64_t)kBlock * r.sp.qpl * r.sp.per_split;
     spec.dev_bytes = dev_bytes;
     spec.host_bytes = off;
+    // the sort above ran without the lock (the worker keeps scheduling)
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->fatal != CSPLAT_OK) return fail(s->fatal, s->fatal_msg);
     const int64_t t = s->sched->submit(spec, now_s());
     if (t < 0) {
         ++s->st.refused;
@@ -604,7 +649,9 @@ static csplat_status collect(csplat_server *s, int64_t t, const csplat_outputs *
             if (!dst) return;
             char *d = static_cast<char *>(dst);
             const char *src = h + off;
-            for (size_t j = 0; j < qn; ++j) std::memcpy(d + (size_t)r.perm[j] * elem, src + j * elem, elem);
+            parallel_rows(qn, [&](size_t j0, size_t j1) {
+                for (size_t j = j0; j < j1; ++j) std::memcpy(d + (size_t)r.perm[j] * elem, src + j * elem, elem);
+            });
         };
         scatter(out->label, r.h_label, 1);
         scatter(out->count, r.h_count, 4);
