@@ -107,6 +107,30 @@ def test_mix_equals_alone_and_eval(cs, env, oracle_mod):
             compare({k: v[sub] for k, v in mix.items()}, ref, tau=o.softmin_tau, gamma=1.0, where=f"serve-{i}")
 
 
+def test_large_request_host_sort(cs, env):
+    """A request of 300,000 spheres (above the size where submission sorts on
+    several host threads and collection scatters on several) gives the same
+    bits as csplat_eval, labels and full outputs."""
+    eng, scenes, handles = env
+    _say("case: 300,000-sphere requests (threaded host sort and scatter) vs csplat_eval")
+    qs = mppi_walk_queries(1172, 256, seed=21)        # 300,032 spheres along walks
+    rng = np.random.default_rng(5)
+    radii = rng.uniform(0.05, 0.3, qs.q).astype(np.float32)
+    req = dict(centers=qs.centers, radii=radii, n_sigma=1.5)
+    srv = cs.csplat_server_create(0, 2 << 30, 4)
+    try:
+        sid = cs.csplat_server_add_scene(srv, handles[0])
+        for kind in (cs.CSPLAT_SERVE_LABELS, cs.CSPLAT_SERVE_COST):
+            t = cs.csplat_server_submit(srv, sid, kind, req["centers"], req["radii"], _opts(cs, kind), 1.5)
+            got = cs.csplat_server_wait(srv, t, qs.q, kind)
+            ev = _alone_eval(cs, eng, handles[0], req, kind)
+            for k in got:
+                a = got[k].reshape(ev[k].shape)
+                assert np.array_equal(a.view(np.uint8), np.asarray(ev[k]).view(np.uint8)), (kind, k)
+    finally:
+        cs.csplat_server_destroy(srv)
+
+
 def test_admission_refusal_and_queueing(cs, env):
     eng, scenes, handles = env
     _say("case: budget refusal and queueing")
