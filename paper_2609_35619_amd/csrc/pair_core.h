@@ -437,6 +437,15 @@ struct TaskQuery {
     float L[ELL ? 9 : 1];
 };
 
+// Per-task constants of the full-output pair step, in units of t: the
+// collision threshold r^2 kq and the variance factors 2 n_v kq (so that
+// t = max(0, D kq - 2 n_v kq sqrt(V)) needs no multiply per n_sigma).
+template <int M>
+struct TaskScale {
+    float thr;
+    float c[M];
+};
+
 template <int M>
 __device__ __forceinline__ void task_reset(TaskAcc<M> &T)
 {
@@ -455,7 +464,8 @@ __device__ __forceinline__ void task_reset(TaskAcc<M> &T)
 // name two scalar operands and copy one of them for every pair).
 template <int M, bool ELL>
 __device__ __forceinline__ void task_pair(const float4 &r0, const float4 &r1, const float4 &r2,
-                                          const TaskQuery<ELL> &Q, const EvalParams &p, float g0, TaskAcc<M> &T)
+                                          const TaskQuery<ELL> &Q, const TaskScale<M> &K, const EvalParams &p,
+                                          float g0, TaskAcc<M> &T)
 {
     const float dx = r0.x - Q.cx, dy = r0.y - Q.cy, dz = r0.z - Q.cz;
     const float Db = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
@@ -465,11 +475,12 @@ __device__ __forceinline__ void task_pair(const float4 &r0, const float4 &r1, co
         float D, W;
         metric_dw<ELL>(gp, Q.L, dx, dy, dz, Db, D, W);
         const float sv = fast_sqrt(W);
+        const float Dk = D * Q.kq;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-            const float x = fmaf(-p.two_n[v], sv, D);  // (r^2) (s^2 - n sqrt(sigma^2))
-            T.cnt[v] += x < Q.r2;                       // s~^2 < 1
-            const float t = fmaxf(x, 0.f) * Q.kq;
+            const float x = fmaf(-K.c[v], sv, Dk);  // kt (s^2 - n sqrt(sigma^2))
+            T.cnt[v] += x < K.thr;                  // s~^2 < 1
+            const float t = fmaxf(x, 0.f);
             // stable log-sum-exp about the task's running minimum (one exp per pair)
             const float e = fast_exp2(-fabsf(t - T.mt[v]));
             const bool lower = t < T.mt[v];
@@ -605,6 +616,12 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
 #pragma unroll
             for (int k = 0; k < 9; ++k) tq.L[k] = lane_shfl(own.L[k], qi);
         }
+        TaskScale<M> K;
+        if constexpr (FULL) {
+            K.thr = tq.r2 * tq.kq;
+#pragma unroll
+            for (int v = 0; v < M; ++v) K.c[v] = p.two_n[v] * tq.kq;
+        }
         TaskAcc<M> T;
         task_reset(T);
         // the scene's records are padded to whole chunks (pad means at +inf)
@@ -620,7 +637,7 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                if constexpr (FULL) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, p, g0v, T);
+                if constexpr (FULL) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, K, p, g0v, T);
                 else task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tq, p, T);
             }
         }
