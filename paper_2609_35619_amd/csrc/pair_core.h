@@ -553,6 +553,7 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
                                                 int q, const EvalParams &p, const Part &part,
                                                 const float *__restrict__ cull, int *tasks_done)
 {
+    static_assert(FULL && BALL, "labels run in eval_tile_label_tasks");
     constexpr int kRing = 128;  // queued tasks per wave: at most 63 waiting + 64 of one sub-chunk
     constexpr int PW = task_words<M, FULL>();
     constexpr int kWaves = kBlock / 64;
@@ -611,17 +612,15 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         tq.cy = lane_shfl(own.cy, qi);
         tq.cz = lane_shfl(own.cz, qi);
         tq.r2 = lane_shfl(own.r2, qi);
-        if constexpr (FULL) tq.kq = lane_shfl(own.kq, qi);
+        tq.kq = lane_shfl(own.kq, qi);
         if constexpr (ELL) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) tq.L[k] = lane_shfl(own.L[k], qi);
         }
         TaskScale<M> K;
-        if constexpr (FULL) {
-            K.thr = tq.r2 * tq.kq;
+        K.thr = tq.r2 * tq.kq;
 #pragma unroll
-            for (int v = 0; v < M; ++v) K.c[v] = p.two_n[v] * tq.kq;
-        }
+        for (int v = 0; v < M; ++v) K.c[v] = p.two_n[v] * tq.kq;
         TaskAcc<M> T;
         task_reset(T);
         // the scene's records are padded to whole chunks (pad means at +inf)
@@ -636,27 +635,21 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
                 r[u][2] = rp[u * (kGaussFloats / 4) + 2];
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                if constexpr (FULL) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, K, p, g0v, T);
-                else task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tq, p, T);
-            }
+            for (int u = 0; u < kUnroll; ++u) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, K, p, g0v, T);
         }
         // the round's partials to LDS (slot = lane), words: cnt | mt | sm | cs | nb
         {
-            constexpr int used = FULL ? 4 * M + 1 : M;
             float w[PW];
 #pragma unroll
             for (int v = 0; v < M; ++v) {
                 w[v] = __int_as_float(T.cnt[v]);
-                if constexpr (FULL) {
-                    w[M + v] = T.mt[v];
-                    w[2 * M + v] = T.sm[v];
-                    w[3 * M + v] = T.cs[v];
-                }
+                w[M + v] = T.mt[v];
+                w[2 * M + v] = T.sm[v];
+                w[3 * M + v] = T.cs[v];
             }
-            if constexpr (FULL) w[4 * M] = __int_as_float(T.nb);
+            w[4 * M] = __int_as_float(T.nb);
 #pragma unroll
-            for (int k = used; k < PW; ++k) w[k] = 0.f;
+            for (int k = 4 * M + 1; k < PW; ++k) w[k] = 0.f;
             float4 *dst = &s_part[wv][lane * (PW / 4)];
 #pragma unroll
             for (int k = 0; k < PW / 4; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
@@ -674,21 +667,16 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
                 const float4 x = src[k];
                 w[4 * k] = x.x, w[4 * k + 1] = x.y, w[4 * k + 2] = x.z, w[4 * k + 3] = x.w;
             }
-            if constexpr (FULL) {
-                TaskAcc<M> X;
+            TaskAcc<M> X;
 #pragma unroll
-                for (int v = 0; v < M; ++v) {
-                    X.cnt[v] = __float_as_int(w[v]);
-                    X.mt[v] = w[M + v];
-                    X.sm[v] = w[2 * M + v];
-                    X.cs[v] = w[3 * M + v];
-                }
-                X.nb = __float_as_int(w[4 * M]);
-                task_fold(A, X);
-            } else {
-#pragma unroll
-                for (int v = 0; v < M; ++v) A.cnt[v] += __float_as_int(w[v]);
+            for (int v = 0; v < M; ++v) {
+                X.cnt[v] = __float_as_int(w[v]);
+                X.mt[v] = w[M + v];
+                X.sm[v] = w[2 * M + v];
+                X.cs[v] = w[3 * M + v];
             }
+            X.nb = __float_as_int(w[4 * M]);
+            task_fold(A, X);
         }
         if (head & 64) own_hi = 0;
         else own_lo = 0;
@@ -734,22 +722,10 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) qkmax = fmaxf(qkmax, __shfl_xor(qkmax, off));
         }
-        // how far from a body's centre a chunk can hold a counted pair: the
-        // ball for full outputs; for labels the collision bound
-        // qk (n s + sqrt(n^2 s^2 + qa)) (s: the chunk's largest scale),
-        // capped by the ball when one is given
-        auto reach_of = [&](const ChunkMeta &m, float a2, float k) {
-            if constexpr (FULL) {
-                return p.r_nbr;
-            } else {
-                const float ns = p.n_max * m.smax;
-                float reach = ns + fast_sqrt(fmaf(ns, ns, a2));  // v_sqrt: ~1 ulp, far inside kCullMargin
-                if constexpr (ELL) reach *= k;
-                if constexpr (BALL) reach = fminf(reach, p.r_nbr);
-                return reach;
-            }
-        };
-        split_walk<!FULL>(
+        // full outputs reduce over the ball: a chunk farther than r_nbr
+        // plus its radius from a body's centre holds no counted pair
+        auto reach_of = [&](const ChunkMeta &, float, float) { return p.r_nbr; };
+        split_walk<false>(
             groups, cull, n_groups, n_chunks, split, S,
             [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m, qamax, qkmax)); },
             [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + reach_of(m, qa, qk)); },
@@ -782,13 +758,206 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         for (int v = 0; v < M; ++v) {
             const size_t o = ((size_t)split * M + v) * q + jq;
             part.cnt[o] = A.cnt[v];
-            if constexpr (FULL) {
-                part.mt[o] = A.mt[v];
-                part.sm[o] = A.sm[v];
-                part.cs[o] = A.cs[v];
+            part.mt[o] = A.mt[v];
+            part.sm[o] = A.sm[v];
+            part.cs[o] = A.cs[v];
+        }
+        part.nb[(size_t)split * q + jq] = A.nb;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Labels as tasks.  Labels read a 48-byte record per pair for about 25
+// operations, so a lane-per-task walk is bound by the return of vector-memory
+// data (counters on the precision workload: texture-data unit busy 88% of
+// the kernel, VALU 43%).  Here the queue pairs the tasks of a sub-chunk: an
+// entry is (sub-chunk, query a, query b), and one lane evaluates both
+// queries against each record it loads.  The task partials are counts, whose
+// sum does not depend on order, so they are added into per-query counters
+// in LDS with integer atomics (no ownership masks, no fold loop).
+template <int M, bool BALL, bool CULL, bool ELL>
+__device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ gs, int n, int S, int split,
+                                                      int tile, const float *__restrict__ centers,
+                                                      const float *__restrict__ radii, int q, const EvalParams &p,
+                                                      const Part &part, const float *__restrict__ cull,
+                                                      int *tasks_done)
+{
+    constexpr int kRing = 128;  // queued entries per wave: at most 63 waiting + 32 of one sub-chunk
+    constexpr int kWaves = kBlock / 64;
+    constexpr unsigned char kNone = 0xFF;
+    __shared__ int s_task[kWaves][kRing];             // sub-chunk of each queued entry
+    __shared__ unsigned char s_qa[kWaves][kRing];     // lane of its first query
+    __shared__ unsigned char s_qb[kWaves][kRing];     // lane of its second query, or kNone
+    __shared__ int s_cnt[kWaves][64 * M];             // the wave's counts, query-major
+    const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+    const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
+    const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
+    TaskQuery<ELL> own;
+    float qa, qk;  // reach constants: smallest semi-axis squared, largest / smallest
+    if constexpr (ELL) {
+        const float4 *b = reinterpret_cast<const float4 *>(centers + (size_t)kBodyFloats * jj);
+        const float4 b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3];
+        own.cx = b0.x, own.cy = b0.y, own.cz = b0.z;
+        own.L[0] = b0.w, own.L[1] = b1.x, own.L[2] = b1.y, own.L[3] = b1.z, own.L[4] = b1.w;
+        own.L[5] = b2.x, own.L[6] = b2.y, own.L[7] = b2.z, own.L[8] = b2.w;
+        own.r2 = 1.f;
+        qa = b3.x;
+        qk = b3.y;
+    } else {
+        own.cx = centers[3 * jj];
+        own.cy = centers[3 * jj + 1];
+        own.cz = centers[3 * jj + 2];
+        const float r = radii[jj];
+        own.r2 = r * r;
+        qa = own.r2;
+        qk = 1.f;
+    }
+    own.kq = 0.f;
+#pragma unroll
+    for (int v = 0; v < M; ++v) s_cnt[wv][lane * M + v] = 0;
+    int head = 0, tail = 0;  // wave-uniform ring positions, counting up
+
+    auto fetch_query = [&](int src, bool ok) {
+        // every lane runs the permutes (a permute reads nothing useful from
+        // an inactive source lane); a query at infinity has no pair
+        TaskQuery<ELL> t;
+        t.cx = lane_shfl(own.cx, src);
+        if (!ok) t.cx = INFINITY;
+        t.cy = lane_shfl(own.cy, src);
+        t.cz = lane_shfl(own.cz, src);
+        t.r2 = lane_shfl(own.r2, src);
+        t.kq = 0.f;
+        if constexpr (ELL) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) t.L[k] = lane_shfl(own.L[k], src);
+        }
+        return t;
+    };
+    auto run_round = [&](int n_t) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const bool valid = lane < n_t;
+        const int pos = (head + lane) & (kRing - 1);
+        const int f = valid ? s_task[wv][pos] : 0;
+        const int ia = valid ? (int)s_qa[wv][pos] : 0;
+        const int ib = valid ? (int)s_qb[wv][pos] : (int)kNone;
+        const TaskQuery<ELL> ta = fetch_query(ia, valid);
+        const TaskQuery<ELL> tb = fetch_query(ib & 63, ib != (int)kNone);
+        TaskAcc<M> A, B;
+        task_reset(A);
+        task_reset(B);
+        // the scene's records are padded to whole chunks (pad means at +inf)
+        const float4 *rp = reinterpret_cast<const float4 *>(gs) + (size_t)f * (kFine * kGaussFloats / 4);
+#pragma unroll 1
+        for (int k = 0; k < kFine; k += kUnroll, rp += kUnroll * (kGaussFloats / 4)) {
+            float4 r[kUnroll][3];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                r[u][0] = rp[u * (kGaussFloats / 4)];
+                r[u][1] = rp[u * (kGaussFloats / 4) + 1];
+                r[u][2] = rp[u * (kGaussFloats / 4) + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], ta, p, A);
+                task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tb, p, B);
             }
         }
-        if constexpr (FULL) part.nb[(size_t)split * q + jq] = A.nb;
+        if (valid) {
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                if (A.cnt[v]) atomicAdd(&s_cnt[wv][ia * M + v], A.cnt[v]);
+                if (ib != (int)kNone && B.cnt[v]) atomicAdd(&s_cnt[wv][(ib & 63) * M + v], B.cnt[v]);
+            }
+        }
+        head += n_t;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // queue sub-chunk fi for the lanes in `lanes`, two queries per entry
+    // (every lane is active)
+    auto enqueue = [&](int fi, unsigned long long lanes) {
+        const int c = __popcll(lanes);
+        const int k = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(lanes >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)lanes, 0u));
+        if ((lanes >> lane) & 1ull) {
+            const int pos = (tail + (k >> 1)) & (kRing - 1);
+            if ((k & 1) == 0) {
+                s_task[wv][pos] = fi;
+                s_qa[wv][pos] = (unsigned char)lane;
+                if (k == c - 1) s_qb[wv][pos] = kNone;  // odd count: the last entry has one query
+            } else {
+                s_qb[wv][pos] = (unsigned char)lane;
+            }
+        }
+        tail += (c + 1) >> 1;
+        if (tasks_done) *tasks_done += c;
+        if (tail - head >= 64) run_round(64);
+    };
+
+    const int n_chunks = (n + kCull - 1) / kCull;
+    const int n_fine = (n + kFine - 1) / kFine;
+    const int n_groups = (n_chunks + kGroup - 1) / kGroup;
+    if constexpr (!CULL) {
+        for (int c = split; c < n_chunks; c += S)
+            for (int k = 0; k < kFinePer; ++k) {
+                const int fi = c * kFinePer + k;
+                if (fi < n_fine) enqueue(fi, ~0ull);
+            }
+    } else {
+        const float *fine = cull + (size_t)n_chunks * kCullFloats;  // the sub-chunk level
+        const float *groups = fine + (size_t)n_fine * kCullFloats;  // the group level
+        float cx[1] = {own.cx}, cy[1] = {own.cy}, cz[1] = {own.cz}, qv[1] = {qa};
+        float wx, wy, wz, spread, qamax;
+        wave_sphere<1>(cx, cy, cz, qv, wx, wy, wz, spread, qamax);
+        float qkmax = qk;
+        if constexpr (ELL) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) qkmax = fmaxf(qkmax, __shfl_xor(qkmax, off));
+        }
+        // the collision bound qk (n s + sqrt(n^2 s^2 + qa)) (s: the chunk's
+        // largest scale), capped by the ball when one is given
+        auto reach_of = [&](const ChunkMeta &m, float a2, float kk) {
+            const float ns = p.n_max * m.smax;
+            float reach = ns + fast_sqrt(fmaf(ns, ns, a2));  // v_sqrt: ~1 ulp, far inside kCullMargin
+            if constexpr (ELL) reach *= kk;
+            if constexpr (BALL) reach = fminf(reach, p.r_nbr);
+            return reach;
+        };
+        split_walk<true>(
+            groups, cull, n_groups, n_chunks, split, S,
+            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m, qamax, qkmax)); },
+            [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + reach_of(m, qa, qk)); },
+            [&](int ci, unsigned long long lanes) {
+                static_assert(kFinePer == 4, "sub-chunk rotation below assumes four");
+                const int f0 = ci * kFinePer;
+                ChunkMeta fm[kFinePer];
+#pragma unroll
+                for (int k = 0; k < kFinePer; ++k) fm[k] = load_chunk(fine, min(f0 + k, n_fine - 1));
+                unsigned long long fl[kFinePer];
+#pragma unroll
+                for (int k = 0; k < kFinePer; ++k) {
+                    const unsigned long long exists = f0 + k < n_fine ? ~0ull : 0ull;
+                    fl[k] = lanes & exists &
+                            __ballot(within(fm[k], own.cx, own.cy, own.cz, fm[k].rad + reach_of(fm[k], qa, qk)));
+                }
+                unsigned long long l0 = fl[0], l1 = fl[1], l2 = fl[2], l3 = fl[3];
+#pragma unroll 1
+                for (int k = 0; k < kFinePer; ++k) {
+                    if (l0) enqueue(f0 + k, l0);
+                    l0 = l1, l1 = l2, l2 = l3, l3 = 0;
+                }
+            });
+    }
+    if (tail > head) run_round(tail - head);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (jq < q) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) part.cnt[((size_t)split * M + v) * q + jq] = s_cnt[wv][lane * M + v];
     }
 }
 
@@ -811,8 +980,12 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                                           int *chunks_done = nullptr)
 {
     if constexpr (uses_tasks<FULL, BALL, QPL, ELL>()) {
-        eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
-                                                  chunks_done);
+        if constexpr (FULL)
+            eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
+                                                      chunks_done);
+        else
+            eval_tile_label_tasks<M, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
+                                                      chunks_done);
         return;
     }
     // Spheres: centers (q x 3) and radii (q).  Ellipsoids (ELL): `centers`
@@ -1038,9 +1211,13 @@ pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
 // query per lane), with its occupancy target.
 // Instances whose state outgrows the cap (ellipsoids with several
 // conservatism values) keep 3 waves per SIMD rather than spill.
+#ifndef CSPLAT_LABEL_WAVES_PER_EU
+#define CSPLAT_LABEL_WAVES_PER_EU 4
+#endif
 template <int M, bool FULL, bool ELL>
 constexpr int task_waves_per_eu()
 {
+    if constexpr (!FULL && !ELL) return CSPLAT_LABEL_WAVES_PER_EU;
     return (ELL && !(FULL && M == 1)) || (FULL && M > 3) ? 3 : CSPLAT_TASK_WAVES_PER_EU;
 }
 
@@ -1056,7 +1233,10 @@ pair_task_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const 
     const int split = b / n_tiles;
     const int tile = b - split * n_tiles;
     int done = 0;
-    eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
+    if constexpr (FULL)
+        eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
+    else
+        eval_tile_label_tasks<M, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
     if (CULL && task_count && (threadIdx.x & 63) == 0) atomicAdd(task_count, (unsigned long long)done);
 }
 
