@@ -85,12 +85,13 @@ typedef struct {
     float gamma;           /* Eq. 11, >= 0 */
     float s_min;           /* Eq. 11, the paper uses 1 */
     int32_t precision;     /* CSPLAT_PRECISION_*; the MFMA forms compute labels/counts */
-    int32_t cull;          /* 1: sort the queries along a Hilbert curve and skip chunks of 64
-                              Gaussians that provably lie outside every query's neighbourhood
-                              ball (or, for labels, beyond the reach bound
+    int32_t cull;          /* 1: sort the queries along a Hilbert curve and skip the
+                              Gaussians (in groups of 1024, chunks of 64 and sub-chunks of 16
+                              consecutive on the scene's curve) that provably lie outside a
+                              query's neighbourhood ball (or, for labels, beyond the reach bound
                               n s_max + sqrt(n^2 s_max^2 + r^2) of Eq. 8); the results are the
-                              same bits as with 0, which evaluates every pair.  Used by the
-                              float32 path; min/softmin/cost with an infinite ball never cull. */
+                              same bits as with 0, which evaluates every pair.  min/softmin/cost
+                              with an infinite ball never cull. */
 } csplat_reduce_opts;
 
 /* Outputs of one evaluation; every pointer is nullable (not computed/written). */
