@@ -564,17 +564,14 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
     const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
     TaskQuery<ELL> own;
-    float qa, qk;  // reach constants: smallest semi-axis squared, largest / smallest
     if constexpr (ELL) {
         const float4 *b = reinterpret_cast<const float4 *>(centers + (size_t)kBodyFloats * jj);
-        const float4 b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3];
+        const float4 b0 = b[0], b1 = b[1], b2 = b[2];
         own.cx = b0.x, own.cy = b0.y, own.cz = b0.z;
         own.L[0] = b0.w, own.L[1] = b1.x, own.L[2] = b1.y, own.L[3] = b1.z, own.L[4] = b1.w;
         own.L[5] = b2.x, own.L[6] = b2.y, own.L[7] = b2.z, own.L[8] = b2.w;
         own.r2 = 1.f;
         own.kq = p.kt;
-        qa = b3.x;
-        qk = b3.y;
     } else {
         own.cx = centers[3 * jj];
         own.cy = centers[3 * jj + 1];
@@ -582,8 +579,6 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         const float r = radii[jj];
         own.r2 = r * r;
         own.kq = p.kt / own.r2;
-        qa = own.r2;
-        qk = 1.f;
     }
     TaskAcc<M> A;
     task_reset(A);
@@ -712,23 +707,18 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
                 if (fi < n_fine) enqueue(fi, ~0ull);
             }
     } else {
-        const float *fine = cull + (size_t)n_chunks * kCullFloats;     // the sub-chunk level
-        const float *groups = fine + (size_t)n_fine * kCullFloats;     // the group level
-        float cx[1] = {own.cx}, cy[1] = {own.cy}, cz[1] = {own.cz}, qv[1] = {qa};
-        float wx, wy, wz, spread, qamax;
-        wave_sphere<1>(cx, cy, cz, qv, wx, wy, wz, spread, qamax);
-        float qkmax = qk;
-        if constexpr (ELL) {
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) qkmax = fmaxf(qkmax, __shfl_xor(qkmax, off));
-        }
-        // full outputs reduce over the ball: a chunk farther than r_nbr
-        // plus its radius from a body's centre holds no counted pair
-        auto reach_of = [&](const ChunkMeta &, float, float) { return p.r_nbr; };
+        const float *fine = cull + (size_t)n_chunks * kCullFloats;  // the sub-chunk level
+        const float *groups = fine + (size_t)n_fine * kCullFloats;  // the group level
+        float cx[1] = {own.cx}, cy[1] = {own.cy}, cz[1] = {own.cz}, r2[1] = {own.r2};
+        float wx, wy, wz, spread, r2max;
+        wave_sphere<1>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
+        // full outputs reduce over the ball: a chunk farther than r_nbr plus
+        // its radius from a body's centre holds no counted pair
+        auto reach_of = [&](const ChunkMeta &) { return p.r_nbr; };
         split_walk<false>(
             groups, cull, n_groups, n_chunks, split, S,
-            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m, qamax, qkmax)); },
-            [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + reach_of(m, qa, qk)); },
+            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m)); },
+            [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + reach_of(m)); },
             [&](int ci, unsigned long long lanes) {
                 // the sub-chunks' records are read together (one latency),
                 // tested, and their lanes rotated through one enqueue site
@@ -742,7 +732,7 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
                 for (int k = 0; k < kFinePer; ++k) {
                     const unsigned long long exists = f0 + k < n_fine ? ~0ull : 0ull;
                     fl[k] = lanes & exists &
-                            __ballot(within(fm[k], own.cx, own.cy, own.cz, fm[k].rad + reach_of(fm[k], qa, qk)));
+                            __ballot(within(fm[k], own.cx, own.cy, own.cz, fm[k].rad + reach_of(fm[k])));
                 }
                 unsigned long long l0 = fl[0], l1 = fl[1], l2 = fl[2], l3 = fl[3];
 #pragma unroll 1
