@@ -760,11 +760,14 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
 // Labels as tasks.  Labels read a 48-byte record per pair for about 25
 // operations, so a lane-per-task walk is bound by the return of vector-memory
 // data (counters on the precision workload: texture-data unit busy 88% of
-// the kernel, VALU 43%).  Here the queue pairs the tasks of a sub-chunk: an
-// entry is (sub-chunk, query a, query b), and one lane evaluates both
-// queries against each record it loads.  The task partials are counts, whose
+// the kernel, VALU 43%).  Here the queue groups the tasks of a sub-chunk: an
+// entry is (sub-chunk, KQ queries), and one lane evaluates all of them
+// against each record it loads.  The task partials are counts, whose
 // sum does not depend on order, so they are added into per-query counters
 // in LDS with integer atomics (no ownership masks, no fold loop).
+#ifndef CSPLAT_LABEL_QUERIES_PER_TASK
+#define CSPLAT_LABEL_QUERIES_PER_TASK 2
+#endif
 template <int M, bool BALL, bool CULL, bool ELL>
 __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ gs, int n, int S, int split,
                                                       int tile, const float *__restrict__ centers,
@@ -772,12 +775,12 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
                                                       const Part &part, const float *__restrict__ cull,
                                                       int *tasks_done)
 {
-    constexpr int kRing = 128;  // queued entries per wave: at most 63 waiting + 32 of one sub-chunk
+    constexpr int KQ = CSPLAT_LABEL_QUERIES_PER_TASK;  // queries per entry
+    constexpr int kRing = 128;  // queued entries per wave: at most 63 waiting + 64 / KQ of one sub-chunk
     constexpr int kWaves = kBlock / 64;
     constexpr unsigned char kNone = 0xFF;
     __shared__ int s_task[kWaves][kRing];             // sub-chunk of each queued entry
-    __shared__ unsigned char s_qa[kWaves][kRing];     // lane of its first query
-    __shared__ unsigned char s_qb[kWaves][kRing];     // lane of its second query, or kNone
+    __shared__ unsigned char s_q[kWaves][KQ][kRing];  // lanes of its queries, kNone for an empty slot
     __shared__ int s_cnt[kWaves][64 * M];             // the wave's counts, query-major
     const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
     const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
@@ -830,13 +833,15 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
         const bool valid = lane < n_t;
         const int pos = (head + lane) & (kRing - 1);
         const int f = valid ? s_task[wv][pos] : 0;
-        const int ia = valid ? (int)s_qa[wv][pos] : 0;
-        const int ib = valid ? (int)s_qb[wv][pos] : (int)kNone;
-        const TaskQuery<ELL> ta = fetch_query(ia, valid);
-        const TaskQuery<ELL> tb = fetch_query(ib & 63, ib != (int)kNone);
-        TaskAcc<M> A, B;
-        task_reset(A);
-        task_reset(B);
+        int iq[KQ];
+        TaskQuery<ELL> tq[KQ];
+        TaskAcc<M> T[KQ];
+#pragma unroll
+        for (int j = 0; j < KQ; ++j) {
+            iq[j] = valid ? (int)s_q[wv][j][pos] : (int)kNone;
+            tq[j] = fetch_query(iq[j] & 63, iq[j] != (int)kNone);
+            task_reset(T[j]);
+        }
         // the scene's records are padded to whole chunks (pad means at +inf)
         const float4 *rp = reinterpret_cast<const float4 *>(gs) + (size_t)f * (kFine * kGaussFloats / 4);
 #pragma unroll 1
@@ -849,40 +854,35 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
                 r[u][2] = rp[u * (kGaussFloats / 4) + 2];
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], ta, p, A);
-                task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tb, p, B);
-            }
-        }
-        if (valid) {
+            for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-            for (int v = 0; v < M; ++v) {
-                if (A.cnt[v]) atomicAdd(&s_cnt[wv][ia * M + v], A.cnt[v]);
-                if (ib != (int)kNone && B.cnt[v]) atomicAdd(&s_cnt[wv][(ib & 63) * M + v], B.cnt[v]);
-            }
+                for (int j = 0; j < KQ; ++j) task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tq[j], p, T[j]);
         }
+#pragma unroll
+        for (int j = 0; j < KQ; ++j)
+#pragma unroll
+            for (int v = 0; v < M; ++v)
+                if (iq[j] != (int)kNone && T[j].cnt[v]) atomicAdd(&s_cnt[wv][iq[j] * M + v], T[j].cnt[v]);
         head += n_t;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    // queue sub-chunk fi for the lanes in `lanes`, two queries per entry
+    // queue sub-chunk fi for the lanes in `lanes`, KQ queries per entry
     // (every lane is active)
     auto enqueue = [&](int fi, unsigned long long lanes) {
         const int c = __popcll(lanes);
         const int k = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(lanes >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((unsigned)lanes, 0u));
         if ((lanes >> lane) & 1ull) {
-            const int pos = (tail + (k >> 1)) & (kRing - 1);
-            if ((k & 1) == 0) {
-                s_task[wv][pos] = fi;
-                s_qa[wv][pos] = (unsigned char)lane;
-                if (k == c - 1) s_qb[wv][pos] = kNone;  // odd count: the last entry has one query
-            } else {
-                s_qb[wv][pos] = (unsigned char)lane;
-            }
+            const int pos = (tail + k / KQ) & (kRing - 1);
+            const int slot = k % KQ;
+            if (slot == 0) s_task[wv][pos] = fi;
+            s_q[wv][slot][pos] = (unsigned char)lane;
+            if (k == c - 1)  // the last entry's empty slots
+                for (int j = slot + 1; j < KQ; ++j) s_q[wv][j][pos] = kNone;
         }
-        tail += (c + 1) >> 1;
+        tail += (c + KQ - 1) / KQ;
         if (tasks_done) *tasks_done += c;
         if (tail - head >= 64) run_round(64);
     };
