@@ -241,6 +241,32 @@ csplat_status device_check(csplat_ctx *ctx, Launch launch, const char *msg)
     return CSPLAT_OK;
 }
 
+// The same check queued without waiting: the flag is copied to pinned host
+// memory behind an event, and wait_device_check() waits for that event only
+// (the work queued after it keeps the device busy meanwhile).
+template <class Launch>
+csplat_status queue_device_check(csplat_ctx *ctx, Launch launch)
+{
+    hipError_t e = ctx->flags.reserve(64);
+    if (e != hipSuccess) return hip_fail(e, "flag workspace");
+    if (!ctx->check_host) CSPLAT_HIP(hipHostMalloc((void **)&ctx->check_host, 64, hipHostMallocDefault));
+    if (!ctx->ev_check) CSPLAT_HIP(hipEventCreateWithFlags(&ctx->ev_check, hipEventDisableTiming));
+    int *bad = ctx->flags.as<int>();
+    CSPLAT_HIP(zero_words(bad, 1, ctx->stream));
+    launch(bad);
+    CSPLAT_HIP(hipGetLastError());
+    CSPLAT_HIP(hipMemcpyAsync(ctx->check_host, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    CSPLAT_HIP(hipEventRecord(ctx->ev_check, ctx->stream));
+    return CSPLAT_OK;
+}
+
+csplat_status wait_device_check(csplat_ctx *ctx, const char *msg)
+{
+    CSPLAT_HIP(hipEventSynchronize(ctx->ev_check));
+    if (*ctx->check_host) return fail(CSPLAT_E_INVALID, msg);
+    return CSPLAT_OK;
+}
+
 // Runs run(dev_inputs, eo) with every input and output on the device: device
 // pointers as given (asynchronous); host inputs staged through the context's
 // staging buffer and host outputs copied back (synchronous).
@@ -350,6 +376,8 @@ csplat_status csplat_ctx_destroy(csplat_ctx *ctx)
     ctx->bodies.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->ev_check) (void)hipEventDestroy(ctx->ev_check);
+    if (ctx->check_host) (void)hipHostFree(ctx->check_host);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return CSPLAT_OK;
@@ -450,14 +478,21 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     reset_stats(ctx, q, sc);
+    std::function<csplat_status()> gate;
     if (kind == 1) {
-        // device inputs: check them on the device before any output is touched
-        s = device_check(
-            ctx,
-            [&](int *bad) {
-                check_queries_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, radii, bad);
-            },
-            bad_msg);
+        // device inputs: checked on the device before any output is touched.
+        // The float32 path queues its sort and pair kernel (which write only
+        // the workspace) before it waits for the check; the precision forms
+        // write labels early and wait first.
+        auto check = [&](int *bad) {
+            check_queries_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, radii, bad);
+        };
+        if (opts->precision == CSPLAT_PRECISION_FP32) {
+            s = queue_device_check(ctx, check);
+            gate = [&]() { return wait_device_check(ctx, bad_msg); };
+        } else {
+            s = device_check(ctx, check, bad_msg);
+        }
         if (s != CSPLAT_OK) return s;
     }
     return on_device(ctx, kind, q, ctx->m, {centers, radii}, {(size_t)q * 12, (size_t)q * 4}, out,
@@ -465,7 +500,7 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
                          const float *c = static_cast<const float *>(in[0]), *r = static_cast<const float *>(in[1]);
                          if (opts->precision != CSPLAT_PRECISION_FP32)
                              return precision_eval(ctx, sc, q, c, r, p, eo, opts->precision);
-                         return fp32_eval(ctx, sc, q, c, r, p, eo, !want_dist);
+                         return fp32_eval(ctx, sc, q, c, r, p, eo, !want_dist, false, gate);
                      });
 }
 

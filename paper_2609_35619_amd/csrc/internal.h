@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 
 #include "../../include/csplat.h"
@@ -168,6 +169,8 @@ struct csplat_ctx {
     bool timing = false;
     bool timed = false;         // events of the last evaluation were recorded
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int *check_host = nullptr;      // pinned: the device-side input check's flag
+    hipEvent_t ev_check = nullptr;  // recorded after that flag's copy
 };
 
 namespace csplat {
@@ -257,9 +260,13 @@ csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const
                              float *rec);
 
 // pair_fp32.hip: the float32 pair kernel and the split combine.
+// `gate`, when given, runs after the pair kernel is queued and before
+// anything that writes the outputs; an error from it is returned with no
+// output written (the queued kernels write only the context's workspace).
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
                         const float *centers, const float *radii, const EvalParams &p,
-                        const EvalOut &out, bool labels_only, bool ell = false);
+                        const EvalOut &out, bool labels_only, bool ell = false,
+                        const std::function<csplat_status()> &gate = {});
 
 // precision.hip: MFMA form with certified recheck (labels and counts).
 csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,

@@ -70,7 +70,8 @@ void launch_pair(const Launch &L)
 }
 
 template <int M>
-void launch_m(csplat_ctx *ctx, bool full, bool ball, bool cull, const Launch &L)
+csplat_status launch_m(csplat_ctx *ctx, bool full, bool ball, bool cull, const Launch &L,
+                       const std::function<csplat_status()> &gate)
 {
     if (L.n > 0) {
         timing_begin(ctx);
@@ -88,9 +89,14 @@ void launch_m(csplat_ctx *ctx, bool full, bool ball, bool cull, const Launch &L)
         }
         timing_end(ctx);
     }
+    if (gate) {
+        const csplat_status s = gate();
+        if (s != CSPLAT_OK) return s;
+    }
     const unsigned cb = (unsigned)(((int64_t)L.q * M + 255) / 256);
     if (full) combine_kernel<M, true><<<cb, 256, 0, L.st>>>(L.q, L.S, L.p, L.part, L.out, L.perm);
     else combine_kernel<M, false><<<cb, 256, 0, L.st>>>(L.q, L.S, L.p, L.part, L.out, L.perm);
+    return CSPLAT_OK;
 }
 
 // Hilbert key of each query centre on the scene's grid (the scene's curve).
@@ -217,7 +223,7 @@ csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const
 
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
                         const float *radii, const EvalParams &p, const EvalOut &out,
-                        bool labels_only, bool ell)
+                        bool labels_only, bool ell, const std::function<csplat_status()> &gate)
 {
     const int q = (int)q64;
     const int n = (int)sc->n;
@@ -269,17 +275,19 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
         const bool tasks = sp.qpl == 1 && (!full || (ball && (!ell || CSPLAT_ELL_FULL_TASKS)));
         ctx->pairs_per_chunk = tasks ? (int64_t)kFine : (int64_t)kCull * 64 * sp.qpl;
     }
+    csplat_status s = CSPLAT_OK;
     switch (M) {
-    case 1: launch_m<1>(ctx, full, ball, cull, L); break;
-    case 2: launch_m<2>(ctx, full, ball, cull, L); break;
-    case 3: launch_m<3>(ctx, full, ball, cull, L); break;
-    case 4: launch_m<4>(ctx, full, ball, cull, L); break;
-    case 5: launch_m<5>(ctx, full, ball, cull, L); break;
-    case 6: launch_m<6>(ctx, full, ball, cull, L); break;
-    case 7: launch_m<7>(ctx, full, ball, cull, L); break;
-    case 8: launch_m<8>(ctx, full, ball, cull, L); break;
+    case 1: s = launch_m<1>(ctx, full, ball, cull, L, gate); break;
+    case 2: s = launch_m<2>(ctx, full, ball, cull, L, gate); break;
+    case 3: s = launch_m<3>(ctx, full, ball, cull, L, gate); break;
+    case 4: s = launch_m<4>(ctx, full, ball, cull, L, gate); break;
+    case 5: s = launch_m<5>(ctx, full, ball, cull, L, gate); break;
+    case 6: s = launch_m<6>(ctx, full, ball, cull, L, gate); break;
+    case 7: s = launch_m<7>(ctx, full, ball, cull, L, gate); break;
+    case 8: s = launch_m<8>(ctx, full, ball, cull, L, gate); break;
     default: return fail(CSPLAT_E_INVALID, "m out of range");
     }
+    if (s != CSPLAT_OK) return s;
     CSPLAT_HIP(hipGetLastError());
     return CSPLAT_OK;
 }
