@@ -48,11 +48,17 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #else
 #define CSPLAT_OCCUPANCY
 #endif
-// The task walk (full outputs over a ball) at 4 waves per SIMD: its vector
-// loads want the latency hiding, and the cap costs it a few spilled bytes
-// (measured on MI355X: 1.25 -> 1.10 ms on the navigation workload).
+// The task walk (full outputs over a ball) at 5 waves per SIMD with records
+// loaded two at a time: its vector loads want the latency hiding, and the
+// cap costs it a few spilled bytes (measured on MI355X, navigation workload:
+// no cap 1.25 ms, 4 waves 1.10, then with other changes 4 waves and four
+// records at a time 1.002 ms, 5 waves and two records 0.987 ms; 5 waves with
+// four records spill 152 bytes and take 1.34 ms).
 #ifndef CSPLAT_TASK_WAVES_PER_EU
-#define CSPLAT_TASK_WAVES_PER_EU 4
+#define CSPLAT_TASK_WAVES_PER_EU 5
+#endif
+#ifndef CSPLAT_TASK_UNROLL
+#define CSPLAT_TASK_UNROLL 2
 #endif
 // Full outputs for ellipsoids over a ball: task walk (1) or wave walk (0).
 // The tabletop workload puts 88% of the pairs the task walk evaluates inside
@@ -69,6 +75,7 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #define CSPLAT_TASK_BLOCKS_PER_CU 32
 #endif
 constexpr int kUnroll = CSPLAT_UNROLL;       // Gaussians per group of scalar loads
+constexpr int kTaskUnroll = CSPLAT_TASK_UNROLL;  // records per group of loads, full-output tasks
 constexpr int kQplFull = CSPLAT_QPL_FULL;    // queries per lane, all outputs
 constexpr int kQplLabels = CSPLAT_QPL_LABELS;  // queries per lane, labels only
 constexpr bool kPipeline = CSPLAT_PIPELINE != 0;
@@ -621,16 +628,16 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         // the scene's records are padded to whole chunks (pad means at +inf)
         const float4 *rp = reinterpret_cast<const float4 *>(gs) + (size_t)f * (kFine * kGaussFloats / 4);
 #pragma unroll 1
-        for (int k = 0; k < kFine; k += kUnroll, rp += kUnroll * (kGaussFloats / 4)) {
-            float4 r[kUnroll][3];
+        for (int k = 0; k < kFine; k += kTaskUnroll, rp += kTaskUnroll * (kGaussFloats / 4)) {
+            float4 r[kTaskUnroll][3];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kTaskUnroll; ++u) {
                 r[u][0] = rp[u * (kGaussFloats / 4)];
                 r[u][1] = rp[u * (kGaussFloats / 4) + 1];
                 r[u][2] = rp[u * (kGaussFloats / 4) + 2];
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, K, p, g0v, T);
+            for (int u = 0; u < kTaskUnroll; ++u) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq, K, p, g0v, T);
         }
         // the round's partials to LDS (slot = lane), words: cnt | mt | sm | cs | nb
         {
