@@ -48,17 +48,19 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #else
 #define CSPLAT_OCCUPANCY
 #endif
-// The task walk (full outputs over a ball) at 5 waves per SIMD with records
-// loaded two at a time: its vector loads want the latency hiding, and the
-// cap costs it a few spilled bytes (measured on MI355X, navigation workload:
-// no cap 1.25 ms, 4 waves 1.10, then with other changes 4 waves and four
-// records at a time 1.002 ms, 5 waves and two records 0.987 ms; 5 waves with
-// four records spill 152 bytes and take 1.34 ms).
+// The task walk (full outputs over a ball) at 5 waves per SIMD: its vector
+// loads want the latency hiding.  Records are loaded four at a time with one
+// conservatism value and two at a time with more, where four would spill
+// under the cap (measured on MI355X: navigation workload, m = 3: no cap
+// 1.25 ms, 4 waves 1.10, then with other changes 4 waves and four records
+// 1.002 ms, 5 waves and two records 0.987 ms, 5 waves and four records 1.34
+// ms with 152 spilled bytes; serving, m = 1: 5 waves and four records 495
+// requests/s, two records 440, 4 waves and four records 468).
 #ifndef CSPLAT_TASK_WAVES_PER_EU
 #define CSPLAT_TASK_WAVES_PER_EU 5
 #endif
 #ifndef CSPLAT_TASK_UNROLL
-#define CSPLAT_TASK_UNROLL 2
+#define CSPLAT_TASK_UNROLL 0  // 0: by the number of conservatism values
 #endif
 // Full outputs for ellipsoids over a ball: task walk (1) or wave walk (0).
 // The tabletop workload puts 88% of the pairs the task walk evaluates inside
@@ -75,7 +77,12 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #define CSPLAT_TASK_BLOCKS_PER_CU 32
 #endif
 constexpr int kUnroll = CSPLAT_UNROLL;       // Gaussians per group of scalar loads
-constexpr int kTaskUnroll = CSPLAT_TASK_UNROLL;  // records per group of loads, full-output tasks
+// records per group of loads in a full-output task with M conservatism values
+template <int M>
+constexpr int task_unroll()
+{
+    return CSPLAT_TASK_UNROLL > 0 ? CSPLAT_TASK_UNROLL : (M == 1 ? 4 : 2);
+}
 constexpr int kQplFull = CSPLAT_QPL_FULL;    // queries per lane, all outputs
 constexpr int kQplLabels = CSPLAT_QPL_LABELS;  // queries per lane, labels only
 constexpr bool kPipeline = CSPLAT_PIPELINE != 0;
@@ -627,6 +634,7 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         task_reset(T);
         // the scene's records are padded to whole chunks (pad means at +inf)
         const float4 *rp = reinterpret_cast<const float4 *>(gs) + (size_t)f * (kFine * kGaussFloats / 4);
+        constexpr int kTaskUnroll = task_unroll<M>();
 #pragma unroll 1
         for (int k = 0; k < kFine; k += kTaskUnroll, rp += kTaskUnroll * (kGaussFloats / 4)) {
             float4 r[kTaskUnroll][3];
