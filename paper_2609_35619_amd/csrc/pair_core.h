@@ -248,6 +248,15 @@ __device__ __forceinline__ float lane_value(float v, int lane)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
+// A value equal on every lane, held in a scalar register (the empty asm
+// keeps the arithmetic that made it ahead of the read, so the scalar
+// register is what later code uses).
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    asm volatile("" : "+v"(v));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 // The metadata held by lane `lane`, as wave-uniform values.
 __device__ __forceinline__ ChunkMeta lane_chunk(const ChunkMeta &m, int lane)
 {
@@ -280,7 +289,9 @@ __device__ __forceinline__ void wave_sphere(const float (&cx)[QPL], const float 
         }
         r2max = fmaxf(r2max, __shfl_xor(r2max, off));
     }
-    wx = 0.5f * (lo[0] + hi[0]), wy = 0.5f * (lo[1] + hi[1]), wz = 0.5f * (lo[2] + hi[2]);
+    // after the butterflies every lane holds the same values
+    wx = wave_uniform(0.5f * (lo[0] + hi[0])), wy = wave_uniform(0.5f * (lo[1] + hi[1]));
+    wz = wave_uniform(0.5f * (lo[2] + hi[2])), r2max = wave_uniform(r2max);
     spread = 0.f;
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
@@ -289,6 +300,7 @@ __device__ __forceinline__ void wave_sphere(const float (&cx)[QPL], const float 
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) spread = fmaxf(spread, __shfl_xor(spread, off));
+    spread = wave_uniform(spread);
 }
 
 // Squared distance of a chunk centre from a point, and the culling test
@@ -371,8 +383,10 @@ __device__ __forceinline__ void split_walk(const float *__restrict__ groups, con
                                            int n_groups, int n_chunks, int split, int S, Coarse coarse, Near near,
                                            Visit visit)
 {
-    const int lane = (int)(threadIdx.x & 63u);
+    const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr bool AHEAD = LABELS;
+    __shared__ unsigned long long s_near[LABELS ? 1 : kBlock / 64][LABELS ? 1 : 64];
+    __shared__ int s_near_at[LABELS ? 1 : kBlock / 64][LABELS ? 1 : 64];
     const bool by_group = LABELS && S <= kGroup;
     const int n_units = by_group ? n_groups : n_chunks;
     const int stride = by_group ? 1 : S;
@@ -420,11 +434,42 @@ __device__ __forceinline__ void split_walk(const float *__restrict__ groups, con
                 cmask = __ballot(cok);
             }
             gmask &= gmask - 1;
-            while (cmask) {
-                const int cb = __builtin_ctzll(cmask);
-                cmask &= cmask - 1;
-                const unsigned long long lanes = __ballot(near(lane_chunk(cm, cb)));
-                if (lanes) visit(c0 + cb * cs, lanes);
+            if constexpr (LABELS) {
+                while (cmask) {
+                    const int cb = __builtin_ctzll(cmask);
+                    cmask &= cmask - 1;
+                    const unsigned long long lanes = __ballot(near(lane_chunk(cm, cb)));
+                    if (lanes) visit(c0 + cb * cs, lanes);
+                }
+            } else {
+                // the near masks of every surviving chunk first, parked in
+                // LDS, so the batch's metadata is dead during the visits
+                // (whose queue work needs every register)
+                int n_near = 0;
+                while (cmask) {
+                    const int cb = __builtin_ctzll(cmask);
+                    cmask &= cmask - 1;
+                    const unsigned long long lanes = __ballot(near(lane_chunk(cm, cb)));
+                    if (lanes) {
+                        if (lane == 0) {
+                            s_near[wv][n_near] = lanes;
+                            s_near_at[wv][n_near] = c0 + cb * cs;
+                        }
+                        ++n_near;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int i = 0; i < n_near; ++i) {
+                    const unsigned long long lanes = s_near[wv][i];
+                    const int c = __builtin_amdgcn_readfirstlane(s_near_at[wv][i]);
+                    visit(c, ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(lanes >> 32)) << 32) |
+                                 (unsigned)__builtin_amdgcn_readfirstlane((unsigned)lanes));
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
     }
@@ -574,7 +619,7 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
     __shared__ int s_task[kWaves][kRing];              // sub-chunk of each queued task
     __shared__ unsigned char s_owner[kWaves][kRing];   // lane of its query
     __shared__ float4 s_part[kWaves][64 * PW / 4];     // partials of a round, PW words per task
-    const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
     TaskQuery<ELL> own;
@@ -797,7 +842,7 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
     __shared__ int s_task[kWaves][kRing];             // sub-chunk of each queued entry
     __shared__ unsigned char s_q[kWaves][KQ][kRing];  // lanes of its queries, kNone for an empty slot
     __shared__ int s_cnt[kWaves][64 * M];             // the wave's counts, query-major
-    const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
     TaskQuery<ELL> own;
