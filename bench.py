@@ -88,10 +88,12 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-ellipsoids", action="store_true", help="skip the ellipsoidal-body workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped context workload")
-    ap.add_argument("--serving-requests", type=int, default=60)
+    ap.add_argument("--no-manip", action="store_true", help="skip the manipulation (sphere chain) workload")
+    ap.add_argument("--serving-requests", type=int, default=500)
     ap.add_argument("--serving-full", action="store_true",
                     help="serve the full-size request law (MPPI K up to 4096 x 32 x 48; long)")
-    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "ellipsoids", "paper", "copy", "digest"), default="all",
+    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "ellipsoids", "manip", "paper", "copy",
+                                          "digest"), default="all",
                     help="run one part only (for profiling); 'copy' is a plain 1 GiB device copy "
                          "used to calibrate the HBM traffic counters")
     args = ap.parse_args()
@@ -105,6 +107,7 @@ def main():
         args.no_serving = args.section not in ("serving",)
         args.no_ellipsoids = args.section not in ("ellipsoids",)
         args.no_paper = args.section not in ("paper",)
+        args.no_manip = args.section not in ("manip",)
         args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -232,6 +235,8 @@ def main():
         res["cpu_baseline"], res["label_accuracy"] = cpu_baseline(sc, qs, p, gpu, args.cpu_seconds, n_kept)
     if not args.no_precision:
         res["precision_form"] = precision_form(cs, eng)
+    if not args.no_manip:
+        res["manip"] = manip(cs, eng, args.steps)
     if not args.no_ellipsoids:
         res["ellipsoids"] = ellipsoids(cs, eng, args.steps)
     if not args.no_paper:
@@ -269,6 +274,52 @@ def _time_eval(eng, h, c, r, opts, want, reps=3):
 
 
 OPS_ELL_SHARED = 36   # L d (9), s^2 (3), L^T e (9), M h (9), W (3), sqrt (2), ball count (1)
+
+
+def manip(cs, eng, steps):
+    """The manipulation workload: the 500k-Gaussian tabletop against 256
+    configurations x 32 steps x 48 spheres of a 7-link chain (393,216
+    spheres), all outputs, n_sigma = 1, neighbourhood ball 0.3 m."""
+    import torch
+    from workloads import config
+    log("bench: manipulation (500k Gaussians x 393,216 chain spheres)")
+    sc, qs, p = config("manip")
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
+    n_kept, _ = cs.csplat_scene_info(h)
+    eng.set_conservatism(p["n_sigma"])
+    m = len(p["n_sigma"])
+    opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"],
+                          s_min=p["s_min"])
+    c = torch.from_numpy(qs.centers).cuda()
+    r = torch.from_numpy(qs.radii).cuda()
+    out = eng.alloc_outputs(qs.q)
+    for _ in range(2):
+        eng.evaluate(h, c, r, opts, out=out)
+    torch.cuda.synchronize()
+    reps = max(5, steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        eng.evaluate(h, c, r, opts, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    cs.csplat_ctx_set_timing(eng.ctx, True)
+    kms = []
+    for _ in range(3):
+        eng.evaluate(h, c, r, opts, out=out)
+        st = cs.csplat_last_stats(eng.ctx)
+        kms.append(st["kernel_ms"])
+    cs.csplat_ctx_set_timing(eng.ctx, False)
+    nbr = int(out["nbr"].cpu().numpy().astype(np.int64).sum())
+    cs.csplat_scene_free(h)
+    ops = OPS_ALL_PAIRS * int(st["kernel_pairs"]) + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr
+    kernel_s = float(np.mean(kms)) / 1e3
+    return {"workload": "manip: 500k-Gaussian tabletop, 256 configurations x 32 steps x 48 chain spheres "
+                        "(r 0.03-0.10 m), n_sigma 1, ball 0.3 m, all outputs",
+            "n_kept": int(n_kept), "queries": int(qs.q), "ms_per_step": dt * 1e3,
+            "pair_evals_per_s": qs.q * n_kept / dt, "queries_per_s": qs.q / dt,
+            "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e9, "peak": PEAK_VALU / 1e9,
+                         "unit": "Gop/s", "frac": ops / kernel_s / PEAK_VALU, "kernel_ms": kernel_s * 1e3,
+                         "evaluated_pairs": int(st["kernel_pairs"]), "in_ball_pairs": nbr}}
 
 
 def ellipsoids(cs, eng, steps):
@@ -414,42 +465,72 @@ def serving(cs, eng, sc_nav, h_nav, n_requests, full):
     n_scene = [cs.csplat_scene_info(h_nav)[0], cs.csplat_scene_info(h4)[0]]
 
     def run(reqs, rate_scale):
+        # one thread submits at the arrival times, another collects finished
+        # requests as they complete (a finished request holds its output
+        # staging until it is collected)
+        import threading
         srv = cs.csplat_server_create(0, 4 << 30, 16)
         ids = [cs.csplat_server_add_scene(srv, h_nav), cs.csplat_server_add_scene(srv, h4)]
+        pending, lock, submitted = {}, threading.Lock(), threading.Event()
+        n_done = [0]
+
+        def collect():
+            last = time.perf_counter()
+            while True:
+                with lock:
+                    items = list(pending.items())
+                if not items and submitted.is_set():
+                    return
+                for t, (kind, q) in items:
+                    if cs.csplat_server_poll(srv, t, q, kind) is not None:
+                        with lock:
+                            del pending[t]
+                        n_done[0] += 1
+                if time.perf_counter() - last > 10.0:
+                    last = time.perf_counter()
+                    log(f"bench: serving: {n_done[0]} of {len(reqs)} requests collected")
+                time.sleep(0.002)
+
+        th = threading.Thread(target=collect)
         t0 = time.perf_counter()
-        tickets = []
+        th.start()
         for rq in reqs:
             while rate_scale and time.perf_counter() - t0 < rq["t"] * rate_scale:
                 time.sleep(0.0002)
             kind = cs.CSPLAT_SERVE_COST if rq["kind"] == "mppi" else cs.CSPLAT_SERVE_LABELS
-            tickets.append((cs.csplat_server_submit(srv, ids[rq["scene"]], kind, rq["centers"], rq["radii"],
-                                                    mppi_opts if kind == 0 else rrt_opts, rq["n_sigma"]),
-                            kind, rq["centers"].shape[0]))
-        last = time.perf_counter()
-        for i, (t, kind, q) in enumerate(tickets):
-            cs.csplat_server_wait(srv, t, q, kind)
-            if time.perf_counter() - last > 10.0:
-                last = time.perf_counter()
-                log(f"bench: serving: {i + 1} of {len(tickets)} requests collected")
+            t = cs.csplat_server_submit(srv, ids[rq["scene"]], kind, rq["centers"], rq["radii"],
+                                        mppi_opts if kind == 0 else rrt_opts, rq["n_sigma"])
+            with lock:
+                pending[t] = (kind, rq["centers"].shape[0])
+        submitted.set()
+        th.join()
         wall = time.perf_counter() - t0
         st = cs.csplat_server_stats(srv)
+        lat = cs.csplat_server_latencies(srv)
         cs.csplat_server_destroy(srv)
-        return st, wall
+        return st, wall, lat
+
+    def boot_ci(x, q, n=2000):
+        # percentile bootstrap: resample the requests' latencies with replacement
+        rng = np.random.default_rng(7)
+        v = np.percentile(x[rng.integers(0, x.size, (n, x.size))], q, axis=1)
+        return [float(np.percentile(v, 2.5)), float(np.percentile(v, 97.5))]
 
     log(f"bench: serving: generating {n_requests} requests")
     reqs = serving_stream(n_requests, seed=105, rate_hz=1.0, **kw)
     pairs = sum(rq["centers"].shape[0] * n_scene[rq["scene"]] for rq in reqs)
-    sat, wall = run(reqs, 0)           # saturated: every request at t = 0
+    sat, wall, _ = run(reqs, 0)        # saturated: every request at t = 0
     sat_rate = len(reqs) / wall
     lam = 0.5 * sat_rate
     reqs2 = serving_stream(n_requests, seed=105, rate_hz=lam, **kw)
-    st, wall2 = run(reqs2, 1.0)
+    st, wall2, lat = run(reqs2, 1.0)
     cs.csplat_scene_free(h4)
     return {"workload": ("full" if full else "reduced") + " serving law: 1M and 4M room scenes resident, "
             f"{n_requests} requests (MPPI K<={kw['max_mppi_k']} x 32 x <= {kw['max_spheres']} spheres, "
             f"RRT <= {kw['max_rrt_points']} points x <= {kw['max_spheres']} spheres), HBM budget 4 GiB, 16 slots",
             "saturated_requests_per_s": sat_rate, "saturated_pair_evals_per_s": pairs / wall,
-            "rate_requests_per_s": lam, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+            "rate_requests_per_s": lam, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "p50_ci95_ms": boot_ci(lat, 50), "p99_ci95_ms": boot_ci(lat, 99), "mean_ms": st["mean_ms"],
             "max_ms": st["max_ms"], "pair_evals_per_s": st["pairs_per_s"], "steps": st["steps"],
             "completed": st["completed"]}
 

@@ -285,6 +285,13 @@ csplat_status csplat_server_wait(csplat_server *srv, uint64_t ticket, const cspl
  * in-flight step).  CSPLAT_E_NOT_FOUND if unknown or already finished. */
 csplat_status csplat_server_cancel(csplat_server *srv, uint64_t ticket);
 csplat_status csplat_server_stats(csplat_server *srv, csplat_serving_stats *stats);
+/* Latencies (submit -> results in host memory, milliseconds) of the completed
+ * requests in completion order, for confidence intervals on the percentiles
+ * of csplat_server_stats.  Copies min(cap, completed) values into `ms` (host
+ * memory owned by the caller; may be NULL when cap is 0) and sets *n to the
+ * number of completed requests.  CSPLAT_E_INVALID for a NULL server or n, or
+ * cap < 0. */
+csplat_status csplat_server_latencies(csplat_server *srv, double *ms, int64_t cap, int64_t *n);
 
 /* Wait for all work queued on the context's stream. */
 csplat_status csplat_synchronize(csplat_ctx *ctx);

@@ -46,7 +46,7 @@ EXPORTS = (
     "csplat_eval_distance", "csplat_eval_ellipsoids", "csplat_ply_read", "csplat_scene_load_ply", "csplat_segment_reduce", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
     "csplat_last_error", "csplat_server_create", "csplat_server_destroy", "csplat_server_add_scene",
     "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
-    "csplat_server_stats",
+    "csplat_server_stats", "csplat_server_latencies",
 )
 CSPLAT_SERVE_COST = 0
 CSPLAT_SERVE_LABELS = 1
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH):
         "csplat_server_wait": [P, ctypes.c_uint64, P, I64],
         "csplat_server_cancel": [P, ctypes.c_uint64],
         "csplat_server_stats": [P, P],
+        "csplat_server_latencies": [P, P, I64, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -355,6 +356,16 @@ def csplat_server_stats(srv) -> dict:
     st = ServerStats()
     _check(load_library().csplat_server_stats(srv, ctypes.byref(st)))
     return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+
+def csplat_server_latencies(srv) -> np.ndarray:
+    """Latencies in ms of the completed requests, in completion order."""
+    lib = load_library()
+    n = ctypes.c_int64(0)
+    _check(lib.csplat_server_latencies(srv, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(n.value, 1), np.float64)
+    _check(lib.csplat_server_latencies(srv, out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(n)))
+    return out[:min(n.value, out.size)].copy()
 
 
 # --- convenience ------------------------------------------------------------

@@ -749,4 +749,14 @@ csplat_status csplat_server_stats(csplat_server *s, csplat_serving_stats *out)
     return CSPLAT_OK;
 }
 
+csplat_status csplat_server_latencies(csplat_server *s, double *ms, int64_t cap, int64_t *n)
+{
+    if (!s || !n || cap < 0 || (cap > 0 && !ms)) return fail(CSPLAT_E_INVALID, "server_latencies: bad argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int64_t have = (int64_t)s->lat_ms.size();
+    std::copy(s->lat_ms.begin(), s->lat_ms.begin() + std::min(cap, have), ms);
+    *n = have;
+    return CSPLAT_OK;
+}
+
 }  // extern "C"

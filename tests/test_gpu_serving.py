@@ -82,6 +82,11 @@ def test_mix_equals_alone_and_eval(cs, env, oracle_mod):
         st = cs.csplat_server_stats(srv)
         _say(f"mix: {st}")
         assert st["completed"] == len(reqs)
+        # the per-request latencies behind the percentiles
+        lat = cs.csplat_server_latencies(srv)
+        assert lat.size == len(reqs) and np.all(lat > 0)
+        assert np.isclose(np.percentile(lat, 50), st["p50_ms"]) and np.isclose(np.percentile(lat, 99), st["p99_ms"])
+        assert np.isclose(lat.max(), st["max_ms"]) and np.isclose(lat.mean(), st["mean_ms"])
         # each request alone on the server
         for (t, kind, r), mix in zip(tickets[:6], mixed[:6]):
             t2 = cs.csplat_server_submit(srv, ids[r["scene"]], kind, r["centers"], r["radii"], _opts(cs, kind),
