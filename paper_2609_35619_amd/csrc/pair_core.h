@@ -528,11 +528,17 @@ __device__ __forceinline__ void task_pair(const float4 &r0, const float4 &r1, co
 {
     const float dx = r0.x - Q.cx, dy = r0.y - Q.cy, dz = r0.z - Q.cz;
     const float Db = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    if (Db <= p.rn2) {
+    const float gp[12] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
+    float D, W;
+    metric_dw<ELL>(gp, Q.L, dx, dy, dz, Db, D, W);
+    // D and W come before the ball test, and W enters it: each lane runs
+    // its own task, so the in-ball block runs for the wave whenever one of
+    // its 64 pairs is inside (nearly always) and this costs no issue slots,
+    // while a test that reads only the mean lets the compiler move the
+    // record's other loads behind it, two memory latencies in a row.  W is
+    // NaN only for padding records, whose means at +inf fail the test anyway.
+    if (Db <= p.rn2 && W >= 0.f) {
         ++T.nb;
-        const float gp[12] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
-        float D, W;
-        metric_dw<ELL>(gp, Q.L, dx, dy, dz, Db, D, W);
         const float sv = fast_sqrt(W);
         const float Dk = D * Q.kq;
 #pragma unroll
