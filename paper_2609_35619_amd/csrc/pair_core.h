@@ -589,13 +589,16 @@ __device__ __forceinline__ void task_fold(TaskAcc<M> &A, const TaskAcc<M> &X)
     for (int v = 0; v < M; ++v) {
         A.cnt[v] += X.cnt[v];
         A.cs[v] += X.cs[v];
+        // log-sum-exp merge: the sum with the larger minimum is scaled by
+        // 2^-(difference); selects instead of branches (a wave's lanes fold
+        // partials of different queries).  An empty partial (minimum +inf,
+        // sum 0) scales by 0 and leaves the totals' bits unchanged, and an
+        // empty total takes the partial as it is (2^-inf = 0).
         const float cm = X.mt[v], tm = A.mt[v];
-        if (cm < tm) {
-            A.sm[v] = fmaf(A.sm[v], fast_exp2(tm == INFINITY ? -INFINITY : cm - tm), X.sm[v]);
-            A.mt[v] = cm;
-        } else if (cm < INFINITY) {
-            A.sm[v] = fmaf(X.sm[v], fast_exp2(tm - cm), A.sm[v]);
-        }
+        const bool lower = cm < tm;
+        const float e = lower || cm < INFINITY ? fast_exp2(lower ? cm - tm : tm - cm) : 0.f;
+        A.sm[v] = lower ? fmaf(A.sm[v], e, X.sm[v]) : fmaf(X.sm[v], e, A.sm[v]);
+        A.mt[v] = lower ? cm : tm;
     }
     A.nb += X.nb;
 }
@@ -709,11 +712,14 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
                 w[3 * M + v] = T.cs[v];
             }
             w[4 * M] = __int_as_float(T.nb);
+            // the padding words after them are never read: only the float4s
+            // that hold data are written (the rest of the last one repeats nb)
+            constexpr int kData = (4 * M + 4) / 4;
 #pragma unroll
-            for (int k = 4 * M + 1; k < PW; ++k) w[k] = 0.f;
+            for (int k = 4 * M + 1; k < 4 * kData; ++k) w[k] = w[4 * M];
             float4 *dst = &s_part[wv][lane * (PW / 4)];
 #pragma unroll
-            for (int k = 0; k < PW / 4; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+            for (int k = 0; k < kData; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -724,7 +730,7 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
             const float4 *src = &s_part[wv][__builtin_ctzll(mine) * (PW / 4)];
             float w[PW];
 #pragma unroll
-            for (int k = 0; k < PW / 4; ++k) {
+            for (int k = 0; k < (4 * M + 4) / 4; ++k) {
                 const float4 x = src[k];
                 w[4 * k] = x.x, w[4 * k + 1] = x.y, w[4 * k + 2] = x.z, w[4 * k + 3] = x.w;
             }
