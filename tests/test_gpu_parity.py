@@ -233,6 +233,33 @@ def test_task_walk_queue_edges(cs, eng, oracle_mod):
     assert np.all(res[1]["nbr"][[100, 101, 102, 193]] == 0)  # far queries: empty ball
 
 
+def test_query_order_and_crowded_cells(cs, eng, oracle_mod):
+    """Queries are evaluated in the scene's curve order and scattered back:
+    2,000 queries at one point (equal keys), queries outside the scene's box
+    (clamped to its edge cells) and uniform ones.  Parity with the oracle,
+    the same bits for the queries given in a shuffled order (a query's
+    results do not depend on which queries share its wave), and the same
+    bits on a repeat."""
+    _say("case: crowded cell, out-of-box and shuffled queries")
+    sc, qs0, p = config("tiny", 0.5)
+    rng = np.random.default_rng(5)
+    same = np.tile(np.array([[1.0, 2.0, 1.0]], np.float32), (2000, 1))
+    out_box = rng.uniform(-3.0, 7.0, (300, 3)).astype(np.float32)
+    centers = np.concatenate([same, out_box, qs0.centers[:700]]).astype(np.float32)
+    radii = rng.uniform(0.05, 0.3, centers.shape[0]).astype(np.float32)
+    qs = Queries(centers, radii)
+    p = dict(p, k=1, tau=0.1, r_nbr=0.6)
+    a = _run(cs, eng, sc, qs, p)
+    sub = np.arange(0, qs.q, 7)
+    _check({k: v[sub] for k, v in a.items()}, _oracle(oracle_mod, sc, qs.subset(sub), p), p, "crowded")
+    perm = rng.permutation(qs.q)
+    b = _run(cs, eng, sc, qs.subset(perm), p)
+    c = _run(cs, eng, sc, qs, p)
+    for k in ALL:
+        assert np.array_equal(a[k][perm].view(np.uint8), b[k].view(np.uint8)), k
+        assert np.array_equal(a[k].view(np.uint8), c[k].view(np.uint8)), k
+
+
 def test_invalid_inputs_are_rejected_without_writing(cs, eng):
     import torch
     _say("case: invalid inputs")
