@@ -160,7 +160,7 @@ __global__ void check_queries_kernel(int64_t q, const float *__restrict__ c, con
     if (j >= q) return;
     bool ok = isfinite(c[3 * j]) && isfinite(c[3 * j + 1]) && isfinite(c[3 * j + 2]) && r[j] > 0.f &&
               isfinite(r[j]);
-    if (!ok) atomicOr(bad, 1);
+    if (!ok) *bad = 1;  // every writer stores the same value
 }
 
 // Ellipsoidal bodies: finite centres, finite nonzero quaternions, finite
@@ -241,28 +241,36 @@ csplat_status device_check(csplat_ctx *ctx, Launch launch, const char *msg)
     return CSPLAT_OK;
 }
 
-// The same check queued without waiting: the flag is copied to pinned host
-// memory behind an event, and wait_device_check() waits for that event only
-// (the work queued after it keeps the device busy meanwhile).
+// The same check queued without waiting: the check kernel stores its flag
+// straight into pinned host memory (cleared by the host first), an event
+// follows it, and wait_device_check() waits for that event only (the work
+// queued after it keeps the device busy meanwhile).
 template <class Launch>
 csplat_status queue_device_check(csplat_ctx *ctx, Launch launch)
 {
-    hipError_t e = ctx->flags.reserve(64);
-    if (e != hipSuccess) return hip_fail(e, "flag workspace");
-    if (!ctx->check_host) CSPLAT_HIP(hipHostMalloc((void **)&ctx->check_host, 64, hipHostMallocDefault));
+    if (!ctx->check_host) {
+        CSPLAT_HIP(hipHostMalloc((void **)&ctx->check_host, 64, hipHostMallocDefault));
+        CSPLAT_HIP(hipHostGetDevicePointer((void **)&ctx->check_dev, ctx->check_host, 0));
+    }
     if (!ctx->ev_check) CSPLAT_HIP(hipEventCreateWithFlags(&ctx->ev_check, hipEventDisableTiming));
-    int *bad = ctx->flags.as<int>();
-    CSPLAT_HIP(zero_words(bad, 1, ctx->stream));
-    launch(bad);
+    // a check of an evaluation that ended early may still be queued: it
+    // finishes before its flag is cleared for this one
+    if (ctx->check_pending) {
+        CSPLAT_HIP(hipEventSynchronize(ctx->ev_check));
+        ctx->check_pending = false;
+    }
+    *ctx->check_host = 0;
+    launch(ctx->check_dev);
     CSPLAT_HIP(hipGetLastError());
-    CSPLAT_HIP(hipMemcpyAsync(ctx->check_host, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     CSPLAT_HIP(hipEventRecord(ctx->ev_check, ctx->stream));
+    ctx->check_pending = true;
     return CSPLAT_OK;
 }
 
 csplat_status wait_device_check(csplat_ctx *ctx, const char *msg)
 {
     CSPLAT_HIP(hipEventSynchronize(ctx->ev_check));
+    ctx->check_pending = false;
     if (*ctx->check_host) return fail(CSPLAT_E_INVALID, msg);
     return CSPLAT_OK;
 }

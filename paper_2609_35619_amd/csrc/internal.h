@@ -170,7 +170,9 @@ struct csplat_ctx {
     bool timed = false;         // events of the last evaluation were recorded
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int *check_host = nullptr;      // pinned: the device-side input check's flag
-    hipEvent_t ev_check = nullptr;  // recorded after that flag's copy
+    int *check_dev = nullptr;       // its device address
+    bool check_pending = false;     // a check is queued and not yet waited for
+    hipEvent_t ev_check = nullptr;  // recorded after the check kernel
 };
 
 namespace csplat {

@@ -48,14 +48,16 @@ constexpr float kCullMargin = 1.0000153f;  // 1 + 2^-16
 #else
 #define CSPLAT_OCCUPANCY
 #endif
-// The task walk (full outputs over a ball) at 5 waves per SIMD: its vector
-// loads want the latency hiding.  Records are loaded four at a time with one
-// conservatism value and two at a time with more, where four would spill
-// under the cap (measured on MI355X: navigation workload, m = 3: no cap
-// 1.25 ms, 4 waves 1.10, then with other changes 4 waves and four records
-// 1.002 ms, 5 waves and two records 0.987 ms, 5 waves and four records 1.34
-// ms with 152 spilled bytes; serving, m = 1: 5 waves and four records 495
-// requests/s, two records 440, 4 waves and four records 468).
+// The task walk (full outputs over a ball) at 5 or more waves per SIMD: its
+// vector loads want the latency hiding.  Records are loaded four at a time
+// with one conservatism value and two at a time with more, where four would
+// spill.  With three values the kernel fits in 78 VGPRs and runs 6 waves
+// (LDS holds six of its blocks per CU).  Measured on MI355X: navigation
+// workload, m = 3: no cap 1.25 ms, 4 waves 1.10, later 4 waves 1.002 ms and
+// 5 waves 0.987 ms, now 6 waves 0.906 ms, 7 waves (partial rows without bank
+// padding, 32 spilled bytes) 0.92-0.93; one value (manipulation 21.6 ms,
+// serving 633 requests/s): 6 waves with 24 spilled bytes 22.2 ms and 599,
+// two records per group at 8 waves 22.1 ms and 585.
 #ifndef CSPLAT_TASK_WAVES_PER_EU
 #define CSPLAT_TASK_WAVES_PER_EU 5
 #endif

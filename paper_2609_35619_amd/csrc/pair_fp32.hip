@@ -99,11 +99,14 @@ csplat_status launch_m(csplat_ctx *ctx, bool full, bool ball, bool cull, const L
     return CSPLAT_OK;
 }
 
-// Hilbert key of each query centre on the scene's grid (the scene's curve).
+// Hilbert key of each query centre on the scene's grid (the scene's curve);
+// thread 0 also clears the pair kernel's task counter.
 __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride, float3 lo, float3 scale,
-                                  uint32_t *__restrict__ code, int32_t *__restrict__ idx)
+                                  uint32_t *__restrict__ code, int32_t *__restrict__ idx,
+                                  unsigned long long *__restrict__ counter)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) *counter = 0;
     if (j >= q) return;
     const float *cj = c + (size_t)stride * j;
     const float fx = (cj[0] - lo.x) * scale.x, fy = (cj[1] - lo.y) * scale.y, fz = (cj[2] - lo.z) * scale.z;
@@ -196,7 +199,7 @@ csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const 
     query_code_kernel<<<qb, 256, 0, st>>>(q, centers, ell ? kBodyFloats : 3,
                                           make_float3(sc->box_lo[0], sc->box_lo[1], sc->box_lo[2]),
                                           make_float3(sc->box_scale[0], sc->box_scale[1], sc->box_scale[2]), code,
-                                          idx);
+                                          idx, counter);
     CSPLAT_HIP(hipGetLastError());
     CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(b + off_tmp, tbytes, code, code2, idx, perm, q, 0, 30, st));
     if (ell)
@@ -205,7 +208,6 @@ csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const 
     else
         query_gather_kernel<<<qb, 256, 0, st>>>(q, perm, centers, radii, sc_c, sc_r);
     CSPLAT_HIP(hipGetLastError());
-    CSPLAT_HIP(zero_words(reinterpret_cast<int32_t *>(counter), 2, st));
     out->c = sc_c;
     out->r = ell ? nullptr : sc_r;
     out->perm = perm;

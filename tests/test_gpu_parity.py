@@ -287,6 +287,12 @@ def test_invalid_inputs_are_rejected_without_writing(cs, eng):
             assert ei.value.status == cs.CSPLAT_E_INVALID
             got = ll.cpu().numpy() if dev else ll
             assert np.all(got == 7), "outputs written on error"
+            if dev:
+                # the device-side flag is cleared for the next evaluation
+                good = torch.from_numpy(qs.centers).cuda(), torch.from_numpy(qs.radii).cuda()
+                cs.csplat_eval_labels(eng.ctx, h, *good, opts, ll)
+                torch.cuda.synchronize()
+                assert np.all(ll.cpu().numpy() <= 1)
     for ns in ([-1.0], [float("nan")], [1.0] * 9):
         with pytest.raises(cs.CsplatError):
             cs.csplat_set_conservatism(eng.ctx, ns)
