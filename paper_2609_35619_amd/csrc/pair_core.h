@@ -1312,18 +1312,16 @@ template <int M, bool FULL>
 __device__ __forceinline__ void combine_one(int j, int v, int q, int S, const EvalParams &p, const Part &part,
                                             const EvalOut &out, const int32_t *perm)
 {
-    constexpr int kAhead = 8;
+    // the splits' words are read kAhead splits at a time (the loads of a
+    // batch are in flight together), the ball sizes with them
+    constexpr int kAhead = 16;
     const int oj = perm ? perm[j] : j;
+    const bool want_nb = FULL && (out.cost || (v == 0 && out.nbr));
     int nb = 0;
-    if constexpr (FULL) {
-        if (out.cost || (v == 0 && out.nbr))
-            for (int s = 0; s < S; ++s) nb += part.nb[(size_t)s * q + j];
-    }
-    if (v == 0 && out.nbr) out.nbr[oj] = nb;
     int cnt = 0;
     float mt = INFINITY, sm = 0.f, cs = 0.f;
     for (int s0 = 0; s0 < S; s0 += kAhead) {
-        int c[kAhead];
+        int c[kAhead], bn[kAhead];
         float bm[kAhead], bs[kAhead], bc[kAhead];
 #pragma unroll
         for (int k = 0; k < kAhead; ++k) {
@@ -1334,6 +1332,7 @@ __device__ __forceinline__ void combine_one(int j, int v, int q, int S, const Ev
                 bm[k] = part.mt[o];
                 bs[k] = part.sm[o];
                 bc[k] = part.cs[o];
+                bn[k] = want_nb ? part.nb[(size_t)s * q + j] : 0;
             }
         }
 #pragma unroll
@@ -1341,6 +1340,7 @@ __device__ __forceinline__ void combine_one(int j, int v, int q, int S, const Ev
             if (s0 + k >= S) break;
             cnt += c[k];
             if constexpr (FULL) {
+                nb += bn[k];
                 cs += bc[k];
                 if (bm[k] < INFINITY) {
                     if (bm[k] < mt) {
@@ -1353,6 +1353,7 @@ __device__ __forceinline__ void combine_one(int j, int v, int q, int S, const Ev
             }
         }
     }
+    if (v == 0 && out.nbr) out.nbr[oj] = nb;
     const size_t o = (size_t)oj * p.m + v;
     if (out.count) out.count[o] = cnt;
     if (out.label) out.label[o] = cnt > p.k ? 1 : 0;
