@@ -842,6 +842,10 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
 #ifndef CSPLAT_LABEL_QUERIES_PER_TASK
 #define CSPLAT_LABEL_QUERIES_PER_TASK 2
 #endif
+#ifndef CSPLAT_LABEL_UNROLL
+#define CSPLAT_LABEL_UNROLL 2  // records per load group of the label task loop
+#endif
+constexpr int kLabelUnroll = CSPLAT_LABEL_UNROLL;
 template <int M, bool BALL, bool CULL, bool ELL>
 __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ gs, int n, int S, int split,
                                                       int tile, const float *__restrict__ centers,
@@ -919,16 +923,16 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
         // the scene's records are padded to whole chunks (pad means at +inf)
         const float4 *rp = reinterpret_cast<const float4 *>(gs) + (size_t)f * (kFine * kGaussFloats / 4);
 #pragma unroll 1
-        for (int k = 0; k < kFine; k += kUnroll, rp += kUnroll * (kGaussFloats / 4)) {
-            float4 r[kUnroll][3];
+        for (int k = 0; k < kFine; k += kLabelUnroll, rp += kLabelUnroll * (kGaussFloats / 4)) {
+            float4 r[kLabelUnroll][3];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kLabelUnroll; ++u) {
                 r[u][0] = rp[u * (kGaussFloats / 4)];
                 r[u][1] = rp[u * (kGaussFloats / 4) + 1];
                 r[u][2] = rp[u * (kGaussFloats / 4) + 2];
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
+            for (int u = 0; u < kLabelUnroll; ++u)
 #pragma unroll
                 for (int j = 0; j < KQ; ++j) task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tq[j], p, T[j]);
         }
