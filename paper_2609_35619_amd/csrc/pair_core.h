@@ -617,6 +617,23 @@ constexpr int task_words()
 
 __device__ __forceinline__ float lane_shfl(float v, int src) { return __shfl(v, src); }
 
+// Queries per queue entry of the full-output task walk.  With one
+// conservatism value a pair costs few operations against its 48-byte record,
+// and the walk is bound by the return of vector-memory data (manipulation
+// workload: texture units ~72% busy, VALU issue 61%), so an entry holds two
+// queries of the same sub-chunk and one lane evaluates both against each
+// record it loads.  Each query still has one task per sub-chunk over the
+// same records in the same order, folded in queue order: the bits do not
+// depend on the entry size.
+#ifndef CSPLAT_FULL_QUERIES_PER_TASK
+#define CSPLAT_FULL_QUERIES_PER_TASK 2
+#endif
+template <int M, bool ELL>
+constexpr int full_entry_queries()
+{
+    return M == 1 && !ELL ? CSPLAT_FULL_QUERIES_PER_TASK : 1;
+}
+
 template <int M, bool FULL, bool BALL, bool CULL, bool ELL>
 __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, int n, int S, int split, int tile,
                                                 const float *__restrict__ centers, const float *__restrict__ radii,
@@ -768,6 +785,251 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
         const int cnt = __popcll(lanes);
         tail += cnt;
         if (tasks_done) *tasks_done += cnt;
+        if (tail - head >= 64) run_round(64);
+    };
+
+    const int n_chunks = (n + kCull - 1) / kCull;
+    const int n_fine = (n + kFine - 1) / kFine;
+    const int n_groups = (n_chunks + kGroup - 1) / kGroup;
+    if constexpr (!CULL) {
+        for (int c = split; c < n_chunks; c += S)
+            for (int k = 0; k < kFinePer; ++k) {
+                const int fi = c * kFinePer + k;
+                if (fi < n_fine) enqueue(fi, ~0ull);
+            }
+    } else {
+        const float *fine = cull + (size_t)n_chunks * kCullFloats;  // the sub-chunk level
+        const float *groups = fine + (size_t)n_fine * kCullFloats;  // the group level
+        float cx[1] = {own.cx}, cy[1] = {own.cy}, cz[1] = {own.cz}, r2[1] = {own.r2};
+        float wx, wy, wz, spread, r2max;
+        wave_sphere<1>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
+        // full outputs reduce over the ball: a chunk farther than r_nbr plus
+        // its radius from a body's centre holds no counted pair
+        auto reach_of = [&](const ChunkMeta &) { return p.r_nbr; };
+        split_walk<false>(
+            groups, cull, n_groups, n_chunks, split, S,
+            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m)); },
+            [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + reach_of(m)); },
+            [&](int ci, unsigned long long lanes) {
+                // the sub-chunks' records are read together (one latency),
+                // tested, and their lanes rotated through one enqueue site
+                static_assert(kFinePer == 4, "sub-chunk rotation below assumes four");
+                const int f0 = ci * kFinePer;
+                ChunkMeta fm[kFinePer];
+#pragma unroll
+                for (int k = 0; k < kFinePer; ++k) fm[k] = load_chunk(fine, min(f0 + k, n_fine - 1));
+                unsigned long long fl[kFinePer];
+#pragma unroll
+                for (int k = 0; k < kFinePer; ++k) {
+                    const unsigned long long exists = f0 + k < n_fine ? ~0ull : 0ull;
+                    fl[k] = lanes & exists &
+                            __ballot(within(fm[k], own.cx, own.cy, own.cz, fm[k].rad + reach_of(fm[k])));
+                }
+                unsigned long long l0 = fl[0], l1 = fl[1], l2 = fl[2], l3 = fl[3];
+#pragma unroll 1
+                for (int k = 0; k < kFinePer; ++k) {
+                    if (l0) enqueue(f0 + k, l0);
+                    l0 = l1, l1 = l2, l2 = l3, l3 = 0;
+                }
+            });
+    }
+    if (tail > head) run_round(tail - head);
+    if (jq < q) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            const size_t o = ((size_t)split * M + v) * q + jq;
+            part.cnt[o] = A.cnt[v];
+            part.mt[o] = A.mt[v];
+            part.sm[o] = A.sm[v];
+            part.cs[o] = A.cs[v];
+        }
+        part.nb[(size_t)split * q + jq] = A.nb;
+    }
+}
+
+// The same walk with KQ > 1 queries per queue entry (one conservatism value).
+template <int M, bool FULL, bool BALL, bool CULL, bool ELL>
+__device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__ gs, int n, int S, int split, int tile,
+                                                const float *__restrict__ centers, const float *__restrict__ radii,
+                                                int q, const EvalParams &p, const Part &part,
+                                                const float *__restrict__ cull, int *tasks_done)
+{
+    static_assert(FULL && BALL, "labels run in eval_tile_label_tasks");
+    constexpr int KQ = full_entry_queries<M, ELL>();  // queries per entry
+    static_assert(KQ > 1, "one query per entry runs in eval_tile_tasks");
+    constexpr int kRing = 128;  // queued entries per wave: at most 63 waiting + 64 / KQ of one sub-chunk
+    constexpr int PW = task_words<M, FULL>();
+    constexpr int kWaves = kBlock / 64;
+    constexpr unsigned char kNone = 0xFF;
+    __shared__ int s_task[kWaves][kRing];                  // sub-chunk of each queued entry
+    __shared__ unsigned char s_q[kWaves][KQ][kRing];       // lanes of its queries, kNone for an empty slot
+    __shared__ float4 s_part[kWaves][KQ * 64 * PW / 4];    // partials of a round, PW words per task
+    const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
+    const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
+    TaskQuery<ELL> own;
+    if constexpr (ELL) {
+        const float4 *b = reinterpret_cast<const float4 *>(centers + (size_t)kBodyFloats * jj);
+        const float4 b0 = b[0], b1 = b[1], b2 = b[2];
+        own.cx = b0.x, own.cy = b0.y, own.cz = b0.z;
+        own.L[0] = b0.w, own.L[1] = b1.x, own.L[2] = b1.y, own.L[3] = b1.z, own.L[4] = b1.w;
+        own.L[5] = b2.x, own.L[6] = b2.y, own.L[7] = b2.z, own.L[8] = b2.w;
+        own.r2 = 1.f;
+        own.kq = p.kt;
+    } else {
+        own.cx = centers[3 * jj];
+        own.cy = centers[3 * jj + 1];
+        own.cz = centers[3 * jj + 2];
+        const float r = radii[jj];
+        own.r2 = r * r;
+        own.kq = p.kt / own.r2;
+    }
+    TaskAcc<M> A;
+    task_reset(A);
+    // ring positions of the lane's own queued tasks (bit k of lo: position k,
+    // of hi: position 64 + k) and, with two queries per entry, which slot of
+    // the entry is the lane's; head, tail: wave-uniform, counting up
+    unsigned long long own_lo = 0, own_hi = 0, slot_lo = 0, slot_hi = 0;
+    int head = 0, tail = 0;
+    float g0v = p.g0;
+    asm volatile("" : "+v"(g0v));
+
+    auto run_round = [&](int n_t) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const bool valid = lane < n_t;
+        const int pos = (head + lane) & (kRing - 1);
+        const int f = valid ? s_task[wv][pos] : 0;
+        TaskQuery<ELL> tq[KQ];
+        TaskScale<M> K[KQ];
+        TaskAcc<M> T[KQ];
+#pragma unroll
+        for (int j = 0; j < KQ; ++j) {
+            const int iq = valid ? (int)s_q[wv][j][pos] : (KQ > 1 ? (int)kNone : 0);
+            const bool ok = KQ > 1 ? iq != (int)kNone : valid;
+            const int qi = KQ > 1 ? iq & 63 : iq;
+            // the lane permutes run with every lane active (a permute reads
+            // nothing useful from an inactive source lane), the selects after
+            tq[j].cx = lane_shfl(own.cx, qi);
+            // a lane without a task walks sub-chunk 0 for a query at
+            // infinity, which has no Gaussian in its ball (its partial is
+            // never folded); so does an empty slot of an entry
+            if (!ok) tq[j].cx = INFINITY;
+            tq[j].cy = lane_shfl(own.cy, qi);
+            tq[j].cz = lane_shfl(own.cz, qi);
+            tq[j].r2 = lane_shfl(own.r2, qi);
+            tq[j].kq = lane_shfl(own.kq, qi);
+            if constexpr (ELL) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) tq[j].L[k] = lane_shfl(own.L[k], qi);
+            }
+            K[j].thr = tq[j].r2 * tq[j].kq;
+#pragma unroll
+            for (int v = 0; v < M; ++v) K[j].c[v] = p.two_n[v] * tq[j].kq;
+            task_reset(T[j]);
+        }
+        // the scene's records are padded to whole chunks (pad means at +inf)
+        const float4 *rp = reinterpret_cast<const float4 *>(gs) + (size_t)f * (kFine * kGaussFloats / 4);
+        constexpr int kTaskUnroll = KQ > 1 ? 2 : task_unroll<M>();
+#pragma unroll 1
+        for (int k = 0; k < kFine; k += kTaskUnroll, rp += kTaskUnroll * (kGaussFloats / 4)) {
+            float4 r[kTaskUnroll][3];
+#pragma unroll
+            for (int u = 0; u < kTaskUnroll; ++u) {
+                r[u][0] = rp[u * (kGaussFloats / 4)];
+                r[u][1] = rp[u * (kGaussFloats / 4) + 1];
+                r[u][2] = rp[u * (kGaussFloats / 4) + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < kTaskUnroll; ++u)
+#pragma unroll
+                for (int j = 0; j < KQ; ++j) task_pair<M, ELL>(r[u][0], r[u][1], r[u][2], tq[j], K[j], p, g0v, T[j]);
+        }
+        // the round's partials to LDS (row = lane KQ + slot), words:
+        // cnt | mt | sm | cs | nb
+#pragma unroll
+        for (int j = 0; j < KQ; ++j) {
+            float w[PW];
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                w[v] = __int_as_float(T[j].cnt[v]);
+                w[M + v] = T[j].mt[v];
+                w[2 * M + v] = T[j].sm[v];
+                w[3 * M + v] = T[j].cs[v];
+            }
+            w[4 * M] = __int_as_float(T[j].nb);
+            // the padding words after them are never read: only the float4s
+            // that hold data are written (the rest of the last one repeats nb)
+            constexpr int kData = (4 * M + 4) / 4;
+#pragma unroll
+            for (int k = 4 * M + 1; k < 4 * kData; ++k) w[k] = w[4 * M];
+            float4 *dst = &s_part[wv][(lane * KQ + j) * (PW / 4)];
+#pragma unroll
+            for (int k = 0; k < kData; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // each query folds its tasks of this round, in queue order; the
+        // round's entry i is ring position head + i, head a multiple of 64
+        const unsigned long long slots = (head & 64) ? slot_hi : slot_lo;
+        for (unsigned long long mine = (head & 64) ? own_hi : own_lo; mine; mine &= mine - 1) {
+            const int e = __builtin_ctzll(mine);
+            const int row = KQ > 1 ? e * KQ + (int)((slots >> e) & 1ull) : e;
+            const float4 *src = &s_part[wv][row * (PW / 4)];
+            float w[PW];
+#pragma unroll
+            for (int k = 0; k < (4 * M + 4) / 4; ++k) {
+                const float4 x = src[k];
+                w[4 * k] = x.x, w[4 * k + 1] = x.y, w[4 * k + 2] = x.z, w[4 * k + 3] = x.w;
+            }
+            TaskAcc<M> X;
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                X.cnt[v] = __float_as_int(w[v]);
+                X.mt[v] = w[M + v];
+                X.sm[v] = w[2 * M + v];
+                X.cs[v] = w[3 * M + v];
+            }
+            X.nb = __float_as_int(w[4 * M]);
+            task_fold(A, X);
+        }
+        if (head & 64) own_hi = 0, slot_hi = 0;
+        else own_lo = 0, slot_lo = 0;
+        head += n_t;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // queue the tasks of sub-chunk fi for the lanes in `lanes`, KQ queries
+    // per entry in lane order (every lane is active)
+    auto enqueue = [&](int fi, unsigned long long lanes) {
+        const int c = __popcll(lanes);
+        const int k = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(lanes >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)lanes, 0u));
+        if ((lanes >> lane) & 1ull) {
+            const int pos = (tail + k / KQ) & (kRing - 1);
+            const int slot = k % KQ;
+            if (slot == 0) s_task[wv][pos] = fi;
+            s_q[wv][slot][pos] = (unsigned char)lane;
+            if (KQ > 1 && k == c - 1)  // the last entry's empty slots
+                for (int j = slot + 1; j < KQ; ++j) s_q[wv][j][pos] = kNone;
+            if constexpr (KQ == 1) {
+                if (pos < 64) own_lo |= 1ull << pos;
+                else own_hi |= 1ull << (pos - 64);
+            } else {
+                // selects, not branches: the four masks stay in registers
+                const unsigned long long bit = 1ull << (pos & 63);
+                const bool hi = pos >= 64;
+                own_lo |= hi ? 0ull : bit;
+                own_hi |= hi ? bit : 0ull;
+                slot_lo |= !hi && slot ? bit : 0ull;
+                slot_hi |= hi && slot ? bit : 0ull;
+            }
+        }
+        tail += (c + KQ - 1) / KQ;
+        if (tasks_done) *tasks_done += c;
         if (tail - head >= 64) run_round(64);
     };
 
@@ -1048,7 +1310,10 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
                                           int *chunks_done = nullptr)
 {
     if constexpr (uses_tasks<FULL, BALL, QPL, ELL>()) {
-        if constexpr (FULL)
+        if constexpr (FULL && full_entry_queries<M, ELL>() > 1)
+            eval_tile_tasks_shared<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part,
+                                                             cull, chunks_done);
+        else if constexpr (FULL)
             eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
                                                       chunks_done);
         else
@@ -1301,7 +1566,10 @@ pair_task_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const 
     const int split = b / n_tiles;
     const int tile = b - split * n_tiles;
     int done = 0;
-    if constexpr (FULL)
+    if constexpr (FULL && full_entry_queries<M, ELL>() > 1)
+        eval_tile_tasks_shared<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
+                                                         &done);
+    else if constexpr (FULL)
         eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
     else
         eval_tile_label_tasks<M, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
