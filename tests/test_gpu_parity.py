@@ -194,15 +194,17 @@ def test_parameter_variants(cs, eng, oracle_mod, variant):
     _check(gpu, ref, p, variant)
 
 
-def test_task_walk_queue_edges(cs, eng, oracle_mod):
+@pytest.mark.parametrize("n_sigma", [[0.0, 1.0, 3.0], [1.0]])
+def test_task_walk_queue_edges(cs, eng, oracle_mod, n_sigma):
     """Full outputs over a ball run as (query, sub-chunk) tasks queued per
-    wave: a cluster inside every query's ball queues up to 64 tasks per
-    sub-chunk (the ring wraps many times), n = 1037 leaves a last sub-chunk
-    of 13 Gaussians plus padding, q = 197 a partial last wave, and far
-    queries have no task at all.  Parity with the oracle on every output and
-    the same bits with culling off."""
+    wave (with one n_sigma value two queries share a queue entry): a cluster
+    inside every query's ball queues up to 64 tasks per sub-chunk (the ring
+    wraps many times; odd counts leave an entry's second slot empty),
+    n = 1037 leaves a last sub-chunk of 13 Gaussians plus padding, q = 197 a
+    partial last wave, and far queries have no task at all.  Parity with the
+    oracle on every output and the same bits with culling off."""
     import torch
-    _say("case: task walk, clustered 1037 Gaussians x 197 queries, ball 0.5")
+    _say(f"case: task walk, clustered 1037 Gaussians x 197 queries, ball 0.5, n_sigma {n_sigma}")
     rng = np.random.default_rng(11)
     q, s, o = common_attrs(rng, 1037)
     m = (0.5 + 0.1 * rng.standard_normal((1037, 3))).astype(np.float32)
@@ -213,7 +215,7 @@ def test_task_walk_queue_edges(cs, eng, oracle_mod):
     centers = np.concatenate([near[:100], far, near[100:], far[:1], m[:3]]).astype(np.float32)
     assert centers.shape[0] == 197
     qs = Queries(centers, rng.uniform(0.02, 0.08, 197).astype(np.float32))
-    p = dict(n_sigma=[0.0, 1.0, 3.0], tau=0.05, k=1, r_nbr=0.5, gamma=1.5, d_max=2.0)
+    p = dict(n_sigma=n_sigma, tau=0.05, k=1, r_nbr=0.5, gamma=1.5, d_max=2.0)
     gpu = _run(cs, eng, sc, qs, p)
     _check(gpu, _oracle(oracle_mod, sc, qs, p), p, "task-walk")
     h = eng.load_scene(sc)
