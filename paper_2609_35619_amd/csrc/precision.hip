@@ -341,8 +341,8 @@ __device__ __forceinline__ bool build_query(float cx, float cy, float cz, float 
 }
 
 // ---------------------------------------------------------------------------
-// Certification kernel: block = 4 waves x 64 queries (two 32-query column
-// blocks per wave); grid = query blocks x S splits, split s taking the tiles
+// Certification kernel: block = 4 waves x 32 kCB queries (kCB 32-query
+// column blocks per wave); grid = query blocks x S splits, split s taking the tiles
 // s, s + S, s + 2S, ... (every split samples the whole scene, so the work of
 // a query block is spread evenly over its S items).
 // With CULL, a column block skips row blocks in pairs (one culling chunk of
@@ -350,6 +350,15 @@ __device__ __forceinline__ bool build_query(float cx, float cy, float cz, float 
 // bound n s_c + sqrt(n^2 s_c^2 + r^2) plus its radius: no pair of them can
 // collide.  Chunks are tested 64 at a time (8 tiles x 8 chunks, one per lane)
 // against the wave's bounding sphere, then each survivor against every query.
+// Column blocks of 32 queries per wave: the A operands of a row block are
+// loaded once and multiplied against every column block that needs them.
+#ifndef CSPLAT_MFMA_COLUMN_BLOCKS
+#define CSPLAT_MFMA_COLUMN_BLOCKS 2
+#endif
+constexpr int kCB = CSPLAT_MFMA_COLUMN_BLOCKS;
+static_assert(kCB == 2 || kCB == 4, "column blocks per wave: 2 or 4");
+constexpr int kQueriesPerBlock = 4 * 32 * kCB;
+
 template <int P, bool CULL>
 __global__ void __launch_bounds__(256)
 mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *__restrict__ meta,
@@ -359,17 +368,18 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
 {
     using T = Prec<P>;
     using vec = typename T::vec;
+    constexpr int kG = kCB / 2;  // queries each lane builds features for
     int b = blockIdx.x;
     const int B = gridDim.x;
     if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few splits
     const int split = b / n_qblocks;
     const int qb = b - split * n_qblocks;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-    float cx[2], cy[2], cz[2], r2[2];
-    int jq[2];
+    float cx[kCB], cy[kCB], cz[kCB], r2[kCB];
+    int jq[kCB];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-        jq[cb] = qb * 256 + wave * 64 + cb * 32 + col;
+    for (int cb = 0; cb < kCB; ++cb) {
+        jq[cb] = qb * kQueriesPerBlock + wave * (32 * kCB) + cb * 32 + col;
         const int jj = jq[cb] < q ? jq[cb] : q - 1;
         cx[cb] = centers[3 * jj];
         cy[cb] = centers[3 * jj + 1];
@@ -377,26 +387,46 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         const float r = radii[jj];
         r2[cb] = r * r;
     }
-    int lo[2] = {0, 0}, hi[2] = {0, 0};
-    bool bad = false;  // a non-finite bound for the lane's own query (column block h)
-    const float ox = h ? cx[1] : cx[0], oy = h ? cy[1] : cy[0], oz = h ? cz[1] : cz[0], or2 = h ? r2[1] : r2[0];
+    int lo[kCB], hi[kCB];
+    bool bad[kG];  // a non-finite bound for the lane's own query of column block pair g
+#pragma unroll
+    for (int cb = 0; cb < kCB; ++cb) lo[cb] = hi[cb] = 0;
+#pragma unroll
+    for (int g = 0; g < kG; ++g) bad[g] = false;
+    // the lane builds the features of query (2 g + h, col) for each pair g
+    float ox[kG], oy[kG], oz[kG], or2[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+        ox[g] = h ? cx[2 * g + 1] : cx[2 * g];
+        oy[g] = h ? cy[2 * g + 1] : cy[2 * g];
+        oz[g] = h ? cz[2 * g + 1] : cz[2 * g];
+        or2[g] = h ? r2[2 * g + 1] : r2[2 * g];
+    }
     const f32x16 zero = {};
     // tile t: row block rb against column block cb where bit rb of rbm[cb]
     // is set (wave-uniform masks)
-    auto do_tile = [&](int t, unsigned rbm0, unsigned rbm1) {
+    auto do_tile = [&](int t, const unsigned (&rbm_cb)[kCB]) {
         const float *mt = meta + (size_t)t * kMeta;  // wave-uniform: scalar loads
-        QFeat<P> Q[2];
-        bad |= !build_query<P>(ox, oy, oz, or2, four_n2, mt, Q);
+        QFeat<P> Q[kCB];
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            QFeat<P> Qg[2];
+            bad[g] |= !build_query<P>(ox[g], oy[g], oz[g], or2[g], four_n2, mt, Qg);
+            Q[2 * g] = Qg[0];
+            Q[2 * g + 1] = Qg[1];
+        }
         const vec *ft = feat + (size_t)t * kRB * kOps * kLanes + lane;
-        unsigned rbm = rbm0 | rbm1;
+        unsigned rbm = 0;
+#pragma unroll
+        for (int cb = 0; cb < kCB; ++cb) rbm |= rbm_cb[cb];
         while (rbm) {
             const int rb = __builtin_ctz(rbm);
             rbm &= rbm - 1;
             const vec *fp = ft + (size_t)rb * kOps * kLanes;
             const vec Aa = fp[0], Aw0 = fp[kLanes], Aw1 = fp[2 * kLanes];
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                if (!(((cb ? rbm1 : rbm0) >> rb) & 1u)) continue;  // no query of cb near the row block
+            for (int cb = 0; cb < kCB; ++cb) {
+                if (!((rbm_cb[cb] >> rb) & 1u)) continue;  // no query of cb near the row block
                 const f32x16 A = T::mfma(Aa, Q[cb].a, zero);
                 f32x16 W = T::mfma(Aw0, Q[cb].w0, zero);
                 W = T::mfma(Aw1, Q[cb].w1, W);
@@ -423,10 +453,13 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         }
     };
     if constexpr (!CULL) {
-        for (int t = split; t < n_tiles; t += S) do_tile(t, 0xffffu, 0xffffu);
+        unsigned all[kCB];
+#pragma unroll
+        for (int cb = 0; cb < kCB; ++cb) all[cb] = 0xffffu;
+        for (int t = split; t < n_tiles; t += S) do_tile(t, all);
     } else {
         float wx, wy, wz, spread, r2max;
-        pair::wave_sphere<2>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
+        pair::wave_sphere<kCB>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
         auto reach_of = [&](const pair::ChunkMeta &m, float rr2) {
             const float ns = n_sigma * m.smax;
             return ns + pair::fast_sqrt(fmaf(ns, ns, rr2));  // ~1 ulp, far inside the culling margin
@@ -450,24 +483,33 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
                 // through its two 16-Gaussian sub-chunks cost more than the
                 // blocks it skipped: 1.19 -> 1.30 ms on the precision workload)
                 const int t = split + (ib + g) * S;
-                unsigned rbm0 = 0, rbm1 = 0;
+                unsigned rbm[kCB];
+#pragma unroll
+                for (int cb = 0; cb < kCB; ++cb) rbm[cb] = 0;
+                unsigned any = 0;
                 while (tm) {
                     const int k = __builtin_ctz(tm);
                     tm &= tm - 1;
                     const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
-                    if (__any(pair::within(c, cx[0], cy[0], cz[0], c.rad + reach_of(c, r2[0])))) rbm0 |= 3u << (2 * k);
-                    if (__any(pair::within(c, cx[1], cy[1], cz[1], c.rad + reach_of(c, r2[1])))) rbm1 |= 3u << (2 * k);
+#pragma unroll
+                    for (int cb = 0; cb < kCB; ++cb)
+                        if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, r2[cb]))))
+                            rbm[cb] |= 3u << (2 * k);
                 }
-                if (rbm0 | rbm1) do_tile(t, rbm0, rbm1);
+#pragma unroll
+                for (int cb = 0; cb < kCB; ++cb) any |= rbm[cb];
+                if (any) do_tile(t, rbm);
             }
         }
     }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < kCB; ++cb) {
         lo[cb] += __shfl_xor(lo[cb], 32);
         hi[cb] += __shfl_xor(hi[cb], 32);
-        const bool other = __shfl_xor((int)bad, 32) != 0;
-        const bool anybad = (h == cb) ? bad : other;
+        // the query of column block cb was built by the lanes of half cb & 1
+        const int g = cb >> 1;
+        const bool other = __shfl_xor((int)bad[g], 32) != 0;
+        const bool anybad = (h == (cb & 1)) ? bad[g] : other;
         if (h == 0 && jq[cb] < q) {
             lo_out[(size_t)split * q + jq[cb]] = lo[cb];
             hi_out[(size_t)split * q + jq[cb]] = anybad ? (1 << 29) : hi[cb];
@@ -662,7 +704,7 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
     const int m = p.m;
     hipStream_t st = ctx->stream;
     const int n_tiles = (int)sc->n_tiles;
-    const int n_qblocks = (q + 255) / 256;
+    const int n_qblocks = (q + kQueriesPerBlock - 1) / kQueriesPerBlock;
     int S = 1;
     if (n_tiles > 0) {
         S = (ctx_target_blocks(ctx) + n_qblocks - 1) / n_qblocks;
