@@ -626,7 +626,7 @@ __device__ __forceinline__ float lane_shfl(float v, int src) { return __shfl(v, 
 // same records in the same order, folded in queue order: the bits do not
 // depend on the entry size.
 #ifndef CSPLAT_FULL_QUERIES_PER_TASK
-#define CSPLAT_FULL_QUERIES_PER_TASK 2
+#define CSPLAT_FULL_QUERIES_PER_TASK 2  // 1 or 2
 #endif
 template <int M, bool ELL>
 constexpr int full_entry_queries()
@@ -856,7 +856,7 @@ __device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__
 {
     static_assert(FULL && BALL, "labels run in eval_tile_label_tasks");
     constexpr int KQ = full_entry_queries<M, ELL>();  // queries per entry
-    static_assert(KQ > 1, "one query per entry runs in eval_tile_tasks");
+    static_assert(KQ == 2, "the slot masks hold one bit per entry: two queries per entry");
     constexpr int kRing = 128;  // queued entries per wave: at most 63 waiting + 64 / KQ of one sub-chunk
     constexpr int PW = task_words<M, FULL>();
     constexpr int kWaves = kBlock / 64;
