@@ -84,7 +84,9 @@ typedef struct {
     float d_max;           /* Eq. 11, > 0 */
     float gamma;           /* Eq. 11, >= 0 */
     float s_min;           /* Eq. 11, the paper uses 1 */
-    int32_t precision;     /* CSPLAT_PRECISION_*; the MFMA forms compute labels/counts */
+    int32_t precision;     /* CSPLAT_PRECISION_*; the MFMA forms compute labels/counts over
+                              every kept Gaussian: they reject a finite neighbor_radius
+                              (CSPLAT_E_INVALID) */
     int32_t cull;          /* 1: sort the queries along a Hilbert curve and skip the
                               Gaussians (in groups of 1024, chunks of 64 and sub-chunks of 16
                               consecutive on the scene's curve) that provably lie outside a

@@ -19,8 +19,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# CSPLAT_LIB selects another build of the same library (tuning sweeps)
-LIB_PATH = os.environ.get("CSPLAT_LIB", os.path.join(_HERE, "libcsplat.so"))
+# the in-tree build (load_library(path) takes another build explicitly)
+LIB_PATH = os.path.join(_HERE, "libcsplat.so")
 
 CSPLAT_OK = 0
 CSPLAT_E_INVALID = 1

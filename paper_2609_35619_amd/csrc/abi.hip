@@ -470,6 +470,9 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     if (opts->precision != CSPLAT_PRECISION_FP32) {
         if (want_dist)
             return fail(CSPLAT_E_INVALID, "eval: the MFMA precision forms compute labels and counts only");
+        if (std::isfinite(opts->neighbor_radius))
+            return fail(CSPLAT_E_INVALID,
+                        "eval: the MFMA precision forms count over every kept Gaussian (neighbor_radius = +inf)");
         uint32_t need = opts->precision == CSPLAT_PRECISION_BF16_RECHECK ? CSPLAT_FEATURES_BF16
                                                                           : CSPLAT_FEATURES_FP16;
         void *f = need == CSPLAT_FEATURES_BF16 ? sc->feat_bf16 : sc->feat_fp16;

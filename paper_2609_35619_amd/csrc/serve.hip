@@ -514,6 +514,9 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
                                    const float *centers, const float *radii, const csplat_reduce_opts *opts,
                                    const float *n_sigma, int32_t m, uint64_t *ticket)
 {
+    // latency counts from entry: validation, the host-side sort and the copy
+    // below are part of what the caller waits for
+    const double t_entry = now_s();
     if (!s || !opts || !n_sigma || !ticket) return fail(CSPLAT_E_INVALID, "server_submit: NULL argument");
     *ticket = 0;
     if (kind != CSPLAT_SERVE_COST && kind != CSPLAT_SERVE_LABELS)
@@ -623,7 +626,7 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     // the sort above ran without the lock (the worker keeps scheduling)
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->fatal != CSPLAT_OK) return fail(s->fatal, s->fatal_msg);
-    const int64_t t = s->sched->submit(spec, now_s());
+    const int64_t t = s->sched->submit(spec, t_entry);
     if (t < 0) {
         ++s->st.refused;
         return fail(CSPLAT_E_BUSY, "server_submit: the request can never fit the memory budget");

@@ -187,6 +187,33 @@ def test_precision_requires_features(cs, eng):
     cs.csplat_scene_free(h)
 
 
+def test_precision_rejects_finite_ball(cs, eng):
+    """The MFMA forms count over every kept Gaussian: a finite neighbourhood
+    ball is refused (CSPLAT_E_INVALID) before any output is written, for host
+    and device pointers alike; the float32 path accepts the same call."""
+    import torch
+    _say("case: precision forms with a finite neighbourhood ball")
+    sc, qs, p = config("tiny", 0.05)
+    h = _load(cs, eng, sc, p)
+    eng.set_conservatism([1.0])
+    for prec in (cs.CSPLAT_PRECISION_BF16_RECHECK, cs.CSPLAT_PRECISION_FP16_RECHECK):
+        lab = np.full((qs.q, 1), 7, np.uint8)
+        with pytest.raises(cs.CsplatError):
+            cs.csplat_eval_labels(eng.ctx, h, qs.centers, qs.radii,
+                                  cs.reduce_opts(k=0, r_nbr=0.3, precision=prec), lab)
+        assert np.all(lab == 7)
+        dlab = torch.full((qs.q, 1), 7, dtype=torch.uint8, device="cuda")
+        with pytest.raises(cs.CsplatError):
+            cs.csplat_eval_labels(eng.ctx, h, torch.from_numpy(qs.centers).cuda(),
+                                  torch.from_numpy(qs.radii).cuda(),
+                                  cs.reduce_opts(k=0, r_nbr=0.3, precision=prec), dlab)
+        torch.cuda.synchronize()
+        assert bool((dlab == 7).all())
+    lab = np.zeros((qs.q, 1), np.uint8)
+    cs.csplat_eval_labels(eng.ctx, h, qs.centers, qs.radii, cs.reduce_opts(k=0, r_nbr=0.3), lab)
+    cs.csplat_scene_free(h)
+
+
 def test_precision_full_size_sampled(cs, eng, oracle_mod):
     """4M Gaussians x 262,144 grid spheres: labels of both precision forms
     equal the float32 path except on oracle-ambiguous queries; a seeded sample
