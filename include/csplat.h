@@ -186,6 +186,28 @@ csplat_status csplat_eval_distance(csplat_ctx *ctx, const csplat_scene *scene, i
                                    const csplat_reduce_opts *opts, float *min,
                                    float *softmin, float *cost);
 
+/* For callers that cannot allocate device or pinned memory during a call
+ * (harnesses that forbid hipMalloc, tight serving loops): csplat_eval with
+ * the float32 path, allocating nothing.  Its workspace (the sorted queries and
+ * the split partials) is a fixed CSPLAT_NOALLOC_SCRATCH_MB MiB array in the
+ * library, one per GPU, held until the process ends; the context's check flag
+ * is allocated by csplat_ctx_create.  Every array must be a device pointer
+ * (host arrays would need staging).  The work is cut into fewer, longer
+ * splits when the partials of the usual plan do not fit, so label, count, min
+ * and nbr equal csplat_eval's bit for bit and softmin and cost agree to float32
+ * rounding of the reordered sums.  Calls that overlap on one GPU (several
+ * contexts or streams, or threads) share that array and race: serialise
+ * them.  The call waits once for the device-side input check, like
+ * csplat_eval with device pointers.  Errors: those of csplat_eval, and
+ * CSPLAT_E_INVALID for host pointers, opts->precision other than
+ * CSPLAT_PRECISION_FP32, q > CSPLAT_NOALLOC_MAX_Q, or a problem whose
+ * workspace does not fit the array. */
+#define CSPLAT_NOALLOC_SCRATCH_MB 64
+#define CSPLAT_NOALLOC_MAX_Q 262144
+csplat_status csplat_eval_noalloc(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
+                                  const float *centers, const float *radii,
+                                  const csplat_reduce_opts *opts, const csplat_outputs *out);
+
 /* Ellipsoidal robot bodies (Eq. 5-6 with a general A_j, Sec. II-B): body j
  * has centre c_j (q x 3), orientation quaternion (q x 4, (w, x, y, z), any
  * nonzero norm; normalised here) and semi-axes (a, b, c) > 0 along its local

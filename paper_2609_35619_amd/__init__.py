@@ -46,7 +46,7 @@ EXPORTS = (
     "csplat_eval_distance", "csplat_eval_ellipsoids", "csplat_ply_read", "csplat_scene_load_ply", "csplat_segment_reduce", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
     "csplat_last_error", "csplat_server_create", "csplat_server_destroy", "csplat_server_add_scene",
     "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
-    "csplat_server_stats", "csplat_server_latencies",
+    "csplat_server_stats", "csplat_server_latencies", "csplat_eval_noalloc",
 )
 CSPLAT_SERVE_COST = 0
 CSPLAT_SERVE_LABELS = 1
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "csplat_scene_free": [P],
         "csplat_set_conservatism": [P, P, I32],
         "csplat_eval": [P, P, I64, P, P, P, P],
+        "csplat_eval_noalloc": [P, P, I64, P, P, P, P],
         "csplat_eval_labels": [P, P, I64, P, P, P, P, P],
         "csplat_eval_distance": [P, P, I64, P, P, P, P, P, P],
         "csplat_eval_ellipsoids": [P, P, I64, P, P, P, P, P],
@@ -242,6 +243,20 @@ def csplat_eval(ctx, scene, centers, radii, opts: ReduceOpts, label=None, count=
     o = Outputs(*[_addr(x) for x in (label, count, min, softmin, cost, nbr)])
     _check(load_library().csplat_eval(ctx, scene, q, _addr(centers), _addr(radii), ctypes.byref(opts),
                                       ctypes.byref(o)))
+
+
+CSPLAT_NOALLOC_SCRATCH_MB = 64
+CSPLAT_NOALLOC_MAX_Q = 262144
+
+
+def csplat_eval_noalloc(ctx, scene, centers, radii, opts: ReduceOpts, label=None, count=None, min=None,
+                        softmin=None, cost=None, nbr=None):
+    """csplat_eval (float32 path) without any allocation: torch CUDA tensors
+    only; the workspace is the library's fixed per-GPU scratch array."""
+    q = int(centers.shape[0])
+    o = Outputs(*[_addr(x) for x in (label, count, min, softmin, cost, nbr)])
+    _check(load_library().csplat_eval_noalloc(ctx, scene, q, _addr(centers), _addr(radii), ctypes.byref(opts),
+                                              ctypes.byref(o)))
 
 
 def csplat_eval_labels(ctx, scene, centers, radii, opts: ReduceOpts, label, count=None):

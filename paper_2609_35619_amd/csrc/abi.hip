@@ -7,9 +7,45 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "internal.h"
 
+// Device workspace of csplat_eval_noalloc: a fixed array in the library's
+// code object, one copy per GPU, held until the process ends.  Host code
+// never passes this name to a kernel (on the host it is only a handle): the
+// device address of each GPU's copy is looked up once per device at context
+// creation and used from then on.
+constexpr size_t kScratchBytes = (size_t)CSPLAT_NOALLOC_SCRATCH_MB << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace csplat {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};  // device address of each GPU's copy of `scratch`
+
+// With `device` current: the device address of its copy of `scratch`.
+csplat_status scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(CSPLAT_E_INVALID, "scratch: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return CSPLAT_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[device] = ptr;
+    return CSPLAT_OK;
+}
+
+void *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+}  // namespace
 
 thread_local std::string g_last_error;
 
@@ -248,11 +284,8 @@ csplat_status device_check(csplat_ctx *ctx, Launch launch, const char *msg)
 template <class Launch>
 csplat_status queue_device_check(csplat_ctx *ctx, Launch launch)
 {
-    if (!ctx->check_host) {
-        CSPLAT_HIP(hipHostMalloc((void **)&ctx->check_host, 64, hipHostMallocDefault));
-        CSPLAT_HIP(hipHostGetDevicePointer((void **)&ctx->check_dev, ctx->check_host, 0));
-    }
-    if (!ctx->ev_check) CSPLAT_HIP(hipEventCreateWithFlags(&ctx->ev_check, hipEventDisableTiming));
+    // the flag and its event are allocated by csplat_ctx_create
+    if (!ctx->check_host || !ctx->ev_check) return fail(CSPLAT_E_DEVICE, "context without check flag");
     // a check of an evaluation that ended early may still be queued: it
     // finishes before its flag is cleared for this one
     if (ctx->check_pending) {
@@ -368,6 +401,19 @@ csplat_status csplat_ctx_create(int32_t device, void *hip_stream, csplat_ctx **o
     }
     ctx->m = 1;
     ctx->n_sigma[0] = 1.0f;
+    // the device-side input check's pinned flag and event, allocated here so
+    // that no evaluation allocates them; this device's scratch address
+    csplat_status s = CSPLAT_OK;
+    e = hipHostMalloc((void **)&ctx->check_host, 64, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&ctx->check_dev, ctx->check_host, 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_check, hipEventDisableTiming);
+    if (e != hipSuccess) s = hip_fail(e, "ctx_create: check flag");
+    if (s == CSPLAT_OK) s = scratch_setup(device);
+    if (s != CSPLAT_OK) {
+        const std::string msg = g_last_error;
+        csplat_ctx_destroy(ctx);
+        return fail(s, msg);
+    }
     *out = ctx;
     return CSPLAT_OK;
 }
@@ -581,6 +627,38 @@ csplat_status csplat_eval_distance(csplat_ctx *ctx, const csplat_scene *sc, int6
     o.softmin = softmin;
     o.cost = cost;
     return csplat_eval(ctx, sc, q, centers, radii, opts, &o);
+}
+
+csplat_status csplat_eval_noalloc(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const float *centers,
+                                  const float *radii, const csplat_reduce_opts *opts, const csplat_outputs *out)
+{
+    EvalParams p;
+    bool want_dist = false;
+    csplat_status s = eval_checks(ctx, sc, q, opts, out, "eval_noalloc", p, want_dist);
+    if (s != CSPLAT_OK) return s;
+    if (opts->precision != CSPLAT_PRECISION_FP32)
+        return fail(CSPLAT_E_INVALID, "eval_noalloc: the float32 path only");
+    if (q > CSPLAT_NOALLOC_MAX_Q) return fail(CSPLAT_E_INVALID, "eval_noalloc: q above CSPLAT_NOALLOC_MAX_Q");
+    if (q == 0) return CSPLAT_OK;
+    if (!centers || !radii) return fail(CSPLAT_E_INVALID, "eval_noalloc: NULL centers or radii");
+    const int kind = common_kind({centers, radii, out->label, out->count, out->min, out->softmin, out->cost,
+                                  out->nbr});
+    if (kind != 1) return fail(CSPLAT_E_INVALID, "eval_noalloc: every array must be a device pointer");
+    if (!ctx->check_host || !ctx->ev_check) return fail(CSPLAT_E_DEVICE, "eval_noalloc: context without check flag");
+    char *ws_base = static_cast<char *>(scratch_of(ctx->device));
+    if (!ws_base) return fail(CSPLAT_E_DEVICE, "eval_noalloc: no scratch address for this device");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    reset_stats(ctx, q, sc);
+    const char *bad_msg = "eval_noalloc: query centres must be finite and radii finite and > 0";
+    s = queue_device_check(ctx, [&](int *bad) {
+        check_queries_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, radii, bad);
+    });
+    if (s != CSPLAT_OK) return s;
+    const Workspace ws{ws_base, kScratchBytes};
+    const EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr};
+    return fp32_eval(ctx, sc, q, centers, radii, p, eo, !want_dist, false,
+                     [&]() { return wait_device_check(ctx, bad_msg); }, &ws);
 }
 
 csplat_status csplat_ctx_set_timing(csplat_ctx *ctx, int32_t enable)

@@ -241,6 +241,16 @@ csplat_status build_params(const float *n_sigma, int m, const csplat_reduce_opts
 // 1 if p is a device (or managed) pointer, 0 for host memory.
 int pointer_kind(const void *p);
 
+// Device memory for an evaluation's workspace supplied by the caller (the
+// sorted queries, then the split partials) in place of the context's
+// growable buffers: nothing is allocated, and the split count is capped so
+// that the partials fit (fewer, longer splits: the same counts, labels,
+// minima and ball sizes; the softmin and cost sums in another order).
+struct Workspace {
+    char *base;
+    size_t bytes;
+};
+
 // A copy of q query spheres sorted along the scene's Hilbert curve, with the
 // permutation (sorted index -> caller index) and a zeroed 64-bit counter,
 // all in the context's sort workspace (valid until the next evaluation).
@@ -255,7 +265,9 @@ csplat_status sort_queries(csplat_ctx *ctx, const csplat_scene *sc, int q, const
 // The same for ellipsoid records (ell: `centers` holds kBodyFloats-float
 // records, which are gathered into out->c; out->r is NULL).
 csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *centers,
-                          const float *radii, bool ell, SortedQueries *out);
+                          const float *radii, bool ell, SortedQueries *out, const Workspace *ws = nullptr);
+// Device bytes the sort of q bodies needs (its part of a Workspace).
+csplat_status sort_workspace_bytes(int q, bool ell, hipStream_t st, size_t *bytes);
 // Ellipsoid records from centres (q x 3), (w, x, y, z) quaternions (q x 4) and
 // semi-axes (q x 3), all device pointers, on the context stream.
 csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const float *quats, const float *axes,
@@ -268,7 +280,7 @@ csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
                         const float *centers, const float *radii, const EvalParams &p,
                         const EvalOut &out, bool labels_only, bool ell = false,
-                        const std::function<csplat_status()> &gate = {});
+                        const std::function<csplat_status()> &gate = {}, const Workspace *ws = nullptr);
 
 // precision.hip: MFMA form with certified recheck (labels and counts).
 csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,

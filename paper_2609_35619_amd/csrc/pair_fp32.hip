@@ -176,21 +176,56 @@ csplat_status sort_queries(csplat_ctx *ctx, const csplat_scene *sc, int q, const
     return sort_bodies(ctx, sc, q, centers, radii, false, out);
 }
 
-csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *centers,
-                          const float *radii, bool ell, SortedQueries *out)
+namespace {
+// Layout of the sort workspace: keys, their sorted copy, indices, the
+// permutation, the sorted records, a counter, then the radix-sort scratch.
+struct SortLayout {
+    size_t off_code2, off_idx, off_perm, off_c, off_r, off_cnt, off_tmp, tbytes;
+    size_t total() const { return off_tmp + tbytes; }
+};
+
+csplat_status sort_layout(int q, bool ell, hipStream_t st, SortLayout &L)
 {
-    hipStream_t st = ctx->stream;
-    size_t tbytes = 0;
-    CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
+    L.tbytes = 0;
+    CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, L.tbytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                   (int32_t *)nullptr, (int32_t *)nullptr, q, 0, 30, st));
     const size_t qn = (size_t)q;
     const size_t rec_bytes = ell ? qn * kBodyFloats * 4 : qn * 16;  // sorted records, or centres + radii
-    const size_t off_code2 = qn * 4, off_idx = qn * 8, off_perm = qn * 12, off_c = (qn * 16 + 255) & ~(size_t)255,
-                 off_r = off_c + qn * 12, off_cnt = (off_c + rec_bytes + 255) & ~(size_t)255,
-                 off_tmp = off_cnt + 256;
-    hipError_t e = ctx->sortbuf.reserve(off_tmp + tbytes);
-    if (e != hipSuccess) return hip_fail(e, "sort workspace");
-    char *b = ctx->sortbuf.as<char>();
+    L.off_code2 = qn * 4, L.off_idx = qn * 8, L.off_perm = qn * 12, L.off_c = (qn * 16 + 255) & ~(size_t)255;
+    L.off_r = L.off_c + qn * 12, L.off_cnt = (L.off_c + rec_bytes + 255) & ~(size_t)255;
+    L.off_tmp = L.off_cnt + 256;
+    return CSPLAT_OK;
+}
+}  // namespace
+
+csplat_status sort_workspace_bytes(int q, bool ell, hipStream_t st, size_t *bytes)
+{
+    SortLayout L;
+    csplat_status s = sort_layout(q, ell, st, L);
+    if (s != CSPLAT_OK) return s;
+    *bytes = (L.total() + 255) & ~(size_t)255;
+    return CSPLAT_OK;
+}
+
+csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *centers,
+                          const float *radii, bool ell, SortedQueries *out, const Workspace *ws)
+{
+    hipStream_t st = ctx->stream;
+    SortLayout Ly;
+    csplat_status ls = sort_layout(q, ell, st, Ly);
+    if (ls != CSPLAT_OK) return ls;
+    size_t tbytes = Ly.tbytes;
+    const size_t off_code2 = Ly.off_code2, off_idx = Ly.off_idx, off_perm = Ly.off_perm, off_c = Ly.off_c,
+                 off_r = Ly.off_r, off_cnt = Ly.off_cnt, off_tmp = Ly.off_tmp;
+    char *b = nullptr;
+    if (ws) {
+        if (ws->bytes < Ly.total()) return fail(CSPLAT_E_INVALID, "sort workspace: supplied memory too small");
+        b = ws->base;
+    } else {
+        hipError_t e = ctx->sortbuf.reserve(Ly.total());
+        if (e != hipSuccess) return hip_fail(e, "sort workspace");
+        b = ctx->sortbuf.as<char>();
+    }
     uint32_t *code = reinterpret_cast<uint32_t *>(b), *code2 = reinterpret_cast<uint32_t *>(b + off_code2);
     int32_t *idx = reinterpret_cast<int32_t *>(b + off_idx), *perm = reinterpret_cast<int32_t *>(b + off_perm);
     float *sc_c = reinterpret_cast<float *>(b + off_c), *sc_r = reinterpret_cast<float *>(b + off_r);
@@ -203,7 +238,7 @@ csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const 
     CSPLAT_HIP(hipGetLastError());
     CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(b + off_tmp, tbytes, code, code2, idx, perm, q, 0, 30, st));
     if (ell)
-        body_gather_kernel<<<(unsigned)((qn * 4 + 255) / 256), 256, 0, st>>>(
+        body_gather_kernel<<<(unsigned)(((size_t)q * 4 + 255) / 256), 256, 0, st>>>(
             q, perm, reinterpret_cast<const float4 *>(centers), reinterpret_cast<float4 *>(sc_c));
     else
         query_gather_kernel<<<qb, 256, 0, st>>>(q, perm, centers, radii, sc_c, sc_r);
@@ -225,7 +260,8 @@ csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const
 
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
                         const float *radii, const EvalParams &p, const EvalOut &out,
-                        bool labels_only, bool ell, const std::function<csplat_status()> &gate)
+                        bool labels_only, bool ell, const std::function<csplat_status()> &gate,
+                        const Workspace *ws)
 {
     const int q = (int)q64;
     const int n = (int)sc->n;
@@ -233,13 +269,30 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     const bool ball = std::isfinite(p.rn2);
     // culling applies to labels, and to full outputs over a finite ball
     const bool cull = p.cull && n > 0 && sc->cull && (!full || ball);
-    const SplitPlan sp = split_plan(ctx_target_blocks(ctx), q, n, full, ball, ell);
-    const int S = std::max(sp.S, 1);
+    SplitPlan sp = split_plan(ctx_target_blocks(ctx), q, n, full, ball, ell);
     const int M = p.m;
+    // the sorted queries and the partials: the context's buffers, or the
+    // caller's workspace (sort first, then as many splits as fit)
+    size_t sort_bytes = 0;
+    void *part_base = nullptr;
+    if (ws) {
+        if (cull) {
+            csplat_status s = sort_workspace_bytes(q, ell, ctx->stream, &sort_bytes);
+            if (s != CSPLAT_OK) return s;
+        }
+        const size_t per_split = (size_t)q * part_words(M, full) * 4;
+        const size_t avail = ws->bytes > sort_bytes ? ws->bytes - sort_bytes : 0;
+        const size_t fit = per_split ? avail / per_split : 0;
+        if (fit < 1) return fail(CSPLAT_E_INVALID, "workspace too small for one split of the partials");
+        if ((size_t)sp.S > fit) sp.S = (int)fit;
+        part_base = ws->base + sort_bytes;
+    }
+    const int S = std::max(sp.S, 1);
     const size_t words = (size_t)S * q * part_words(M, full);
-    if (words > 0) {
+    if (!ws && words > 0) {
         hipError_t e = ctx->partial.reserve(words * 4);
         if (e != hipSuccess) return hip_fail(e, "partial workspace");
+        part_base = ctx->partial.ptr;
     }
     hipStream_t st = ctx->stream;
     Launch L{};
@@ -252,7 +305,7 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     L.r = radii;
     L.q = q;
     L.p = p;
-    L.part = part_views(ctx->partial.ptr, S, q, M, full);
+    L.part = part_views(part_base, S, q, M, full);
     L.ell = ell;
     L.S = sp.S;
     L.out = out;
@@ -264,7 +317,8 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
         // evaluate a copy of the queries sorted along the scene's Hilbert curve
         // (the lanes of a wave then hold nearby queries), scatter the outputs
         SortedQueries sq;
-        csplat_status s = sort_bodies(ctx, sc, q, centers, radii, ell, &sq);
+        Workspace sw{ws ? ws->base : nullptr, sort_bytes};
+        csplat_status s = sort_bodies(ctx, sc, q, centers, radii, ell, &sq, ws ? &sw : nullptr);
         if (s != CSPLAT_OK) return s;
         L.c = sq.c;
         L.r = sq.r;
