@@ -92,8 +92,12 @@ typedef struct {
                               consecutive on the scene's curve) that provably lie outside a
                               query's neighbourhood ball (or, for labels, beyond the reach bound
                               n s_max + sqrt(n^2 s_max^2 + r^2) of Eq. 8); the results are the
-                              same bits as with 0, which evaluates every pair.  min/softmin/cost
-                              with an infinite ball never cull. */
+                              same bits as with 0, which evaluates every pair.  With an infinite
+                              ball, min without softmin, cost and nbr (labels and counts
+                              optional) runs as passes of a threshold search that skip every
+                              Gaussian provably above the query's minimum (the same bits as
+                              every pair; one host synchronisation per pass); softmin and
+                              cost with an infinite ball never cull. */
 } csplat_reduce_opts;
 
 /* Outputs of one evaluation; every pointer is nullable (not computed/written). */
@@ -118,6 +122,8 @@ typedef struct {
                                measured with HIP events on the context stream; else -1 */
     uint64_t workspace_bytes; /* device bytes the context holds (partials, sorted queries,
                                  staging, body records, counters) */
+    int32_t min_passes;     /* minimum over every kept Gaussian: walks of the threshold search
+                               (kernel_ms then sums their pair kernels); else 0 */
 } csplat_eval_stats;
 
 /* Context: a device, a stream (its own if hip_stream is NULL, else the given

@@ -79,7 +79,8 @@ class EvalStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("flagged", ctypes.c_int64),
                 ("flagged_fp64", ctypes.c_int64), ("splits", ctypes.c_int32),
                 ("queries_per_lane", ctypes.c_int32), ("kernel_pairs", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_float), ("workspace_bytes", ctypes.c_uint64)]
+                ("kernel_ms", ctypes.c_float), ("workspace_bytes", ctypes.c_uint64),
+                ("min_passes", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):

@@ -362,6 +362,7 @@ void reset_stats(csplat_ctx *ctx, int64_t q, const csplat_scene *sc)
     std::memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->stats.pairs = q * sc->n;
     ctx->timed = false;
+    ctx->timed_ms = -1.f;
     ctx->flag_counts = nullptr;
     ctx->flag_m = 0;
     ctx->chunk_counter = nullptr;
@@ -428,6 +429,7 @@ csplat_status csplat_ctx_destroy(csplat_ctx *ctx)
     ctx->flags.release();
     ctx->sortbuf.release();
     ctx->bodies.release();
+    ctx->minbuf.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->ev_check) (void)hipEventDestroy(ctx->ev_check);
@@ -680,7 +682,7 @@ csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats)
     *stats = ctx->stats;
     stats->kernel_ms = -1.f;
     stats->workspace_bytes = ctx->partial.bytes + ctx->staging.bytes + ctx->flags.bytes + ctx->sortbuf.bytes +
-                             ctx->bodies.bytes;
+                             ctx->bodies.bytes + ctx->minbuf.bytes;
     if (ctx->chunk_counter) {  // culled evaluation: pairs the kernel actually evaluated
         DeviceGuard g(ctx->device);
         unsigned long long chunks = 0;
@@ -701,7 +703,9 @@ csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats)
         ctx->stats.flagged = tot;
         ctx->stats.flagged_fp64 = tot;
     }
-    if (ctx->timing && ctx->timed) {
+    if (ctx->timing && ctx->timed && ctx->timed_ms >= 0.f) {
+        stats->kernel_ms = ctx->timed_ms;
+    } else if (ctx->timing && ctx->timed) {
         DeviceGuard g(ctx->device);
         CSPLAT_HIP(hipEventSynchronize(ctx->ev1));
         float ms = 0.f;

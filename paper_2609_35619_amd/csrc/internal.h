@@ -161,6 +161,7 @@ struct csplat_ctx {
     csplat::DevBuf flags;      // validation flag; precision form: recheck counters
     csplat::DevBuf sortbuf;    // spatial sort of the queries (codes, permutation, sorted copies)
     csplat::DevBuf bodies;     // prepared ellipsoid records
+    csplat::DevBuf minbuf;     // minimum search: per-query state, lists, gathered queries
     csplat_eval_stats stats{};
     int32_t *flag_counts = nullptr;  // device: rechecked queries per n_sigma (last eval)
     int32_t flag_m = 0;
@@ -169,6 +170,7 @@ struct csplat_ctx {
     bool timing = false;
     bool timed = false;         // events of the last evaluation were recorded
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float timed_ms = -1.f;      // >= 0: the dominant kernel's time summed over several launches
     int *check_host = nullptr;      // pinned: the device-side input check's flag
     int *check_dev = nullptr;       // its device address
     bool check_pending = false;     // a check is queued and not yet waited for
@@ -281,6 +283,13 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
                         const float *centers, const float *radii, const EvalParams &p,
                         const EvalOut &out, bool labels_only, bool ell = false,
                         const std::function<csplat_status()> &gate = {}, const Workspace *ws = nullptr);
+
+// The minimum of s~^2 over every kept Gaussian for spheres (labels and
+// counts optional), by the threshold passes of the task walk; the passes
+// synchronise with the host once each (the next pass's size).
+csplat_status fp32_min_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q, const float *centers,
+                            const float *radii, const EvalParams &p, const EvalOut &out,
+                            const std::function<csplat_status()> &gate = {});
 
 // precision.hip: MFMA form with certified recheck (labels and counts).
 csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,

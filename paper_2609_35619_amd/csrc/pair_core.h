@@ -583,6 +583,32 @@ __device__ __forceinline__ void task_pair_label(const float4 &r0, const float4 &
     for (int v = 0; v < M; ++v) T.cnt[v] += in && (aa < p.four_n2[v] * W);
 }
 
+// One pair for labels and the minimum (spheres, every kept Gaussian): the
+// label test as in task_pair_label, and t = max(0, D - 2 n_v sqrt(V)) =
+// r^2 s~^2 (Eq. 8 in r^2 units) folded into the task's minimum.  Padding
+// records (mean at +inf, M = 0) give W = NaN and are skipped by the W >= 0
+// test, so they never lower the minimum.
+template <int M, bool COUNT>
+__device__ __forceinline__ void task_pair_label_min(const float4 &r0, const float4 &r1, const float4 &r2,
+                                                    const TaskQuery<false> &Q, const EvalParams &p, TaskAcc<M> &T)
+{
+    const float dx = r0.x - Q.cx, dy = r0.y - Q.cy, dz = r0.z - Q.cz;
+    const float gp[12] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x, r2.y, r2.z, r2.w};
+    const float Db = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    float D, W;
+    metric_dw<false>(gp, Q.L, dx, dy, dz, Db, D, W);
+    if constexpr (COUNT) {
+        const float a = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, -Q.r2)));  // as task_pair_label
+        const float aa = a * fabsf(a);
+#pragma unroll
+        for (int v = 0; v < M; ++v) T.cnt[v] += aa < p.four_n2[v] * W;
+    }
+    const float sv = fast_sqrt(W);
+    const bool real = W >= 0.f;
+#pragma unroll
+    for (int v = 0; v < M; ++v) T.mt[v] = fminf(T.mt[v], real ? fmaxf(fmaf(-p.two_n[v], sv, D), 0.f) : INFINITY);
+}
+
 // Fold a task partial X into the totals A (first-level sums into the second).
 template <int M>
 __device__ __forceinline__ void task_fold(TaskAcc<M> &A, const TaskAcc<M> &X)
@@ -1108,20 +1134,29 @@ __device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__
 #define CSPLAT_LABEL_UNROLL 2  // records per load group of the label task loop
 #endif
 constexpr int kLabelUnroll = CSPLAT_LABEL_UNROLL;
-template <int M, bool BALL, bool CULL, bool ELL>
+// With MINW (spheres, every kept Gaussian) the walk also folds each query's
+// minimum of t = r^2 s~^2 over the pairs it evaluates (LDS atomic minimum on
+// the bits of non-negative floats: order-free), and query j's reach is that
+// of the threshold s~^2 < thr[j] instead of 1 (thr NULL: 1): every pair with
+// s~^2 < thr[j] is evaluated.  COUNT = false skips the label counts (the
+// later passes of the minimum search).
+template <int M, bool BALL, bool CULL, bool ELL, bool COUNT = true, bool MINW = false>
 __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ gs, int n, int S, int split,
                                                       int tile, const float *__restrict__ centers,
                                                       const float *__restrict__ radii, int q, const EvalParams &p,
                                                       const Part &part, const float *__restrict__ cull,
-                                                      int *tasks_done)
+                                                      int *tasks_done, const float *__restrict__ thr = nullptr)
 {
+    static_assert(!MINW || (!ELL && !BALL), "the minimum search runs for spheres over every kept Gaussian");
+    static_assert(COUNT || MINW, "nothing to compute");
     constexpr int KQ = CSPLAT_LABEL_QUERIES_PER_TASK;  // queries per entry
     constexpr int kRing = 128;  // queued entries per wave: at most 63 waiting + 64 / KQ of one sub-chunk
     constexpr int kWaves = kBlock / 64;
     constexpr unsigned char kNone = 0xFF;
     __shared__ int s_task[kWaves][kRing];             // sub-chunk of each queued entry
     __shared__ unsigned char s_q[kWaves][KQ][kRing];  // lanes of its queries, kNone for an empty slot
-    __shared__ int s_cnt[kWaves][64 * M];             // the wave's counts, query-major
+    __shared__ int s_cnt[kWaves][COUNT ? 64 * M : 1]; // the wave's counts, query-major
+    __shared__ int s_mt[kWaves][MINW ? 64 * M : 1];   // the wave's minima (float bits), query-major
     const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
@@ -1142,12 +1177,18 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
         own.cz = centers[3 * jj + 2];
         const float r = radii[jj];
         own.r2 = r * r;
-        qa = own.r2;
+        qa = MINW && thr ? own.r2 * thr[jj] : own.r2;  // s~^2 < T  <=>  (r^2 units) t < T r^2
         qk = 1.f;
     }
     own.kq = 0.f;
+    if constexpr (COUNT) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) s_cnt[wv][lane * M + v] = 0;
+        for (int v = 0; v < M; ++v) s_cnt[wv][lane * M + v] = 0;
+    }
+    if constexpr (MINW) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) s_mt[wv][lane * M + v] = __float_as_int(INFINITY);
+    }
     int head = 0, tail = 0;  // wave-uniform ring positions, counting up
 
     auto fetch_query = [&](int src, bool ok) {
@@ -1196,13 +1237,23 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
 #pragma unroll
             for (int u = 0; u < kLabelUnroll; ++u)
 #pragma unroll
-                for (int j = 0; j < KQ; ++j) task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tq[j], p, T[j]);
+                for (int j = 0; j < KQ; ++j) {
+                    if constexpr (MINW)
+                        task_pair_label_min<M, COUNT>(r[u][0], r[u][1], r[u][2], tq[j], p, T[j]);
+                    else
+                        task_pair_label<M, BALL, ELL>(r[u][0], r[u][1], r[u][2], tq[j], p, T[j]);
+                }
         }
 #pragma unroll
         for (int j = 0; j < KQ; ++j)
 #pragma unroll
-            for (int v = 0; v < M; ++v)
-                if (iq[j] != (int)kNone && T[j].cnt[v]) atomicAdd(&s_cnt[wv][iq[j] * M + v], T[j].cnt[v]);
+            for (int v = 0; v < M; ++v) {
+                if constexpr (COUNT)
+                    if (iq[j] != (int)kNone && T[j].cnt[v]) atomicAdd(&s_cnt[wv][iq[j] * M + v], T[j].cnt[v]);
+                if constexpr (MINW)
+                    if (iq[j] != (int)kNone && T[j].mt[v] < INFINITY)
+                        atomicMin(&s_mt[wv][iq[j] * M + v], __float_as_int(T[j].mt[v]));
+            }
         head += n_t;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1287,7 +1338,10 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (jq < q) {
 #pragma unroll
-        for (int v = 0; v < M; ++v) part.cnt[((size_t)split * M + v) * q + jq] = s_cnt[wv][lane * M + v];
+        for (int v = 0; v < M; ++v) {
+            if constexpr (COUNT) part.cnt[((size_t)split * M + v) * q + jq] = s_cnt[wv][lane * M + v];
+            if constexpr (MINW) part.mt[((size_t)split * M + v) * q + jq] = __int_as_float(s_mt[wv][lane * M + v]);
+        }
     }
 }
 
@@ -1574,6 +1628,134 @@ pair_task_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const 
     else
         eval_tile_label_tasks<M, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
     if (CULL && task_count && (threadIdx.x & 63) == 0) atomicAdd(task_count, (unsigned long long)done);
+}
+
+// ---------------------------------------------------------------------------
+// The minimum of s~^2 over every kept Gaussian (Eq. 8; labels optional), by
+// passes of the label task walk with a rising threshold.  Pass 1 runs at
+// threshold 1 (the labels' own reach) and also folds each query's minimum of
+// t = r^2 s~^2 over the pairs it evaluates.  A query is resolved when that
+// minimum lies below its threshold: every pair with s~^2 < T was evaluated,
+// so no skipped pair can be lower.  An unresolved query is walked again with
+// a threshold just above its minimum so far (an upper bound of the true
+// minimum: the next pass resolves it), or four times the last one when it had
+// no pair at all.  Skipped pairs never lower a minimum and the per-pair
+// arithmetic does not depend on the pass, so the result is the same bits as
+// the minimum over every pair.  Thresholds carry a relative margin of 2^-10
+// (resolution) and 2^-8 (next threshold), far above float32 rounding.
+constexpr float kMinResolve = 0.9990234375f;  // 1 - 2^-10
+constexpr float kMinNext = 1.00390625f;       // 1 + 2^-8
+
+template <int M, bool COUNT, bool CULL>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CSPLAT_LABEL_WAVES_PER_EU)))
+pair_min_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const float *__restrict__ centers,
+                const float *__restrict__ radii, const float *__restrict__ thr, int q, const EvalParams p, Part part,
+                const float *__restrict__ cull, unsigned long long *__restrict__ task_count)
+{
+    int b = blockIdx.x;
+    const int B = gridDim.x;
+    if ((B & 7) == 0) b = (b & 7) * (B >> 3) + (b >> 3);  // XCD-major: one XCD, few ranges
+    const int split = b / n_tiles;
+    const int tile = b - split * n_tiles;
+    int done = 0;
+    eval_tile_label_tasks<M, false, CULL, false, COUNT, true>(gs, n, S, split, tile, centers, radii, q, p, part,
+                                                              cull, &done, thr);
+    if (CULL && task_count && (threadIdx.x & 63) == 0) atomicAdd(task_count, (unsigned long long)done);
+}
+
+// Pass 1: counts (summed over splits) to the outputs at row perm[j], minima
+// (over splits) to the search state st_mt[j][v], threshold 1, and the flag of
+// queries whose minimum is not yet certain.
+template <int M, bool COUNT>
+__global__ void __launch_bounds__(256)
+min_first_combine_kernel(int q, int S, const EvalParams p, Part part, const float *__restrict__ radii,
+                         const int32_t *__restrict__ perm, uint8_t *label, int32_t *count,
+                         float *__restrict__ st_mt, float *__restrict__ st_thr, uint8_t *__restrict__ flag)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    const int oj = perm ? perm[j] : j;
+    const float r = radii[j], r2 = r * r;
+    bool unresolved = false;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        int cnt = 0;
+        float mt = INFINITY;
+        for (int s = 0; s < S; ++s) {
+            const size_t o = ((size_t)s * M + v) * q + j;
+            if constexpr (COUNT) cnt += part.cnt[o];
+            mt = fminf(mt, part.mt[o]);
+        }
+        if constexpr (COUNT) {
+            if (count) count[(size_t)oj * p.m + v] = cnt;
+            if (label) label[(size_t)oj * p.m + v] = cnt > p.k ? 1 : 0;
+        }
+        st_mt[(size_t)j * M + v] = mt;
+        unresolved |= !(mt < r2 * kMinResolve);
+    }
+    st_thr[j] = 1.f;
+    flag[j] = unresolved ? 1 : 0;
+}
+
+// Before pass k > 1: the listed (unresolved) queries' centres, radii and new
+// thresholds, gathered in list order (sorted order: waves stay compact).
+template <int M>
+__global__ void __launch_bounds__(256)
+min_gather_kernel(int nl, const int32_t *__restrict__ list, const float *__restrict__ centers,
+                  const float *__restrict__ radii, const float *__restrict__ st_mt, float *__restrict__ st_thr,
+                  float *__restrict__ cc, float *__restrict__ rr, float *__restrict__ tt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    const int j = list[i];
+    const float r = radii[j], r2 = r * r;
+    float mx = 0.f;
+#pragma unroll
+    for (int v = 0; v < M; ++v) mx = fmaxf(mx, st_mt[(size_t)j * M + v]);
+    // just above the minimum so far (an upper bound of the true minimum), or
+    // four times the last threshold when no pair was in reach
+    const float t = mx < INFINITY ? mx / r2 * kMinNext : 4.f * st_thr[j];
+    st_thr[j] = t;
+    tt[i] = t;
+    cc[3 * i] = centers[3 * j];
+    cc[3 * i + 1] = centers[3 * j + 1];
+    cc[3 * i + 2] = centers[3 * j + 2];
+    rr[i] = r;
+}
+
+// After pass k > 1: the listed queries' minima and flags.
+template <int M>
+__global__ void __launch_bounds__(256)
+min_next_combine_kernel(int nl, int S, Part part, const int32_t *__restrict__ list, const float *__restrict__ radii,
+                        const float *__restrict__ st_thr, float *__restrict__ st_mt, uint8_t *__restrict__ flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    const int j = list[i];
+    const float r = radii[j], lim = r * r * st_thr[j] * kMinResolve;
+    bool unresolved = false;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        float mt = st_mt[(size_t)j * M + v];
+        for (int s = 0; s < S; ++s) mt = fminf(mt, part.mt[((size_t)s * M + v) * nl + i]);
+        st_mt[(size_t)j * M + v] = mt;
+        unresolved |= !(mt < lim);
+    }
+    flag[j] = unresolved ? 1 : 0;
+}
+
+// The minima in s~^2 units at row perm[j].
+template <int M>
+__global__ void __launch_bounds__(256)
+min_output_kernel(int q, int m, const float *__restrict__ radii, const int32_t *__restrict__ perm,
+                  const float *__restrict__ st_mt, float *__restrict__ out_min)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    const int oj = perm ? perm[j] : j;
+    const float r = radii[j], r2 = r * r;
+#pragma unroll
+    for (int v = 0; v < M; ++v) out_min[(size_t)oj * m + v] = st_mt[(size_t)j * M + v] / r2;
 }
 
 // Merge the split partials of query j, conservatism value v, in split order

@@ -258,11 +258,166 @@ csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const
     return CSPLAT_OK;
 }
 
+namespace {
+template <int M>
+csplat_status min_search(csplat_ctx *ctx, const csplat_scene *sc, int q, const float *c, const float *r,
+                         const int32_t *perm, bool cull, unsigned long long *counter, const EvalParams &p,
+                         const EvalOut &out, const std::function<csplat_status()> &gate)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)sc->n;
+    const bool want_count = out.label || out.count;
+    const size_t qn = (size_t)q;
+    // search state, lists and gathered queries in the min workspace
+    size_t sel_bytes = 0;
+    CSPLAT_HIP(hipcub::DeviceSelect::Flagged(nullptr, sel_bytes, hipcub::CountingInputIterator<int32_t>(0),
+                                             (const uint8_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, q,
+                                             st));
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_mt = 0, o_thr = o_mt + al(qn * M * 4), o_flag = o_thr + al(qn * 4), o_list = o_flag + al(qn),
+                 o_nl = o_list + al(qn * 4), o_cc = o_nl + 256, o_rr = o_cc + al(qn * 12), o_tt = o_rr + al(qn * 4),
+                 o_sel = o_tt + al(qn * 4), total = o_sel + al(sel_bytes);
+    hipError_t e = ctx->minbuf.reserve(total);
+    if (e != hipSuccess) return hip_fail(e, "minimum-search workspace");
+    char *b = ctx->minbuf.as<char>();
+    float *st_mt = reinterpret_cast<float *>(b + o_mt), *st_thr = reinterpret_cast<float *>(b + o_thr);
+    uint8_t *flag = reinterpret_cast<uint8_t *>(b + o_flag);
+    int32_t *list = reinterpret_cast<int32_t *>(b + o_list), *n_list = reinterpret_cast<int32_t *>(b + o_nl);
+    float *cc = reinterpret_cast<float *>(b + o_cc), *rr = reinterpret_cast<float *>(b + o_rr),
+          *tt = reinterpret_cast<float *>(b + o_tt);
+    void *sel_tmp = b + o_sel;
+    float total_ms = 0.f;
+    // one pass of the walk over nq queries (thr: their thresholds, NULL = 1)
+    auto pass = [&](bool first, int nq, const float *pc, const float *pr, const float *pt, Part &part, int &S) {
+        SplitPlan sp = split_plan(ctx_target_blocks(ctx), nq, n, false, false);
+        S = std::max(sp.S, 1);
+        const size_t words = (size_t)S * nq * M * (first && want_count ? 2 : 1);
+        hipError_t pe = ctx->partial.reserve(words * 4);
+        if (pe != hipSuccess) return hip_fail(pe, "partial workspace");
+        char *pb = ctx->partial.as<char>();
+        part = Part{};
+        part.cnt = reinterpret_cast<int32_t *>(pb);
+        part.mt = reinterpret_cast<float *>(pb + (first && want_count ? (size_t)S * nq * M * 4 : 0));
+        if (n == 0) return CSPLAT_OK;
+        const dim3 grid((unsigned)(sp.n_tiles * S));
+        if (ctx->timing) (void)hipEventRecord(ctx->ev0, st);
+        if (first && want_count) {
+            if (cull) pair_min_kernel<M, true, true><<<grid, kBlock, 0, st>>>(sc->gauss, n, S, sp.n_tiles, pc, pr, pt, nq, p, part, sc->cull, counter);
+            else pair_min_kernel<M, true, false><<<grid, kBlock, 0, st>>>(sc->gauss, n, S, sp.n_tiles, pc, pr, pt, nq, p, part, sc->cull, counter);
+        } else {
+            if (cull) pair_min_kernel<M, false, true><<<grid, kBlock, 0, st>>>(sc->gauss, n, S, sp.n_tiles, pc, pr, pt, nq, p, part, sc->cull, counter);
+            else pair_min_kernel<M, false, false><<<grid, kBlock, 0, st>>>(sc->gauss, n, S, sp.n_tiles, pc, pr, pt, nq, p, part, sc->cull, counter);
+        }
+        CSPLAT_HIP(hipGetLastError());
+        if (ctx->timing) (void)hipEventRecord(ctx->ev1, st);
+        if (first) ctx->stats.splits = S;
+        return CSPLAT_OK;
+    };
+    auto pass_ms = [&]() {
+        if (!ctx->timing || n == 0) return CSPLAT_OK;
+        float ms = 0.f;
+        CSPLAT_HIP(hipEventSynchronize(ctx->ev1));
+        CSPLAT_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        total_ms += ms;
+        return CSPLAT_OK;
+    };
+    Part part;
+    int S = 0;
+    csplat_status s = pass(true, q, c, r, nullptr, part, S);
+    if (s != CSPLAT_OK) return s;
+    s = pass_ms();
+    if (s != CSPLAT_OK) return s;
+    if (gate) {  // nothing that writes an output is queued before the input check passed
+        s = gate();
+        if (s != CSPLAT_OK) return s;
+    }
+    const unsigned qb = (unsigned)((q + 255) / 256);
+    const int Sf = n > 0 ? S : 0;
+    if (want_count)
+        min_first_combine_kernel<M, true><<<qb, 256, 0, st>>>(q, Sf, p, part, r, perm, out.label, out.count, st_mt,
+                                                              st_thr, flag);
+    else
+        min_first_combine_kernel<M, false><<<qb, 256, 0, st>>>(q, Sf, p, part, r, perm, nullptr, nullptr, st_mt,
+                                                               st_thr, flag);
+    CSPLAT_HIP(hipGetLastError());
+    int passes = 1;
+    for (; n > 0; ++passes) {
+        CSPLAT_HIP(hipcub::DeviceSelect::Flagged(sel_tmp, sel_bytes, hipcub::CountingInputIterator<int32_t>(0), flag,
+                                                 list, n_list, q, st));
+        int nl = 0;
+        CSPLAT_HIP(hipMemcpyAsync(&nl, n_list, sizeof(int), hipMemcpyDeviceToHost, st));
+        CSPLAT_HIP(hipStreamSynchronize(st));
+        if (nl == 0) break;
+        // every pass either resolves a query or quadruples its threshold; 64
+        // passes cover any float32 threshold
+        if (passes >= 64) return fail(CSPLAT_E_DEVICE, "minimum search: thresholds did not converge");
+        const unsigned lb = (unsigned)((nl + 255) / 256);
+        min_gather_kernel<M><<<lb, 256, 0, st>>>(nl, list, c, r, st_mt, st_thr, cc, rr, tt);
+        CSPLAT_HIP(hipGetLastError());
+        s = pass(false, nl, cc, rr, tt, part, S);
+        if (s != CSPLAT_OK) return s;
+        s = pass_ms();
+        if (s != CSPLAT_OK) return s;
+        min_next_combine_kernel<M><<<lb, 256, 0, st>>>(nl, S, part, list, r, st_thr, st_mt, flag);
+        CSPLAT_HIP(hipGetLastError());
+    }
+    min_output_kernel<M><<<qb, 256, 0, st>>>(q, p.m, r, perm, st_mt, out.min);
+    CSPLAT_HIP(hipGetLastError());
+    ctx->stats.min_passes = passes;
+    if (ctx->timing) {
+        ctx->timed = true;
+        ctx->timed_ms = total_ms;
+    }
+    return CSPLAT_OK;
+}
+}  // namespace
+
+csplat_status fp32_min_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
+                            const float *radii, const EvalParams &p, const EvalOut &out,
+                            const std::function<csplat_status()> &gate)
+{
+    const int q = (int)q64;
+    const int n = (int)sc->n;
+    const bool cull = p.cull && n > 0 && sc->cull;
+    ctx->stats.queries_per_lane = 1;
+    ctx->stats.kernel_pairs = (int64_t)q * n;
+    ctx->chunk_counter = nullptr;
+    const float *c = centers, *r = radii;
+    const int32_t *perm = nullptr;
+    unsigned long long *counter = nullptr;
+    if (cull) {
+        SortedQueries sq;
+        csplat_status s = sort_queries(ctx, sc, q, centers, radii, &sq);
+        if (s != CSPLAT_OK) return s;
+        c = sq.c;
+        r = sq.r;
+        perm = sq.perm;
+        counter = sq.counter;
+        ctx->chunk_counter = sq.counter;
+        ctx->pairs_per_chunk = kFine;  // the counter counts (query, sub-chunk) tasks of every pass
+    }
+    switch (p.m) {
+    case 1: return min_search<1>(ctx, sc, q, c, r, perm, cull, counter, p, out, gate);
+    case 2: return min_search<2>(ctx, sc, q, c, r, perm, cull, counter, p, out, gate);
+    case 3: return min_search<3>(ctx, sc, q, c, r, perm, cull, counter, p, out, gate);
+    case 4: return min_search<4>(ctx, sc, q, c, r, perm, cull, counter, p, out, gate);
+    case 5: return min_search<5>(ctx, sc, q, c, r, perm, cull, counter, p, out, gate);
+    case 6: return min_search<6>(ctx, sc, q, c, r, perm, cull, counter, p, out, gate);
+    case 7: return min_search<7>(ctx, sc, q, c, r, perm, cull, counter, p, out, gate);
+    case 8: return min_search<8>(ctx, sc, q, c, r, perm, cull, counter, p, out, gate);
+    default: return fail(CSPLAT_E_INVALID, "m out of range");
+    }
+}
+
 csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
                         const float *radii, const EvalParams &p, const EvalOut &out,
                         bool labels_only, bool ell, const std::function<csplat_status()> &gate,
                         const Workspace *ws)
 {
+    // the minimum over every kept Gaussian (labels optional): threshold passes
+    // of the task walk instead of the dense walk
+    if (!ws && !ell && !std::isfinite(p.rn2) && out.min && !out.softmin && !out.cost && !out.nbr)
+        return fp32_min_eval(ctx, sc, q64, centers, radii, p, out, gate);
     const int q = (int)q64;
     const int n = (int)sc->n;
     const bool full = !labels_only;
