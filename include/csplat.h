@@ -84,9 +84,10 @@ typedef struct {
     float d_max;           /* Eq. 11, > 0 */
     float gamma;           /* Eq. 11, >= 0 */
     float s_min;           /* Eq. 11, the paper uses 1 */
-    int32_t precision;     /* CSPLAT_PRECISION_*; the MFMA forms compute labels/counts over
-                              every kept Gaussian: they reject a finite neighbor_radius
-                              (CSPLAT_E_INVALID) */
+    int32_t precision;     /* CSPLAT_PRECISION_*; the MFMA forms compute labels, counts (exact:
+                              certified, the rest rechecked in fp64) and min with its error bound
+                              err, over every kept Gaussian: they reject a finite neighbor_radius,
+                              softmin, cost and nbr (CSPLAT_E_INVALID) */
     int32_t cull;          /* 1: sort the queries along a Hilbert curve and skip the
                               Gaussians (in groups of 1024, chunks of 64 and sub-chunks of 16
                               consecutive on the scene's curve) that provably lie outside a
@@ -108,6 +109,10 @@ typedef struct {
     float *softmin;  /* q x m */
     float *cost;     /* q x m */
     int32_t *nbr;    /* q, |N_j| (size of the neighbourhood ball) */
+    float *err;      /* q x m, precision forms only (with or without min): a certified bound
+                        on |min - exact minimum| in s~^2 units (the minimum from the bf16/fp16
+                        contraction is the middle of a certified interval; err is its
+                        half-width plus float32 rounding) */
 } csplat_outputs;
 
 /* Statistics of the last evaluation on a context. */

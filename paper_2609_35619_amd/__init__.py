@@ -72,7 +72,8 @@ class ReduceOpts(ctypes.Structure):
 
 class Outputs(ctypes.Structure):
     _fields_ = [("label", ctypes.c_void_p), ("count", ctypes.c_void_p), ("min", ctypes.c_void_p),
-                ("softmin", ctypes.c_void_p), ("cost", ctypes.c_void_p), ("nbr", ctypes.c_void_p)]
+                ("softmin", ctypes.c_void_p), ("cost", ctypes.c_void_p), ("nbr", ctypes.c_void_p),
+                ("err", ctypes.c_void_p)]
 
 
 class EvalStats(ctypes.Structure):
@@ -237,11 +238,11 @@ def reduce_opts(k=0, tau=0.0, r_nbr=math.inf, d_max=1.0, gamma=1.0, s_min=1.0,
 
 
 def csplat_eval(ctx, scene, centers, radii, opts: ReduceOpts, label=None, count=None, min=None,
-                softmin=None, cost=None, nbr=None):
+                softmin=None, cost=None, nbr=None, err=None):
     """Evaluate into caller-provided outputs (all torch CUDA tensors or all
     numpy arrays, matching centers/radii)."""
     q = int(centers.shape[0])
-    o = Outputs(*[_addr(x) for x in (label, count, min, softmin, cost, nbr)])
+    o = Outputs(*[_addr(x) for x in (label, count, min, softmin, cost, nbr, err)])
     _check(load_library().csplat_eval(ctx, scene, q, _addr(centers), _addr(radii), ctypes.byref(opts),
                                       ctypes.byref(o)))
 
@@ -426,7 +427,7 @@ class Engine:
         """Output buffers: torch CUDA tensors (like="cuda") or numpy arrays."""
         m = self.m
         shapes = dict(label=((q, m), "u8"), count=((q, m), "i32"), min=((q, m), "f32"),
-                      softmin=((q, m), "f32"), cost=((q, m), "f32"), nbr=((q,), "i32"))
+                      softmin=((q, m), "f32"), cost=((q, m), "f32"), nbr=((q,), "i32"), err=((q, m), "f32"))
         out = {}
         if like == "cuda":
             import torch

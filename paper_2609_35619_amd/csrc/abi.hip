@@ -242,8 +242,10 @@ csplat_status eval_checks(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     csplat_status s = build_params(ctx->n_sigma, ctx->m, *opts, p);
     if (s != CSPLAT_OK) return s;
     want_dist = out->min || out->softmin || out->cost || out->nbr;
-    if (!want_dist && !out->label && !out->count)
+    if (!want_dist && !out->label && !out->count && !out->err)
         return fail(CSPLAT_E_INVALID, std::string(who) + ": no output requested");
+    if (out->err && opts->precision == CSPLAT_PRECISION_FP32)
+        return fail(CSPLAT_E_INVALID, std::string(who) + ": err is an output of the precision forms");
     return CSPLAT_OK;
 }
 
@@ -317,7 +319,7 @@ csplat_status on_device(csplat_ctx *ctx, int kind, int64_t q, int m, std::initia
 {
     std::vector<const void *> dev_in(in);
     if (kind == 1) {
-        EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr};
+        EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr, out->err};
         return run(dev_in, eo);
     }
     const size_t qm = (size_t)q * m;
@@ -332,6 +334,7 @@ csplat_status on_device(csplat_ctx *ctx, int kind, int64_t q, int m, std::initia
     const size_t o_lab = out->label ? take(qm) : 0, o_cnt = out->count ? take(qm * 4) : 0;
     const size_t o_min = out->min ? take(qm * 4) : 0, o_sm = out->softmin ? take(qm * 4) : 0;
     const size_t o_cs = out->cost ? take(qm * 4) : 0, o_nb = out->nbr ? take((size_t)q * 4) : 0;
+    const size_t o_er = out->err ? take(qm * 4) : 0;
     hipError_t e = ctx->staging.reserve(off);
     if (e != hipSuccess) return hip_fail(e, "staging workspace");
     char *b = ctx->staging.as<char>();
@@ -344,7 +347,8 @@ csplat_status on_device(csplat_ctx *ctx, int kind, int64_t q, int m, std::initia
     }
     EvalOut eo{out->label ? (uint8_t *)(b + o_lab) : nullptr, out->count ? (int32_t *)(b + o_cnt) : nullptr,
                out->min ? (float *)(b + o_min) : nullptr, out->softmin ? (float *)(b + o_sm) : nullptr,
-               out->cost ? (float *)(b + o_cs) : nullptr, out->nbr ? (int32_t *)(b + o_nb) : nullptr};
+               out->cost ? (float *)(b + o_cs) : nullptr, out->nbr ? (int32_t *)(b + o_nb) : nullptr,
+               out->err ? (float *)(b + o_er) : nullptr};
     csplat_status s = run(dev_in, eo);
     if (s != CSPLAT_OK) return s;
     if (out->label) CSPLAT_HIP(hipMemcpyAsync(out->label, eo.label, qm, hipMemcpyDeviceToHost, st));
@@ -353,6 +357,7 @@ csplat_status on_device(csplat_ctx *ctx, int kind, int64_t q, int m, std::initia
     if (out->softmin) CSPLAT_HIP(hipMemcpyAsync(out->softmin, eo.softmin, qm * 4, hipMemcpyDeviceToHost, st));
     if (out->cost) CSPLAT_HIP(hipMemcpyAsync(out->cost, eo.cost, qm * 4, hipMemcpyDeviceToHost, st));
     if (out->nbr) CSPLAT_HIP(hipMemcpyAsync(out->nbr, eo.nbr, (size_t)q * 4, hipMemcpyDeviceToHost, st));
+    if (out->err) CSPLAT_HIP(hipMemcpyAsync(out->err, eo.err, qm * 4, hipMemcpyDeviceToHost, st));
     CSPLAT_HIP(hipStreamSynchronize(st));
     return CSPLAT_OK;
 }
@@ -516,8 +521,8 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     csplat_status s = eval_checks(ctx, sc, q, opts, out, "eval", p, want_dist);
     if (s != CSPLAT_OK) return s;
     if (opts->precision != CSPLAT_PRECISION_FP32) {
-        if (want_dist)
-            return fail(CSPLAT_E_INVALID, "eval: the MFMA precision forms compute labels and counts only");
+        if (out->softmin || out->cost || out->nbr)
+            return fail(CSPLAT_E_INVALID, "eval: the MFMA precision forms compute labels, counts and min only");
         if (std::isfinite(opts->neighbor_radius))
             return fail(CSPLAT_E_INVALID,
                         "eval: the MFMA precision forms count over every kept Gaussian (neighbor_radius = +inf)");
@@ -530,7 +535,7 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     if (q == 0) return CSPLAT_OK;
     if (!centers || !radii) return fail(CSPLAT_E_INVALID, "eval: NULL centers or radii");
     const int kind = common_kind({centers, radii, out->label, out->count, out->min, out->softmin, out->cost,
-                                  out->nbr});
+                                  out->nbr, out->err});
     if (kind < 0) return fail(CSPLAT_E_INVALID, "eval: mix of host and device pointers");
     const char *bad_msg = "eval: query centres must be finite and radii finite and > 0";
     if (kind == 0 && !queries_valid_host(q, centers, radii)) return fail(CSPLAT_E_INVALID, bad_msg);
@@ -658,7 +663,7 @@ csplat_status csplat_eval_noalloc(csplat_ctx *ctx, const csplat_scene *sc, int64
     });
     if (s != CSPLAT_OK) return s;
     const Workspace ws{ws_base, kScratchBytes};
-    const EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr};
+    const EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr, nullptr};
     return fp32_eval(ctx, sc, q, centers, radii, p, eo, !want_dist, false,
                      [&]() { return wait_device_check(ctx, bad_msg); }, &ws);
 }

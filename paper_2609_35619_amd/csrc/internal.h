@@ -235,6 +235,7 @@ struct EvalOut {
     float *softmin;
     float *cost;
     int32_t *nbr;
+    float *err;  // precision forms: certified bound of |min - exact minimum|
 };
 
 // Evaluation parameters from conservatism values and reduction options

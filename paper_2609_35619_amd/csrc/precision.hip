@@ -242,6 +242,7 @@ template <int P>
 struct QFeat {
     typename Prec<P>::vec a, w0, w1;
     float two_ea, c0;
+    float ec;  // certified bound of |a - a~| + |sqrt(w) - sqrt(w~)| (the minimum's epilogue)
 };
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -327,6 +328,8 @@ __device__ __forceinline__ bool build_query(float cx, float cy, float cz, float 
     const float ea = 1.1f * (ue * sa + T::eta * sa_abs + 4.f * kU32 * (c2 + r2));
     const float ew = 1.1f * (ue * sw + T::eta * sw_abs);
     const float two_ea = 2.f * ea, c0 = fmaf(ea, ea, ew) * 1.0001f;
+    // |sqrt(x) - sqrt(y)| <= sqrt(|x - y|) for x, y >= 0
+    const float ec = (ea + sqrtf(ew)) * 1.0001f;
     swap_halves(Q[0].a, Q[1].a);
     swap_halves(Q[0].w0, Q[1].w0);
     swap_halves(Q[0].w1, Q[1].w1);
@@ -335,8 +338,10 @@ __device__ __forceinline__ bool build_query(float cx, float cy, float cz, float 
     // column block 1's to the second
     Q[0].two_ea = Q[1].two_ea = two_ea;
     Q[0].c0 = Q[1].c0 = c0;
+    Q[0].ec = Q[1].ec = ec;
     swap_halves(Q[0].two_ea, Q[1].two_ea);
     swap_halves(Q[0].c0, Q[1].c0);
+    swap_halves(Q[0].ec, Q[1].ec);
     return isfinite(two_ea) && isfinite(c0) && isfinite(sa) && isfinite(sw);
 }
 
@@ -359,13 +364,25 @@ constexpr int kCB = CSPLAT_MFMA_COLUMN_BLOCKS;
 static_assert(kCB == 2 || kCB == 4, "column blocks per wave: 2 or 4");
 constexpr int kQueriesPerBlock = 4 * 32 * kCB;
 
-template <int P, bool CULL>
+// The minimum (MINW): per pair v~ = a~ - sqrt(max(w~, 0)), the computed value
+// of v = a - sqrt(w) = r^2 (s~^2 - 1) before the clamp, and a certified bound
+// e >= |v~ - v|: the contraction's bounds (ec) plus the float32 rounding of
+// the square root and the difference (8 u (|a~| + sqrt(w~)), generous).  The
+// lane keeps lo = min(v~ - e) and up = min(v~ + e), so the exact minimum over
+// the evaluated pairs lies in [lo, up].  With `thr` (per query; NULL: 1) the
+// reach is that of s~^2 < thr[j]: every pair below the threshold is
+// evaluated (the passes of the minimum search).  COUNT = false skips the
+// label counts.
+template <int P, bool CULL, bool COUNT = true, bool MINW = false>
 __global__ void __launch_bounds__(256)
 mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *__restrict__ meta,
                   int n_tiles, int S, int n_qblocks, const float *__restrict__ cull, int n_chunks,
                   const float *__restrict__ centers, const float *__restrict__ radii, int q, float four_n2,
-                  float n_sigma, int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out)
+                  float n_sigma, int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out,
+                  const float *__restrict__ thr = nullptr, float *__restrict__ mlo_out = nullptr,
+                  float *__restrict__ mup_out = nullptr, unsigned long long *__restrict__ blocks_done = nullptr)
 {
+    static_assert(COUNT || MINW, "nothing to compute");
     using T = Prec<P>;
     using vec = typename T::vec;
     constexpr int kG = kCB / 2;  // queries each lane builds features for
@@ -375,7 +392,7 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
     const int split = b / n_qblocks;
     const int qb = b - split * n_qblocks;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-    float cx[kCB], cy[kCB], cz[kCB], r2[kCB];
+    float cx[kCB], cy[kCB], cz[kCB], r2[kCB], qa[kCB];  // qa: the reach's r^2 (times the threshold)
     int jq[kCB];
 #pragma unroll
     for (int cb = 0; cb < kCB; ++cb) {
@@ -386,7 +403,12 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         cz[cb] = centers[3 * jj + 2];
         const float r = radii[jj];
         r2[cb] = r * r;
+        qa[cb] = MINW && thr ? r2[cb] * thr[jj] : r2[cb];
     }
+    float mlo[kCB], mup[kCB];
+#pragma unroll
+    for (int cb = 0; cb < kCB; ++cb) mlo[cb] = mup[cb] = INFINITY;
+    unsigned long long n_blocks = 0;
     int lo[kCB], hi[kCB];
     bool bad[kG];  // a non-finite bound for the lane's own query of column block pair g
 #pragma unroll
@@ -427,26 +449,41 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
 #pragma unroll
             for (int cb = 0; cb < kCB; ++cb) {
                 if (!((rbm_cb[cb] >> rb) & 1u)) continue;  // no query of cb near the row block
+                ++n_blocks;
                 const f32x16 A = T::mfma(Aa, Q[cb].a, zero);
                 f32x16 W = T::mfma(Aw0, Q[cb].w0, zero);
                 W = T::mfma(Aw1, Q[cb].w1, W);
-                const float te = Q[cb].two_ea, c0 = Q[cb].c0;
-                float f[16], bnd[16];
-                bool poss = false;
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const float a = A[i], aa = fabsf(a);
-                    f[i] = fmaf(-a, aa, W[i]);      // w - a|a|: > 0 iff collision
-                    bnd[i] = fmaf(aa, te, c0);      // certified |f - f_exact| bound
-                    poss |= f[i] > -bnd[i];
-                }
-                // most blocks hold no possible collision (and so no certain
-                // one): count only where some lane has one
-                if (__any(poss)) {
+                if constexpr (COUNT) {
+                    const float te = Q[cb].two_ea, c0 = Q[cb].c0;
+                    float f[16], bnd[16];
+                    bool poss = false;
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
-                        lo[cb] += f[i] > bnd[i];    // certainly in collision
-                        hi[cb] += f[i] > -bnd[i];   // possibly in collision
+                        const float a = A[i], aa = fabsf(a);
+                        f[i] = fmaf(-a, aa, W[i]);      // w - a|a|: > 0 iff collision
+                        bnd[i] = fmaf(aa, te, c0);      // certified |f - f_exact| bound
+                        poss |= f[i] > -bnd[i];
+                    }
+                    // most blocks hold no possible collision (and so no certain
+                    // one): count only where some lane has one
+                    if (__any(poss)) {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            lo[cb] += f[i] > bnd[i];    // certainly in collision
+                            hi[cb] += f[i] > -bnd[i];   // possibly in collision
+                        }
+                    }
+                }
+                if constexpr (MINW) {
+                    const float ec = Q[cb].ec;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const float a = A[i];
+                        const float sq = pair::fast_sqrt(fmaxf(W[i], 0.f));
+                        const float v = a - sq;
+                        const float e = fmaf(fabsf(a) + sq, 8.f * kU32, ec);
+                        mlo[cb] = fminf(mlo[cb], v - e);
+                        mup[cb] = fminf(mup[cb], v + e);
                     }
                 }
             }
@@ -459,7 +496,7 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         for (int t = split; t < n_tiles; t += S) do_tile(t, all);
     } else {
         float wx, wy, wz, spread, r2max;
-        pair::wave_sphere<kCB>(cx, cy, cz, r2, wx, wy, wz, spread, r2max);
+        pair::wave_sphere<kCB>(cx, cy, cz, qa, wx, wy, wz, spread, r2max);
         auto reach_of = [&](const pair::ChunkMeta &m, float rr2) {
             const float ns = n_sigma * m.smax;
             return ns + pair::fast_sqrt(fmaf(ns, ns, rr2));  // ~1 ulp, far inside the culling margin
@@ -493,7 +530,7 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
                     const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
 #pragma unroll
                     for (int cb = 0; cb < kCB; ++cb)
-                        if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, r2[cb]))))
+                        if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, qa[cb]))))
                             rbm[cb] |= 3u << (2 * k);
                 }
 #pragma unroll
@@ -506,15 +543,25 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
     for (int cb = 0; cb < kCB; ++cb) {
         lo[cb] += __shfl_xor(lo[cb], 32);
         hi[cb] += __shfl_xor(hi[cb], 32);
+        mlo[cb] = fminf(mlo[cb], __shfl_xor(mlo[cb], 32));
+        mup[cb] = fminf(mup[cb], __shfl_xor(mup[cb], 32));
         // the query of column block cb was built by the lanes of half cb & 1
         const int g = cb >> 1;
         const bool other = __shfl_xor((int)bad[g], 32) != 0;
         const bool anybad = (h == (cb & 1)) ? bad[g] : other;
         if (h == 0 && jq[cb] < q) {
-            lo_out[(size_t)split * q + jq[cb]] = lo[cb];
-            hi_out[(size_t)split * q + jq[cb]] = anybad ? (1 << 29) : hi[cb];
+            if constexpr (COUNT) {
+                lo_out[(size_t)split * q + jq[cb]] = lo[cb];
+                hi_out[(size_t)split * q + jq[cb]] = anybad ? (1 << 29) : hi[cb];
+            }
+            if constexpr (MINW) {
+                // a bound that is not finite leaves the interval open: (-inf, up]
+                mlo_out[(size_t)split * q + jq[cb]] = anybad ? -INFINITY : mlo[cb];
+                mup_out[(size_t)split * q + jq[cb]] = anybad ? INFINITY : mup[cb];
+            }
         }
     }
+    if (blocks_done && lane == 0) atomicAdd(blocks_done, n_blocks);
 }
 
 // Merge the splits, decide certified labels (written to the caller's row
@@ -644,6 +691,133 @@ __global__ void finish_kernel(int m, int v, int k, const int32_t *__restrict__ l
     if (count) count[(size_t)oj * m + v] = exact[li];
 }
 
+// ---------------------------------------------------------------------------
+// The minimum of s~^2 over every kept Gaussian in the precision forms: passes
+// of mfma_label_kernel with the minimum's epilogue and a rising threshold
+// (as the float32 search: every pair with s~^2 < T is evaluated; a query is
+// resolved once its certified upper bound lies below T; otherwise the next
+// threshold lies just above that bound, or four times the last one when no
+// pair was in reach).  State per query (sorted order): the interval
+// [lo, up] of v = r^2 (s~^2 - 1), the threshold, and a flag (0 resolved,
+// 1 searching, 2 fp64 fallback: a low-precision bound was not finite).
+constexpr float kMinResolveP = 0.9990234375f;  // 1 - 2^-10
+constexpr float kMinNextP = 1.00390625f;       // 1 + 2^-8
+
+__global__ void __launch_bounds__(256)
+pmin_combine_kernel(int nq, int S, const int32_t *__restrict__ list, const float *__restrict__ radii,
+                    const float *__restrict__ mlo, const float *__restrict__ mup, float *__restrict__ st_lo,
+                    float *__restrict__ st_up, float *__restrict__ st_thr, uint8_t *__restrict__ flag, bool first)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const int j = list ? list[i] : i;
+    float lo = INFINITY, up = INFINITY;
+    for (int s = 0; s < S; ++s) {
+        lo = fminf(lo, mlo[(size_t)s * nq + i]);
+        up = fminf(up, mup[(size_t)s * nq + i]);
+    }
+    if (first) st_thr[j] = 1.f;
+    const float r = radii[j], r2 = r * r;
+    st_lo[j] = lo;
+    st_up[j] = up;
+    // resolved: the exact minimum over the evaluated pairs (<= up + r^2) lies
+    // below the threshold, so no skipped pair is lower
+    flag[j] = lo == -INFINITY ? 2 : (up + r2 < r2 * st_thr[j] * kMinResolveP ? 0 : 1);
+}
+
+__global__ void __launch_bounds__(256)
+pmin_gather_kernel(int nl, const int32_t *__restrict__ list, const float *__restrict__ centers,
+                   const float *__restrict__ radii, const float *__restrict__ st_up, float *__restrict__ st_thr,
+                   float *__restrict__ cc, float *__restrict__ rr, float *__restrict__ tt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    const int j = list[i];
+    const float r = radii[j], r2 = r * r;
+    const float up = st_up[j];
+    // just above the certified upper bound of the minimum, or four times the
+    // last threshold when no pair was in reach
+    const float t = up < INFINITY ? fmaxf(up + r2, 0.f) / r2 * kMinNextP : 4.f * st_thr[j];
+    st_thr[j] = fmaxf(t, st_thr[j] * kMinNextP);
+    tt[i] = st_thr[j];
+    cc[3 * i] = centers[3 * j];
+    cc[3 * i + 1] = centers[3 * j + 1];
+    cc[3 * i + 2] = centers[3 * j + 2];
+    rr[i] = r;
+}
+
+// fp64 minimum of t = |d|^2 - 2 n sqrt(d^T Sigma d) (clamped at 0; r^2
+// s~^2) over every kept Gaussian for the listed queries: one wave per (listed
+// query, split of kRecheckSplits), strided Gaussians, a wave minimum, and an
+// atomic minimum on the bits of the non-negative double.
+__global__ void __launch_bounds__(64 * kRecheckWaves)
+min_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restrict__ centers, float n_sigma,
+                const int32_t *__restrict__ list, const int32_t *__restrict__ n_list,
+                unsigned long long *__restrict__ best)
+{
+    const int nl = *n_list;
+    const long items = (long)nl * kRecheckSplits;
+    const int lane = (int)(threadIdx.x & 63u);
+    const long wave0 = (long)blockIdx.x * kRecheckWaves + (long)(threadIdx.x >> 6);
+    const long waves = (long)gridDim.x * kRecheckWaves;
+    const double two_n = 2.0 * (double)n_sigma;
+    for (long item = wave0; item < items; item += waves) {
+        const int li = (int)(item / kRecheckSplits), split = (int)(item - (long)li * kRecheckSplits);
+        const int j = list[li];
+        const double cx = centers[3 * j], cy = centers[3 * j + 1], cz = centers[3 * j + 2];
+        double best_t = INFINITY;
+        for (long g = (long)split * 64 + lane; g < n; g += 64L * kRecheckSplits) {
+            const float *p = gauss + (size_t)kGaussFloats * g;
+            const double dx = (double)p[0] - cx, dy = (double)p[1] - cy, dz = (double)p[2] - cz;
+            const double e0 = (double)p[3] * dx + (double)p[4] * dy + (double)p[5] * dz;
+            const double e1 = (double)p[6] * dx + (double)p[7] * dy + (double)p[8] * dz;
+            const double e2 = (double)p[9] * dx + (double)p[10] * dy + (double)p[11] * dz;
+            const double t = dx * dx + dy * dy + dz * dz - two_n * sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+            best_t = fmin(best_t, t > 0.0 ? t : 0.0);
+        }
+        for (int off = 32; off >= 1; off >>= 1) best_t = fmin(best_t, __shfl_xor(best_t, off));
+        if (lane == 0 && best_t < INFINITY) atomicMin(best + li, (unsigned long long)__double_as_longlong(best_t));
+    }
+}
+
+// Results at row perm[j]: min = the middle of the clamped interval over r^2,
+// err = its half-width plus the float32 rounding of the additions and the
+// division; fp64 fallback queries (flag 2, listed in `list2` with `best`):
+// the fp64 minimum rounded to float32 (err: one float32 ulp of it).
+__global__ void __launch_bounds__(256)
+pmin_output_kernel(int q, int m, int v, const float *__restrict__ radii, const int32_t *__restrict__ perm,
+                   const float *__restrict__ st_lo, const float *__restrict__ st_up, const uint8_t *__restrict__ flag,
+                   const int32_t *__restrict__ slot, const unsigned long long *__restrict__ best, float *out_min,
+                   float *out_err)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    const int oj = perm ? perm[j] : j;
+    const float r = radii[j], r2 = r * r;
+    float mn, err;
+    if (flag[j] == 2) {
+        const double t = __longlong_as_double((long long)best[slot[j]]);
+        mn = (float)(t / ((double)r * (double)r));
+        err = 1.1920929e-07f * mn;  // 2^-23 |min|
+    } else {
+        const float tl = fmaxf(st_lo[j] + r2, 0.f), tu = fmaxf(st_up[j] + r2, 0.f);
+        const float mid = 0.5f * (tl + tu);
+        const float half = 0.5f * (tu - tl) + 4.f * kU32 * (fabsf(st_lo[j]) + fabsf(st_up[j]) + 2.f * r2);
+        mn = mid / r2;
+        err = half / r2 * 1.000001f + 2.f * kU32 * mn;
+    }
+    if (out_min) out_min[(size_t)oj * m + v] = mn;
+    if (out_err) out_err[(size_t)oj * m + v] = err;
+}
+
+// Slot of each fp64 fallback query in the list (filled for the listed ones).
+__global__ void pmin_slot_kernel(const int32_t *__restrict__ list, const int32_t *__restrict__ n_list,
+                                 int32_t *__restrict__ slot)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < *n_list) slot[list[i]] = i;
+}
+
 template <int P>
 csplat_status build_one(csplat_ctx *ctx, csplat_scene *sc, void **feat_out)
 {
@@ -696,6 +870,60 @@ csplat_status precision_build(csplat_ctx *ctx, csplat_scene *sc, uint32_t featur
     return CSPLAT_OK;
 }
 
+namespace {
+struct IsOne {
+    __host__ __device__ uint8_t operator()(uint8_t x) const { return x == 1; }
+};
+struct IsTwo {
+    __host__ __device__ uint8_t operator()(uint8_t x) const { return x == 2; }
+};
+
+// One launch of mfma_label_kernel for dtype `precision`.
+template <bool COUNT, bool MINW>
+void launch_mfma(int precision, bool cull, dim3 grid, hipStream_t st, const csplat_scene *sc, int n_qblocks, int S,
+                 int n_chunks, const float *c, const float *r, int q, float four_n2, float nv, int32_t *lo,
+                 int32_t *hi, const float *thr, float *mlo, float *mup, unsigned long long *blocks)
+{
+    const int n_tiles = (int)sc->n_tiles;
+    if (precision == CSPLAT_PRECISION_BF16_RECHECK) {
+        const auto *f = static_cast<const bf16x8 *>(sc->feat_bf16);
+        if (cull)
+            mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, true, COUNT, MINW><<<grid, 256, 0, st>>>(
+                f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, thr, mlo,
+                mup, blocks);
+        else
+            mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, false, COUNT, MINW><<<grid, 256, 0, st>>>(
+                f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, thr, mlo,
+                mup, blocks);
+    } else {
+        const auto *f = static_cast<const f16x8 *>(sc->feat_fp16);
+        if (cull)
+            mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, true, COUNT, MINW><<<grid, 256, 0, st>>>(
+                f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, thr, mlo,
+                mup, blocks);
+        else
+            mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, false, COUNT, MINW><<<grid, 256, 0, st>>>(
+                f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, thr, mlo,
+                mup, blocks);
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, int n, unsigned long long v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Splits of a launch over q queries (blocks of kQueriesPerBlock).
+int mfma_splits(const csplat_ctx *ctx, int q, int n_tiles)
+{
+    const int n_qblocks = (q + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    if (n_tiles <= 0) return 1;
+    const int S = (ctx_target_blocks(ctx) + n_qblocks - 1) / n_qblocks;
+    return std::max(1, std::min(S, n_tiles));
+}
+}  // namespace
+
 csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
                              const float *radii, const EvalParams &p, const EvalOut &out, int precision)
 {
@@ -705,15 +933,14 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
     hipStream_t st = ctx->stream;
     const int n_tiles = (int)sc->n_tiles;
     const int n_qblocks = (q + kQueriesPerBlock - 1) / kQueriesPerBlock;
-    int S = 1;
-    if (n_tiles > 0) {
-        S = (ctx_target_blocks(ctx) + n_qblocks - 1) / n_qblocks;
-        S = std::max(1, std::min(S, n_tiles));
-    }
+    const int S = mfma_splits(ctx, q, n_tiles);
     const int n_chunks = (n + pair::kCull - 1) / pair::kCull;
     const bool cull = p.cull && n > 0 && sc->cull;
+    const bool want_count = out.label || out.count;
+    const bool want_min = out.min || out.err;
     const float *c = centers, *r = radii;
     const int32_t *perm = nullptr;
+    unsigned long long *blocks = nullptr;
     if (cull) {
         SortedQueries sq;
         csplat_status s = sort_queries(ctx, sc, q, centers, radii, &sq);
@@ -721,6 +948,9 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
         c = sq.c;
         r = sq.r;
         perm = sq.perm;
+        blocks = sq.counter;  // 32 x 32 MFMA blocks evaluated (every pass, every n_sigma)
+        ctx->chunk_counter = sq.counter;
+        ctx->pairs_per_chunk = 32 * 32;
     }
     // workspace: lo/hi partials, the recheck list, exact counts, flags, compaction scratch
     size_t sel_bytes = 0;
@@ -739,6 +969,30 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
     int32_t *exact = reinterpret_cast<int32_t *>(base + off_exact);
     uint8_t *flag = reinterpret_cast<uint8_t *>(base + off_flag);
     void *sel_tmp = base + off_sel;
+    // the minimum search's state and partials
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t qn = (size_t)q, mpart = (size_t)ctx_target_blocks(ctx) * kQueriesPerBlock + part;
+    const size_t o_lo = 0, o_up = o_lo + al(qn * 4), o_thr = o_up + al(qn * 4), o_mflag = o_thr + al(qn * 4),
+                 o_mlist = o_mflag + al(qn), o_nl = o_mlist + al(qn * 4), o_cc = o_nl + 256, o_rr = o_cc + al(qn * 12),
+                 o_tt = o_rr + al(qn * 4), o_slot = o_tt + al(qn * 4), o_best = o_slot + al(qn * 4),
+                 o_mlo = o_best + al(qn * 8), o_mup = o_mlo + al(mpart * 4), o_msel = o_mup + al(mpart * 4),
+                 m_total = o_msel + al(sel_bytes);
+    char *mb = nullptr;
+    if (want_min) {
+        e = ctx->minbuf.reserve(m_total);
+        if (e != hipSuccess) return hip_fail(e, "minimum-search workspace");
+        mb = ctx->minbuf.as<char>();
+    }
+    float *st_lo = reinterpret_cast<float *>(mb + o_lo), *st_up = reinterpret_cast<float *>(mb + o_up),
+          *st_thr = reinterpret_cast<float *>(mb + o_thr);
+    uint8_t *mflag = reinterpret_cast<uint8_t *>(mb + o_mflag);
+    int32_t *mlist = reinterpret_cast<int32_t *>(mb + o_mlist), *mnl = reinterpret_cast<int32_t *>(mb + o_nl),
+            *slot = reinterpret_cast<int32_t *>(mb + o_slot);
+    float *cc = reinterpret_cast<float *>(mb + o_cc), *rr = reinterpret_cast<float *>(mb + o_rr),
+          *tt = reinterpret_cast<float *>(mb + o_tt), *mlo = reinterpret_cast<float *>(mb + o_mlo),
+          *mup = reinterpret_cast<float *>(mb + o_mup);
+    auto *best = reinterpret_cast<unsigned long long *>(mb + o_best);
+    void *msel = mb + o_msel;
     e = ctx->flags.reserve((size_t)CSPLAT_MAX_M * sizeof(int32_t) + 64);
     if (e != hipSuccess) return hip_fail(e, "flag counters");
     int32_t *n_list = ctx->flags.as<int32_t>();
@@ -746,47 +1000,102 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
     ctx->stats.splits = S;
     ctx->stats.queries_per_lane = 2;
     ctx->stats.kernel_pairs = (int64_t)q * n;
-    ctx->flag_counts = n_list;
-    ctx->flag_m = m;
-    const bool want_count = out.count != nullptr;
+    ctx->flag_counts = want_count ? n_list : nullptr;
+    ctx->flag_m = want_count ? m : 0;
     const unsigned qb = (unsigned)((q + 255) / 256);
+    float total_ms = 0.f;
+    int passes = 0;
+    auto time_pass = [&](bool begin) {
+        if (!ctx->timing) return;
+        (void)hipEventRecord(begin ? ctx->ev0 : ctx->ev1, st);
+    };
+    auto add_ms = [&]() {
+        if (!ctx->timing) return CSPLAT_OK;
+        float ms = 0.f;
+        CSPLAT_HIP(hipEventSynchronize(ctx->ev1));
+        CSPLAT_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        total_ms += ms;
+        return CSPLAT_OK;
+    };
     for (int v = 0; v < m; ++v) {
+        const float nv = p.n_sigma[v];
+        // pass 1: labels (certified counts) and the minimum's interval
         if (n_tiles > 0) {
-            if (v == 0) timing_begin(ctx);
-            dim3 grid((unsigned)(n_qblocks * S));
-            const float nv = p.n_sigma[v];
-            if (precision == CSPLAT_PRECISION_BF16_RECHECK) {
-                const auto *f = static_cast<const bf16x8 *>(sc->feat_bf16);
-                if (cull)
-                    mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, true><<<grid, 256, 0, st>>>(
-                        f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, p.four_n2[v], nv, lo, hi);
-                else
-                    mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, false><<<grid, 256, 0, st>>>(
-                        f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, p.four_n2[v], nv, lo, hi);
-            } else {
-                const auto *f = static_cast<const f16x8 *>(sc->feat_fp16);
-                if (cull)
-                    mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, true><<<grid, 256, 0, st>>>(
-                        f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, p.four_n2[v], nv, lo, hi);
-                else
-                    mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, false><<<grid, 256, 0, st>>>(
-                        f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, p.four_n2[v], nv, lo, hi);
-            }
-            if (v == 0) timing_end(ctx);
+            const dim3 grid((unsigned)(n_qblocks * S));
+            time_pass(true);
+            if (want_count && want_min)
+                launch_mfma<true, true>(precision, cull, grid, st, sc, n_qblocks, S, n_chunks, c, r, q, p.four_n2[v],
+                                        nv, lo, hi, nullptr, mlo, mup, blocks);
+            else if (want_count)
+                launch_mfma<true, false>(precision, cull, grid, st, sc, n_qblocks, S, n_chunks, c, r, q,
+                                         p.four_n2[v], nv, lo, hi, nullptr, nullptr, nullptr, blocks);
+            else
+                launch_mfma<false, true>(precision, cull, grid, st, sc, n_qblocks, S, n_chunks, c, r, q,
+                                         p.four_n2[v], nv, nullptr, nullptr, nullptr, mlo, mup, blocks);
+            time_pass(false);
+            CSPLAT_HIP(hipGetLastError());
+            csplat_status ts = add_ms();
+            if (ts != CSPLAT_OK) return ts;
+        }
+        if (want_count) {
+            decide_kernel<<<qb, 256, 0, st>>>(q, n_tiles > 0 ? S : 0, m, v, p.k, out.count != nullptr, lo, hi, perm,
+                                              out.label, out.count, flag);
+            CSPLAT_HIP(hipGetLastError());
+            // the undecided queries, in (sorted) query order
+            CSPLAT_HIP(hipcub::DeviceSelect::Flagged(sel_tmp, sel_bytes, hipcub::CountingInputIterator<int32_t>(0),
+                                                     flag, list, n_list + v, q, st));
+            CSPLAT_HIP(zero_words(exact, (size_t)q, st));
+            if (n > 0)
+                recheck_fp64_kernel<<<kRecheckGrid, 64 * kRecheckWaves, 0, st>>>(
+                    sc->gauss, n, cull ? sc->cull : nullptr, c, r, p.n_sigma[v], list, n_list + v, exact);
+            finish_kernel<<<qb, 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, perm, out.label, out.count);
             CSPLAT_HIP(hipGetLastError());
         }
-        decide_kernel<<<qb, 256, 0, st>>>(q, n_tiles > 0 ? S : 0, m, v, p.k, want_count, lo, hi, perm, out.label,
-                                          out.count, flag);
+        if (!want_min) continue;
+        // the minimum: later passes for the queries not yet resolved
+        pmin_combine_kernel<<<qb, 256, 0, st>>>(q, n_tiles > 0 ? S : 0, nullptr, r, mlo, mup, st_lo, st_up, st_thr,
+                                                mflag, true);
         CSPLAT_HIP(hipGetLastError());
-        // the undecided queries, in (sorted) query order
-        CSPLAT_HIP(hipcub::DeviceSelect::Flagged(sel_tmp, sel_bytes, hipcub::CountingInputIterator<int32_t>(0), flag,
-                                                 list, n_list + v, q, st));
-        CSPLAT_HIP(zero_words(exact, (size_t)q, st));
+        int pass = 1;
+        for (; n > 0; ++pass) {
+            CSPLAT_HIP(hipcub::DeviceSelect::Flagged(msel, sel_bytes, hipcub::CountingInputIterator<int32_t>(0),
+                                                     hipcub::TransformInputIterator<uint8_t, IsOne, const uint8_t *>(mflag, IsOne()),
+                                                     mlist, mnl, q, st));
+            int nl = 0;
+            CSPLAT_HIP(hipMemcpyAsync(&nl, mnl, sizeof(int), hipMemcpyDeviceToHost, st));
+            CSPLAT_HIP(hipStreamSynchronize(st));
+            if (nl == 0) break;
+            if (pass >= 64) return fail(CSPLAT_E_DEVICE, "minimum search: thresholds did not converge");
+            const unsigned lb = (unsigned)((nl + 255) / 256);
+            pmin_gather_kernel<<<lb, 256, 0, st>>>(nl, mlist, c, r, st_up, st_thr, cc, rr, tt);
+            const int nqb = (nl + kQueriesPerBlock - 1) / kQueriesPerBlock;
+            const int S2 = mfma_splits(ctx, nl, n_tiles);
+            time_pass(true);
+            launch_mfma<false, true>(precision, cull, dim3((unsigned)(nqb * S2)), st, sc, nqb, S2, n_chunks, cc, rr,
+                                     nl, p.four_n2[v], nv, nullptr, nullptr, tt, mlo, mup, blocks);
+            time_pass(false);
+            CSPLAT_HIP(hipGetLastError());
+            csplat_status ts = add_ms();
+            if (ts != CSPLAT_OK) return ts;
+            pmin_combine_kernel<<<lb, 256, 0, st>>>(nl, S2, mlist, r, mlo, mup, st_lo, st_up, st_thr, mflag, false);
+            CSPLAT_HIP(hipGetLastError());
+        }
+        passes = std::max(passes, pass);
+        // queries whose low-precision bound was not finite: fp64 over every kept Gaussian
+        CSPLAT_HIP(hipcub::DeviceSelect::Flagged(msel, sel_bytes, hipcub::CountingInputIterator<int32_t>(0),
+                                                 hipcub::TransformInputIterator<uint8_t, IsTwo, const uint8_t *>(mflag, IsTwo()),
+                                                 mlist, mnl, q, st));
+        fill_u64_kernel<<<qb, 256, 0, st>>>(best, q, 0x7FF0000000000000ull);
+        pmin_slot_kernel<<<qb, 256, 0, st>>>(mlist, mnl, slot);
         if (n > 0)
-            recheck_fp64_kernel<<<kRecheckGrid, 64 * kRecheckWaves, 0, st>>>(sc->gauss, n, cull ? sc->cull : nullptr, c, r,
-                                                             p.n_sigma[v], list, n_list + v, exact);
-        finish_kernel<<<qb, 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, perm, out.label, out.count);
+            min_fp64_kernel<<<kRecheckGrid, 64 * kRecheckWaves, 0, st>>>(sc->gauss, n, c, nv, mlist, mnl, best);
+        pmin_output_kernel<<<qb, 256, 0, st>>>(q, m, v, r, perm, st_lo, st_up, mflag, slot, best, out.min, out.err);
         CSPLAT_HIP(hipGetLastError());
+    }
+    ctx->stats.min_passes = want_min ? passes : 0;
+    if (ctx->timing) {
+        ctx->timed = true;
+        ctx->timed_ms = total_ms;
     }
     return CSPLAT_OK;
 }

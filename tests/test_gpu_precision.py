@@ -176,14 +176,17 @@ def test_precision_requires_features(cs, eng):
         cs.csplat_eval_labels(eng.ctx, h, qs.centers, qs.radii,
                               cs.reduce_opts(precision=cs.CSPLAT_PRECISION_BF16_RECHECK),
                               np.zeros((qs.q, 1), np.uint8))
-    with pytest.raises(cs.CsplatError):   # distances are float32-path outputs
+    with pytest.raises(cs.CsplatError):   # softmin and cost are float32-path outputs
         h2 = _load(cs, eng, sc, p)
         try:
             cs.csplat_eval_distance(eng.ctx, h2, qs.centers, qs.radii,
                                     cs.reduce_opts(precision=cs.CSPLAT_PRECISION_BF16_RECHECK),
-                                    np.zeros((qs.q, 1), np.float32))
+                                    np.zeros((qs.q, 1), np.float32), softmin=np.zeros((qs.q, 1), np.float32))
         finally:
             cs.csplat_scene_free(h2)
+    with pytest.raises(cs.CsplatError):   # err is an output of the precision forms
+        cs.csplat_eval(eng.ctx, h, qs.centers, qs.radii, cs.reduce_opts(),
+                       min=np.zeros((qs.q, 1), np.float32), err=np.zeros((qs.q, 1), np.float32))
     cs.csplat_scene_free(h)
 
 
@@ -238,3 +241,62 @@ def test_precision_full_size_sampled(cs, eng, oracle_mod):
         compare({"label": res[name]["label"][idx]}, ref, tau=0.0, gamma=1.0, where=f"full-{name}")
     assert diff.sum() <= 64, f"{diff.sum()} label disagreements between precision forms and float32"
     del torch
+
+
+def _min_err_check(gpu, ref, where):
+    """The certified bar: |min - oracle| <= err on every query; returns the
+    error distribution."""
+    g, o, e = (np.asarray(gpu["min"], np.float64), ref["min"], np.asarray(gpu["err"], np.float64))
+    inf = np.isinf(o)
+    assert np.array_equal(np.isinf(g), inf), f"{where}: min infinities differ"
+    assert np.all(np.isfinite(e[~inf])) and np.all(e >= 0), f"{where}: err not finite"
+    d = np.abs(g[~inf] - o[~inf])
+    bad = d > e[~inf]
+    assert not bad.any(), f"{where}: {bad.sum()} minima outside their certified bound, e.g. {d[bad][:3]} > {e[~inf][bad][:3]}"
+    rel = d / np.maximum(1.0, np.abs(o[~inf]))
+    return dict(max_abs=float(d.max(initial=0)), p99_abs=float(np.percentile(d, 99)) if d.size else 0.0,
+                max_rel=float(rel.max(initial=0)), max_err=float(e[~inf].max(initial=0)),
+                p99_err=float(np.percentile(e[~inf], 99)) if d.size else 0.0)
+
+
+@pytest.mark.parametrize("prec", PRECISIONS)
+@pytest.mark.parametrize("want", [("label", "count", "min", "err"), ("min", "err")])
+def test_precision_min_certified(cs, eng, oracle_mod, prec, want):
+    _say(f"case: precision {prec} minimum, outputs {want}")
+    sc = uniform_box_scene(20_000, seed=331, box=(3, 3, 1.5))
+    qs = uniform_queries(3000, seed=332, box=(3, 3, 1.5), radius=0.08)
+    qs = Queries(qs.centers, (qs.radii * np.random.default_rng(333).uniform(0.5, 3.0, qs.q)).astype(np.float32))
+    p = dict(n_sigma=[0.0, 1.0, 2.0], k=2)
+    h = _load(cs, eng, sc, p)
+    gpu, st = _eval(cs, eng, h, qs, p, _prec(cs, prec), want=want)
+    f32, _ = _eval(cs, eng, h, qs, p, cs.CSPLAT_PRECISION_FP32, want=("min",))
+    cs.csplat_scene_free(h)
+    ref = _oracle(oracle_mod, sc, qs, p)
+    if "label" in want:
+        compare({k: gpu[k] for k in ("label", "count")}, ref, tau=0.0, gamma=1.0, where=f"min-labels-{prec}")
+    e = _min_err_check(gpu, ref, f"min-{prec}")
+    _say(f"{prec}: passes {st['min_passes']}, blocks {st['kernel_pairs'] // 1024}, {e}")
+    # the float32 search lies inside the same certified interval (both bracket the exact value)
+    fin = np.isfinite(ref["min"])
+    assert np.all(np.abs(f32["min"][fin] - gpu["min"][fin]) <= gpu["err"][fin] * 1.001 + 1e-5 * np.maximum(1, ref["tstar"][fin]))
+
+
+def test_precision_min_fp64_fallback(cs, eng, oracle_mod):
+    """fp16 query features overflow for spheres 300 units from the scene: those
+    minima come from the fp64 fallback, still within err of the oracle."""
+    _say("case: fp16 minimum with queries far from the scene (fp64 fallback)")
+    sc = uniform_box_scene(5_000, seed=341, box=(2, 2, 1))
+    qs = uniform_queries(500, seed=342, box=(2, 2, 1), radius=0.1)
+    far = np.array([[300.0, 1.0, 0.5], [1.0, -350.0, 0.5], [1.0, 1.0, 400.0]], np.float32)
+    qq = Queries(np.concatenate([qs.centers, far]), np.concatenate([qs.radii, np.full(3, 0.2, np.float32)]))
+    p = dict(n_sigma=[1.0], k=1)
+    h = _load(cs, eng, sc, p)
+    res = {}
+    for prec in PRECISIONS:
+        res[prec], st = _eval(cs, eng, h, qq, p, _prec(cs, prec), want=("label", "min", "err"))
+        _say(f"{prec}: passes {st['min_passes']}")
+    cs.csplat_scene_free(h)
+    ref = _oracle(oracle_mod, sc, qq, p)
+    for prec in PRECISIONS:
+        compare({"label": res[prec]["label"]}, ref, tau=0.0, gamma=1.0, where=f"far-{prec}")
+        _say(f"{prec}: {_min_err_check(res[prec], ref, f'far-min-{prec}')}")
