@@ -28,9 +28,29 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sphere-Gaussian pair evals/s + queries/s at stated label accuracy; p50/p99 latency"
 PEAK_VALU = 256 * 4 * 16 * 2.4e9   # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz (one VALU slot per lane-cycle)
-# Transcendentals (v_sqrt, v_exp) issue at half the FMA rate on gfx950
-# (measured: 0.5 against 0.9-1.0 wave instructions per CU per cycle), so each
-# counts 2 VALU slots.
+PEAK_MFMA_BF16 = 2.5e15            # dense bf16/fp16 MFMA FLOP/s (published, no sparsity)
+
+
+# The roofline's operation counts come from the method, not from the emitted
+# instructions: FMA = 1, compare or count = 1, a transcendental (sqrt, exp) = 4.
+def ops_full_in_ball(m):
+    """All outputs, per pair inside the ball: shared d 3, |d|^2 3, M d 9, V 3,
+    sqrt 4; per conservatism value about 30 (label 5, s~^2 with min and
+    softmin 13, cost 10 and the sums): 22 + 30 m (110 for m = 3, 52 for m = 1)."""
+    return 22 + 30 * m
+
+
+def ops_labels(m):
+    """Labels, per evaluated pair: d 3, D 3, M d 9, V 3; per value a, w, a|a|, cmp, count 5."""
+    return 18 + 5 * m
+
+
+OPS_MFMA_EPILOGUE = 7              # per pair of an evaluated 32 x 32 block: a, a|a|, f, cmp, count, bound, flag
+FLOP_MFMA_PAIR = 64                # two contractions over K = 16 (padded from 10), 2 FLOP per MAC
+
+
+# The tighter per-launch count of the kernels' own work (transcendentals at
+# their measured half rate, 2 slots), reported beside the method's count.
 OPS_ALL_PAIRS = 7                  # d (3), |d|^2 (3), ball test (1)
 OPS_IN_BALL_SHARED = 15            # M d (9), V (3), sqrt (2 slots), ball count (1)
 OPS_IN_BALL_PER_NSIGMA = 15        # s~^2 (2), label (2), min (1), softmin (exp 2 + 2), cost (exp 2 + 4)
@@ -89,11 +109,12 @@ def main():
     ap.add_argument("--no-ellipsoids", action="store_true", help="skip the ellipsoidal-body workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped context workload")
     ap.add_argument("--no-manip", action="store_true", help="skip the manipulation (sphere chain) workload")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the plain tiny configuration")
     ap.add_argument("--serving-requests", type=int, default=500)
-    ap.add_argument("--serving-full", action="store_true",
-                    help="serve the full-size request law (MPPI K up to 4096 x 32 x 48; long)")
-    ap.add_argument("--section", choices=("all", "main", "precision", "serving", "ellipsoids", "manip", "paper", "copy",
-                                          "digest"), default="all",
+    ap.add_argument("--serving-reduced", action="store_true",
+                    help="serve a reduced request law (MPPI K <= 512 x 32 x <= 8 spheres; quick)")
+    ap.add_argument("--section", choices=("all", "main", "precision", "precision-kernels", "serving", "ellipsoids",
+                                          "manip", "paper", "tiny", "copy", "digest"), default="all",
                     help="run one part only (for profiling); 'copy' is a plain 1 GiB device copy "
                          "used to calibrate the HBM traffic counters")
     args = ap.parse_args()
@@ -102,12 +123,19 @@ def main():
     if args.section == "digest":
         print(kernel_digest())
         return None
+    if args.section == "precision-kernels":
+        import paper_2609_35619_amd as cs
+        cs.load_library()
+        with cs.Engine(0) as eng:
+            print(json.dumps(precision_kernels(cs, eng)), flush=True)
+        return None
     if args.section != "all":
         args.no_precision = args.section not in ("precision",)
         args.no_serving = args.section not in ("serving",)
         args.no_ellipsoids = args.section not in ("ellipsoids",)
         args.no_paper = args.section not in ("paper",)
         args.no_manip = args.section not in ("manip",)
+        args.no_tiny = args.section not in ("tiny",)
         args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -194,8 +222,8 @@ def main():
     # skipped by the exact reach-bound test cost no arithmetic (every in-ball
     # pair is evaluated); the dense count is reported beside it
     evaluated = int(st["kernel_pairs"])
-    ops = OPS_ALL_PAIRS * evaluated + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr_total
-    dense_ops = OPS_ALL_PAIRS * pairs + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr_total
+    ops = ops_full_in_ball(m) * nbr_total
+    ops_tight = OPS_ALL_PAIRS * evaluated + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr_total
     achieved = ops / kernel_s
     res = {
         "metric": METRIC,
@@ -227,14 +255,17 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU / 1e9, "unit": "Gop/s",
                      "frac": achieved / PEAK_VALU, "traffic": traffic_from_profile(), "traffic_unit": "bytes",
                      "kernel": "pair_task_kernel<3,cull,sphere>", "kernel_ms": kernel_s * 1e3,
-                     "ops_per_launch": ops, "in_ball_pairs": nbr_total, "evaluated_pairs": evaluated,
-                     "dense_pairs": pairs, "dense_ops_per_launch": dense_ops,
-                     "dense_equivalent_frac": dense_ops / kernel_s / PEAK_VALU},
+                     "ops_per_unit": ops_full_in_ball(m), "unit_of_work": "pair inside the 1 m ball",
+                     "units_per_launch": nbr_total, "ops_per_launch": ops, "evaluated_pairs": evaluated,
+                     "tight_ops_per_launch": ops_tight, "frac_tight_count": ops_tight / kernel_s / PEAK_VALU,
+                     "dense_pairs": pairs},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"], res["label_accuracy"] = cpu_baseline(sc, qs, p, gpu, args.cpu_seconds, n_kept)
     if not args.no_precision:
-        res["precision_form"] = precision_form(cs, eng)
+        res["precision_form"] = precision_form(cs, eng, not args.no_cpu_baseline)
+    if not args.no_tiny:
+        res["tiny"] = tiny(cs, eng, args.steps)
     if not args.no_manip:
         res["manip"] = manip(cs, eng, args.steps)
     if not args.no_ellipsoids:
@@ -242,7 +273,7 @@ def main():
     if not args.no_paper:
         res["paper_context"] = paper_context(cs, eng)
     if not args.no_serving:
-        res["serving"] = serving(cs, eng, sc, h, args.serving_requests, args.serving_full)
+        res["serving"] = serving(cs, eng, sc, h, args.serving_requests, args.serving_reduced)
     cs.csplat_scene_free(h)
     eng.close()
     print(json.dumps(res), flush=True)
@@ -311,7 +342,8 @@ def manip(cs, eng, steps):
     cs.csplat_ctx_set_timing(eng.ctx, False)
     nbr = int(out["nbr"].cpu().numpy().astype(np.int64).sum())
     cs.csplat_scene_free(h)
-    ops = OPS_ALL_PAIRS * int(st["kernel_pairs"]) + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr
+    ops = ops_full_in_ball(m) * nbr
+    tight = OPS_ALL_PAIRS * int(st["kernel_pairs"]) + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr
     kernel_s = float(np.mean(kms)) / 1e3
     return {"workload": "manip: 500k-Gaussian tabletop, 256 configurations x 32 steps x 48 chain spheres "
                         "(r 0.03-0.10 m), n_sigma 1, ball 0.3 m, all outputs",
@@ -319,7 +351,9 @@ def manip(cs, eng, steps):
             "pair_evals_per_s": qs.q * n_kept / dt, "queries_per_s": qs.q / dt,
             "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e9, "peak": PEAK_VALU / 1e9,
                          "unit": "Gop/s", "frac": ops / kernel_s / PEAK_VALU, "kernel_ms": kernel_s * 1e3,
-                         "evaluated_pairs": int(st["kernel_pairs"]), "in_ball_pairs": nbr}}
+                         "ops_per_unit": ops_full_in_ball(m), "unit_of_work": "pair inside the 0.3 m ball",
+                         "units_per_launch": nbr, "frac_tight_count": tight / kernel_s / PEAK_VALU,
+                         "evaluated_pairs": int(st["kernel_pairs"])}}
 
 
 def ellipsoids(cs, eng, steps):
@@ -356,7 +390,8 @@ def ellipsoids(cs, eng, steps):
     cs.csplat_ctx_set_timing(eng.ctx, False)
     nbr = int(out["nbr"].cpu().numpy().astype(np.int64).sum())
     cs.csplat_scene_free(h)
-    ops = OPS_ALL_PAIRS * int(st["kernel_pairs"]) + (OPS_ELL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr
+    ops = (ops_full_in_ball(m) + 18) * nbr   # L d, L^T e: +18 over a sphere
+    tight = OPS_ALL_PAIRS * int(st["kernel_pairs"]) + (OPS_ELL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr
     kernel_s = float(np.mean(kms)) / 1e3
     return {"workload": "manip_ell: 500k-Gaussian tabletop, 256 configurations x 32 steps x 7 link ellipsoids "
                         "(semi-axes r, r, L/2 + r), n_sigma 1, ball 0.4 m, all outputs",
@@ -364,7 +399,9 @@ def ellipsoids(cs, eng, steps):
             "pair_evals_per_s": b.q * n_kept / dt, "queries_per_s": b.q / dt,
             "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e9, "peak": PEAK_VALU / 1e9,
                          "unit": "Gop/s", "frac": ops / kernel_s / PEAK_VALU, "kernel_ms": kernel_s * 1e3,
-                         "evaluated_pairs": int(st["kernel_pairs"]), "in_ball_pairs": nbr}}
+                         "ops_per_unit": ops_full_in_ball(m) + 18, "unit_of_work": "pair inside the 0.4 m ball",
+                         "units_per_launch": nbr, "frac_tight_count": tight / kernel_s / PEAK_VALU,
+                         "evaluated_pairs": int(st["kernel_pairs"])}}
 
 
 def paper_context(cs, eng):
@@ -394,85 +431,230 @@ def paper_context(cs, eng):
     return out
 
 
-def precision_form(cs, eng):
-    """Labels of the 4M-Gaussian x 262,144-sphere grid workload: float32 pair
-    kernel vs the bf16 / fp16 MFMA forms (certified, rechecked in fp64)."""
+def _timed(cs, eng, h, c, r, opts, want, reps=5):
+    """Mean wall time per evaluation (after one warm-up) and the statistics
+    of one more with the kernel timing on."""
     import torch
-    from workloads import config
-    log("bench: precision form (4M Gaussians x 262,144 grid spheres, labels)")
+    out = eng.alloc_outputs(c.shape[0], want)
+    eng.evaluate(h, c, r, opts, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        eng.evaluate(h, c, r, opts, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    cs.csplat_ctx_set_timing(eng.ctx, True)
+    eng.evaluate(h, c, r, opts, out=out)
+    st = cs.csplat_last_stats(eng.ctx)
+    rk = cs.csplat_last_rechecked(eng.ctx)
+    cs.csplat_ctx_set_timing(eng.ctx, False)
+    torch.cuda.synchronize()
+    return dt, st, rk, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def precision_form(cs, eng, cpu_baseline_on):
+    """The 4M-Gaussian x 262,144-sphere grid workload (and its stress variant,
+    half the points near a surface): labels, and labels plus the hard minimum,
+    in fp32, bf16 and fp16; rooflines of the float32 label kernel and the MFMA
+    kernel; accuracy against the FP64 oracle on 1,024 seeded queries per
+    radius class plus every query a precision form rechecked."""
+    import torch
+    import oracle
+    from workloads import config, grid_queries
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import compare
+    log("bench: precision form (4M Gaussians x 262,144 grid spheres)")
     sc, qs, p = config("precision")
     h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"],
                        precision_features=cs.CSPLAT_FEATURES_BF16 | cs.CSPLAT_FEATURES_FP16)
     n_kept, nbytes = cs.csplat_scene_info(h)
     eng.set_conservatism(p["n_sigma"])
-    c = torch.from_numpy(qs.centers).cuda()
-    r = torch.from_numpy(qs.radii).cuda()
     out = {"workload": "precision: 4M-Gaussian room scene, 64^3 grid spheres in 4 radius classes "
-                       "{0.05,0.1,0.2,0.4} m, n_sigma 1, k=2, labels", "n_kept": int(n_kept),
-           "queries": int(qs.q), "scene_bytes_with_features": int(nbytes)}
-    labels = {}
-    for name, prec in (("fp32", cs.CSPLAT_PRECISION_FP32), ("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK),
-                       ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK)):
-        opts = cs.reduce_opts(k=p["k"], r_nbr=math.inf, precision=prec)
-        dt, res = _time_eval(eng, h, c, r, opts, ("label",))
-        cs.csplat_ctx_set_timing(eng.ctx, True)
-        eng.evaluate(h, c, r, opts, want=("label",))
-        st = cs.csplat_last_stats(eng.ctx)
-        cs.csplat_ctx_set_timing(eng.ctx, False)
-        labels[name] = res["label"][:, 0]
-        flagged = int(st["flagged"])
-        per_class = {}
-        if prec != cs.CSPLAT_PRECISION_FP32:
-            per_class = {"rechecked_fraction": flagged / qs.q}
-        if prec == cs.CSPLAT_PRECISION_FP32:
-            per_class = {"evaluated_pairs": int(st["kernel_pairs"])}
-        out[name] = {"ms": dt * 1e3, "pair_evals_per_s": qs.q * n_kept / dt, "kernel_ms": st["kernel_ms"],
-                     "rechecked_queries": flagged, **per_class}
-        log(f"bench: precision {name}: {dt*1e3:.1f} ms")
-    for name in ("bf16", "fp16"):
-        out[name]["label_disagreements_vs_fp32"] = int((labels[name] != labels["fp32"]).sum())
-        out[name]["speedup_vs_fp32"] = out["fp32"]["ms"] / out[name]["ms"]
-    # the certified-bound flag rate per radius class (one extra launch per dtype
-    # with counts off: the decide step lists the undecided queries)
+                       "{0.05,0.1,0.2,0.4} m, n_sigma 1, k=2; labels, and labels plus the hard minimum",
+           "n_kept": int(n_kept), "queries": int(qs.q), "scene_bytes_with_features": int(nbytes)}
+    dtypes = (("fp32", cs.CSPLAT_PRECISION_FP32), ("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK),
+              ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK))
     radii = np.unique(qs.radii)
-    for name, prec in (("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK), ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK)):
-        cls = {}
-        for rv in radii:
-            sel = np.nonzero(qs.radii == rv)[0]
-            cc, rr = c[torch.from_numpy(sel).cuda()], r[torch.from_numpy(sel).cuda()]
-            eng.evaluate(h, cc.contiguous(), rr.contiguous(), cs.reduce_opts(k=p["k"], r_nbr=math.inf, precision=prec),
-                         want=("label",))
-            torch.cuda.synchronize()
-            cls[f"r={rv:.2f}"] = cs.csplat_last_stats(eng.ctx)["flagged"] / sel.size
-        out[name]["rechecked_fraction_per_radius_class"] = cls
+
+    def run_set(queries, tag):
+        c = torch.from_numpy(queries.centers).cuda()
+        r = torch.from_numpy(queries.radii).cuda()
+        res, lab, mins, rk_all = {}, {}, {}, []
+        for name, prec in dtypes:
+            opts = cs.reduce_opts(k=p["k"], r_nbr=math.inf, precision=prec)
+            dt, st, rk, o = _timed(cs, eng, h, c, r, opts, ("label",))
+            d = {"labels_ms": dt * 1e3, "labels_kernel_ms": st["kernel_ms"], "rechecked_queries": int(rk.size),
+                 "rechecked_fraction_per_radius_class":
+                     {f"r={rv:.2f}": float(np.isin(rk, np.nonzero(queries.radii == rv)[0]).sum() /
+                                           max(1, (queries.radii == rv).sum())) for rv in radii}}
+            k_s = st["kernel_ms"] / 1e3
+            if prec == cs.CSPLAT_PRECISION_FP32:
+                ev = int(st["kernel_pairs"])
+                d["labels_roofline"] = {"bound": "alu", "kernel": "pair_task_kernel<1,labels,cull>",
+                                        "ops_per_unit": ops_labels(1), "unit_of_work": "evaluated pair",
+                                        "units_per_launch": ev, "achieved": ops_labels(1) * ev / k_s / 1e9,
+                                        "peak": PEAK_VALU / 1e9, "unit": "Gop/s",
+                                        "frac": ops_labels(1) * ev / k_s / PEAK_VALU, "kernel_ms": k_s * 1e3}
+            else:
+                blocks = int(st["kernel_pairs"]) // 1024
+                bp = blocks * 1024
+                d["labels_roofline"] = {"bound": "alu", "kernel": f"mfma_label_kernel<{name}>",
+                                        "unit_of_work": "pair of an evaluated 32x32 block", "units_per_launch": bp,
+                                        "blocks": blocks, "ops_per_unit": OPS_MFMA_EPILOGUE,
+                                        "achieved": OPS_MFMA_EPILOGUE * bp / k_s / 1e9, "peak": PEAK_VALU / 1e9,
+                                        "unit": "Gop/s", "frac": OPS_MFMA_EPILOGUE * bp / k_s / PEAK_VALU,
+                                        "mfma_tflops": FLOP_MFMA_PAIR * bp / k_s / 1e12,
+                                        "mfma_frac": FLOP_MFMA_PAIR * bp / k_s / PEAK_MFMA_BF16, "kernel_ms": k_s * 1e3}
+                rk_all.append(rk)
+            lab[name] = o["label"]
+            want = ("label", "min") + (("err",) if prec != cs.CSPLAT_PRECISION_FP32 else ())
+            dt2, st2, _, o2 = _timed(cs, eng, h, c, r, opts, want, reps=3)
+            d.update({"labels_min_ms": dt2 * 1e3, "labels_min_kernel_ms": st2["kernel_ms"],
+                      "min_passes": int(st2["min_passes"])})
+            mins[name] = o2
+            res[name] = d
+            log(f"bench: precision {tag} {name}: labels {dt * 1e3:.2f} ms, labels+min {dt2 * 1e3:.2f} ms")
+        for name in ("bf16", "fp16"):
+            res[name]["labels_speedup_vs_fp32"] = res["fp32"]["labels_ms"] / res[name]["labels_ms"]
+            res[name]["labels_min_speedup_vs_fp32"] = res["fp32"]["labels_min_ms"] / res[name]["labels_min_ms"]
+        return res, lab, mins, rk_all
+
+    def accuracy(queries, lab, mins, rk_all, per_class, seed, max_rechecked=None):
+        rng = np.random.default_rng(seed)
+        idx = [rng.choice(np.nonzero(queries.radii == rv)[0], per_class, replace=False) for rv in radii]
+        rk = np.unique(np.concatenate(rk_all)) if rk_all else np.zeros(0, np.int64)
+        if max_rechecked is not None and rk.size > max_rechecked:
+            rk = np.sort(rng.choice(rk, max_rechecked, replace=False))
+        idx = np.unique(np.concatenate(idx + [rk]))
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        oracle.build(force=False)
+        _, mu, sig = oracle.prepare_scene(sc.means, sc.quats, sc.scales, sc.opacity,
+                                          alpha_f=p["alpha_f"], extent_f=p["extent_f"])
+        sub = queries.subset(idx)
+        t0 = time.perf_counter()
+        ref = oracle.evaluate(mu, sig, sub.centers, oracle.sphere_bodies(sub.radii), p["n_sigma"], k=p["k"],
+                              nthreads=threads)
+        o_s = time.perf_counter() - t0
+        amb = ref["ambiguous"][:, 0].astype(bool)
+        acc = {"sample_queries": int(idx.size), "ambiguous_queries": int(amb.sum()),
+               "sample": f"{per_class} seeded queries per radius class plus {rk.size} of the "
+                         f"{sum(x.size for x in rk_all)} queries the precision forms rechecked"}
+        fin = np.isfinite(ref["min"][:, 0])
+        for name in lab:
+            flips = lab[name][idx, 0] != ref["label"][:, 0]
+            g = mins[name]["min"][idx, 0].astype(np.float64)
+            e = np.abs(g[fin] - ref["min"][fin, 0])
+            rel = e / np.maximum(1.0, np.abs(ref["min"][fin, 0]))
+            a = {"label_flips_outside_eps_band": int((flips & ~amb).sum()),
+                 "label_flips_inside_eps_band": int((flips & amb).sum()),
+                 "labels_min_label_flips_outside_eps_band": int(((mins[name]["label"][idx, 0] != ref["label"][:, 0])
+                                                                  & ~amb).sum()),
+                 "min_abs_error_max": float(e.max(initial=0)), "min_abs_error_p99": float(np.percentile(e, 99)),
+                 "min_rel_error_max": float(rel.max(initial=0)), "min_rel_error_p99": float(np.percentile(rel, 99))}
+            if "err" in mins[name]:
+                eb = mins[name]["err"][idx, 0].astype(np.float64)[fin]
+                a["min_outside_certified_err"] = int((e > eb).sum())
+                a["certified_err_p50"] = float(np.median(eb))
+                a["certified_err_p99"] = float(np.percentile(eb, 99))
+            else:
+                st_ = compare({"min": mins[name]["min"][idx]}, ref, tau=0.0, gamma=1.0, where="bench-precision")
+                a["min_within_tolerance"] = True
+                a.update(st_)
+            acc[name] = a
+        cpu = {"value": idx.size * n_kept / o_s, "unit": "pair evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"{idx.size} of {queries.q} queries against all {n_kept} kept Gaussians, labels and min, FP64",
+               "seconds": o_s, "queries_per_s": idx.size / o_s}
+        return acc, cpu
+
+    res, lab, mins, rk_all = run_set(qs, "grid")
+    out.update(res)
+    out["accuracy_vs_oracle"], cpu = accuracy(qs, lab, mins, rk_all, 1024, 4)
+    if cpu_baseline_on:
+        out["cpu_baseline"] = cpu
+    log("bench: precision stress variant (half the points near a surface)")
+    qs2 = grid_queries(64, stress_scene=sc, seed=104)
+    res2, lab2, mins2, rk2 = run_set(qs2, "stress")
+    acc2, _ = accuracy(qs2, lab2, mins2, rk2, 256, 5, max_rechecked=2048)
+    out["stress"] = {"workload": "stress: half of the 64^3 grid points replaced by points at 0.5-1.5 r from a mean",
+                     **res2, "accuracy_vs_oracle": acc2}
     cs.csplat_scene_free(h)
     return out
 
 
-def serving(cs, eng, sc_nav, h_nav, n_requests, full):
+def precision_kernels(cs, eng):
+    """Config 4's kernels alone, for profiling: labels in fp32, bf16 and fp16
+    (three evaluations each), then labels plus the minimum in fp32 and bf16
+    (one each)."""
+    import torch
+    from workloads import config
+    sc, qs, p = config("precision")
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"],
+                       precision_features=cs.CSPLAT_FEATURES_BF16 | cs.CSPLAT_FEATURES_FP16)
+    eng.set_conservatism(p["n_sigma"])
+    c = torch.from_numpy(qs.centers).cuda()
+    r = torch.from_numpy(qs.radii).cuda()
+    res = {}
+    for name, prec in (("fp32", cs.CSPLAT_PRECISION_FP32), ("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK),
+                       ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK)):
+        opts = cs.reduce_opts(k=p["k"], r_nbr=math.inf, precision=prec)
+        dt, st, _, _ = _timed(cs, eng, h, c, r, opts, ("label",), reps=3)
+        res[name] = {"labels_ms": dt * 1e3, "kernel_ms": st["kernel_ms"], "kernel_pairs": st["kernel_pairs"]}
+        if name != "fp16":
+            want = ("label", "min") + (("err",) if name != "fp32" else ())
+            dt2, st2, _, _ = _timed(cs, eng, h, c, r, opts, want, reps=1)
+            res[name].update({"labels_min_ms": dt2 * 1e3, "labels_min_kernel_ms": st2["kernel_ms"]})
+    cs.csplat_scene_free(h)
+    return res
+
+
+def tiny(cs, eng, steps):
+    """The plain tiny configuration: 10,000 Gaussians in a 4 x 4 x 2 m box x
+    4,096 spheres (r = 0.1), n_sigma 1, every output over every Gaussian."""
+    import torch
+    from workloads import config
+    sc, qs, p = config("tiny")
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
+    n_kept, _ = cs.csplat_scene_info(h)
+    eng.set_conservatism(p["n_sigma"])
+    opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=math.inf, d_max=p["d_max"], gamma=p["gamma"],
+                          s_min=p["s_min"])
+    c = torch.from_numpy(qs.centers).cuda()
+    r = torch.from_numpy(qs.radii).cuda()
+    dt, st, _, _ = _timed(cs, eng, h, c, r, opts, ("label", "count", "min", "softmin", "cost", "nbr"),
+                          reps=max(10, steps))
+    cs.csplat_scene_free(h)
+    return {"workload": "tiny: 10k Gaussians uniform in 4x4x2 m, 4,096 spheres r = 0.1 m, n_sigma 1, all outputs",
+            "n_kept": int(n_kept), "queries": int(qs.q), "ms_per_step": dt * 1e3,
+            "pair_evals_per_s": qs.q * n_kept / dt, "queries_per_s": qs.q / dt, "kernel_ms": st["kernel_ms"]}
+
+
+def serving(cs, eng, sc_nav, h_nav, n_requests, reduced):
     """The serving form with the 1M (navigation) and 4M (room) scenes resident:
-    a Poisson stream mixing MPPI batches and RRT edge checks.  The saturated
-    request rate is measured first (all requests at once); the stream then
-    arrives at half that rate and p50/p99 latency is reported."""
+    a Poisson stream mixing MPPI batches (K in {256..4096} x 32 steps x 1-48
+    spheres) and RRT edge checks (1-10,000 points x 1-48 spheres).  The
+    saturated request rate is measured first (every request at t = 0); the
+    same stream then arrives at half that rate.  Latency is reported from the
+    library's submit entry to results in host memory, and from each request's
+    scheduled arrival to the moment a client thread collected it."""
+    import threading
     from workloads import config, serving_stream
     log("bench: serving (1M + 4M resident scenes)")
     sc4, _, p4 = config("precision")
     h4 = eng.load_scene(sc4, floater_opacity_max=p4["alpha_f"], floater_extent_min=p4["extent_f"])
-    kw = dict(max_mppi_k=4096, max_rrt_points=10000, max_spheres=48) if full else \
-        dict(max_mppi_k=512, max_rrt_points=4000, max_spheres=8)
+    kw = dict(max_mppi_k=512, max_rrt_points=4000, max_spheres=8) if reduced else \
+        dict(max_mppi_k=4096, max_rrt_points=10000, max_spheres=48)
     mppi_opts = cs.reduce_opts(k=2, tau=0.1, r_nbr=1.0, d_max=1.0, gamma=1.0, s_min=1.0)
     rrt_opts = cs.reduce_opts(k=2, r_nbr=math.inf)
     n_scene = [cs.csplat_scene_info(h_nav)[0], cs.csplat_scene_info(h4)[0]]
 
-    def run(reqs, rate_scale):
+    def run(reqs, rate):
         # one thread submits at the arrival times, another collects finished
         # requests as they complete (a finished request holds its output
         # staging until it is collected)
-        import threading
         srv = cs.csplat_server_create(0, 4 << 30, 16)
         ids = [cs.csplat_server_add_scene(srv, h_nav), cs.csplat_server_add_scene(srv, h4)]
         pending, lock, submitted = {}, threading.Lock(), threading.Event()
-        n_done = [0]
+        arrival_lat = {}
 
         def collect():
             last = time.perf_counter()
@@ -481,34 +663,37 @@ def serving(cs, eng, sc_nav, h_nav, n_requests, full):
                     items = list(pending.items())
                 if not items and submitted.is_set():
                     return
-                for t, (kind, q) in items:
+                for t, (kind, q, t_arr, i) in items:
                     if cs.csplat_server_poll(srv, t, q, kind) is not None:
+                        arrival_lat[i] = time.perf_counter() - t_arr
                         with lock:
                             del pending[t]
-                        n_done[0] += 1
                 if time.perf_counter() - last > 10.0:
                     last = time.perf_counter()
-                    log(f"bench: serving: {n_done[0]} of {len(reqs)} requests collected")
-                time.sleep(0.002)
+                    log(f"bench: serving: {len(arrival_lat)} of {len(reqs)} requests collected")
+                time.sleep(0.001)
 
         th = threading.Thread(target=collect)
         t0 = time.perf_counter()
         th.start()
-        for rq in reqs:
-            while rate_scale and time.perf_counter() - t0 < rq["t"] * rate_scale:
+        for i, rq in enumerate(reqs):
+            t_arr = t0 + (rq["t"] / rate if rate else 0.0)
+            while time.perf_counter() < t_arr:
                 time.sleep(0.0002)
             kind = cs.CSPLAT_SERVE_COST if rq["kind"] == "mppi" else cs.CSPLAT_SERVE_LABELS
             t = cs.csplat_server_submit(srv, ids[rq["scene"]], kind, rq["centers"], rq["radii"],
                                         mppi_opts if kind == 0 else rrt_opts, rq["n_sigma"])
             with lock:
-                pending[t] = (kind, rq["centers"].shape[0])
+                pending[t] = (kind, rq["centers"].shape[0], t_arr, i)
+        t_last_submit = time.perf_counter() - t0
         submitted.set()
         th.join()
         wall = time.perf_counter() - t0
         st = cs.csplat_server_stats(srv)
         lat = cs.csplat_server_latencies(srv)
         cs.csplat_server_destroy(srv)
-        return st, wall, lat
+        arr = np.array([arrival_lat[i] for i in range(len(reqs))]) * 1e3
+        return st, wall, lat, arr, t_last_submit
 
     def boot_ci(x, q, n=2000):
         # percentile bootstrap: resample the requests' latencies with replacement
@@ -517,22 +702,35 @@ def serving(cs, eng, sc_nav, h_nav, n_requests, full):
         return [float(np.percentile(v, 2.5)), float(np.percentile(v, 97.5))]
 
     log(f"bench: serving: generating {n_requests} requests")
-    reqs = serving_stream(n_requests, seed=105, rate_hz=1.0, **kw)
-    pairs = sum(rq["centers"].shape[0] * n_scene[rq["scene"]] for rq in reqs)
-    sat, wall, _ = run(reqs, 0)        # saturated: every request at t = 0
+    reqs = serving_stream(n_requests, seed=105, rate_hz=1.0, **kw)   # unit-rate arrival times, scaled below
+    sizes = np.array([rq["centers"].shape[0] for rq in reqs])
+    pairs = sum(int(sz) * n_scene[rq["scene"]] for sz, rq in zip(sizes, reqs))
+    sat, wall, _, _, _ = run(reqs, 0)        # saturated: every request at t = 0
     sat_rate = len(reqs) / wall
     lam = 0.5 * sat_rate
-    reqs2 = serving_stream(n_requests, seed=105, rate_hz=lam, **kw)
-    st, wall2, lat = run(reqs2, 1.0)
+    log(f"bench: serving: saturated {sat_rate:.1f} requests/s; stream at {lam:.1f} requests/s")
+    st, wall2, lat, arr, t_sub = run(reqs, lam)
     cs.csplat_scene_free(h4)
-    return {"workload": ("full" if full else "reduced") + " serving law: 1M and 4M room scenes resident, "
-            f"{n_requests} requests (MPPI K<={kw['max_mppi_k']} x 32 x <= {kw['max_spheres']} spheres, "
-            f"RRT <= {kw['max_rrt_points']} points x <= {kw['max_spheres']} spheres), HBM budget 4 GiB, 16 slots",
+    small = sizes < 100_000
+    by_class = {}
+    for name, sel in (("under_100k_spheres", small), ("100k_to_1M", (sizes >= 100_000) & (sizes < 1_000_000)),
+                      ("1M_and_more", sizes >= 1_000_000)):
+        if sel.any():
+            by_class[name] = {"requests": int(sel.sum()), "p50_ms": float(np.percentile(arr[sel], 50)),
+                              "p99_ms": float(np.percentile(arr[sel], 99))}
+    return {"workload": ("reduced" if reduced else "config-5") + " serving law: 1M and 4M room scenes resident, "
+            f"{n_requests} Poisson requests (MPPI K in {{256..{kw['max_mppi_k']}}} x 32 x 1-{kw['max_spheres']} "
+            f"spheres, RRT 1-{kw['max_rrt_points']} points x 1-{kw['max_spheres']} spheres), HBM budget 4 GiB, "
+            "16 slots",
+            "spheres_total": int(sizes.sum()), "largest_request_spheres": int(sizes.max()),
             "saturated_requests_per_s": sat_rate, "saturated_pair_evals_per_s": pairs / wall,
-            "rate_requests_per_s": lam, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-            "p50_ci95_ms": boot_ci(lat, 50), "p99_ci95_ms": boot_ci(lat, 99), "mean_ms": st["mean_ms"],
-            "max_ms": st["max_ms"], "pair_evals_per_s": st["pairs_per_s"], "steps": st["steps"],
-            "completed": st["completed"]}
+            "rate_requests_per_s": lam, "achieved_rate_requests_per_s": len(reqs) / max(t_sub, 1e-9),
+            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "p50_ci95_ms": boot_ci(lat, 50),
+            "p99_ci95_ms": boot_ci(lat, 99), "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+            "from_arrival": {"p50_ms": float(np.percentile(arr, 50)), "p99_ms": float(np.percentile(arr, 99)),
+                             "p50_ci95_ms": boot_ci(arr, 50), "p99_ci95_ms": boot_ci(arr, 99)},
+            "from_arrival_by_size": by_class,
+            "pair_evals_per_s": st["pairs_per_s"], "steps": st["steps"], "completed": st["completed"]}
 
 
 def cpu_baseline(sc, qs, p, gpu, target_s, n_kept):

@@ -286,6 +286,8 @@ typedef struct {
     double mean_ms, max_ms;
     double pairs_per_s;       /* Q x N_kept of completed requests / serving wall time */
     double busy_s;            /* first admission to last completion */
+    int64_t shared_steps;     /* steps that evaluated work items of two or more requests */
+    int32_t max_requests_per_step;
 } csplat_serving_stats;
 
 /* Create a server on `device` with `hbm_budget` bytes of device arena (and as
@@ -327,6 +329,14 @@ csplat_status csplat_server_stats(csplat_server *srv, csplat_serving_stats *stat
  * number of completed requests.  CSPLAT_E_INVALID for a NULL server or n, or
  * cap < 0. */
 csplat_status csplat_server_latencies(csplat_server *srv, double *ms, int64_t cap, int64_t *n);
+
+/* Precision forms: the queries of the last evaluation (its last conservatism
+ * value) whose label the certified bound left undecided and which were
+ * rechecked in fp64, as indices into the caller's query array in sorted
+ * (curve) order.  Copies min(cap, count) indices into `idx` (host memory of
+ * the caller; NULL when cap is 0) and sets *n to the count (0 after a float32
+ * evaluation).  Synchronises the context's stream. */
+csplat_status csplat_last_rechecked(csplat_ctx *ctx, int32_t *idx, int64_t cap, int64_t *n);
 
 /* Wait for all work queued on the context's stream. */
 csplat_status csplat_synchronize(csplat_ctx *ctx);

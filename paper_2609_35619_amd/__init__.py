@@ -46,7 +46,7 @@ EXPORTS = (
     "csplat_eval_distance", "csplat_eval_ellipsoids", "csplat_ply_read", "csplat_scene_load_ply", "csplat_segment_reduce", "csplat_ctx_set_timing", "csplat_last_stats", "csplat_synchronize",
     "csplat_last_error", "csplat_server_create", "csplat_server_destroy", "csplat_server_add_scene",
     "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
-    "csplat_server_stats", "csplat_server_latencies", "csplat_eval_noalloc",
+    "csplat_server_stats", "csplat_server_latencies", "csplat_eval_noalloc", "csplat_last_rechecked",
 )
 CSPLAT_SERVE_COST = 0
 CSPLAT_SERVE_LABELS = 1
@@ -88,7 +88,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("cancelled", ctypes.c_int64), ("refused", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
-                ("max_ms", ctypes.c_double), ("pairs_per_s", ctypes.c_double), ("busy_s", ctypes.c_double)]
+                ("max_ms", ctypes.c_double), ("pairs_per_s", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("shared_steps", ctypes.c_int64), ("max_requests_per_step", ctypes.c_int32)]
 
 
 _lib = None
@@ -105,6 +106,12 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise CsplatError(-1, f"{path} is missing: build it with paper_2609_35619_amd/build.py")
+    # torch first: its HIP runtime must be the one the library binds to (a
+    # runtime loaded by the library first makes torch's kernels unlaunchable)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     sig = {
@@ -124,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         "csplat_segment_reduce": [P, I64, I32, I64, P, P, P, P, P],
         "csplat_ctx_set_timing": [P, I32],
         "csplat_last_stats": [P, P],
+        "csplat_last_rechecked": [P, P, I64, P],
         "csplat_synchronize": [P],
         "csplat_server_create": [I32, ctypes.c_uint64, I32, P],
         "csplat_server_destroy": [P],
@@ -301,6 +309,17 @@ def csplat_last_stats(ctx) -> dict:
     st = EvalStats()
     _check(load_library().csplat_last_stats(ctx, ctypes.byref(st)))
     return {k: getattr(st, k) for k, _ in EvalStats._fields_}
+
+
+def csplat_last_rechecked(ctx) -> np.ndarray:
+    """Indices (caller order) of the queries the last precision-form
+    evaluation rechecked in fp64."""
+    lib = load_library()
+    n = ctypes.c_int64(0)
+    _check(lib.csplat_last_rechecked(ctx, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(int(n.value), 1), np.int32)
+    _check(lib.csplat_last_rechecked(ctx, out.ctypes.data_as(ctypes.c_void_p), int(n.value), ctypes.byref(n)))
+    return out[:int(n.value)].copy()
 
 
 def csplat_synchronize(ctx):

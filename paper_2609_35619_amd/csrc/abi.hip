@@ -371,6 +371,8 @@ void reset_stats(csplat_ctx *ctx, int64_t q, const csplat_scene *sc)
     ctx->flag_counts = nullptr;
     ctx->flag_m = 0;
     ctx->chunk_counter = nullptr;
+    ctx->rk_list = ctx->rk_n = ctx->rk_perm = nullptr;
+    ctx->rk_q = 0;
 }
 
 }  // namespace
@@ -717,6 +719,30 @@ csplat_status csplat_last_stats(csplat_ctx *ctx, csplat_eval_stats *stats)
         CSPLAT_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         stats->kernel_ms = ms;
     }
+    return CSPLAT_OK;
+}
+
+csplat_status csplat_last_rechecked(csplat_ctx *ctx, int32_t *idx, int64_t cap, int64_t *n)
+{
+    if (!ctx || !n || cap < 0 || (cap > 0 && !idx)) return fail(CSPLAT_E_INVALID, "last_rechecked: bad argument");
+    *n = 0;
+    if (!ctx->rk_list) return CSPLAT_OK;
+    DeviceGuard g(ctx->device);
+    int32_t nl = 0;
+    CSPLAT_HIP(hipMemcpyAsync(&nl, ctx->rk_n, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    CSPLAT_HIP(hipStreamSynchronize(ctx->stream));
+    *n = nl;
+    const int64_t k = std::min<int64_t>(cap, nl);
+    if (k == 0) return CSPLAT_OK;
+    std::vector<int32_t> list((size_t)k), perm;
+    CSPLAT_HIP(hipMemcpyAsync(list.data(), ctx->rk_list, (size_t)k * 4, hipMemcpyDeviceToHost, ctx->stream));
+    if (ctx->rk_perm) {
+        perm.resize((size_t)ctx->rk_q);
+        CSPLAT_HIP(hipMemcpyAsync(perm.data(), ctx->rk_perm, (size_t)ctx->rk_q * 4, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+    }
+    CSPLAT_HIP(hipStreamSynchronize(ctx->stream));
+    for (int64_t i = 0; i < k; ++i) idx[i] = ctx->rk_perm ? perm[(size_t)list[(size_t)i]] : list[(size_t)i];
     return CSPLAT_OK;
 }
 

@@ -171,6 +171,10 @@ struct csplat_ctx {
     bool timed = false;         // events of the last evaluation were recorded
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float timed_ms = -1.f;      // >= 0: the dominant kernel's time summed over several launches
+    // precision forms: the last value's recheck list (sorted indices), its
+    // length and the sort permutation, all device memory of the workspace
+    const int32_t *rk_list = nullptr, *rk_n = nullptr, *rk_perm = nullptr;
+    int64_t rk_q = 0;
     int *check_host = nullptr;      // pinned: the device-side input check's flag
     int *check_dev = nullptr;       // its device address
     bool check_pending = false;     // a check is queued and not yet waited for

@@ -1723,25 +1723,31 @@ min_gather_kernel(int nl, const int32_t *__restrict__ list, const float *__restr
     rr[i] = r;
 }
 
-// After pass k > 1: the listed queries' minima and flags.
+// After pass k > 1: the listed queries' minima and flags.  A later pass has
+// few queries and many splits: one wave per listed query, its lanes striding
+// over the splits (a minimum: any order).
 template <int M>
 __global__ void __launch_bounds__(256)
 min_next_combine_kernel(int nl, int S, Part part, const int32_t *__restrict__ list, const float *__restrict__ radii,
                         const float *__restrict__ st_thr, float *__restrict__ st_mt, uint8_t *__restrict__ flag)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nl) return;
+    const int i = (int)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = (int)(threadIdx.x & 63u);
+    if (i >= nl) return;  // wave-uniform
     const int j = list[i];
     const float r = radii[j], lim = r * r * st_thr[j] * kMinResolve;
     bool unresolved = false;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        float mt = st_mt[(size_t)j * M + v];
-        for (int s = 0; s < S; ++s) mt = fminf(mt, part.mt[((size_t)s * M + v) * nl + i]);
-        st_mt[(size_t)j * M + v] = mt;
+        float mt = INFINITY;
+        for (int s = lane; s < S; s += 64) mt = fminf(mt, part.mt[((size_t)s * M + v) * nl + i]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mt = fminf(mt, __shfl_xor(mt, off));
+        mt = fminf(mt, st_mt[(size_t)j * M + v]);
+        if (lane == 0) st_mt[(size_t)j * M + v] = mt;
         unresolved |= !(mt < lim);
     }
-    flag[j] = unresolved ? 1 : 0;
+    if (lane == 0) flag[j] = unresolved ? 1 : 0;
 }
 
 // The minima in s~^2 units at row perm[j].

@@ -358,7 +358,8 @@ csplat_status min_search(csplat_ctx *ctx, const csplat_scene *sc, int q, const f
         if (s != CSPLAT_OK) return s;
         s = pass_ms();
         if (s != CSPLAT_OK) return s;
-        min_next_combine_kernel<M><<<lb, 256, 0, st>>>(nl, S, part, list, r, st_thr, st_mt, flag);
+        min_next_combine_kernel<M><<<(unsigned)((nl + 3) / 4), 256, 0, st>>>(nl, S, part, list, r, st_thr, st_mt,
+                                                                            flag);
         CSPLAT_HIP(hipGetLastError());
     }
     min_output_kernel<M><<<qb, 256, 0, st>>>(q, p.m, r, perm, st_mt, out.min);

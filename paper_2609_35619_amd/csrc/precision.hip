@@ -242,7 +242,9 @@ template <int P>
 struct QFeat {
     typename Prec<P>::vec a, w0, w1;
     float two_ea, c0;
-    float ec;  // certified bound of |a - a~| + |sqrt(w) - sqrt(w~)| (the minimum's epilogue)
+    // the minimum's epilogue: bounds of |a - a~| and of |w - w~| (inflated for
+    // their own rounding) and sqrt of the latter
+    float ea, ew, sew;
 };
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -328,8 +330,7 @@ __device__ __forceinline__ bool build_query(float cx, float cy, float cz, float 
     const float ea = 1.1f * (ue * sa + T::eta * sa_abs + 4.f * kU32 * (c2 + r2));
     const float ew = 1.1f * (ue * sw + T::eta * sw_abs);
     const float two_ea = 2.f * ea, c0 = fmaf(ea, ea, ew) * 1.0001f;
-    // |sqrt(x) - sqrt(y)| <= sqrt(|x - y|) for x, y >= 0
-    const float ec = (ea + sqrtf(ew)) * 1.0001f;
+
     swap_halves(Q[0].a, Q[1].a);
     swap_halves(Q[0].w0, Q[1].w0);
     swap_halves(Q[0].w1, Q[1].w1);
@@ -338,10 +339,14 @@ __device__ __forceinline__ bool build_query(float cx, float cy, float cz, float 
     // column block 1's to the second
     Q[0].two_ea = Q[1].two_ea = two_ea;
     Q[0].c0 = Q[1].c0 = c0;
-    Q[0].ec = Q[1].ec = ec;
+    Q[0].ea = Q[1].ea = ea * 1.0001f;
+    Q[0].ew = Q[1].ew = ew * 1.0001f;
+    Q[0].sew = Q[1].sew = sqrtf(ew);
     swap_halves(Q[0].two_ea, Q[1].two_ea);
     swap_halves(Q[0].c0, Q[1].c0);
-    swap_halves(Q[0].ec, Q[1].ec);
+    swap_halves(Q[0].ea, Q[1].ea);
+    swap_halves(Q[0].ew, Q[1].ew);
+    swap_halves(Q[0].sew, Q[1].sew);
     return isfinite(two_ea) && isfinite(c0) && isfinite(sa) && isfinite(sw);
 }
 
@@ -366,10 +371,13 @@ constexpr int kQueriesPerBlock = 4 * 32 * kCB;
 
 // The minimum (MINW): per pair v~ = a~ - sqrt(max(w~, 0)), the computed value
 // of v = a - sqrt(w) = r^2 (s~^2 - 1) before the clamp, and a certified bound
-// e >= |v~ - v|: the contraction's bounds (ec) plus the float32 rounding of
-// the square root and the difference (8 u (|a~| + sqrt(w~)), generous).  The
-// lane keeps lo = min(v~ - e) and up = min(v~ + e), so the exact minimum over
-// the evaluated pairs lies in [lo, up].  With `thr` (per query; NULL: 1) the
+// e >= |v~ - v|: the contraction's bound E_a on a, E_w / max(sqrt(w~),
+// sqrt(E_w)) on the square root (for w~ >= E_w, |sqrt(w) - sqrt(w~)| <=
+// E_w / sqrt(w~); below, <= sqrt(E_w)), and the float32 rounding of the
+// square root and the difference (8 u (|a~| + sqrt(w~)), generous).  The lane
+// keeps the computed minimum m = min v~, lo = min(v~ - e) and
+// up = min(v~ + e): the exact minimum over the evaluated pairs lies in
+// [lo, up], and so does m.  With `thr` (per query; NULL: 1) the
 // reach is that of s~^2 < thr[j]: every pair below the threshold is
 // evaluated (the passes of the minimum search).  COUNT = false skips the
 // label counts.
@@ -405,9 +413,9 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         r2[cb] = r * r;
         qa[cb] = MINW && thr ? r2[cb] * thr[jj] : r2[cb];
     }
-    float mlo[kCB], mup[kCB];
+    float mlo[kCB], mup[kCB], mmv[kCB];
 #pragma unroll
-    for (int cb = 0; cb < kCB; ++cb) mlo[cb] = mup[cb] = INFINITY;
+    for (int cb = 0; cb < kCB; ++cb) mlo[cb] = mup[cb] = mmv[cb] = INFINITY;
     unsigned long long n_blocks = 0;
     int lo[kCB], hi[kCB];
     bool bad[kG];  // a non-finite bound for the lane's own query of column block pair g
@@ -475,13 +483,17 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
                     }
                 }
                 if constexpr (MINW) {
-                    const float ec = Q[cb].ec;
+                    const float ea = Q[cb].ea, ew = Q[cb].ew, sew = Q[cb].sew;
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
                         const float a = A[i];
                         const float sq = pair::fast_sqrt(fmaxf(W[i], 0.f));
                         const float v = a - sq;
-                        const float e = fmaf(fabsf(a) + sq, 8.f * kU32, ec);
+                        // v_rcp: ~1 ulp, covered by the 1.0001 of ew; the floor keeps
+                        // es = 0 (not 0 x inf) when E_w = 0 (n_sigma = 0)
+                        const float es = ew * __builtin_amdgcn_rcpf(fmaxf(fmaxf(sq, sew), 1e-30f));
+                        const float e = fmaf(fabsf(a) + sq, 8.f * kU32, ea + es);
+                        mmv[cb] = fminf(mmv[cb], v);
                         mlo[cb] = fminf(mlo[cb], v - e);
                         mup[cb] = fminf(mup[cb], v + e);
                     }
@@ -545,6 +557,7 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         hi[cb] += __shfl_xor(hi[cb], 32);
         mlo[cb] = fminf(mlo[cb], __shfl_xor(mlo[cb], 32));
         mup[cb] = fminf(mup[cb], __shfl_xor(mup[cb], 32));
+        mmv[cb] = fminf(mmv[cb], __shfl_xor(mmv[cb], 32));
         // the query of column block cb was built by the lanes of half cb & 1
         const int g = cb >> 1;
         const bool other = __shfl_xor((int)bad[g], 32) != 0;
@@ -558,6 +571,7 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
                 // a bound that is not finite leaves the interval open: (-inf, up]
                 mlo_out[(size_t)split * q + jq[cb]] = anybad ? -INFINITY : mlo[cb];
                 mup_out[(size_t)split * q + jq[cb]] = anybad ? INFINITY : mup[cb];
+                mlo_out[((size_t)S + split) * q + jq[cb]] = mmv[cb];  // the computed minimum after the bounds
             }
         }
     }
@@ -706,20 +720,32 @@ constexpr float kMinNextP = 1.00390625f;       // 1 + 2^-8
 __global__ void __launch_bounds__(256)
 pmin_combine_kernel(int nq, int S, const int32_t *__restrict__ list, const float *__restrict__ radii,
                     const float *__restrict__ mlo, const float *__restrict__ mup, float *__restrict__ st_lo,
-                    float *__restrict__ st_up, float *__restrict__ st_thr, uint8_t *__restrict__ flag, bool first)
+                    float *__restrict__ st_up, float *__restrict__ st_mv, float *__restrict__ st_thr,
+                    uint8_t *__restrict__ flag, bool first)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq) return;
+    // one wave per query, its lanes striding over the splits (minima: any order)
+    const int i = (int)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = (int)(threadIdx.x & 63u);
+    if (i >= nq) return;  // wave-uniform
     const int j = list ? list[i] : i;
-    float lo = INFINITY, up = INFINITY;
-    for (int s = 0; s < S; ++s) {
+    float lo = INFINITY, up = INFINITY, mv = INFINITY;
+    for (int s = lane; s < S; s += 64) {
         lo = fminf(lo, mlo[(size_t)s * nq + i]);
         up = fminf(up, mup[(size_t)s * nq + i]);
+        mv = fminf(mv, mlo[((size_t)S + s) * nq + i]);
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, off));
+        up = fminf(up, __shfl_xor(up, off));
+        mv = fminf(mv, __shfl_xor(mv, off));
+    }
+    if (lane != 0) return;
     if (first) st_thr[j] = 1.f;
     const float r = radii[j], r2 = r * r;
     st_lo[j] = lo;
     st_up[j] = up;
+    st_mv[j] = mv;
     // resolved: the exact minimum over the evaluated pairs (<= up + r^2) lies
     // below the threshold, so no skipped pair is lower
     flag[j] = lo == -INFINITY ? 2 : (up + r2 < r2 * st_thr[j] * kMinResolveP ? 0 : 1);
@@ -780,13 +806,15 @@ min_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restrict_
     }
 }
 
-// Results at row perm[j]: min = the middle of the clamped interval over r^2,
-// err = its half-width plus the float32 rounding of the additions and the
-// division; fp64 fallback queries (flag 2, listed in `list2` with `best`):
-// the fp64 minimum rounded to float32 (err: one float32 ulp of it).
+// Results at row perm[j]: min = the computed minimum (clamped) over r^2,
+// err = its distance to the farther end of the clamped certified interval
+// plus the float32 rounding of the additions and the division; fp64 fallback
+// queries (flag 2, listed in `list2` with `best`): the fp64 minimum rounded
+// to float32 (err: one float32 ulp of it).
 __global__ void __launch_bounds__(256)
 pmin_output_kernel(int q, int m, int v, const float *__restrict__ radii, const int32_t *__restrict__ perm,
-                   const float *__restrict__ st_lo, const float *__restrict__ st_up, const uint8_t *__restrict__ flag,
+                   const float *__restrict__ st_lo, const float *__restrict__ st_up,
+                   const float *__restrict__ st_mv, const uint8_t *__restrict__ flag,
                    const int32_t *__restrict__ slot, const unsigned long long *__restrict__ best, float *out_min,
                    float *out_err)
 {
@@ -799,12 +827,15 @@ pmin_output_kernel(int q, int m, int v, const float *__restrict__ radii, const i
         const double t = __longlong_as_double((long long)best[slot[j]]);
         mn = (float)(t / ((double)r * (double)r));
         err = 1.1920929e-07f * mn;  // 2^-23 |min|
+    } else if (!(st_up[j] < INFINITY)) {  // no Gaussian at all
+        mn = INFINITY;
+        err = 0.f;
     } else {
         const float tl = fmaxf(st_lo[j] + r2, 0.f), tu = fmaxf(st_up[j] + r2, 0.f);
-        const float mid = 0.5f * (tl + tu);
-        const float half = 0.5f * (tu - tl) + 4.f * kU32 * (fabsf(st_lo[j]) + fabsf(st_up[j]) + 2.f * r2);
-        mn = mid / r2;
-        err = half / r2 * 1.000001f + 2.f * kU32 * mn;
+        const float tm = fminf(fmaxf(st_mv[j] + r2, tl), tu);
+        const float dev = fmaxf(tm - tl, tu - tm) + 4.f * kU32 * (fabsf(st_lo[j]) + fabsf(st_up[j]) + 2.f * r2);
+        mn = tm / r2;
+        err = dev / r2 * 1.000001f + 2.f * kU32 * mn;
     }
     if (out_min) out_min[(size_t)oj * m + v] = mn;
     if (out_err) out_err[(size_t)oj * m + v] = err;
@@ -975,8 +1006,8 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
     const size_t o_lo = 0, o_up = o_lo + al(qn * 4), o_thr = o_up + al(qn * 4), o_mflag = o_thr + al(qn * 4),
                  o_mlist = o_mflag + al(qn), o_nl = o_mlist + al(qn * 4), o_cc = o_nl + 256, o_rr = o_cc + al(qn * 12),
                  o_tt = o_rr + al(qn * 4), o_slot = o_tt + al(qn * 4), o_best = o_slot + al(qn * 4),
-                 o_mlo = o_best + al(qn * 8), o_mup = o_mlo + al(mpart * 4), o_msel = o_mup + al(mpart * 4),
-                 m_total = o_msel + al(sel_bytes);
+                 o_mlo = o_best + al(qn * 8), o_mup = o_mlo + al(2 * mpart * 4), o_msel = o_mup + al(mpart * 4),
+                 o_mv = o_msel + al(sel_bytes), m_total = o_mv + al(qn * 4);
     char *mb = nullptr;
     if (want_min) {
         e = ctx->minbuf.reserve(m_total);
@@ -984,7 +1015,7 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
         mb = ctx->minbuf.as<char>();
     }
     float *st_lo = reinterpret_cast<float *>(mb + o_lo), *st_up = reinterpret_cast<float *>(mb + o_up),
-          *st_thr = reinterpret_cast<float *>(mb + o_thr);
+          *st_thr = reinterpret_cast<float *>(mb + o_thr), *st_mv = reinterpret_cast<float *>(mb + o_mv);
     uint8_t *mflag = reinterpret_cast<uint8_t *>(mb + o_mflag);
     int32_t *mlist = reinterpret_cast<int32_t *>(mb + o_mlist), *mnl = reinterpret_cast<int32_t *>(mb + o_nl),
             *slot = reinterpret_cast<int32_t *>(mb + o_slot);
@@ -1050,11 +1081,15 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
                     sc->gauss, n, cull ? sc->cull : nullptr, c, r, p.n_sigma[v], list, n_list + v, exact);
             finish_kernel<<<qb, 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, perm, out.label, out.count);
             CSPLAT_HIP(hipGetLastError());
+            ctx->rk_list = list;
+            ctx->rk_n = n_list + v;
+            ctx->rk_perm = perm;
+            ctx->rk_q = q;
         }
         if (!want_min) continue;
         // the minimum: later passes for the queries not yet resolved
-        pmin_combine_kernel<<<qb, 256, 0, st>>>(q, n_tiles > 0 ? S : 0, nullptr, r, mlo, mup, st_lo, st_up, st_thr,
-                                                mflag, true);
+        pmin_combine_kernel<<<(unsigned)((q + 3) / 4), 256, 0, st>>>(q, n_tiles > 0 ? S : 0, nullptr, r, mlo, mup,
+                                                                     st_lo, st_up, st_mv, st_thr, mflag, true);
         CSPLAT_HIP(hipGetLastError());
         int pass = 1;
         for (; n > 0; ++pass) {
@@ -1077,7 +1112,8 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
             CSPLAT_HIP(hipGetLastError());
             csplat_status ts = add_ms();
             if (ts != CSPLAT_OK) return ts;
-            pmin_combine_kernel<<<lb, 256, 0, st>>>(nl, S2, mlist, r, mlo, mup, st_lo, st_up, st_thr, mflag, false);
+            pmin_combine_kernel<<<(unsigned)((nl + 3) / 4), 256, 0, st>>>(nl, S2, mlist, r, mlo, mup, st_lo, st_up,
+                                                                          st_mv, st_thr, mflag, false);
             CSPLAT_HIP(hipGetLastError());
         }
         passes = std::max(passes, pass);
@@ -1089,7 +1125,8 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
         pmin_slot_kernel<<<qb, 256, 0, st>>>(mlist, mnl, slot);
         if (n > 0)
             min_fp64_kernel<<<kRecheckGrid, 64 * kRecheckWaves, 0, st>>>(sc->gauss, n, c, nv, mlist, mnl, best);
-        pmin_output_kernel<<<qb, 256, 0, st>>>(q, m, v, r, perm, st_lo, st_up, mflag, slot, best, out.min, out.err);
+        pmin_output_kernel<<<qb, 256, 0, st>>>(q, m, v, r, perm, st_lo, st_up, st_mv, mflag, slot, best, out.min,
+                                               out.err);
         CSPLAT_HIP(hipGetLastError());
     }
     ctx->stats.min_passes = want_min ? passes : 0;

@@ -310,6 +310,14 @@ void launch_step(csplat_server *s, const StepPlan &plan)
     }
     s->inflight.push_back({plan.step, k, plan.pairs >= s->sched->step_pairs()});
     ++s->st.steps;
+    // how many requests the step serves together (continuous batching)
+    int32_t reqs = 0;
+    std::vector<int32_t> seen;
+    for (const Item &it : plan.items)
+        if (std::find(seen.begin(), seen.end(), it.slot) == seen.end()) seen.push_back(it.slot);
+    reqs = (int32_t)seen.size();
+    if (reqs >= 2) ++s->st.shared_steps;
+    s->st.max_requests_per_step = std::max(s->st.max_requests_per_step, reqs);
 }
 
 void worker_main(csplat_server *s)

@@ -319,7 +319,7 @@ def test_invalid_inputs_are_rejected_without_writing(cs, eng):
 
 # --- full-size workloads in the launch configuration the benchmark times -------
 
-@pytest.mark.parametrize("name,sample", [("mppi_nav", 384), ("manip", 384), ("precision", 96)])
+@pytest.mark.parametrize("name,sample", [("mppi_nav", 1024), ("manip", 1024), ("precision", 96)])
 def test_full_size_sampled(cs, eng, oracle_mod, name, sample):
     import torch
     _say(f"case: full-size {name}, oracle on {sample} sampled queries")

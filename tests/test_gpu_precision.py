@@ -217,30 +217,42 @@ def test_precision_rejects_finite_ball(cs, eng):
     cs.csplat_scene_free(h)
 
 
-def test_precision_full_size_sampled(cs, eng, oracle_mod):
-    """4M Gaussians x 262,144 grid spheres: labels of both precision forms
-    equal the float32 path except on oracle-ambiguous queries; a seeded sample
-    is checked against the oracle."""
-    import torch
-    _say("case: full-size precision workload (4M x 262144)")
+@pytest.mark.parametrize("variant", ["grid", "stress"])
+def test_precision_full_size_against_oracle(cs, eng, oracle_mod, variant):
+    """4M Gaussians x 262,144 spheres (the 64^3 grid, or its stress variant with
+    half the points near a surface): labels and minima of fp32, bf16 and fp16,
+    each against the oracle on 1,024 seeded queries per radius class plus every
+    query a precision form rechecked in fp64."""
+    from workloads import grid_queries
+    _say(f"case: full-size precision workload (4M x 262144), {variant}")
     sc, qs, p = config("precision")
+    if variant == "stress":
+        qs = grid_queries(64, stress_scene=sc, seed=104)
     h = _load(cs, eng, sc, p)
-    res = {}
+    res, rechecked = {}, {}
     for name, prec in (("fp32", cs.CSPLAT_PRECISION_FP32), ("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK),
                        ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK)):
-        res[name], st = _eval(cs, eng, h, qs, p, prec, want=("label",))
-        _say(f"{name}: rechecked {st['flagged']} of {qs.q}")
+        want = ("label", "min") + (("err",) if name != "fp32" else ())
+        res[name], st = _eval(cs, eng, h, qs, p, prec, want=want)
+        if name != "fp32":
+            rechecked[name] = cs.csplat_last_rechecked(eng.ctx)
+        _say(f"{name}: rechecked {st['flagged']} of {qs.q}, min passes {st['min_passes']}")
     cs.csplat_scene_free(h)
-    idx = np.sort(np.random.default_rng(3).choice(qs.q, 96, replace=False))
-    diff = np.zeros(qs.q, bool)
-    for name in ("bf16", "fp16"):
-        diff |= (res[name]["label"] != res["fp32"]["label"])[:, 0]
-    idx = np.unique(np.concatenate([idx, np.nonzero(diff)[0][:64], [qs.q - 1]]))
+    rng = np.random.default_rng(4)
+    classes = np.unique(qs.radii)
+    idx = [rng.choice(np.nonzero(qs.radii == rc)[0], 1024, replace=False) for rc in classes]
+    idx = np.unique(np.concatenate(idx + list(rechecked.values()) + [[qs.q - 1]]))
+    _say(f"oracle on {idx.size} queries ({sum(v.size for v in rechecked.values())} rechecked)")
     ref = _oracle(oracle_mod, sc, qs.subset(idx), p)
-    for name in res:
-        compare({"label": res[name]["label"][idx]}, ref, tau=0.0, gamma=1.0, where=f"full-{name}")
-    assert diff.sum() <= 64, f"{diff.sum()} label disagreements between precision forms and float32"
-    del torch
+    compare({"label": res["fp32"]["label"][idx], "min": res["fp32"]["min"][idx]}, ref, tau=0.0, gamma=1.0,
+            where=f"full-fp32-{variant}")
+    for name in ("bf16", "fp16"):
+        compare({"label": res[name]["label"][idx]}, ref, tau=0.0, gamma=1.0, where=f"full-{name}-{variant}")
+        e = _min_err_check({k: v[idx] for k, v in res[name].items()}, ref, f"full-min-{name}-{variant}")
+        amb = ref["ambiguous"][:, 0].astype(bool)
+        flips = int(((res[name]["label"][idx, 0] != ref["label"][:, 0]) & amb).sum())
+        _say(f"{name}: label flips inside the eps band {flips}, min error {e}")
+
 
 
 def _min_err_check(gpu, ref, where):

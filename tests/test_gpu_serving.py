@@ -72,8 +72,10 @@ def test_mix_equals_alone_and_eval(cs, env, oracle_mod):
         reqs = _stream(24, seed=105, scale=0.5)
         t0 = time.perf_counter()
         tickets = []
-        for r in reqs:   # arrivals spread over time: later requests join running steps
-            while time.perf_counter() - t0 < r["t"]:
+        for i, r in enumerate(reqs):
+            # a burst of eight at t = 0 (they must share steps), then arrivals
+            # spread over time (later requests join running steps)
+            while i >= 8 and time.perf_counter() - t0 < r["t"]:
                 time.sleep(0.0005)
             kind = cs.CSPLAT_SERVE_COST if r["kind"] == "mppi" else cs.CSPLAT_SERVE_LABELS
             tickets.append((cs.csplat_server_submit(srv, ids[r["scene"]], kind, r["centers"], r["radii"],
@@ -82,6 +84,8 @@ def test_mix_equals_alone_and_eval(cs, env, oracle_mod):
         st = cs.csplat_server_stats(srv)
         _say(f"mix: {st}")
         assert st["completed"] == len(reqs)
+        # steps really held work items of several requests at once
+        assert st["shared_steps"] >= 1 and st["max_requests_per_step"] >= 2
         # the per-request latencies behind the percentiles
         lat = cs.csplat_server_latencies(srv)
         assert lat.size == len(reqs) and np.all(lat > 0)
@@ -134,6 +138,42 @@ def test_large_request_host_sort(cs, env):
                 assert np.array_equal(a.view(np.uint8), np.asarray(ev[k]).view(np.uint8)), (kind, k)
     finally:
         cs.csplat_server_destroy(srv)
+
+
+def test_largest_request_of_the_serving_law(cs, env, oracle_mod):
+    """The largest request of the serving law: an MPPI batch of 4,096 rollouts
+    x 32 steps x 48 spheres (6,291,456 spheres, a rigid template carried along
+    random walks) with all outputs over the 1 m ball: the server's results are
+    the bits of csplat_eval, and a sample agrees with the oracle."""
+    from workloads import Queries
+    eng, scenes, handles = env
+    _say("case: one 6,291,456-sphere MPPI request (server vs csplat_eval, oracle sample)")
+    walks = mppi_walk_queries(4096, 32, seed=31).centers.astype(np.float64)
+    rng = np.random.default_rng(32)
+    offs = rng.uniform(-0.3, 0.3, (48, 3))
+    rad = rng.uniform(0.03, 0.10, 48)
+    c = (walks[:, None, :] + offs[None]).reshape(-1, 3).astype(np.float32)
+    r = np.tile(rad, walks.shape[0]).astype(np.float32)
+    assert c.shape[0] == 6_291_456
+    req = dict(centers=c, radii=r, n_sigma=1.0)
+    kind = cs.CSPLAT_SERVE_COST
+    srv = cs.csplat_server_create(0, 4 << 30, 4)
+    try:
+        sid = cs.csplat_server_add_scene(srv, handles[1])
+        t = cs.csplat_server_submit(srv, sid, kind, c, r, _opts(cs, kind), 1.0)
+        got = cs.csplat_server_wait(srv, t, c.shape[0], kind)
+    finally:
+        cs.csplat_server_destroy(srv)
+    ev = _alone_eval(cs, eng, handles[1], req, kind)
+    for k in got:
+        a = got[k].reshape(ev[k].shape)
+        assert np.array_equal(a.view(np.uint8), np.asarray(ev[k]).view(np.uint8)), k
+    sub = np.sort(rng.choice(c.shape[0], 256, replace=False))
+    o = _opts(cs, kind)
+    ref = oracle_mod.evaluate_spheres(scenes[1], Queries(c[sub], r[sub]), [1.0], alpha_f=0.05, extent_f=0.1, k=2,
+                                      tau=o.softmin_tau, r_nbr=o.neighbor_radius)
+    compare({k_: v.reshape(ev[k_].shape)[sub] for k_, v in got.items()}, ref, tau=o.softmin_tau, gamma=1.0,
+            where="serve-largest")
 
 
 def test_admission_refusal_and_queueing(cs, env):
