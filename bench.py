@@ -110,11 +110,12 @@ def main():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped context workload")
     ap.add_argument("--no-manip", action="store_true", help="skip the manipulation (sphere chain) workload")
     ap.add_argument("--no-tiny", action="store_true", help="skip the plain tiny configuration")
+    ap.add_argument("--no-rrt", action="store_true", help="skip the batched RRT steps")
     ap.add_argument("--serving-requests", type=int, default=500)
     ap.add_argument("--serving-reduced", action="store_true",
                     help="serve a reduced request law (MPPI K <= 512 x 32 x <= 8 spheres; quick)")
     ap.add_argument("--section", choices=("all", "main", "precision", "precision-kernels", "serving", "ellipsoids",
-                                          "manip", "paper", "tiny", "copy", "digest"), default="all",
+                                          "manip", "paper", "tiny", "rrt", "copy", "digest"), default="all",
                     help="run one part only (for profiling); 'copy' is a plain 1 GiB device copy "
                          "used to calibrate the HBM traffic counters")
     args = ap.parse_args()
@@ -136,6 +137,7 @@ def main():
         args.no_paper = args.section not in ("paper",)
         args.no_manip = args.section not in ("manip",)
         args.no_tiny = args.section not in ("tiny",)
+        args.no_rrt = args.section not in ("rrt",)
         args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -272,6 +274,8 @@ def main():
         res["ellipsoids"] = ellipsoids(cs, eng, args.steps)
     if not args.no_paper:
         res["paper_context"] = paper_context(cs, eng)
+    if not args.no_rrt:
+        res["rrt"] = rrt(cs, eng, h, 100)
     if not args.no_serving:
         res["serving"] = serving(cs, eng, sc, h, args.serving_requests, args.serving_reduced)
     cs.csplat_scene_free(h)
@@ -605,6 +609,38 @@ def precision_kernels(cs, eng):
             res[name].update({"labels_min_ms": dt2 * 1e3, "labels_min_kernel_ms": st2["kernel_ms"]})
     cs.csplat_scene_free(h)
     return res
+
+
+def rrt(cs, eng, h_nav, n_steps):
+    """The batched RRT step (Sec. II-E) on the 1M navigation scene: a robot of
+    three link spheres translating in the room, strides of 0.5 m checked every
+    5 cm (10 states per edge), n_sigma 1, k = 2; the paper's 32 samples per
+    step, and 1,024."""
+    import torch
+    log("bench: RRT steps on the navigation scene")
+    links = np.array([[0.0, 0.0, 0.0], [0.15, 0.0, 0.0], [0.0, 0.0, 0.25]], np.float32)
+    radii = np.array([0.12, 0.08, 0.06], np.float32)
+    out = {"workload": "rrt: 1M-Gaussian room, 3-link robot (r 0.12, 0.08, 0.06 m) translating in "
+                       "[0.3, 9.7]^2 x [0.2, 2.5], stride 0.5 m, checks every 0.05 m (10 states per edge), "
+                       "n_sigma 1, k 2, root (3, 3, 1) m, samples drawn on the device"}
+    for nb in (32, 1024):
+        t = cs.Rrt(eng.ctx, h_nav, (0.3, 0.3, 0.2), (9.7, 9.7, 2.5), 0.5, 0.05, 1.0, 2, links, radii,
+                   (3.0, 3.0, 1.0), 2_000_000, seed=3)
+        for _ in range(3):
+            t.step(nb)
+        torch.cuda.synchronize()
+        cs.csplat_synchronize(eng.ctx)
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            t.step(nb)
+        cs.csplat_synchronize(eng.ctx)
+        dt = (time.perf_counter() - t0) / n_steps
+        nodes, _ = t.nodes()
+        t.close()
+        out[f"batch_{nb}"] = {"ms_per_step": dt * 1e3, "steps_per_s": 1 / dt, "edges_per_s": nb / dt,
+                              "sphere_checks_per_s": nb * 10 * 3 / dt, "nodes_after": int(nodes.shape[0]),
+                              "steps": n_steps + 3}
+    return out
 
 
 def tiny(cs, eng, steps):

@@ -253,6 +253,59 @@ csplat_status csplat_segment_reduce(csplat_ctx *ctx, int64_t q, int32_t m, int64
                                     const int64_t *offsets, const uint8_t *label, const float *cost,
                                     uint8_t *seg_any, float *seg_cost);
 
+/* ---------------------------------------------------------------------------
+ * Batched RRT step on the GPU (Sec. II-E): the tree lives in device memory.
+ * Each step draws n_batch configuration samples (or takes the caller's), finds
+ * each sample's nearest tree node (Euclidean; ties to the lowest index),
+ * expands it toward the sample by at most `step` (steer), checks the edge at
+ * n_strides = ceil(step / resolution) points (the float32 quotient) spaced evenly from the node
+ * (exclusive) to the new end (inclusive), each point placing the robot's
+ * n_links spheres (a rigid template: offsets and radii), and appends the
+ * collision-free edges' ends as new nodes in batch order.  A state is in
+ * collision when any link has more than k Gaussians with s~^2 < 1 for the
+ * conservatism n_sigma (the label of csplat_eval, over every kept Gaussian).
+ * A configuration is the template's origin in 3-D (a rigid body that
+ * translates).  Zero-length edges (a sample on its nearest node) are not
+ * appended.  The collision check runs the float32 label path (culled, the same
+ * labels as csplat_eval) on the context's stream; a step does not wait for
+ * the device unless n_added is requested.
+ */
+typedef struct csplat_rrt csplat_rrt;
+typedef struct {
+    float lo[3], hi[3];     /* sampling box of configurations (lo < hi on every axis) */
+    float step;             /* largest stride of an edge (> 0) */
+    float resolution;       /* spacing of the collision checks along an edge (> 0) */
+    float n_sigma;          /* conservatism (Eq. 8), finite and >= 0 */
+    int32_t k;              /* label = count > k (k >= 0) */
+    int32_t n_links;        /* spheres of the robot template (1..64) */
+    const float *link_offsets; /* n_links x 3, host memory, copied at creation */
+    const float *link_radii;   /* n_links, finite and > 0, host memory, copied */
+    uint64_t seed;          /* of the counter-based sample generator (SplitMix64) */
+} csplat_rrt_opts;
+
+/* A tree with one root node (3 floats, host) and room for max_nodes nodes,
+ * on the context's device and stream, over a loaded scene (which must outlive
+ * the tree).  Errors: CSPLAT_E_INVALID (bad options, max_nodes < 1 or above
+ * 2^26), CSPLAT_E_OOM, CSPLAT_E_DEVICE. */
+csplat_status csplat_rrt_create(csplat_ctx *ctx, const csplat_scene *scene, const csplat_rrt_opts *opts,
+                                int32_t max_nodes, const float *root, csplat_rrt **out);
+csplat_status csplat_rrt_destroy(csplat_rrt *rrt);
+/* One step with n_batch samples (1..65536; n_batch x n_strides x n_links <=
+ * 2^24 spheres): `samples` (n_batch x 3, a device pointer; NULL: drawn
+ * uniformly in the box by SplitMix64 on counter (seed, step, sample, axis)).
+ * Nodes beyond max_nodes are dropped (the tree stops growing).  With n_added
+ * (host) the call waits and reports the nodes appended.  Errors:
+ * CSPLAT_E_INVALID, CSPLAT_E_DEVICE. */
+csplat_status csplat_rrt_step(csplat_rrt *rrt, int32_t n_batch, const float *samples, int32_t *n_added);
+/* The tree (waits for the stream): up to cap nodes' positions (cap x 3) and
+ * parents (the root's is -1), host memory of the caller (either may be NULL);
+ * *n = the number of nodes. */
+csplat_status csplat_rrt_nodes(csplat_rrt *rrt, float *pos, int32_t *parent, int32_t cap, int32_t *n);
+/* The last step's edges (waits for the stream), host arrays of its n_batch
+ * entries (any may be NULL): the nearest node, the edge's end, and 1 if the
+ * edge was collision-free and of positive length. */
+csplat_status csplat_rrt_last_edges(csplat_rrt *rrt, int32_t *nearest, float *end, uint8_t *valid);
+
 /* Timing mode (off by default): when on, every evaluation records HIP events
  * around its dominant kernel and csplat_last_stats waits for the second one. */
 csplat_status csplat_ctx_set_timing(csplat_ctx *ctx, int32_t enable);

@@ -207,3 +207,57 @@ def evaluate_spheres(scene, queries, n_sigma, raw_mode=False, alpha_f=0.0, exten
                                raw_mode=raw_mode, alpha_f=alpha_f, extent_f=extent_f)
     return evaluate(mu, sig, queries.centers.astype(np.float64), sphere_bodies(queries.radii),
                     n_sigma, **reduce)
+
+
+def rrt_step(mu, sigma, nodes, parents, samples, link_offsets, link_radii, step, resolution, n_sigma, k,
+             max_nodes, eps=1e-5):
+    """One batched RRT step (Sec. II-E) in float64.  For each sample: the
+    nearest tree node (Euclidean, the lowest index among equal distances), the
+    edge from it toward the sample of length at most `step`, the edge's states
+    at n_strides = ceil(step / resolution) (the float32 quotient) evenly spaced points (the node
+    excluded, the end included), each state placing the robot's link spheres
+    (a rigid template: the state plus each link's offset), and the label of
+    every sphere (more than k Gaussians with s~^2 < 1, every kept Gaussian).
+    An edge is kept when no state is in collision and its length is positive;
+    kept edges' ends are appended in batch order while room remains.
+
+    Returns a dict: nearest (B,), ties (B, list of node indices within eps of
+    the nearest distance), end (B, 3), length (B,), valid (B,), ambiguous (B,:
+    some sphere of the edge is ambiguous for the label), nodes, parents (the
+    grown tree)."""
+    nodes = np.asarray(nodes, np.float64).reshape(-1, 3)
+    parents = np.asarray(parents, np.int64).reshape(-1)
+    smp = np.asarray(samples, np.float64).reshape(-1, 3)
+    off = np.asarray(link_offsets, np.float64).reshape(-1, 3)
+    rad = np.asarray(link_radii, np.float64).reshape(-1)
+    B, L = smp.shape[0], rad.size
+    d2 = ((smp[:, None, :] - nodes[None, :, :]) ** 2).sum(-1)
+    nearest = np.argmin(d2, axis=1)                     # the first of equal minima
+    dmin = d2[np.arange(B), nearest]
+    ties = [np.nonzero(d2[b] <= dmin[b] * (1 + eps) + 1e-30)[0].tolist() for b in range(B)]
+    base = nodes[nearest]
+    dv = smp - base
+    d = np.linalg.norm(dv, axis=1)
+    f = np.where(d > step, step / np.where(d > 0, d, 1.0), 1.0)
+    end = base + dv * f[:, None]
+    length = d * f
+    # the count of checks per edge from the float32 parameters, as the ABI
+    # takes them (the ceiling of their float32 quotient)
+    T = max(1, int(math.ceil(float(np.float32(step) / np.float32(resolution)))))
+    w = np.arange(1, T + 1, dtype=np.float64) / T
+    states = base[:, None, :] + w[None, :, None] * (end - base)[:, None, :]        # (B, T, 3)
+    centers = (states[:, :, None, :] + off[None, None, :, :]).reshape(-1, 3)      # (B * T * L, 3)
+    radii = np.broadcast_to(rad[None, None, :], (B, T, L)).reshape(-1)
+    out = evaluate(mu, sigma, centers, sphere_bodies(radii), [n_sigma], k=k, eps=eps)
+    lab = out["label"][:, 0].reshape(B, T * L)
+    amb = out["ambiguous"][:, 0].reshape(B, T * L)
+    valid = (length > 0) & ~lab.any(axis=1)
+    new_nodes, new_par = [nodes], [parents]
+    n = nodes.shape[0]
+    for b in range(B):
+        if valid[b] and n < max_nodes:
+            new_nodes.append(end[b][None])
+            new_par.append(np.array([nearest[b]]))
+            n += 1
+    return dict(nearest=nearest, ties=ties, end=end, length=length, valid=valid, ambiguous=amb.any(axis=1),
+                nodes=np.concatenate(new_nodes), parents=np.concatenate(new_par), n_strides=T)

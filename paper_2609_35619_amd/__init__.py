@@ -47,6 +47,7 @@ EXPORTS = (
     "csplat_last_error", "csplat_server_create", "csplat_server_destroy", "csplat_server_add_scene",
     "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
     "csplat_server_stats", "csplat_server_latencies", "csplat_eval_noalloc", "csplat_last_rechecked",
+    "csplat_rrt_create", "csplat_rrt_destroy", "csplat_rrt_step", "csplat_rrt_nodes", "csplat_rrt_last_edges",
 )
 CSPLAT_SERVE_COST = 0
 CSPLAT_SERVE_LABELS = 1
@@ -132,6 +133,11 @@ def load_library(path: str = LIB_PATH):
         "csplat_ctx_set_timing": [P, I32],
         "csplat_last_stats": [P, P],
         "csplat_last_rechecked": [P, P, I64, P],
+        "csplat_rrt_create": [P, P, P, I32, P, P],
+        "csplat_rrt_destroy": [P],
+        "csplat_rrt_step": [P, I32, P, P],
+        "csplat_rrt_nodes": [P, P, P, I32, P],
+        "csplat_rrt_last_edges": [P, P, P, P],
         "csplat_synchronize": [P],
         "csplat_server_create": [I32, ctypes.c_uint64, I32, P],
         "csplat_server_destroy": [P],
@@ -320,6 +326,65 @@ def csplat_last_rechecked(ctx) -> np.ndarray:
     out = np.zeros(max(int(n.value), 1), np.int32)
     _check(lib.csplat_last_rechecked(ctx, out.ctypes.data_as(ctypes.c_void_p), int(n.value), ctypes.byref(n)))
     return out[:int(n.value)].copy()
+
+
+class RrtOpts(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3), ("step", ctypes.c_float),
+                ("resolution", ctypes.c_float), ("n_sigma", ctypes.c_float), ("k", ctypes.c_int32),
+                ("n_links", ctypes.c_int32), ("link_offsets", ctypes.c_void_p), ("link_radii", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64)]
+
+
+class Rrt:
+    """A GPU-resident batched RRT (Sec. II-E) over a loaded scene: a rigid
+    robot of link spheres translating in 3-D."""
+
+    def __init__(self, ctx, scene, lo, hi, step, resolution, n_sigma, k, link_offsets, link_radii, root,
+                 max_nodes, seed=0):
+        lib = load_library()
+        self._off = np.ascontiguousarray(link_offsets, np.float32).reshape(-1, 3)
+        self._rad = np.ascontiguousarray(link_radii, np.float32).reshape(-1)
+        o = RrtOpts((ctypes.c_float * 3)(*lo), (ctypes.c_float * 3)(*hi), float(step), float(resolution),
+                    float(n_sigma), int(k), int(self._rad.size), self._off.ctypes.data_as(ctypes.c_void_p),
+                    self._rad.ctypes.data_as(ctypes.c_void_p), int(seed))
+        r = np.ascontiguousarray(root, np.float32).reshape(3)
+        h = ctypes.c_void_p()
+        _check(lib.csplat_rrt_create(ctx, scene, ctypes.byref(o), int(max_nodes), r.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.byref(h)))
+        self.h = h
+        self.max_nodes = int(max_nodes)
+
+    def step(self, n_batch, samples=None, wait=False):
+        """One step; samples: None (drawn on the device) or a torch CUDA
+        tensor (n_batch x 3).  With wait, returns the nodes appended."""
+        n = ctypes.c_int32(0)
+        _check(load_library().csplat_rrt_step(self.h, int(n_batch), _addr(samples),
+                                              ctypes.byref(n) if wait else None))
+        return int(n.value) if wait else None
+
+    def nodes(self):
+        lib = load_library()
+        n = ctypes.c_int32(0)
+        _check(lib.csplat_rrt_nodes(self.h, None, None, 0, ctypes.byref(n)))
+        pos = np.zeros((max(n.value, 1), 3), np.float32)
+        par = np.zeros(max(n.value, 1), np.int32)
+        _check(lib.csplat_rrt_nodes(self.h, pos.ctypes.data_as(ctypes.c_void_p), par.ctypes.data_as(ctypes.c_void_p),
+                                    n.value, ctypes.byref(n)))
+        return pos[:n.value].copy(), par[:n.value].copy()
+
+    def last_edges(self, n_batch):
+        near = np.zeros(n_batch, np.int32)
+        end = np.zeros((n_batch, 3), np.float32)
+        valid = np.zeros(n_batch, np.uint8)
+        _check(load_library().csplat_rrt_last_edges(self.h, near.ctypes.data_as(ctypes.c_void_p),
+                                                    end.ctypes.data_as(ctypes.c_void_p),
+                                                    valid.ctypes.data_as(ctypes.c_void_p)))
+        return near, end, valid
+
+    def close(self):
+        if self.h:
+            load_library().csplat_rrt_destroy(self.h)
+            self.h = None
 
 
 def csplat_synchronize(ctx):

@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libcsplat.so")
 ARCH = os.environ.get("CSPLAT_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["abi.hip", "scene.hip", "pair_fp32.hip", "precision.hip", "serve.hip", "segment.hip", "ply.cpp", "sched.cpp"]
+SOURCES = ["abi.hip", "scene.hip", "pair_fp32.hip", "precision.hip", "serve.hip", "segment.hip", "rrt.hip", "ply.cpp",
+           "sched.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
