@@ -11,12 +11,14 @@
 
 namespace csplat {
 
-// Per-Gaussian record of the float32 pair kernel: 16 floats (64 B), read by
-// scalar (wave-uniform) loads.  M = diag(s) R^T, so that for d = mu - c the
-// linearised variance term V = d^T Sigma d = |M d|^2 is a sum of squares;
-// -2 mu and |mu|^2 complete the record to 16 floats (the expanded form
-// |mu|^2 - 2 mu.c + |c|^2 of |d|^2; unused by the current kernels).
-constexpr int kGaussFloats = 16;  // mx my mz | M00..M22 (row-major) | -2mx -2my -2mz | |mu|^2
+// Per-Gaussian record of the float32 pair kernel: 12 floats (48 B, three
+// float4s).  M = diag(s) R^T, so that for d = mu - c the linearised variance
+// term V = d^T Sigma d = |M d|^2 is a sum of squares.
+#ifndef CSPLAT_GAUSS_FLOATS
+#define CSPLAT_GAUSS_FLOATS 12
+#endif
+constexpr int kGaussFloats = CSPLAT_GAUSS_FLOATS;  // mx my mz | M00..M22 (row-major) [| padding]
+static_assert(kGaussFloats == 12 || kGaussFloats == 16, "records are three float4s, or four");
 // Position of an integer cell (10 bits per axis) along a 3-D Hilbert curve
 // (30-bit key), by Skilling's transform of the axes to the transposed index
 // ("Programming the Hilbert curve", 2004) followed by bit interleaving.

@@ -631,6 +631,76 @@ __device__ __forceinline__ void task_fold(TaskAcc<M> &A, const TaskAcc<M> &X)
     A.nb += X.nb;
 }
 
+// A task partial as PW words in LDS (cnt | mt | sm | cs | nb), and back.
+template <int M, int PW>
+__device__ __forceinline__ void task_store(float4 *dst, const TaskAcc<M> &T)
+{
+    float w[4 * ((4 * M + 4) / 4)];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        w[v] = __int_as_float(T.cnt[v]);
+        w[M + v] = T.mt[v];
+        w[2 * M + v] = T.sm[v];
+        w[3 * M + v] = T.cs[v];
+    }
+    w[4 * M] = __int_as_float(T.nb);
+#pragma unroll
+    for (int k = 4 * M + 1; k < 4 * ((4 * M + 4) / 4); ++k) w[k] = w[4 * M];
+#pragma unroll
+    for (int k = 0; k < (4 * M + 4) / 4; ++k) dst[k] = make_float4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+}
+
+template <int M, int PW>
+__device__ __forceinline__ TaskAcc<M> task_load(const float4 *src)
+{
+    float w[4 * ((4 * M + 4) / 4)];
+#pragma unroll
+    for (int k = 0; k < (4 * M + 4) / 4; ++k) {
+        const float4 x = src[k];
+        w[4 * k] = x.x, w[4 * k + 1] = x.y, w[4 * k + 2] = x.z, w[4 * k + 3] = x.w;
+    }
+    TaskAcc<M> X;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        X.cnt[v] = __float_as_int(w[v]);
+        X.mt[v] = w[M + v];
+        X.sm[v] = w[2 * M + v];
+        X.cs[v] = w[3 * M + v];
+    }
+    X.nb = __float_as_int(w[4 * M]);
+    return X;
+}
+
+// The end of a full-output work item.  With G = 1 each wave writes its
+// queries' totals as partial record `item`.  With G > 1 the G consecutive
+// waves of a query group walked splits item G, ..., item G + G - 1 for the
+// same queries: their totals meet in LDS (each wave's area of `lds`, free
+// after its rounds) and the group's first wave folds them in split order
+// (the fold of the combine) and writes one record, so the partials take G
+// times fewer words.  Every wave of the block calls this (G is uniform).
+template <int M, int PW>
+__device__ __forceinline__ void full_item_out(TaskAcc<M> A, int G, int item, int jq, int q, const Part &part,
+                                              float4 *lds, int wave_f4, int wv, int lane)
+{
+    if (G > 1) {
+        task_store<M, PW>(lds + (size_t)wv * wave_f4 + lane * (PW / 4), A);
+        __syncthreads();
+        if (wv % G != 0) return;
+        for (int k = 1; k < G; ++k) task_fold(A, task_load<M, PW>(lds + (size_t)(wv + k) * wave_f4 + lane * (PW / 4)));
+    }
+    if (jq < q) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            const size_t o = ((size_t)item * M + v) * q + jq;
+            part.cnt[o] = A.cnt[v];
+            part.mt[o] = A.mt[v];
+            part.sm[o] = A.sm[v];
+            part.cs[o] = A.cs[v];
+        }
+        part.nb[(size_t)item * q + jq] = A.nb;
+    }
+}
+
 // Words of a task partial in LDS (4M + 1 for full outputs, M for labels)
 // rounded up to whole float4s, and kept off a multiple of 8 words so that the
 // lanes' rows spread over banks.
@@ -661,10 +731,10 @@ constexpr int full_entry_queries()
 }
 
 template <int M, bool FULL, bool BALL, bool CULL, bool ELL>
-__device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, int n, int S, int split, int tile,
-                                                const float *__restrict__ centers, const float *__restrict__ radii,
-                                                int q, const EvalParams &p, const Part &part,
-                                                const float *__restrict__ cull, int *tasks_done)
+__device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, int n, int S, int G, int item,
+                                                int tile, const float *__restrict__ centers,
+                                                const float *__restrict__ radii, int q, const EvalParams &p,
+                                                const Part &part, const float *__restrict__ cull, int *tasks_done)
 {
     static_assert(FULL && BALL, "labels run in eval_tile_label_tasks");
     constexpr int kRing = 128;  // queued tasks per wave: at most 63 waiting + 64 of one sub-chunk
@@ -674,7 +744,9 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
     __shared__ unsigned char s_owner[kWaves][kRing];   // lane of its query
     __shared__ float4 s_part[kWaves][64 * PW / 4];     // partials of a round, PW words per task
     const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
+    // wave wv: the (wv / G)-th 64 queries of the tile, split item G + wv % G
+    const int split = item * G + wv % G;
+    const int jq = tile * (kBlock / G) + (wv / G) * 64 + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
     TaskQuery<ELL> own;
     if constexpr (ELL) {
@@ -860,25 +932,16 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
             });
     }
     if (tail > head) run_round(tail - head);
-    if (jq < q) {
-#pragma unroll
-        for (int v = 0; v < M; ++v) {
-            const size_t o = ((size_t)split * M + v) * q + jq;
-            part.cnt[o] = A.cnt[v];
-            part.mt[o] = A.mt[v];
-            part.sm[o] = A.sm[v];
-            part.cs[o] = A.cs[v];
-        }
-        part.nb[(size_t)split * q + jq] = A.nb;
-    }
+    full_item_out<M, PW>(A, G, item, jq, q, part, &s_part[0][0], (int)(sizeof(s_part[0]) / sizeof(float4)), wv, lane);
 }
 
 // The same walk with KQ > 1 queries per queue entry (one conservatism value).
 template <int M, bool FULL, bool BALL, bool CULL, bool ELL>
-__device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__ gs, int n, int S, int split, int tile,
-                                                const float *__restrict__ centers, const float *__restrict__ radii,
-                                                int q, const EvalParams &p, const Part &part,
-                                                const float *__restrict__ cull, int *tasks_done)
+__device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__ gs, int n, int S, int G, int item,
+                                                       int tile, const float *__restrict__ centers,
+                                                       const float *__restrict__ radii, int q, const EvalParams &p,
+                                                       const Part &part, const float *__restrict__ cull,
+                                                       int *tasks_done)
 {
     static_assert(FULL && BALL, "labels run in eval_tile_label_tasks");
     constexpr int KQ = full_entry_queries<M, ELL>();  // queries per entry
@@ -891,7 +954,9 @@ __device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__
     __shared__ unsigned char s_q[kWaves][KQ][kRing];       // lanes of its queries, kNone for an empty slot
     __shared__ float4 s_part[kWaves][KQ * 64 * PW / 4];    // partials of a round, PW words per task
     const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
+    // wave wv: the (wv / G)-th 64 queries of the tile, split item G + wv % G
+    const int split = item * G + wv % G;
+    const int jq = tile * (kBlock / G) + (wv / G) * 64 + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
     TaskQuery<ELL> own;
     if constexpr (ELL) {
@@ -1105,17 +1170,7 @@ __device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__
             });
     }
     if (tail > head) run_round(tail - head);
-    if (jq < q) {
-#pragma unroll
-        for (int v = 0; v < M; ++v) {
-            const size_t o = ((size_t)split * M + v) * q + jq;
-            part.cnt[o] = A.cnt[v];
-            part.mt[o] = A.mt[v];
-            part.sm[o] = A.sm[v];
-            part.cs[o] = A.cs[v];
-        }
-        part.nb[(size_t)split * q + jq] = A.nb;
-    }
+    full_item_out<M, PW>(A, G, item, jq, q, part, &s_part[0][0], (int)(sizeof(s_part[0]) / sizeof(float4)), wv, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1357,7 +1412,7 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
 // contribute nothing, and the order of every sum is unchanged: the results
 // are the same bits.
 template <int M, bool FULL, bool BALL, int QPL, bool CULL = false, bool ELL = false>
-__device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, int S, int split,
+__device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, int S, int G, int split,
                                           int tile, const float *__restrict__ centers,
                                           const float *__restrict__ radii, int q, const EvalParams &p,
                                           const Part &part, const float *__restrict__ cull = nullptr,
@@ -1365,10 +1420,10 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
 {
     if constexpr (uses_tasks<FULL, BALL, QPL, ELL>()) {
         if constexpr (FULL && full_entry_queries<M, ELL>() > 1)
-            eval_tile_tasks_shared<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part,
+            eval_tile_tasks_shared<M, FULL, BALL, CULL, ELL>(gs, n, S, G, split, tile, centers, radii, q, p, part,
                                                              cull, chunks_done);
         else if constexpr (FULL)
-            eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
+            eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, G, split, tile, centers, radii, q, p, part, cull,
                                                       chunks_done);
         else
             eval_tile_label_tasks<M, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
@@ -1578,7 +1633,7 @@ __device__ __forceinline__ void eval_tile(const float *__restrict__ gs, int n, i
 
 template <int M, bool FULL, bool BALL, int QPL, bool CULL, bool ELL>
 __global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY
-pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
+pair_kernel(const float *__restrict__ gs, int n, int S, int G, int n_tiles,
             const float *__restrict__ centers, const float *__restrict__ radii, int q,
             const EvalParams p, Part part, const float *__restrict__ cull,
             unsigned long long *__restrict__ chunk_count)
@@ -1589,8 +1644,8 @@ pair_kernel(const float *__restrict__ gs, int n, int S, int n_tiles,
     const int split = b / n_tiles;
     const int tile = b - split * n_tiles;
     int done = 0;
-    eval_tile<M, FULL, BALL, QPL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
-                                        &done);
+    eval_tile<M, FULL, BALL, QPL, CULL, ELL>(gs, n, S, G, split, tile, centers, radii, q, p, part, cull,
+                                             &done);
     if (CULL && chunk_count && (threadIdx.x & 63) == 0) atomicAdd(chunk_count, (unsigned long long)done);
 }
 
@@ -1610,7 +1665,7 @@ constexpr int task_waves_per_eu()
 
 template <int M, bool FULL, bool BALL, bool CULL, bool ELL>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(task_waves_per_eu<M, FULL, ELL>())))
-pair_task_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const float *__restrict__ centers,
+pair_task_kernel(const float *__restrict__ gs, int n, int S, int G, int n_tiles, const float *__restrict__ centers,
                  const float *__restrict__ radii, int q, const EvalParams p, Part part,
                  const float *__restrict__ cull, unsigned long long *__restrict__ task_count)
 {
@@ -1621,10 +1676,11 @@ pair_task_kernel(const float *__restrict__ gs, int n, int S, int n_tiles, const 
     const int tile = b - split * n_tiles;
     int done = 0;
     if constexpr (FULL && full_entry_queries<M, ELL>() > 1)
-        eval_tile_tasks_shared<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull,
-                                                         &done);
+        eval_tile_tasks_shared<M, FULL, BALL, CULL, ELL>(gs, n, S, G, split, tile, centers, radii, q, p, part,
+                                                         cull, &done);
     else if constexpr (FULL)
-        eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
+        eval_tile_tasks<M, FULL, BALL, CULL, ELL>(gs, n, S, G, split, tile, centers, radii, q, p, part, cull,
+                                                  &done);
     else
         eval_tile_label_tasks<M, BALL, CULL, ELL>(gs, n, S, split, tile, centers, radii, q, p, part, cull, &done);
     if (CULL && task_count && (threadIdx.x & 63) == 0) atomicAdd(task_count, (unsigned long long)done);
@@ -1844,14 +1900,25 @@ combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out, const i
     combine_one<M, FULL>(j, v, q, S, p, part, out, perm);
 }
 
-// How an evaluation of q queries against n Gaussians is cut into work items:
-// query tiles of kBlock x QPL queries times S splits of the Gaussian chunks
-// (split s takes every S-th chunk from s), enough items to fill the device
-// several times over and at least 16 chunks per split.  Depends only on (q, n, mode, device), so a
-// request gives the same partial reductions wherever it runs.  per_split:
-// Gaussians of the largest split.
+#ifndef CSPLAT_FULL_GROUP
+#define CSPLAT_FULL_GROUP 4
+#endif
+constexpr int kFullGroup = CSPLAT_FULL_GROUP;  // splits merged per full-output work item (1, 2 or 4)
+static_assert(kFullGroup == 1 || kFullGroup == 2 || kFullGroup == 4, "a work item holds four waves");
+
+// How an evaluation of q queries against n Gaussians is cut into work items.
+// The Gaussian chunks form S splits (split s takes every S-th chunk from s),
+// enough to fill the device several times over with at least 16 chunks per
+// split.  A work item is a block of four waves: with G = 1, kBlock x QPL
+// queries against one split; with G = 4 (full outputs as tasks), 64 queries
+// against G consecutive splits, merged in LDS into one partial record, so
+// the partials hold S / G records per query.  Depends only on (q, n, mode,
+// device), so a request gives the same partial reductions wherever it runs.
+// per_split: Gaussians of the largest split.
 struct SplitPlan {
     int n_tiles, S, per_split, qpl;
+    int G;      // splits per work item (full outputs as tasks: 4 when S allows, else 1)
+    int parts;  // partial records per query: S / G
 };
 
 inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool ball, bool ell = false)
@@ -1861,14 +1928,20 @@ inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool bal
     const bool tasks = sp.qpl == 1 && (!full || (ball && (!ell || CSPLAT_ELL_FULL_TASKS)));
     if (tasks)
         target_blocks = (int)((int64_t)target_blocks * CSPLAT_TASK_BLOCKS_PER_CU / CSPLAT_BLOCKS_PER_CU);
-    sp.n_tiles = (q + kBlock * sp.qpl - 1) / (kBlock * sp.qpl);
     const int n_chunks = (n + kCull - 1) / kCull;
+    const int tiles256 = (q + kBlock * sp.qpl - 1) / (kBlock * sp.qpl);
     int S = 0;
     if (n > 0) {
-        S = sp.n_tiles > 0 ? (target_blocks + sp.n_tiles - 1) / sp.n_tiles : 1;
+        S = tiles256 > 0 ? (target_blocks + tiles256 - 1) / tiles256 : 1;
         S = std::max(1, std::min(S, n_chunks / 16));
     }
+    // full outputs as tasks merge the splits of four waves in LDS (a work
+    // item: 64 queries x 4 splits); S rounds up to a multiple of four
+    sp.G = full && tasks && S >= kFullGroup ? kFullGroup : 1;
+    if (sp.G > 1) S = (S + sp.G - 1) / sp.G * sp.G;
     sp.S = S;
+    sp.parts = S / sp.G;
+    sp.n_tiles = (q + kBlock / sp.G * sp.qpl - 1) / (kBlock / sp.G * sp.qpl);
     sp.per_split = S > 0 ? (n_chunks + S - 1) / S * kCull : 0;
     return sp;
 }

@@ -40,7 +40,7 @@ struct Launch {
     bool ell;
     const float *cull;
     unsigned long long *chunk_count;
-    int S;
+    int S, G, parts;  // splits, splits per work item, partial records per query
     EvalOut out;
     const int32_t *perm;
 };
@@ -52,20 +52,20 @@ void launch_pair(const Launch &L)
     if constexpr (QPL == 1 && (BALL || !FULL)) {
         if (L.ell && !uses_tasks<FULL, BALL, QPL, true>())
             pair_kernel<M, FULL, BALL, QPL, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
-                L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
+                L.gs, L.n, L.S, L.G, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
         else if (L.ell)
             pair_task_kernel<M, FULL, BALL, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
-                L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
+                L.gs, L.n, L.S, L.G, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
         else
             pair_task_kernel<M, FULL, BALL, CULL, false><<<L.grid, kBlock, 0, L.st>>>(
-                L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
+                L.gs, L.n, L.S, L.G, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
     } else {
         if (L.ell)
             pair_kernel<M, FULL, BALL, QPL, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
-                L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
+                L.gs, L.n, L.S, L.G, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
         else
             pair_kernel<M, FULL, BALL, QPL, CULL, false><<<L.grid, kBlock, 0, L.st>>>(
-                L.gs, L.n, L.S, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
+                L.gs, L.n, L.S, L.G, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
     }
 }
 
@@ -94,8 +94,8 @@ csplat_status launch_m(csplat_ctx *ctx, bool full, bool ball, bool cull, const L
         if (s != CSPLAT_OK) return s;
     }
     const unsigned cb = (unsigned)(((int64_t)L.q * M + 255) / 256);
-    if (full) combine_kernel<M, true><<<cb, 256, 0, L.st>>>(L.q, L.S, L.p, L.part, L.out, L.perm);
-    else combine_kernel<M, false><<<cb, 256, 0, L.st>>>(L.q, L.S, L.p, L.part, L.out, L.perm);
+    if (full) combine_kernel<M, true><<<cb, 256, 0, L.st>>>(L.q, L.parts, L.p, L.part, L.out, L.perm);
+    else combine_kernel<M, false><<<cb, 256, 0, L.st>>>(L.q, L.parts, L.p, L.part, L.out, L.perm);
     return CSPLAT_OK;
 }
 
@@ -436,15 +436,19 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
             csplat_status s = sort_workspace_bytes(q, ell, ctx->stream, &sort_bytes);
             if (s != CSPLAT_OK) return s;
         }
-        const size_t per_split = (size_t)q * part_words(M, full) * 4;
+        const size_t per_part = (size_t)q * part_words(M, full) * 4;
         const size_t avail = ws->bytes > sort_bytes ? ws->bytes - sort_bytes : 0;
-        const size_t fit = per_split ? avail / per_split : 0;
+        const size_t fit = per_part ? avail / per_part : 0;
         if (fit < 1) return fail(CSPLAT_E_INVALID, "workspace too small for one split of the partials");
-        if ((size_t)sp.S > fit) sp.S = (int)fit;
+        if ((size_t)sp.parts > fit) {
+            sp.parts = (int)fit;
+            sp.S = sp.parts * sp.G;
+        }
         part_base = ws->base + sort_bytes;
     }
     const int S = std::max(sp.S, 1);
-    const size_t words = (size_t)S * q * part_words(M, full);
+    const int parts = std::max(sp.parts, 1);
+    const size_t words = (size_t)parts * q * part_words(M, full);
     if (!ws && words > 0) {
         hipError_t e = ctx->partial.reserve(words * 4);
         if (e != hipSuccess) return hip_fail(e, "partial workspace");
@@ -452,7 +456,7 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     }
     hipStream_t st = ctx->stream;
     Launch L{};
-    L.grid = dim3((unsigned)(sp.n_tiles * S));
+    L.grid = dim3((unsigned)(sp.n_tiles * parts));
     L.st = st;
     L.gs = sc->gauss;
     L.n = n;
@@ -461,9 +465,11 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     L.r = radii;
     L.q = q;
     L.p = p;
-    L.part = part_views(part_base, S, q, M, full);
+    L.part = part_views(part_base, parts, q, M, full);
     L.ell = ell;
     L.S = sp.S;
+    L.G = sp.G;
+    L.parts = sp.parts;  // 0 for an empty scene: the combine then folds nothing
     L.out = out;
     ctx->stats.splits = S;
     ctx->stats.queries_per_lane = sp.qpl;

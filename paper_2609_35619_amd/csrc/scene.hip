@@ -92,10 +92,7 @@ __global__ void __launch_bounds__(256) prep_kernel(int64_t n, const float *__res
                 r[2] = mz;
                 for (int k = 0; k < 3; ++k)       // row k of M = s_k * (column k of R)^T
                     for (int c = 0; c < 3; ++c) r[3 + 3 * k + c] = (float)(s[k] * R[c][k]);
-                r[12] = -2.f * mx;  // exact
-                r[13] = -2.f * my;
-                r[14] = -2.f * mz;
-                r[15] = (float)((double)mx * mx + (double)my * my + (double)mz * mz);
+                for (int k = 12; k < kGaussFloats; ++k) r[k] = 0.f;
                 lane_box[0] = lane_box[3] = float_key(mx);
                 lane_box[1] = lane_box[4] = float_key(my);
                 lane_box[2] = lane_box[5] = float_key(mz);

@@ -36,7 +36,8 @@ enum class State : int { Queued = 0, Active = 1, Done = 2, Cancelled = 3, Finish
 // What the scheduler needs to know about a request.
 struct ReqSpec {
     int32_t tiles = 0;       // query tiles
-    int32_t splits = 0;      // Gaussian ranges (fixed per request: results never depend on the mix)
+    int32_t splits = 0;      // work items per query tile, each a group of Gaussian splits (fixed per
+                             // request: results never depend on the mix)
     int32_t variant = 0;     // which step kernel evaluates its items
     int64_t item_pairs = 0;  // pair evaluations of one item (step budget accounting)
     uint64_t dev_bytes = 0;  // device arena bytes (inputs, partial reductions)

@@ -50,6 +50,7 @@ struct ReqDesc {
     const float *centers;
     const float *radii;
     int32_t n, per_split, S, q;
+    int32_t G, parts;  // splits per work item, partial records per query
     int32_t full;
     const float *cull;  // the scene's culling chunks
     EvalParams p;
@@ -100,7 +101,7 @@ __device__ __forceinline__ void step_body(const char *__restrict__ stage, int va
         if (it >= b1) break;
         const Item w = items[it];
         const ReqDesc &R = reqs[__builtin_amdgcn_readfirstlane(w.slot)];
-        eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.S, __builtin_amdgcn_readfirstlane(w.split),
+        eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.S, R.G, __builtin_amdgcn_readfirstlane(w.split),
                                             __builtin_amdgcn_readfirstlane(w.tile), R.centers, R.radii, R.q, R.p,
                                             R.part, R.cull, nullptr);
     }
@@ -129,8 +130,8 @@ __global__ void __launch_bounds__(256) serve_combine_kernel(const char *__restri
     for (int d = 0; d < h->n_done; ++d) {
         const ReqDesc &R = reqs[h->done[d]];
         for (int j = (int)(blockIdx.x * blockDim.x + threadIdx.x); j < R.q; j += (int)(gridDim.x * blockDim.x)) {
-            if (R.full) combine_query<1, true>(j, R.q, R.S, R.p, R.part, R.out);
-            else combine_query<1, false>(j, R.q, R.S, R.p, R.part, R.out);
+            if (R.full) combine_query<1, true>(j, R.q, R.parts, R.p, R.part, R.out);
+            else combine_query<1, false>(j, R.q, R.parts, R.p, R.part, R.out);
         }
     }
 }
@@ -260,11 +261,13 @@ void setup_request(csplat_server *s, int64_t t)
     d.n = (int32_t)sc->n;
     d.per_split = r.sp.per_split;
     d.S = r.sp.S;
+    d.G = r.sp.G;
+    d.parts = r.sp.parts;  // 0 for an empty scene: the combine then folds nothing
     d.q = (int32_t)r.q;
     d.full = r.full ? 1 : 0;
     d.cull = sc->cull;
     d.p = r.p;
-    d.part = part_views(dbase + r.d_part, r.sp.S, (int)r.q, 1, r.full);
+    d.part = part_views(dbase + r.d_part, std::max(d.parts, 1), (int)r.q, 1, r.full);
     char *hd = s->host_arena_dev + ri->host_off;
     d.out.label = reinterpret_cast<uint8_t *>(hd + r.h_label);
     d.out.count = reinterpret_cast<int32_t *>(hd + r.h_count);
@@ -603,11 +606,11 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
         });
     }
     const size_t qn = (size_t)q;
-    const int S = std::max(r.sp.S, 1);
+    const int parts = std::max(r.sp.parts, 1);
     // device arena: inputs, then partial reductions
     r.d_centers = 0;
     r.d_part = align256(qn * 16);
-    const uint64_t dev_bytes = r.d_part + align256((size_t)S * qn * part_words(1, r.full) * 4);
+    const uint64_t dev_bytes = r.d_part + align256((size_t)parts * qn * part_words(1, r.full) * 4);
     // pinned host arena: input staging, then outputs
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -626,7 +629,7 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     }
     ReqSpec spec;
     spec.tiles = r.sp.n_tiles;
-    spec.splits = r.sp.S;
+    spec.splits = parts;  // work items per tile
     spec.variant = (r.full ? 2 : 0) + (r.ball ? 1 : 0);
     spec.item_pairs = (int64_t)kBlock * r.sp.qpl * r.sp.per_split;
     spec.dev_bytes = dev_bytes;
