@@ -1904,6 +1904,7 @@ combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out, const i
 #define CSPLAT_FULL_GROUP 4
 #endif
 constexpr int kFullGroup = CSPLAT_FULL_GROUP;  // splits merged per full-output work item (1, 2 or 4)
+constexpr int kMaxSplitChunks = 2048;          // culling chunks per split of a full-output plan, at most
 static_assert(kFullGroup == 1 || kFullGroup == 2 || kFullGroup == 4, "a work item holds four waves");
 
 // How an evaluation of q queries against n Gaussians is cut into work items.
@@ -1933,6 +1934,11 @@ inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool bal
     int S = 0;
     if (n > 0) {
         S = tiles256 > 0 ? (target_blocks + tiles256 - 1) / tiles256 : 1;
+        // full outputs: at most kMaxSplitChunks chunks per split, so that one
+        // work item (up to 256 queries over a 1 m ball) stays a few
+        // milliseconds of one block even when the queries alone fill the
+        // device (a serving step lasts as long as its slowest item)
+        if (full) S = std::max(S, (n_chunks + kMaxSplitChunks - 1) / kMaxSplitChunks);
         S = std::max(1, std::min(S, n_chunks / 16));
     }
     // full outputs as tasks merge the splits of four waves in LDS (a work
