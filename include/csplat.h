@@ -173,6 +173,11 @@ csplat_status csplat_scene_load_ply(csplat_ctx *ctx, const char *path,
 /* Kept Gaussians and device bytes held by the scene (the VRAM figure). */
 csplat_status csplat_scene_info(const csplat_scene *scene, int64_t *n_kept,
                                 uint64_t *device_bytes);
+/* Free the scene.  Returns without waiting: its device memory is released in
+ * stream order once every evaluation queued on it (by any context, or an RRT
+ * tree) has finished; only those streams are waited for (a stream that ran
+ * csplat_eval_noalloc on the scene and nothing else is waited for whole).  A
+ * server that serves the scene must be destroyed first. */
 csplat_status csplat_scene_free(csplat_scene *scene);
 
 /* The conservatism n_sigma of Eq. 8: m values (1..8), each finite and >= 0.

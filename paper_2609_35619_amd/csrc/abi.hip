@@ -95,14 +95,11 @@ hipError_t zero_words(int32_t *p, size_t n, hipStream_t st)
 hipError_t DevBuf::reserve(size_t want)
 {
     if (want <= bytes) return hipSuccess;
-    // earlier asynchronous work may still use the old buffer: wait for it
-    if (ptr) {
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return e;
-    }
+    // earlier work on the owner's stream may still use the old block: it is
+    // released in stream order, after that work
     release();
     size_t grow = want + want / 4;
-    hipError_t e = hipMalloc(&ptr, grow);
+    hipError_t e = hipMallocAsync(&ptr, grow, stream);
     if (e != hipSuccess) {
         ptr = nullptr;
         bytes = 0;
@@ -114,9 +111,39 @@ hipError_t DevBuf::reserve(size_t want)
 
 void DevBuf::release()
 {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) (void)hipFreeAsync(ptr, stream);
     ptr = nullptr;
     bytes = 0;
+}
+
+void scene_note_use(const csplat_scene *sc, hipStream_t st, bool may_create)
+{
+    if (!sc) return;
+    std::lock_guard<std::mutex> lk(sc->use_mu);
+    for (auto &u : sc->uses)
+        if (u.first == st) {
+            if (u.second) (void)hipEventRecord(u.second, st);
+            return;
+        }
+    hipEvent_t ev = nullptr;
+    // without an event (not created, or not allowed to be: the allocation-free
+    // entry point) freeing the scene waits for the whole stream instead
+    if (may_create && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+    sc->uses.emplace_back(st, ev);
+    if (ev) (void)hipEventRecord(ev, st);
+}
+
+// A non-blocking stream per device on which scene memory is released (after
+// waiting for the scene's users), created on first use.
+hipStream_t release_stream(int device)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!streams[device] && hipStreamCreateWithFlags(&streams[device], hipStreamNonBlocking) != hipSuccess)
+        streams[device] = nullptr;
+    return streams[device];
 }
 
 // 0: host, 1: device
@@ -407,6 +434,8 @@ csplat_status csplat_ctx_create(int32_t device, void *hip_stream, csplat_ctx **o
         }
         ctx->own_stream = true;
     }
+    for (DevBuf *b : {&ctx->partial, &ctx->staging, &ctx->flags, &ctx->sortbuf, &ctx->bodies, &ctx->minbuf})
+        b->stream = ctx->stream;
     ctx->m = 1;
     ctx->n_sigma[0] = 1.0f;
     // the device-side input check's pinned flag and event, allocated here so
@@ -430,13 +459,13 @@ csplat_status csplat_ctx_destroy(csplat_ctx *ctx)
 {
     if (!ctx) return CSPLAT_OK;
     DeviceGuard g(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
     ctx->partial.release();
     ctx->staging.release();
     ctx->flags.release();
     ctx->sortbuf.release();
     ctx->bodies.release();
     ctx->minbuf.release();
+    (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->ev_check) (void)hipEventDestroy(ctx->ev_check);
@@ -476,7 +505,8 @@ csplat_status csplat_scene_load(csplat_ctx *ctx, int64_t n, const float *means, 
     if (s == CSPLAT_OK && o.precision_features && sc->n > 0)
         s = precision_build(ctx, sc, o.precision_features);
     if (s != CSPLAT_OK) {
-        scene_release(sc);
+        scene_release(sc, ctx->stream);
+        (void)hipStreamSynchronize(ctx->stream);
         delete sc;
         return s;
     }
@@ -496,8 +526,21 @@ csplat_status csplat_scene_free(csplat_scene *sc)
 {
     if (!sc) return CSPLAT_OK;
     DeviceGuard g(sc->device);
-    (void)hipDeviceSynchronize();
-    scene_release(sc);
+    hipStream_t rs = release_stream(sc->device);
+    {
+        std::lock_guard<std::mutex> lk(sc->use_mu);
+        for (auto &u : sc->uses) {
+            if (u.second && rs) {
+                (void)hipStreamWaitEvent(rs, u.second, 0);
+                (void)hipEventDestroy(u.second);
+            } else {
+                (void)hipStreamSynchronize(u.first);
+                if (u.second) (void)hipEventDestroy(u.second);
+            }
+        }
+        sc->uses.clear();
+    }
+    scene_release(sc, rs);
     delete sc;
     return CSPLAT_OK;
 }
@@ -561,13 +604,15 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
         }
         if (s != CSPLAT_OK) return s;
     }
-    return on_device(ctx, kind, q, ctx->m, {centers, radii}, {(size_t)q * 12, (size_t)q * 4}, out,
-                     [&](const std::vector<const void *> &in, const EvalOut &eo) {
-                         const float *c = static_cast<const float *>(in[0]), *r = static_cast<const float *>(in[1]);
-                         if (opts->precision != CSPLAT_PRECISION_FP32)
-                             return precision_eval(ctx, sc, q, c, r, p, eo, opts->precision);
-                         return fp32_eval(ctx, sc, q, c, r, p, eo, !want_dist, false, gate);
-                     });
+    s = on_device(ctx, kind, q, ctx->m, {centers, radii}, {(size_t)q * 12, (size_t)q * 4}, out,
+                  [&](const std::vector<const void *> &in, const EvalOut &eo) {
+                      const float *c = static_cast<const float *>(in[0]), *r = static_cast<const float *>(in[1]);
+                      if (opts->precision != CSPLAT_PRECISION_FP32)
+                          return precision_eval(ctx, sc, q, c, r, p, eo, opts->precision);
+                      return fp32_eval(ctx, sc, q, c, r, p, eo, !want_dist, false, gate);
+                  });
+    scene_note_use(sc, ctx->stream);
+    return s;
 }
 
 csplat_status csplat_eval_ellipsoids(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const float *centers,
@@ -603,16 +648,17 @@ csplat_status csplat_eval_ellipsoids(csplat_ctx *ctx, const csplat_scene *sc, in
     }
     hipError_t e = ctx->bodies.reserve((size_t)q * kBodyFloats * 4);
     if (e != hipSuccess) return hip_fail(e, "body workspace");
-    return on_device(ctx, kind, q, ctx->m, {centers, quats, axes},
-                     {(size_t)q * 12, (size_t)q * 16, (size_t)q * 12}, out,
-                     [&](const std::vector<const void *> &in, const EvalOut &eo) {
-                         float *rec = ctx->bodies.as<float>();
-                         csplat_status st = prepare_bodies(ctx, (int)q, static_cast<const float *>(in[0]),
-                                                           static_cast<const float *>(in[1]),
-                                                           static_cast<const float *>(in[2]), rec);
-                         if (st != CSPLAT_OK) return st;
-                         return fp32_eval(ctx, sc, q, rec, nullptr, p, eo, !want_dist, true);
-                     });
+    s = on_device(ctx, kind, q, ctx->m, {centers, quats, axes}, {(size_t)q * 12, (size_t)q * 16, (size_t)q * 12},
+                  out, [&](const std::vector<const void *> &in, const EvalOut &eo) {
+                      float *rec = ctx->bodies.as<float>();
+                      csplat_status st = prepare_bodies(ctx, (int)q, static_cast<const float *>(in[0]),
+                                                        static_cast<const float *>(in[1]),
+                                                        static_cast<const float *>(in[2]), rec);
+                      if (st != CSPLAT_OK) return st;
+                      return fp32_eval(ctx, sc, q, rec, nullptr, p, eo, !want_dist, true);
+                  });
+    scene_note_use(sc, ctx->stream);
+    return s;
 }
 
 csplat_status csplat_eval_labels(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, const float *centers,
@@ -666,8 +712,10 @@ csplat_status csplat_eval_noalloc(csplat_ctx *ctx, const csplat_scene *sc, int64
     if (s != CSPLAT_OK) return s;
     const Workspace ws{ws_base, kScratchBytes};
     const EvalOut eo{out->label, out->count, out->min, out->softmin, out->cost, out->nbr, nullptr};
-    return fp32_eval(ctx, sc, q, centers, radii, p, eo, !want_dist, false,
-                     [&]() { return wait_device_check(ctx, bad_msg); }, &ws);
+    s = fp32_eval(ctx, sc, q, centers, radii, p, eo, !want_dist, false,
+                  [&]() { return wait_device_check(ctx, bad_msg); }, &ws);
+    scene_note_use(sc, ctx->stream, false);
+    return s;
 }
 
 csplat_status csplat_ctx_set_timing(csplat_ctx *ctx, int32_t enable)

@@ -5,6 +5,9 @@
 
 #include <cstdint>
 #include <functional>
+#include <mutex>
+#include <utility>
+#include <vector>
 #include <string>
 
 #include "../../include/csplat.h"
@@ -120,9 +123,13 @@ struct DeviceGuard {
 };
 
 // A device buffer that grows on demand (never shrinks until freed).
+// A growable device buffer, allocated and freed in the order of its owner's
+// stream (stream-ordered allocation): growing it waits for nothing, the old
+// block is released once the stream's earlier work is done.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    hipStream_t stream = nullptr;  // the owner's stream (set before the first reserve)
     hipError_t reserve(size_t want);
     void release();
     template <class T> T *as() const { return static_cast<T *>(ptr); }
@@ -134,7 +141,7 @@ struct csplat_scene {
     int device = 0;
     int64_t n_input = 0;
     int64_t n = 0;            // kept Gaussians
-    float *gauss = nullptr;   // 16-float records in Hilbert order of the means, padded to whole
+    float *gauss = nullptr;   // 12-float records in Hilbert order of the means, padded to whole
                               // culling chunks of 64 (pad records: mean at +inf, zero covariance)
     float mu_max = 0.f;       // max |mu| over the kept Gaussians
     float *cull = nullptr;    // per chunk of 64, then per sub-chunk of 16 (from record ceil(n / 64)),
@@ -150,6 +157,11 @@ struct csplat_scene {
     void *feat_fp16 = nullptr;
     float *meta_fp16 = nullptr;
     uint64_t device_bytes = 0;
+    // streams that read the scene, each with an event recorded after its
+    // last use: freeing the scene waits for those events only (in stream
+    // order, without blocking the host or other streams)
+    mutable std::mutex use_mu;
+    mutable std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 struct csplat_ctx {
@@ -214,7 +226,12 @@ hipError_t zero_words(int32_t *p, size_t n, hipStream_t st);
 csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const float *quats,
                           const float *scales, const float *opacity,
                           const csplat_scene_opts &opts, csplat_scene *scene);
-void scene_release(csplat_scene *scene);
+// Frees the scene's device memory in the order of `st` (stream-ordered
+// frees: the memory was allocated with hipMallocAsync).
+void scene_release(csplat_scene *scene, hipStream_t st);
+// abi.hip: records that `st` has queued work reading the scene (an event after
+// it), so that freeing the scene waits for exactly that work.
+void scene_note_use(const csplat_scene *scene, hipStream_t st, bool may_create = true);
 
 // Parameters of one evaluation, precomputed on the host from the options.
 struct EvalParams {

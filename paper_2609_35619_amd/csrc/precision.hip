@@ -857,20 +857,21 @@ csplat_status build_one(csplat_ctx *ctx, csplat_scene *sc, void **feat_out)
     // the per-tile scale and coefficient maxima are dtype specific: each dtype
     // owns its metadata
     float *meta = nullptr;
-    CSPLAT_HIP(hipMalloc(&meta, (size_t)nt * kMeta * sizeof(float)));
+    // stream-ordered, like the scene's other buffers (freed with them)
+    CSPLAT_HIP(hipMallocAsync(&meta, (size_t)nt * kMeta * sizeof(float), ctx->stream));
     vec *feat = nullptr;
     const size_t fbytes = (size_t)nt * kRB * kOps * kLanes * sizeof(vec);
-    hipError_t e = hipMalloc(&feat, fbytes);
+    hipError_t e = hipMallocAsync(&feat, fbytes, ctx->stream);
     if (e != hipSuccess) {
-        (void)hipFree(meta);
+        (void)hipFreeAsync(meta, ctx->stream);
         return hip_fail(e, "precision features");
     }
     build_tiles_kernel<P><<<(unsigned)nt, kPT, 0, ctx->stream>>>(sc->gauss, sc->n, meta, feat);
     hipError_t le = hipGetLastError();
     if (le == hipSuccess) le = hipStreamSynchronize(ctx->stream);
     if (le != hipSuccess) {
-        (void)hipFree(meta);
-        (void)hipFree(feat);
+        (void)hipFreeAsync(meta, ctx->stream);
+        (void)hipFreeAsync(feat, ctx->stream);
         return hip_fail(le, "build_tiles_kernel");
     }
     feat_out[0] = feat;

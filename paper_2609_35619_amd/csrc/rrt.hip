@@ -229,6 +229,7 @@ csplat_status csplat_rrt_create(csplat_ctx *ctx, const csplat_scene *scene, cons
     csplat_rrt *t = new (std::nothrow) csplat_rrt();
     if (!t) return fail(CSPLAT_E_OOM, "rrt_create: host allocation");
     t->ctx = ctx;
+    t->work.stream = ctx->stream;
     t->scene = scene;
     t->opts = *o;
     t->opts.link_offsets = nullptr;
@@ -324,6 +325,7 @@ csplat_status csplat_rrt_step(csplat_rrt *t, int32_t n_batch, const float *sampl
     if (s != CSPLAT_OK) return s;
     EvalOut eo{label, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     s = fp32_eval(ctx, t->scene, q, centers, radii, p, eo, true, false);
+    scene_note_use(t->scene, st);
     if (s != CSPLAT_OK) return s;
     rrt_append_kernel<<<1, 1024, 0, st>>>(n_batch, per_edge, t->max_nodes, label, nearest, end, len,
                                           reinterpret_cast<float4 *>(t->nodes), t->parent, t->counts, valid);

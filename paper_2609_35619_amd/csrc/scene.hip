@@ -211,16 +211,19 @@ __global__ void cull_meta_kernel(int64_t n, int csz, const float *__restrict__ g
     m[5] = m[6] = m[7] = 0.f;
 }
 
+// Temporaries of a scene build, in the order of its stream.
 struct Tmp {
+    hipStream_t st;
     std::vector<void *> ptrs;
+    explicit Tmp(hipStream_t s) : st(s) {}
     ~Tmp()
     {
-        for (void *p : ptrs) (void)hipFree(p);
+        for (void *p : ptrs) (void)hipFreeAsync(p, st);
     }
     template <class T> hipError_t alloc(T **p, size_t bytes)
     {
         void *v = nullptr;
-        hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+        hipError_t e = hipMallocAsync(&v, bytes ? bytes : 16, st);
         if (e == hipSuccess) ptrs.push_back(v);
         *p = static_cast<T *>(v);
         return e;
@@ -240,7 +243,7 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
     if (n == 0) return CSPLAT_OK;
     if (n > (int64_t)0x7FFFFFFF)
         return fail(CSPLAT_E_INVALID, "scene_load: more than 2^31-1 Gaussians");
-    Tmp tmp;
+    Tmp tmp(st);
     float *d_in = nullptr, *d_rec = nullptr;
     uint32_t *d_keep = nullptr, *d_code = nullptr, *d_idx = nullptr, *d_code2 = nullptr,
              *d_idx2 = nullptr;
@@ -312,7 +315,7 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
     const int64_t n_chunks = ((int64_t)kept + kCullChunk - 1) / kCullChunk;
     const int64_t n_pad = n_chunks * kCullChunk;
     float *g = nullptr;
-    if (hipMalloc(&g, (size_t)n_pad * kGaussFloats * sizeof(float)) != hipSuccess)
+    if (hipMallocAsync(&g, (size_t)n_pad * kGaussFloats * sizeof(float), st) != hipSuccess)
         return fail(CSPLAT_E_OOM, "scene_load: scene allocation");
     sc->gauss = g;
     sc->device_bytes += (uint64_t)n_pad * kGaussFloats * sizeof(float);
@@ -328,7 +331,7 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
     const int64_t n_group = ((int64_t)kept + kGroupChunk - 1) / kGroupChunk;
     const int64_t n_meta = n_chunks + n_fine + n_group;
     float *cm = nullptr;
-    if (hipMalloc(&cm, (size_t)n_meta * 8 * sizeof(float)) != hipSuccess)
+    if (hipMallocAsync(&cm, (size_t)n_meta * 8 * sizeof(float), st) != hipSuccess)
         return fail(CSPLAT_E_OOM, "scene_load: culling metadata");
     sc->cull = cm;
     sc->device_bytes += (uint64_t)n_meta * 8 * sizeof(float);
@@ -350,12 +353,12 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
     return CSPLAT_OK;
 }
 
-void scene_release(csplat_scene *sc)
+void scene_release(csplat_scene *sc, hipStream_t st)
 {
     if (!sc) return;
     void *ptrs[] = {sc->gauss, sc->cull, sc->feat_bf16, sc->meta_bf16, sc->feat_fp16, sc->meta_fp16};
     for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFreeAsync(p, st);
     sc->gauss = nullptr;
     sc->cull = nullptr;
     sc->feat_bf16 = sc->feat_fp16 = nullptr;

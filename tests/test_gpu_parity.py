@@ -369,3 +369,45 @@ def test_cull_is_bit_identical_to_dense(cs, eng, name, scale, want):
     cs.csplat_scene_free(h)
     for k in want:
         assert np.array_equal(res[0][k].view(np.uint8), res[1][k].view(np.uint8)), k
+
+
+def test_scene_free_behind_queued_work(cs, eng):
+    """Freeing a scene right after queuing evaluations on it (no wait in
+    between) releases its memory only after they have run, and the context's
+    workspace, grown between the calls, is replaced in stream order: the
+    queued results equal those of the same calls on a scene that is kept."""
+    import torch
+    _say("case: scene freed behind queued work, growing workspace")
+    sc, qs, p = config("tiny")
+    kw = dict(floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
+    eng.set_conservatism(p["n_sigma"])
+    opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"],
+                          s_min=p["s_min"])
+    c = torch.from_numpy(qs.centers).cuda()
+    r = torch.from_numpy(qs.radii).cuda()
+    sizes = (qs.q // 8, qs.q // 2, qs.q)
+    kept = eng.load_scene(sc, **kw)
+    ref = []
+    for n in sizes:
+        o = eng.evaluate(kept, c[:n], r[:n], opts, ALL)
+        torch.cuda.synchronize()
+        ref.append({k: v.cpu().numpy() for k, v in o.items()})
+    cs.csplat_scene_free(kept)
+    # a fresh context: its workspace grows with each call
+    e2 = cs.Engine(0)
+    try:
+        e2.set_conservatism(p["n_sigma"])
+        h = e2.load_scene(sc, **kw)
+        outs = [e2.evaluate(h, c[:n], r[:n], opts, ALL) for n in sizes]
+        cs.csplat_scene_free(h)
+        # new allocations right away may take the freed blocks, in stream order
+        filler = e2.load_scene(uniform_box_scene(20_000, seed=9))
+        junk = e2.evaluate(filler, c, r, opts, ALL)
+        torch.cuda.synchronize()
+        for n, o, rf in zip(sizes, outs, ref):
+            for k in ALL:
+                assert np.array_equal(o[k].cpu().numpy(), rf[k], equal_nan=True), (n, k)
+        assert junk["label"].shape[0] == qs.q
+        cs.csplat_scene_free(filler)
+    finally:
+        e2.close()
