@@ -66,9 +66,13 @@ typedef struct csplat_server csplat_server;
 #define CSPLAT_PRECISION_BF16_RECHECK 1 /* bf16 MFMA + certified fp32/fp64 recheck */
 #define CSPLAT_PRECISION_FP16_RECHECK 2 /* fp16 MFMA + certified fp32/fp64 recheck */
 
-/* Bits of csplat_scene_opts.precision_features. */
+/* Bits of csplat_scene_opts.precision_features: the packed MFMA operands of
+ * the precision forms for spheres (96 B per Gaussian and dtype) and for
+ * ellipsoidal bodies (320 B per Gaussian and dtype). */
 #define CSPLAT_FEATURES_BF16 1u
 #define CSPLAT_FEATURES_FP16 2u
+#define CSPLAT_FEATURES_ELL_BF16 4u
+#define CSPLAT_FEATURES_ELL_FP16 8u
 
 typedef struct {
     int32_t param_mode;          /* CSPLAT_PARAM_* */
@@ -231,9 +235,16 @@ csplat_status csplat_eval_noalloc(csplat_ctx *ctx, const csplat_scene *scene, in
  * s~^2 = max(0, s^2 - n sqrt(sigma^2)) with s^2 = d^T A d and
  * sigma^2 = 4 d^T A Sigma A d (Eq. 7-8).  A sphere is a = b = c = r.
  * Outputs, options, pointer rules and the neighbourhood ball (about c_j) are
- * those of csplat_eval; only opts->precision = CSPLAT_PRECISION_FP32 is
- * accepted.  Errors: CSPLAT_E_INVALID (as csplat_eval, or a non-finite
- * centre, a zero or non-finite quaternion, a semi-axis not finite and > 0). */
+ * those of csplat_eval.  The MFMA precision forms (opts->precision
+ * BF16_RECHECK or FP16_RECHECK; the scene loaded with CSPLAT_FEATURES_ELL_BF16
+ * or _ELL_FP16) compute labels and counts over every kept Gaussian: a
+ * certified bound decides each pair, the undecided bodies are rechecked in
+ * fp64, and both take B = L^T L in float32 from L = diag(1/a, 1/b, 1/c) R^T
+ * (float32), so the counts are exact for that B (within float32 rounding of
+ * A_j).  They reject min, softmin, cost, nbr, err and a finite
+ * neighbor_radius.  Errors: CSPLAT_E_INVALID (as csplat_eval, or a
+ * non-finite centre, a zero or non-finite quaternion, a semi-axis not finite
+ * and > 0, or a precision form whose features the scene lacks). */
 csplat_status csplat_eval_ellipsoids(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
                                      const float *centers, const float *quats, const float *axes,
                                      const csplat_reduce_opts *opts, const csplat_outputs *out);

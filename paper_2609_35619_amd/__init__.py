@@ -38,6 +38,8 @@ CSPLAT_PRECISION_BF16_RECHECK = 1
 CSPLAT_PRECISION_FP16_RECHECK = 2
 CSPLAT_FEATURES_BF16 = 1
 CSPLAT_FEATURES_FP16 = 2
+CSPLAT_FEATURES_ELL_BF16 = 4
+CSPLAT_FEATURES_ELL_FP16 = 8
 
 # every symbol declared in include/csplat.h (checked by the test suite)
 EXPORTS = (

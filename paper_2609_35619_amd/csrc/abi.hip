@@ -491,7 +491,8 @@ csplat_status csplat_scene_load(csplat_ctx *ctx, int64_t n, const float *means, 
         return fail(CSPLAT_E_INVALID, "scene_load: unknown param_mode");
     if (!std::isfinite(o.floater_opacity_max) || !std::isfinite(o.floater_extent_min))
         return fail(CSPLAT_E_INVALID, "scene_load: non-finite floater thresholds");
-    if (o.precision_features & ~(CSPLAT_FEATURES_BF16 | CSPLAT_FEATURES_FP16))
+    if (o.precision_features &
+        ~(CSPLAT_FEATURES_BF16 | CSPLAT_FEATURES_FP16 | CSPLAT_FEATURES_ELL_BF16 | CSPLAT_FEATURES_ELL_FP16))
         return fail(CSPLAT_E_INVALID, "scene_load: unknown precision feature bits");
     if (n > 0) {  // the scene arrays are host arrays: reject device pointers early
         if (pointer_kind(means) || pointer_kind(quats) || pointer_kind(scales) || pointer_kind(opacity))
@@ -623,8 +624,17 @@ csplat_status csplat_eval_ellipsoids(csplat_ctx *ctx, const csplat_scene *sc, in
     bool want_dist = false;
     csplat_status s = eval_checks(ctx, sc, q, opts, out, "eval_ellipsoids", p, want_dist);
     if (s != CSPLAT_OK) return s;
-    if (opts->precision != CSPLAT_PRECISION_FP32)
-        return fail(CSPLAT_E_INVALID, "eval_ellipsoids: ellipsoidal bodies use the float32 path only");
+    if (opts->precision != CSPLAT_PRECISION_FP32) {
+        if (out->min || out->softmin || out->cost || out->nbr || out->err)
+            return fail(CSPLAT_E_INVALID, "eval_ellipsoids: the MFMA precision forms compute labels and counts only");
+        if (std::isfinite(opts->neighbor_radius))
+            return fail(CSPLAT_E_INVALID,
+                        "eval_ellipsoids: the MFMA precision forms count over every kept Gaussian (neighbor_radius = +inf)");
+        const void *f = opts->precision == CSPLAT_PRECISION_BF16_RECHECK ? sc->feat_ell_bf16 : sc->feat_ell_fp16;
+        if (sc->n > 0 && !f)
+            return fail(CSPLAT_E_INVALID,
+                        "eval_ellipsoids: scene was loaded without the requested ellipsoid precision features");
+    }
     if (q == 0) return CSPLAT_OK;
     if (!centers || !quats || !axes) return fail(CSPLAT_E_INVALID, "eval_ellipsoids: NULL body array");
     const int kind = common_kind({centers, quats, axes, out->label, out->count, out->min, out->softmin,
@@ -655,6 +665,8 @@ csplat_status csplat_eval_ellipsoids(csplat_ctx *ctx, const csplat_scene *sc, in
                                                         static_cast<const float *>(in[1]),
                                                         static_cast<const float *>(in[2]), rec);
                       if (st != CSPLAT_OK) return st;
+                      if (opts->precision != CSPLAT_PRECISION_FP32)
+                          return precision_eval_ell(ctx, sc, q, rec, p, eo, opts->precision);
                       return fp32_eval(ctx, sc, q, rec, nullptr, p, eo, !want_dist, true);
                   });
     scene_note_use(sc, ctx->stream);

@@ -156,6 +156,11 @@ struct csplat_scene {
     float *meta_bf16 = nullptr;
     void *feat_fp16 = nullptr;
     float *meta_fp16 = nullptr;
+    // the same for ellipsoidal bodies (320 B per Gaussian, 24 floats per tile)
+    void *feat_ell_bf16 = nullptr;
+    float *meta_ell_bf16 = nullptr;
+    void *feat_ell_fp16 = nullptr;
+    float *meta_ell_fp16 = nullptr;
     uint64_t device_bytes = 0;
     // streams that read the scene, each with an event recorded after its
     // last use: freeing the scene waits for those events only (in stream
@@ -319,6 +324,10 @@ csplat_status fp32_min_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t 
 csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
                              const float *centers, const float *radii, const EvalParams &p,
                              const EvalOut &out, int precision);
+// Labels and counts of ellipsoid records (kBodyFloats floats each, the
+// caller's order) in an MFMA precision form.
+csplat_status precision_eval_ell(csplat_ctx *ctx, const csplat_scene *scene, int64_t q, const float *rec,
+                                 const EvalParams &p, const EvalOut &out, int precision);
 csplat_status precision_build(csplat_ctx *ctx, csplat_scene *scene, uint32_t features);
 
 }  // namespace csplat

@@ -849,6 +849,576 @@ __global__ void pmin_slot_kernel(const int32_t *__restrict__ list, const int32_t
     if (i < *n_list) slot[list[i]] = i;
 }
 
+// ---------------------------------------------------------------------------
+// The MFMA form for ellipsoidal bodies (Eq. 5-6 with a general A).
+//
+// For a body with centre c, its float32 L (A = L^T L) and B = L^T L formed
+// once in float32 (the fp64 recheck takes the same L and B), and a Gaussian
+// (mu, M), with d = mu - c:
+//   a = |L d|^2 - 1 = sum_k f_k^2 - 1,          f_k = L_k . d      (s^2 - 1)
+//   w = 4 n^2 |M B d|^2 = sum_k e_k^2,          e_k = 2n M_k . (B d) (n^2 sigma^2)
+// and s~^2 < 1  <=>  a |a| < w.  About a tile origin o (mu' = mu - o,
+// c' = c - o, beta = B c'), each is a dot product of Gaussian and body
+// features:
+//   f_k = [mu'x, mu'y, mu'z, 1] . [L_k0, L_k1, L_k2, -(L c')_k]
+//   e_k = [M_kp mu'_m (p, m = 0..2), M_k0, M_k1, M_k2]
+//       . 2n [B_pm (p, m = 0..2), -beta_0, -beta_1, -beta_2]
+// (the Gaussian side of the three f_k and the body side of the three e_k are
+// shared): per 32 x 32 block one MFMA for each f_k (K = 16 with the three
+// hi/lo products) and three for each e_k (K = 48), and the squares are
+// summed per pair.  Linear forms keep the cancellation about the tile origin
+// to |o - c| / |d| (the quadratic form of a, or of w with its 60 features
+// Sigma x mu mu^T, squares it).
+//
+// Bounds per (body, tile): E_f >= |f~_k - f_k| and E_e >= |e~_k - e_k| as for
+// spheres (3.1 u^2 of sum |g||q| for the split, 64 u32 for the fp32 sums of
+// up to 48 exact products, the fp32 errors of the body features, eta per
+// value for fp16 subnormals).  Per pair, with F = sum |f~_k| and
+// S = sum |e~_k|:
+//   |a~ - a| <= E_a = 2 E_f F + 3 E_f^2 + 2 u32 (|a~| + 1)
+//   |w~ - w| <= E_w = 2 E_e S + 3 E_e^2 + 6 u32 w~
+// and w~ - a~|a~| is within 2 |a~| E_a + E_a^2 + E_w (+ its rounding) of w - a|a|.
+constexpr int kEllF = 4, kEllE = 12;   // features of each f_k and of each e_k
+constexpr int kEllOps = 1 + 3 * 3;     // Gaussian operand vectors per row block: f (1), e_0, e_1, e_2 (3 each)
+constexpr int kEllMeta = 24;  // floats per tile: o(3), 1/scale of e, Gf[4], Ge[12], radius, largest scale, 0 0
+
+// Slot s of an operand with nf features: hi.hi (nf) | hi.lo (nf) | lo.hi (nf) | 0;
+// the Gaussian side takes its lo part in the second group, the body side in the third.
+__host__ __device__ inline int eslot_feat(int s, int nf) { return s < 3 * nf ? s % nf : -1; }
+__host__ __device__ inline bool eslot_glo(int s, int nf) { return s >= nf && s < 2 * nf; }
+__host__ __device__ inline bool eslot_qlo(int s, int nf) { return s >= 2 * nf && s < 3 * nf; }
+
+// Load time: one block per tile of kPT Gaussians; thread i holds Gaussian i.
+template <int P>
+__global__ void __launch_bounds__(kPT)
+build_tiles_ell_kernel(const float *__restrict__ gauss, int64_t n, float *__restrict__ meta,
+                       typename Prec<P>::vec *__restrict__ feat)
+{
+    using T = Prec<P>;
+    using elem = typename T::elem;
+    using vec = typename T::vec;
+    __shared__ float red[kEllF + kEllE][kPT];
+    __shared__ float box[6];
+    __shared__ double s_scale;
+    const int64_t t = blockIdx.x;
+    const int i = threadIdx.x;
+    const int64_t gi = t * kPT + i;
+    const bool valid = gi < n;
+    const float *r = gauss + (size_t)kGaussFloats * (valid ? gi : 0);
+    const float mu[3] = {r[0], r[1], r[2]};
+    for (int k = 0; k < 3; ++k) {
+        red[k][i] = valid ? mu[k] : INFINITY;
+        red[3 + k][i] = valid ? mu[k] : -INFINITY;
+    }
+    __syncthreads();
+    if (i < 6) {
+        float v = red[i][0];
+        for (int j = 1; j < kPT; ++j) v = i < 3 ? fminf(v, red[i][j]) : fmaxf(v, red[i][j]);
+        box[i] = v;
+    }
+    __syncthreads();
+    const float o[3] = {0.5f * box[0] + 0.5f * box[3], 0.5f * box[1] + 0.5f * box[4],
+                        0.5f * box[2] + 0.5f * box[5]};
+    double gf[kEllF] = {}, ge[3][kEllE] = {};
+    if (valid) {
+        double mp[3];
+        for (int k = 0; k < 3; ++k) mp[k] = (double)mu[k] - (double)o[k];  // exact
+        gf[0] = mp[0];
+        gf[1] = mp[1];
+        gf[2] = mp[2];
+        gf[3] = 1.0;
+        for (int k = 0; k < 3; ++k)
+            for (int p = 0; p < 3; ++p) {
+                const double mkp = r[3 + 3 * k + p];  // M = diag(s) R^T, row-major
+                for (int m = 0; m < 3; ++m) ge[k][3 * p + m] = mkp * mp[m];
+                ge[k][9 + p] = mkp;
+            }
+    } else {
+        // padding row: f_k = far (L_k0 + L_k1 + L_k2), nonzero for some k
+        // (the row sums of L are R^T (1, 1, 1) over the semi-axes), w = 0:
+        // certainly free
+        gf[0] = gf[1] = gf[2] = T::far;
+    }
+    // per-tile power-of-two scale of the e coefficients (keeps fp16 away from
+    // its subnormal range; exact, undone on the body side)
+    double mx = 0.0;
+    for (int k = 0; k < 3; ++k)
+        for (int f = 0; f < kEllE; ++f) mx = fmax(mx, fabs(ge[k][f]));
+    red[0][i] = (float)mx;
+    __syncthreads();
+    if (i == 0) {
+        float v = 0.f;
+        for (int j = 0; j < kPT; ++j) v = fmaxf(v, red[0][j]);
+        s_scale = v > 0.f ? ldexp(1.0, 4 - ilogb((double)v)) : 1.0;
+    }
+    __syncthreads();
+    const double scale = s_scale;
+    float hf[kEllF], lf[kEllF], he[3][kEllE], le[3][kEllE];
+    for (int f = 0; f < kEllF; ++f) {
+        hf[f] = (float)(elem)(float)gf[f];
+        lf[f] = (float)(elem)(float)(gf[f] - (double)hf[f]);
+    }
+    for (int k = 0; k < 3; ++k)
+        for (int f = 0; f < kEllE; ++f) {
+            const double x = ge[k][f] * scale;
+            he[k][f] = (float)(elem)(float)x;
+            le[k][f] = (float)(elem)(float)(x - (double)he[k][f]);
+        }
+    // packed operands: row block rb = i / 32, row m = i % 32; lane m + 32 h
+    // holds K slots 16 j + 8 h .. + 7 of operand j
+    const int rb = i >> 5, m = i & 31;
+    for (int h = 0; h < 2; ++h) {
+        const int lane = m + 32 * h;
+        const size_t base = ((size_t)(t * kRB + rb) * kEllOps) * kLanes + lane;
+        {
+            vec v;
+            for (int jj = 0; jj < 8; ++jj) {
+                const int s = 8 * h + jj, f = eslot_feat(s, kEllF);
+                v[jj] = (elem)(f < 0 ? 0.f : (eslot_glo(s, kEllF) ? lf[f] : hf[f]));
+            }
+            feat[base] = v;
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) {
+                vec v;
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int s = 16 * j + 8 * h + jj, f = eslot_feat(s, kEllE);
+                    v[jj] = (elem)(f < 0 ? 0.f : (eslot_glo(s, kEllE) ? le[k][f] : he[k][f]));
+                }
+                feat[base + (size_t)(1 + 3 * k + j) * kLanes] = v;
+            }
+    }
+    // tile maxima of |hi| over the real rows (Ge over the three e_k), the
+    // tile's radius about the origin and its largest scale
+    double rad = 0.0, smax = 0.0;
+    if (valid) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double dk = (double)mu[k] - (double)o[k];
+            d2 += dk * dk;
+            const double a = r[3 + 3 * k], b = r[4 + 3 * k], c = r[5 + 3 * k];
+            smax = fmax(smax, sqrt(a * a + b * b + c * c));
+        }
+        rad = sqrt(d2);
+    }
+    __syncthreads();
+    for (int f = 0; f < kEllF; ++f) red[f][i] = valid ? fabsf(hf[f]) : 0.f;
+    for (int f = 0; f < kEllE; ++f)
+        red[kEllF + f][i] = valid ? fmaxf(fabsf(he[0][f]), fmaxf(fabsf(he[1][f]), fabsf(he[2][f]))) : 0.f;
+    __syncthreads();
+    if (i < kEllF + kEllE) {
+        float v = 0.f;
+        for (int j = 0; j < kPT; ++j) v = fmaxf(v, red[i][j]);
+        meta[t * kEllMeta + 4 + i] = v;
+    }
+    __syncthreads();
+    red[0][i] = (float)(rad * (1.0 + 1e-6));
+    red[1][i] = (float)(smax * (1.0 + 1e-6));
+    __syncthreads();
+    if (i < 2) {
+        float v = 0.f;
+        for (int j = 0; j < kPT; ++j) v = fmaxf(v, red[i][j]);
+        meta[t * kEllMeta + 20 + i] = v;
+    }
+    if (i == 0) {
+        meta[t * kEllMeta + 0] = o[0];
+        meta[t * kEllMeta + 1] = o[1];
+        meta[t * kEllMeta + 2] = o[2];
+        meta[t * kEllMeta + 3] = (float)(1.0 / scale);
+        meta[t * kEllMeta + 22] = meta[t * kEllMeta + 23] = 0.f;
+    }
+}
+
+// B = L^T L of each body record (float32, a fixed order of fused products):
+// xx, yy, zz, xy, xz, yz.  The MFMA form and its fp64 recheck both read it.
+__global__ void ell_bmat_kernel(int q, const float *__restrict__ rec, float *__restrict__ bq)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    const float *L = rec + (size_t)kBodyFloats * j + 3;  // row-major 3 x 3
+    auto b = [&](int p, int m) { return fmaf(L[6 + p], L[6 + m], fmaf(L[3 + p], L[3 + m], L[p] * L[m])); };
+    float *o = bq + (size_t)6 * j;
+    o[0] = b(0, 0);
+    o[1] = b(1, 1);
+    o[2] = b(2, 2);
+    o[3] = b(0, 1);
+    o[4] = b(0, 2);
+    o[5] = b(1, 2);
+}
+
+template <int P>
+struct QFeatE {
+    typename Prec<P>::vec f[3], e[3];
+    float ef, ee;  // E_f, E_e
+};
+
+// Features of the lane's own body (centre, L, B) about tile origin mt,
+// exchanged into Q[0], Q[1] as build_query does; false when a bound is not
+// finite.
+template <int P>
+__device__ __forceinline__ bool build_query_ell(float cx, float cy, float cz, const float (&L)[9], const float (&B)[6],
+                                                float two_n, const float *__restrict__ mt, QFeatE<P> (&Q)[2])
+{
+    using T = Prec<P>;
+    using elem = typename T::elem;
+    const float xp = cx - mt[0], yp = cy - mt[1], zp = cz - mt[2];
+    const float ax = fabsf(xp), ay = fabsf(yp), az = fabsf(zp);
+    const float *Gf = mt + 4, *Ge = mt + 4 + kEllF;
+    const float ue = 3.1f * T::u * T::u + 64.f * kU32;
+    // f_k: [L_k0, L_k1, L_k2, -(L c')_k]; the fp32 error of (L c')_k is within
+    // 4 u32 sum_m |L_km| |c'_m| (its products and the rounding of c')
+    float ef = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float lc = fmaf(L[3 * k + 2], zp, fmaf(L[3 * k + 1], yp, L[3 * k] * xp));
+        const float la = fmaf(fabsf(L[3 * k + 2]), az, fmaf(fabsf(L[3 * k + 1]), ay, fabsf(L[3 * k]) * ax));
+        const float qf[kEllF] = {L[3 * k], L[3 * k + 1], L[3 * k + 2], -lc};
+        float h[kEllF], l[kEllF], s = 0.f, sabs = 0.f;
+#pragma unroll
+        for (int f = 0; f < kEllF; ++f) {
+            h[f] = (float)(elem)qf[f];
+            l[f] = (float)(elem)(qf[f] - h[f]);
+            s = fmaf(fabsf(h[f]), Gf[f], s);
+            sabs += fabsf(h[f]) + Gf[f];
+        }
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            auto slot = [&](int sl) {
+                const int f = eslot_feat(sl, kEllF);
+                return (elem)(f < 0 ? 0.f : (eslot_qlo(sl, kEllF) ? l[f] : h[f]));
+            };
+            Q[0].f[k][jj] = slot(jj);
+            Q[1].f[k][jj] = slot(8 + jj);
+        }
+        ef = fmaxf(ef, ue * s + T::eta * sabs + 4.f * kU32 * Gf[3] * la);
+    }
+    // e_k: 2n / scale [B_pm, -beta_p]; g B within u32 |g B|, g beta_p within
+    // 5 u32 |g| sum_m |B_pm| |c'_m|
+    const float bx = fmaf(B[4], zp, fmaf(B[3], yp, B[0] * xp));
+    const float by = fmaf(B[5], zp, fmaf(B[1], yp, B[3] * xp));
+    const float bz = fmaf(B[2], zp, fmaf(B[5], yp, B[4] * xp));
+    const float Bx = fmaf(fabsf(B[4]), az, fmaf(fabsf(B[3]), ay, fabsf(B[0]) * ax));
+    const float By = fmaf(fabsf(B[5]), az, fmaf(fabsf(B[1]), ay, fabsf(B[3]) * ax));
+    const float Bz = fmaf(fabsf(B[2]), az, fmaf(fabsf(B[5]), ay, fabsf(B[4]) * ax));
+    const float g = two_n * mt[3];
+    const float qe[kEllE] = {g * B[0], g * B[3], g * B[4], g * B[3], g * B[1], g * B[5],
+                             g * B[4], g * B[5], g * B[2], -g * bx, -g * by, -g * bz};
+    float he[kEllE], le[kEllE], se = 0.f, se_abs = 0.f, de = 0.f;
+#pragma unroll
+    for (int f = 0; f < kEllE; ++f) {
+        he[f] = (float)(elem)qe[f];
+        le[f] = (float)(elem)(qe[f] - he[f]);
+        se = fmaf(fabsf(he[f]), Ge[f], se);
+        se_abs += fabsf(he[f]) + Ge[f];
+        if (f < 9) de = fmaf(Ge[f], fabsf(qe[f]), de);
+    }
+    de = kU32 * de + fabsf(g) * (5.f * kU32) * (Ge[9] * Bx + Ge[10] * By + Ge[11] * Bz);
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+        auto slot = [&](int sl) {
+            const int f = eslot_feat(sl, kEllE);
+            return (elem)(f < 0 ? 0.f : (eslot_qlo(sl, kEllE) ? le[f] : he[f]));
+        };
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            Q[0].e[j][jj] = slot(16 * j + jj);
+            Q[1].e[j][jj] = slot(16 * j + 8 + jj);
+        }
+    }
+    const float Ef = 1.1f * ef;
+    const float Ee = 1.1f * (ue * se + T::eta * se_abs + de);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        swap_halves(Q[0].f[k], Q[1].f[k]);
+        swap_halves(Q[0].e[k], Q[1].e[k]);
+    }
+    Q[0].ef = Q[1].ef = Ef;
+    Q[0].ee = Q[1].ee = Ee;
+    swap_halves(Q[0].ef, Q[1].ef);
+    swap_halves(Q[0].ee, Q[1].ee);
+    return isfinite(Ef) && isfinite(Ee) && isfinite(Ef * Ef) && isfinite(Ee * Ee);
+}
+
+// Certification kernel for ellipsoids: the layout of mfma_label_kernel (block
+// = 4 waves x kCB 32-body column blocks; grid = query blocks x S tile splits)
+// with the operands above; labels and counts.  With CULL a column block skips
+// a chunk's two row blocks when each of its bodies is beyond the chunk's
+// reach qk (n s_c + sqrt(n^2 s_c^2 + qa)) plus its radius (qa: the smallest
+// semi-axis squared, qk: largest over smallest, as in the float32 walk).
+template <int P, bool CULL>
+__global__ void __launch_bounds__(256)
+mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *__restrict__ meta, int n_tiles,
+                      int S, int n_qblocks, const float *__restrict__ cull, int n_chunks,
+                      const float *__restrict__ rec, const float *__restrict__ bq, int q, float n_sigma,
+                      int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out,
+                      unsigned long long *__restrict__ blocks_done)
+{
+    using T = Prec<P>;
+    using vec = typename T::vec;
+    static_assert(kCB == 2, "one body per lane builds its features (two column blocks per wave)");
+    int b = blockIdx.x;
+    const int Bn = gridDim.x;
+    if ((Bn & 7) == 0) b = (b & 7) * (Bn >> 3) + (b >> 3);  // XCD-major: one XCD, few splits
+    const int split = b / n_qblocks;
+    const int qb = b - split * n_qblocks;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
+    float cx[kCB], cy[kCB], cz[kCB], qa[kCB], qk[kCB];
+    int jq[kCB];
+#pragma unroll
+    for (int cb = 0; cb < kCB; ++cb) {
+        jq[cb] = qb * kQueriesPerBlock + wave * (32 * kCB) + cb * 32 + col;
+        const int jj = jq[cb] < q ? jq[cb] : q - 1;
+        const float *rj = rec + (size_t)kBodyFloats * jj;
+        cx[cb] = rj[0];
+        cy[cb] = rj[1];
+        cz[cb] = rj[2];
+        qa[cb] = rj[12];
+        qk[cb] = rj[13];
+    }
+    // the lane builds the features of body (h, col)
+    const int own = jq[h] < q ? jq[h] : q - 1;
+    float Lm[9], Bm[6];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Lm[k] = rec[(size_t)kBodyFloats * own + 3 + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Bm[k] = bq[(size_t)6 * own + k];
+    const float ox = h ? cx[1] : cx[0], oy = h ? cy[1] : cy[0], oz = h ? cz[1] : cz[0];
+    const float two_n = 2.f * n_sigma;
+    unsigned long long n_blocks = 0;
+    int lo[kCB] = {0, 0}, hi[kCB] = {0, 0};
+    bool bad = false;
+    const f32x16 zero = {};
+    auto do_tile = [&](int t, const unsigned (&rbm_cb)[kCB]) {
+        const float *mt = meta + (size_t)t * kEllMeta;  // wave-uniform: scalar loads
+        QFeatE<P> Q[2];
+        bad |= !build_query_ell<P>(ox, oy, oz, Lm, Bm, two_n, mt, Q);
+        const vec *ft = feat + (size_t)t * kRB * kEllOps * kLanes + lane;
+        unsigned rbm = rbm_cb[0] | rbm_cb[1];
+        while (rbm) {
+            const int rb = __builtin_ctz(rbm);
+            rbm &= rbm - 1;
+            const vec *fp = ft + (size_t)rb * kEllOps * kLanes;
+            vec G[kEllOps];
+#pragma unroll
+            for (int k = 0; k < kEllOps; ++k) G[k] = fp[(size_t)k * kLanes];
+#pragma unroll
+            for (int cb = 0; cb < kCB; ++cb) {
+                if (!((rbm_cb[cb] >> rb) & 1u)) continue;  // no body of cb near the row block
+                ++n_blocks;
+                // a~ = sum f~_k^2 - 1 and its bound E_a per pair
+                f32x16 A2, Fa;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const f32x16 Fk = T::mfma(G[0], Q[cb].f[k], zero);
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        A2[i] = k == 0 ? Fk[i] * Fk[i] : fmaf(Fk[i], Fk[i], A2[i]);
+                        Fa[i] = k == 0 ? fabsf(Fk[i]) : Fa[i] + fabsf(Fk[i]);
+                    }
+                }
+                const float ef = Q[cb].ef, ee = Q[cb].ee;
+                const float ca = fmaf(3.f * ef, ef, 2.f * kU32);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const float a = A2[i] - 1.f;
+                    A2[i] = a;
+                    Fa[i] = fmaf(2.f * ef, Fa[i], fmaf(fabsf(a), 2.f * kU32, ca));  // E_a
+                }
+                // w~ = sum e~_k^2 and S = sum |e~_k|
+                f32x16 W, Se;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    f32x16 E = T::mfma(G[1 + 3 * k], Q[cb].e[0], zero);
+                    E = T::mfma(G[2 + 3 * k], Q[cb].e[1], E);
+                    E = T::mfma(G[3 + 3 * k], Q[cb].e[2], E);
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        W[i] = k == 0 ? E[i] * E[i] : fmaf(E[i], E[i], W[i]);
+                        Se[i] = k == 0 ? fabsf(E[i]) : Se[i] + fabsf(E[i]);
+                    }
+                }
+                const float ce = 3.f * ee * ee;
+                // w - a|a| (> 0 iff collision) against its certified bound
+                auto fb = [&](int i, float &f, float &bnd) {
+                    const float a = A2[i], aa = fabsf(a), Ea = Fa[i];
+                    const float Ew = fmaf(W[i], 6.f * kU32, fmaf(2.f * ee, Se[i], ce));
+                    f = fmaf(-a, aa, W[i]);
+                    bnd = fmaf(aa, fmaf(aa, 2.f * kU32, 2.f * Ea), fmaf(Ea, Ea, Ew)) * 1.0001f;
+                };
+                bool poss = false;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    float f, bnd;
+                    fb(i, f, bnd);
+                    poss |= f > -bnd;
+                }
+                if (__any(poss)) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        float f, bnd;
+                        fb(i, f, bnd);
+                        lo[cb] += f > bnd;   // certainly in collision
+                        hi[cb] += f > -bnd;  // possibly in collision
+                    }
+                }
+            }
+        }
+    };
+    if constexpr (!CULL) {
+        const unsigned all[kCB] = {0xffffu, 0xffffu};
+        for (int t = split; t < n_tiles; t += S) do_tile(t, all);
+    } else {
+        float wx, wy, wz, spread, qamax;
+        pair::wave_sphere<kCB>(cx, cy, cz, qa, wx, wy, wz, spread, qamax);
+        float qkmax = fmaxf(qk[0], qk[1]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) qkmax = fmaxf(qkmax, __shfl_xor(qkmax, off));
+        qkmax = pair::wave_uniform(qkmax);
+        auto reach_of = [&](const pair::ChunkMeta &m, float a2, float kk) {
+            const float ns = n_sigma * m.smax;
+            return kk * (ns + pair::fast_sqrt(fmaf(ns, ns, a2)));  // ~1 ulp, far inside the culling margin
+        };
+        for (int ib = 0; split + ib * S < n_tiles; ib += 64 / kChunksPerTile) {
+            const int t = split + (ib + lane / kChunksPerTile) * S;
+            const int ci = t * kChunksPerTile + lane % kChunksPerTile;
+            pair::ChunkMeta m{0.f, 0.f, 0.f, 0.f, 0.f};
+            bool pass = false;
+            if (t < n_tiles && ci < n_chunks) {
+                m = pair::load_chunk(cull, ci);
+                pass = pair::within(m, wx, wy, wz, spread + m.rad + reach_of(m, qamax, qkmax));
+            }
+            unsigned long long mask = __ballot(pass);
+            while (mask) {
+                const int g = __builtin_ctzll(mask) / kChunksPerTile;
+                unsigned tm = (unsigned)(mask >> (kChunksPerTile * g)) & ((1u << kChunksPerTile) - 1u);
+                mask &= ~((((unsigned long long)1 << kChunksPerTile) - 1ull) << (kChunksPerTile * g));
+                const int t = split + (ib + g) * S;
+                unsigned rbm[kCB] = {0u, 0u};
+                while (tm) {
+                    const int k = __builtin_ctz(tm);
+                    tm &= tm - 1;
+                    const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
+#pragma unroll
+                    for (int cb = 0; cb < kCB; ++cb)
+                        if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, qa[cb], qk[cb]))))
+                            rbm[cb] |= 3u << (2 * k);
+                }
+                if (rbm[0] | rbm[1]) do_tile(t, rbm);
+            }
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < kCB; ++cb) {
+        lo[cb] += __shfl_xor(lo[cb], 32);
+        hi[cb] += __shfl_xor(hi[cb], 32);
+        // body cb was built by the lanes of half cb
+        const bool other = __shfl_xor((int)bad, 32) != 0;
+        const bool anybad = (h == cb) ? bad : other;
+        if (h == 0 && jq[cb] < q) {
+            lo_out[(size_t)split * q + jq[cb]] = lo[cb];
+            hi_out[(size_t)split * q + jq[cb]] = anybad ? (1 << 29) : hi[cb];
+        }
+    }
+    if (blocks_done && lane == 0) atomicAdd(blocks_done, n_blocks);
+}
+
+// fp64 recheck of the listed bodies: recheck_fp64_kernel's walk with the
+// ellipsoid test (s^2 = |L d|^2, sigma^2 / 4 = |M B d|^2, L and B as the MFMA
+// form took them) and the ellipsoid reach.
+__global__ void __launch_bounds__(64 * kRecheckWaves)
+recheck_ell_fp64_kernel(const float *__restrict__ gauss, int n, const float *__restrict__ cull,
+                        const float *__restrict__ rec, const float *__restrict__ bq, float n_sigma,
+                        const int32_t *__restrict__ list, const int32_t *__restrict__ n_list,
+                        int32_t *__restrict__ exact)
+{
+    const int nl = *n_list;
+    const int tiles = (nl + 63) / 64;
+    const long items = (long)tiles * kRecheckSplits;
+    const int n_chunks = (n + pair::kCull - 1) / pair::kCull;
+    const int lane = (int)(threadIdx.x & 63u);
+    const double four_n2 = 4.0 * (double)n_sigma * (double)n_sigma;
+    const long wave0 = (long)blockIdx.x * kRecheckWaves + (long)(threadIdx.x >> 6);
+    const long waves = (long)gridDim.x * kRecheckWaves;
+    for (long item = wave0; item < items; item += waves) {
+        const int tile = (int)(item / kRecheckSplits), split = (int)(item - (long)tile * kRecheckSplits);
+        const int li = tile * 64 + lane;
+        const bool valid = li < nl;
+        const int j = list[valid ? li : nl - 1];
+        const float *rj = rec + (size_t)kBodyFloats * j;
+        float fc[3][1] = {{rj[0]}, {rj[1]}, {rj[2]}};
+        float fa[1] = {rj[12]};
+        const float fk = rj[13];
+        float Bm[6], Lm[9];
+        for (int k = 0; k < 6; ++k) Bm[k] = bq[(size_t)6 * j + k];
+        for (int k = 0; k < 9; ++k) Lm[k] = rj[3 + k];
+        int cnt = 0;
+        auto chunk = [&](int ci, unsigned long long qmask) {
+            const int g = ci * pair::kCull + lane;
+            const bool real = g < n;
+            const float *p = gauss + (size_t)kGaussFloats * (real ? g : n - 1);
+            double mu[3], M[9];
+            for (int k = 0; k < 3; ++k) mu[k] = p[k];
+            for (int k = 0; k < 9; ++k) M[k] = p[3 + k];
+            while (qmask) {
+                const int b = __builtin_ctzll(qmask);
+                qmask &= qmask - 1;
+                const double cx = pair::lane_value(fc[0][0], b), cy = pair::lane_value(fc[1][0], b),
+                             cz = pair::lane_value(fc[2][0], b);
+                double B[6], L[9];
+                for (int k = 0; k < 6; ++k) B[k] = pair::lane_value(Bm[k], b);
+                for (int k = 0; k < 9; ++k) L[k] = pair::lane_value(Lm[k], b);
+                const double dx = mu[0] - cx, dy = mu[1] - cy, dz = mu[2] - cz;
+                const double f0 = L[0] * dx + L[1] * dy + L[2] * dz;
+                const double f1 = L[3] * dx + L[4] * dy + L[5] * dz;
+                const double f2 = L[6] * dx + L[7] * dy + L[8] * dz;
+                const double a = f0 * f0 + f1 * f1 + f2 * f2 - 1.0;
+                const double ux = B[0] * dx + B[3] * dy + B[4] * dz;
+                const double uy = B[3] * dx + B[1] * dy + B[5] * dz;
+                const double uz = B[4] * dx + B[5] * dy + B[2] * dz;
+                const double e0 = M[0] * ux + M[1] * uy + M[2] * uz;
+                const double e1 = M[3] * ux + M[4] * uy + M[5] * uz;
+                const double e2 = M[6] * ux + M[7] * uy + M[8] * uz;
+                const bool hit = real && a * fabs(a) < four_n2 * (e0 * e0 + e1 * e1 + e2 * e2);
+                const int hcount = __popcll(__ballot(hit));
+                if (lane == b) cnt += hcount;
+            }
+        };
+        const unsigned long long vmask = __ballot(valid);
+        if (cull) {
+            float wx, wy, wz, spread, amax;
+            pair::wave_sphere<1>(fc[0], fc[1], fc[2], fa, wx, wy, wz, spread, amax);
+            float kmax = fk;
+            for (int off = 32; off >= 1; off >>= 1) kmax = fmaxf(kmax, __shfl_xor(kmax, off));
+            kmax = pair::wave_uniform(kmax);
+            auto reach_of = [&](const pair::ChunkMeta &m, float a2, float kk) {
+                const float ns = n_sigma * m.smax;
+                return kk * (ns + pair::fast_sqrt(fmaf(ns, ns, a2)));
+            };
+            for (int ib = 0; split + ib * kRecheckSplits < n_chunks; ib += 64) {
+                const int ci = split + (ib + lane) * kRecheckSplits;
+                pair::ChunkMeta m{0.f, 0.f, 0.f, 0.f, 0.f};
+                bool pass = false;
+                if (ci < n_chunks) {
+                    m = pair::load_chunk(cull, ci);
+                    pass = pair::within(m, wx, wy, wz, spread + m.rad + reach_of(m, amax, kmax));
+                }
+                unsigned long long mask = __ballot(pass);
+                while (mask) {
+                    const int bit = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    const pair::ChunkMeta k = pair::lane_chunk(m, bit);
+                    const bool near = pair::within(k, fc[0][0], fc[1][0], fc[2][0], k.rad + reach_of(k, fa[0], fk));
+                    const unsigned long long qmask = __ballot(near) & vmask;
+                    if (qmask) chunk(split + (ib + bit) * kRecheckSplits, qmask);
+                }
+            }
+        } else {
+            for (int ci = split; ci < n_chunks; ci += kRecheckSplits) chunk(ci, vmask);
+        }
+        if (valid && cnt) atomicAdd(exact + li, cnt);
+    }
+}
+
 template <int P>
 csplat_status build_one(csplat_ctx *ctx, csplat_scene *sc, void **feat_out)
 {
@@ -882,6 +1452,11 @@ csplat_status build_one(csplat_ctx *ctx, csplat_scene *sc, void **feat_out)
 
 }  // namespace
 
+namespace {
+template <int P>
+csplat_status build_ell_one(csplat_ctx *ctx, csplat_scene *sc, void **feat_out);
+}  // namespace
+
 csplat_status precision_build(csplat_ctx *ctx, csplat_scene *sc, uint32_t features)
 {
     sc->n_tiles = (sc->n + kPT - 1) / kPT;
@@ -898,6 +1473,20 @@ csplat_status precision_build(csplat_ctx *ctx, csplat_scene *sc, uint32_t featur
         if (s != CSPLAT_OK) return s;
         sc->feat_fp16 = out[0];
         sc->meta_fp16 = static_cast<float *>(out[1]);
+    }
+    if (features & CSPLAT_FEATURES_ELL_BF16) {
+        void *out[2];
+        csplat_status s = build_ell_one<CSPLAT_PRECISION_BF16_RECHECK>(ctx, sc, out);
+        if (s != CSPLAT_OK) return s;
+        sc->feat_ell_bf16 = out[0];
+        sc->meta_ell_bf16 = static_cast<float *>(out[1]);
+    }
+    if (features & CSPLAT_FEATURES_ELL_FP16) {
+        void *out[2];
+        csplat_status s = build_ell_one<CSPLAT_PRECISION_FP16_RECHECK>(ctx, sc, out);
+        if (s != CSPLAT_OK) return s;
+        sc->feat_ell_fp16 = out[0];
+        sc->meta_ell_fp16 = static_cast<float *>(out[1]);
     }
     return CSPLAT_OK;
 }
@@ -1131,6 +1720,157 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
         CSPLAT_HIP(hipGetLastError());
     }
     ctx->stats.min_passes = want_min ? passes : 0;
+    if (ctx->timing) {
+        ctx->timed = true;
+        ctx->timed_ms = total_ms;
+    }
+    return CSPLAT_OK;
+}
+
+namespace {
+template <int P>
+csplat_status build_ell_one(csplat_ctx *ctx, csplat_scene *sc, void **feat_out)
+{
+    using vec = typename Prec<P>::vec;
+    const int64_t nt = (sc->n + kPT - 1) / kPT;
+    float *meta = nullptr;
+    CSPLAT_HIP(hipMallocAsync(&meta, (size_t)nt * kEllMeta * sizeof(float), ctx->stream));
+    vec *feat = nullptr;
+    const size_t fbytes = (size_t)nt * kRB * kEllOps * kLanes * sizeof(vec);
+    hipError_t e = hipMallocAsync(&feat, fbytes, ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(meta, ctx->stream);
+        return hip_fail(e, "ellipsoid precision features");
+    }
+    build_tiles_ell_kernel<P><<<(unsigned)nt, kPT, 0, ctx->stream>>>(sc->gauss, sc->n, meta, feat);
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) le = hipStreamSynchronize(ctx->stream);
+    if (le != hipSuccess) {
+        (void)hipFreeAsync(meta, ctx->stream);
+        (void)hipFreeAsync(feat, ctx->stream);
+        return hip_fail(le, "build_tiles_ell_kernel");
+    }
+    feat_out[0] = feat;
+    feat_out[1] = meta;
+    sc->device_bytes += fbytes + (uint64_t)nt * kEllMeta * sizeof(float);
+    return CSPLAT_OK;
+}
+
+void launch_mfma_ell(int precision, bool cull, dim3 grid, hipStream_t st, const csplat_scene *sc, int n_qblocks,
+                     int S, int n_chunks, const float *rec, const float *bq, int q, float nv, int32_t *lo, int32_t *hi,
+                     unsigned long long *blocks)
+{
+    const int n_tiles = (int)sc->n_tiles;
+    if (precision == CSPLAT_PRECISION_BF16_RECHECK) {
+        const auto *f = static_cast<const bf16x8 *>(sc->feat_ell_bf16);
+        if (cull)
+            mfma_ell_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, true><<<grid, 256, 0, st>>>(
+                f, sc->meta_ell_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, blocks);
+        else
+            mfma_ell_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, false><<<grid, 256, 0, st>>>(
+                f, sc->meta_ell_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, blocks);
+    } else {
+        const auto *f = static_cast<const f16x8 *>(sc->feat_ell_fp16);
+        if (cull)
+            mfma_ell_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, true><<<grid, 256, 0, st>>>(
+                f, sc->meta_ell_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, blocks);
+        else
+            mfma_ell_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, false><<<grid, 256, 0, st>>>(
+                f, sc->meta_ell_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, blocks);
+    }
+}
+}  // namespace
+
+csplat_status precision_eval_ell(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *rec_in,
+                                 const EvalParams &p, const EvalOut &out, int precision)
+{
+    const int q = (int)q64;
+    const int n = (int)sc->n;
+    const int m = p.m;
+    hipStream_t st = ctx->stream;
+    const int n_tiles = (int)sc->n_tiles;
+    const int n_qblocks = (q + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    const int S = mfma_splits(ctx, q, n_tiles);
+    const int n_chunks = (n + pair::kCull - 1) / pair::kCull;
+    const bool cull = p.cull && n > 0 && sc->cull;
+    const float *rec = rec_in;
+    const int32_t *perm = nullptr;
+    unsigned long long *blocks = nullptr;
+    if (cull) {
+        SortedQueries sq;
+        csplat_status s = sort_bodies(ctx, sc, q, rec_in, nullptr, true, &sq);
+        if (s != CSPLAT_OK) return s;
+        rec = sq.c;
+        perm = sq.perm;
+        blocks = sq.counter;  // 32 x 32 MFMA blocks evaluated (every n_sigma)
+        ctx->chunk_counter = sq.counter;
+        ctx->pairs_per_chunk = 32 * 32;
+    }
+    // workspace: lo/hi partials, the recheck list, exact counts, flags, B of
+    // every body, compaction scratch
+    size_t sel_bytes = 0;
+    CSPLAT_HIP(hipcub::DeviceSelect::Flagged(nullptr, sel_bytes, hipcub::CountingInputIterator<int32_t>(0),
+                                             (const uint8_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, q,
+                                             st));
+    const size_t part = (size_t)S * q;
+    const size_t off_list = 2 * part * 4, off_exact = off_list + (size_t)q * 4, off_flag = off_exact + (size_t)q * 4,
+                 off_bq = (off_flag + (size_t)q + 255) & ~(size_t)255,
+                 off_sel = (off_bq + (size_t)q * 24 + 255) & ~(size_t)255;
+    hipError_t e = ctx->partial.reserve(off_sel + sel_bytes + 256);
+    if (e != hipSuccess) return hip_fail(e, "precision workspace");
+    char *base = ctx->partial.as<char>();
+    int32_t *lo = reinterpret_cast<int32_t *>(base);
+    int32_t *hi = lo + part;
+    int32_t *list = reinterpret_cast<int32_t *>(base + off_list);
+    int32_t *exact = reinterpret_cast<int32_t *>(base + off_exact);
+    uint8_t *flag = reinterpret_cast<uint8_t *>(base + off_flag);
+    float *bq = reinterpret_cast<float *>(base + off_bq);
+    void *sel_tmp = base + off_sel;
+    e = ctx->flags.reserve((size_t)CSPLAT_MAX_M * sizeof(int32_t) + 64);
+    if (e != hipSuccess) return hip_fail(e, "flag counters");
+    int32_t *n_list = ctx->flags.as<int32_t>();
+    CSPLAT_HIP(zero_words(n_list, CSPLAT_MAX_M, st));
+    const unsigned qb = (unsigned)((q + 255) / 256);
+    ell_bmat_kernel<<<qb, 256, 0, st>>>(q, rec, bq);
+    CSPLAT_HIP(hipGetLastError());
+    ctx->stats.splits = S;
+    ctx->stats.queries_per_lane = 2;
+    ctx->stats.kernel_pairs = (int64_t)q * n;
+    ctx->flag_counts = n_list;
+    ctx->flag_m = m;
+    float total_ms = 0.f;
+    for (int v = 0; v < m; ++v) {
+        const float nv = p.n_sigma[v];
+        if (n_tiles > 0) {
+            if (ctx->timing) (void)hipEventRecord(ctx->ev0, st);
+            launch_mfma_ell(precision, cull, dim3((unsigned)(n_qblocks * S)), st, sc, n_qblocks, S, n_chunks, rec,
+                            bq, q, nv, lo, hi, blocks);
+            CSPLAT_HIP(hipGetLastError());
+            if (ctx->timing) {
+                float ms = 0.f;
+                (void)hipEventRecord(ctx->ev1, st);
+                CSPLAT_HIP(hipEventSynchronize(ctx->ev1));
+                CSPLAT_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+                total_ms += ms;
+            }
+        }
+        decide_kernel<<<qb, 256, 0, st>>>(q, n_tiles > 0 ? S : 0, m, v, p.k, out.count != nullptr, lo, hi, perm,
+                                          out.label, out.count, flag);
+        CSPLAT_HIP(hipGetLastError());
+        CSPLAT_HIP(hipcub::DeviceSelect::Flagged(sel_tmp, sel_bytes, hipcub::CountingInputIterator<int32_t>(0), flag,
+                                                 list, n_list + v, q, st));
+        CSPLAT_HIP(zero_words(exact, (size_t)q, st));
+        if (n > 0)
+            recheck_ell_fp64_kernel<<<kRecheckGrid, 64 * kRecheckWaves, 0, st>>>(
+                sc->gauss, n, cull ? sc->cull : nullptr, rec, bq, nv, list, n_list + v, exact);
+        finish_kernel<<<qb, 256, 0, st>>>(m, v, p.k, list, n_list + v, exact, perm, out.label, out.count);
+        CSPLAT_HIP(hipGetLastError());
+        ctx->rk_list = list;
+        ctx->rk_n = n_list + v;
+        ctx->rk_perm = perm;
+        ctx->rk_q = q;
+    }
+    ctx->stats.min_passes = 0;
     if (ctx->timing) {
         ctx->timed = true;
         ctx->timed_ms = total_ms;

@@ -356,13 +356,14 @@ csplat_status scene_build(csplat_ctx *ctx, int64_t n, const float *means, const 
 void scene_release(csplat_scene *sc, hipStream_t st)
 {
     if (!sc) return;
-    void *ptrs[] = {sc->gauss, sc->cull, sc->feat_bf16, sc->meta_bf16, sc->feat_fp16, sc->meta_fp16};
+    void *ptrs[] = {sc->gauss,         sc->cull,          sc->feat_bf16,     sc->meta_bf16,    sc->feat_fp16,
+                    sc->meta_fp16,     sc->feat_ell_bf16, sc->meta_ell_bf16, sc->feat_ell_fp16, sc->meta_ell_fp16};
     for (void *p : ptrs)
         if (p) (void)hipFreeAsync(p, st);
     sc->gauss = nullptr;
     sc->cull = nullptr;
-    sc->feat_bf16 = sc->feat_fp16 = nullptr;
-    sc->meta_bf16 = sc->meta_fp16 = nullptr;
+    sc->feat_bf16 = sc->feat_fp16 = sc->feat_ell_bf16 = sc->feat_ell_fp16 = nullptr;
+    sc->meta_bf16 = sc->meta_fp16 = sc->meta_ell_bf16 = sc->meta_ell_fp16 = nullptr;
 }
 
 }  // namespace csplat
