@@ -378,6 +378,16 @@ csplat_status csplat_server_submit(csplat_server *srv, int32_t scene_id, int32_t
                                    const float *centers, const float *radii,
                                    const csplat_reduce_opts *opts, const float *n_sigma,
                                    int32_t m, uint64_t *ticket);
+/* The same for q ellipsoidal bodies (Eq. 5-6, host arrays as in
+ * csplat_eval_ellipsoids: centres q x 3, (w, x, y, z) quaternions q x 4,
+ * semi-axes q x 3).  The bodies are prepared on the device by the kernel
+ * csplat_eval_ellipsoids uses, so the results are the same bits as that call
+ * with one conservatism value.  Errors: those of csplat_server_submit, and
+ * CSPLAT_E_INVALID for the body checks of csplat_eval_ellipsoids. */
+csplat_status csplat_server_submit_ellipsoids(csplat_server *srv, int32_t scene_id, int32_t kind, int64_t q,
+                                              const float *centers, const float *quats, const float *axes,
+                                              const csplat_reduce_opts *opts, const float *n_sigma, int32_t m,
+                                              uint64_t *ticket);
 /* Non-blocking: CSPLAT_E_PENDING while queued or running; CSPLAT_OK once
  * done, after copying the non-NULL outputs (host pointers, q x 1 each) and
  * forgetting the ticket; CSPLAT_E_CANCELLED (ticket forgotten);

@@ -50,6 +50,7 @@ EXPORTS = (
     "csplat_server_submit", "csplat_server_poll", "csplat_server_wait", "csplat_server_cancel",
     "csplat_server_stats", "csplat_server_latencies", "csplat_eval_noalloc", "csplat_last_rechecked",
     "csplat_rrt_create", "csplat_rrt_destroy", "csplat_rrt_step", "csplat_rrt_nodes", "csplat_rrt_last_edges",
+    "csplat_server_submit_ellipsoids",
 )
 CSPLAT_SERVE_COST = 0
 CSPLAT_SERVE_LABELS = 1
@@ -145,6 +146,7 @@ def load_library(path: str = LIB_PATH):
         "csplat_server_destroy": [P],
         "csplat_server_add_scene": [P, P, P],
         "csplat_server_submit": [P, I32, I32, I64, P, P, P, P, I32, P],
+        "csplat_server_submit_ellipsoids": [P, I32, I32, I64, P, P, P, P, P, I32, P],
         "csplat_server_poll": [P, ctypes.c_uint64, P],
         "csplat_server_wait": [P, ctypes.c_uint64, P, I64],
         "csplat_server_cancel": [P, ctypes.c_uint64],
@@ -421,6 +423,21 @@ def csplat_server_submit(srv, scene_id, kind, centers, radii, opts: ReduceOpts, 
     _check(load_library().csplat_server_submit(srv, scene_id, kind, c.shape[0], _addr(c) if c.size else None,
                                                _addr(r) if r.size else None, ctypes.byref(opts), _addr(ns),
                                                ns.size, ctypes.byref(t)))
+    return t.value
+
+
+def csplat_server_submit_ellipsoids(srv, scene_id, kind, centers, quats, axes, opts: ReduceOpts, n_sigma) -> int:
+    """Ellipsoidal bodies (host arrays: centres q x 3, quaternions q x 4,
+    semi-axes q x 3); otherwise as csplat_server_submit."""
+    c = np.ascontiguousarray(centers, np.float32)
+    qt = np.ascontiguousarray(quats, np.float32)
+    ax = np.ascontiguousarray(axes, np.float32)
+    ns = np.ascontiguousarray(np.atleast_1d(n_sigma), np.float32)
+    t = ctypes.c_uint64()
+    nz = c.shape[0] > 0
+    _check(load_library().csplat_server_submit_ellipsoids(srv, scene_id, kind, c.shape[0], _addr(c) if nz else None,
+                                                          _addr(qt) if nz else None, _addr(ax) if nz else None,
+                                                          ctypes.byref(opts), _addr(ns), ns.size, ctypes.byref(t)))
     return t.value
 
 

@@ -226,6 +226,8 @@ __global__ void check_queries_kernel(int64_t q, const float *__restrict__ c, con
     if (!ok) *bad = 1;  // every writer stores the same value
 }
 
+}  // namespace
+
 // Ellipsoidal bodies: finite centres, finite nonzero quaternions, finite
 // semi-axes > 0.
 bool bodies_valid_host(int64_t q, const float *c, const float *quat, const float *ax)
@@ -242,6 +244,8 @@ bool bodies_valid_host(int64_t q, const float *c, const float *quat, const float
     }
     return true;
 }
+
+namespace {
 
 __global__ void check_bodies_kernel(int64_t q, const float *__restrict__ c, const float *__restrict__ quat,
                                     const float *__restrict__ ax, int *bad)

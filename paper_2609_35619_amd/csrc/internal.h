@@ -303,6 +303,12 @@ csplat_status sort_workspace_bytes(int q, bool ell, hipStream_t st, size_t *byte
 // semi-axes (q x 3), all device pointers, on the context stream.
 csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const float *quats, const float *axes,
                              float *rec);
+// Host-side check of ellipsoidal bodies: finite centres, finite nonzero
+// quaternions, finite semi-axes > 0.
+bool bodies_valid_host(int64_t q, const float *c, const float *quat, const float *ax);
+// The same on any stream (the serving form's copy stream).
+hipError_t prepare_bodies_on(hipStream_t st, int q, const float *centers, const float *quats, const float *axes,
+                             float *rec);
 
 // pair_fp32.hip: the float32 pair kernel and the split combine.
 // `gate`, when given, runs after the pair kernel is queued and before

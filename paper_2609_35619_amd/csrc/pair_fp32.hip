@@ -253,9 +253,16 @@ csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const 
 csplat_status prepare_bodies(csplat_ctx *ctx, int q, const float *centers, const float *quats, const float *axes,
                              float *rec)
 {
-    body_prep_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, quats, axes, rec);
-    CSPLAT_HIP(hipGetLastError());
+    CSPLAT_HIP(prepare_bodies_on(ctx->stream, q, centers, quats, axes, rec));
     return CSPLAT_OK;
+}
+
+hipError_t prepare_bodies_on(hipStream_t st, int q, const float *centers, const float *quats, const float *axes,
+                             float *rec)
+{
+    if (q <= 0) return hipSuccess;
+    body_prep_kernel<<<(unsigned)((q + 255) / 256), 256, 0, st>>>(q, centers, quats, axes, rec);
+    return hipGetLastError();
 }
 
 namespace {

@@ -32,7 +32,7 @@ using serve::Scheduler;
 using serve::State;
 using serve::StepPlan;
 
-constexpr int kVariants = 4;        // 0 labels/no ball, 1 labels/ball, 2 full/no ball, 3 full/ball
+constexpr int kVariants = 8;        // bit 0: a ball; bit 1: full outputs; bit 2: ellipsoidal bodies
 constexpr int kStepBlocks = 2048;   // persistent grid of each step kernel (8 blocks per CU)
 constexpr int kMaxItems = 16384;    // work items per step
 constexpr int kMaxSlots = 64;
@@ -77,7 +77,7 @@ struct StageLayout {
     }
 };
 
-template <bool FULL, bool BALL>
+template <bool FULL, bool BALL, bool ELL>
 __device__ __forceinline__ void step_body(const char *__restrict__ stage, int variant, size_t desc_off,
                                           size_t items_off, int32_t *__restrict__ next)
 {
@@ -101,26 +101,27 @@ __device__ __forceinline__ void step_body(const char *__restrict__ stage, int va
         if (it >= b1) break;
         const Item w = items[it];
         const ReqDesc &R = reqs[__builtin_amdgcn_readfirstlane(w.slot)];
-        eval_tile<1, FULL, BALL, QPL, CULL>(R.gs, R.n, R.S, R.G, __builtin_amdgcn_readfirstlane(w.split),
+        eval_tile<1, FULL, BALL, QPL, CULL, ELL>(R.gs, R.n, R.S, R.G, __builtin_amdgcn_readfirstlane(w.split),
                                             __builtin_amdgcn_readfirstlane(w.tile), R.centers, R.radii, R.q, R.p,
                                             R.part, R.cull, nullptr);
     }
 }
 
-template <bool FULL, bool BALL>
+template <bool FULL, bool BALL, bool ELL>
 __global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const char *__restrict__ stage, int variant,
                                                                           size_t desc_off, size_t items_off,
                                                                           int32_t *__restrict__ next)
 {
-    step_body<FULL, BALL>(stage, variant, desc_off, items_off, next);
+    step_body<FULL, BALL, ELL>(stage, variant, desc_off, items_off, next);
 }
 
 // Full outputs over a ball (the task walk), at its own occupancy target.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CSPLAT_TASK_WAVES_PER_EU)))
+template <bool ELL>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(task_waves_per_eu<1, true, ELL>())))
 step_task_kernel(const char *__restrict__ stage, int variant, size_t desc_off, size_t items_off,
                  int32_t *__restrict__ next)
 {
-    step_body<true, true>(stage, variant, desc_off, items_off, next);
+    step_body<true, true, ELL>(stage, variant, desc_off, items_off, next);
 }
 
 __global__ void __launch_bounds__(256) serve_combine_kernel(const char *__restrict__ stage, size_t desc_off)
@@ -168,13 +169,15 @@ struct Rec {
     int32_t scene = 0, kind = 0;
     int64_t q = 0;
     std::vector<float> centers, radii;  // until admission, in curve order
+    std::vector<float> quats, axes;     // ellipsoidal bodies: orientation and semi-axes, the same order
     std::vector<int32_t> perm;          // curve position -> the caller's query index
     EvalParams p{};
     SplitPlan sp{};
-    bool full = false, ball = false;
+    bool full = false, ball = false, ell = false;
     int64_t pairs = 0;
-    // arena layout of the request
-    size_t d_centers = 0, d_radii = 0, d_part = 0;
+    // arena layout of the request (ellipsoids: the prepared body records at
+    // d_centers, the raw bodies uploaded at d_raw)
+    size_t d_centers = 0, d_raw = 0, d_part = 0;
     size_t h_in = 0, h_label = 0, h_count = 0, h_min = 0, h_soft = 0, h_cost = 0, h_nbr = 0;
 };
 
@@ -242,22 +245,43 @@ void setup_request(csplat_server *s, int64_t t)
     Rec &r = s->recs[t];
     const size_t qn = (size_t)r.q;
     char *hbase = s->host_arena + ri->host_off;
-    std::memcpy(hbase + r.h_in, r.centers.data(), qn * 12);
-    std::memcpy(hbase + r.h_in + qn * 12, r.radii.data(), qn * 4);
+    char *dbase = s->dev_arena + ri->dev_off;
+    if (!r.ell) {
+        std::memcpy(hbase + r.h_in, r.centers.data(), qn * 12);
+        std::memcpy(hbase + r.h_in + qn * 12, r.radii.data(), qn * 4);
+        if (qn) {
+            hipError_t e = hipMemcpyAsync(dbase + r.d_centers, hbase + r.h_in, qn * 16, hipMemcpyHostToDevice,
+                                          s->copy_stream);
+            if (e != hipSuccess) set_fatal(s, e, "input upload");
+            s->copies_pending = true;
+        }
+    } else {
+        // the raw bodies, then their records prepared on the device by the
+        // kernel csplat_eval_ellipsoids uses (the same bits)
+        std::memcpy(hbase + r.h_in, r.centers.data(), qn * 12);
+        std::memcpy(hbase + r.h_in + qn * 12, r.quats.data(), qn * 16);
+        std::memcpy(hbase + r.h_in + qn * 28, r.axes.data(), qn * 12);
+        if (qn) {
+            char *raw = dbase + r.d_raw;
+            hipError_t e = hipMemcpyAsync(raw, hbase + r.h_in, qn * 40, hipMemcpyHostToDevice, s->copy_stream);
+            if (e == hipSuccess)
+                e = prepare_bodies_on(s->copy_stream, (int)qn, reinterpret_cast<const float *>(raw),
+                                      reinterpret_cast<const float *>(raw + qn * 12),
+                                      reinterpret_cast<const float *>(raw + qn * 28),
+                                      reinterpret_cast<float *>(dbase + r.d_centers));
+            if (e != hipSuccess) set_fatal(s, e, "input upload");
+            s->copies_pending = true;
+        }
+    }
     std::vector<float>().swap(r.centers);
     std::vector<float>().swap(r.radii);
-    char *dbase = s->dev_arena + ri->dev_off;
-    if (qn) {
-        hipError_t e = hipMemcpyAsync(dbase + r.d_centers, hbase + r.h_in, qn * 16, hipMemcpyHostToDevice,
-                                      s->copy_stream);
-        if (e != hipSuccess) set_fatal(s, e, "input upload");
-        s->copies_pending = true;
-    }
+    std::vector<float>().swap(r.quats);
+    std::vector<float>().swap(r.axes);
     const csplat_scene *sc = s->scenes[(size_t)r.scene];
     ReqDesc d{};
     d.gs = sc->gauss;
     d.centers = reinterpret_cast<const float *>(dbase + r.d_centers);
-    d.radii = reinterpret_cast<const float *>(dbase + r.d_centers + qn * 12);
+    d.radii = r.ell ? nullptr : reinterpret_cast<const float *>(dbase + r.d_centers + qn * 12);
     d.n = (int32_t)sc->n;
     d.per_split = r.sp.per_split;
     d.S = r.sp.S;
@@ -401,10 +425,14 @@ csplat_status capture_graphs(csplat_server *s)
         int32_t *ctr = reinterpret_cast<StepHeader *>(s->stage_dev[k])->next;
         const size_t dof = s->layout.desc, iof = s->layout.items;
         if (e == hipSuccess) {
-            step_kernel<false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 0, dof, iof, ctr + 0);
-            step_kernel<false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 1, dof, iof, ctr + 1);
-            step_kernel<true, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 2, dof, iof, ctr + 2);
-            step_task_kernel<<<kStepBlocks, kBlock, 0, s->stream>>>(st, 3, dof, iof, ctr + 3);
+            step_kernel<false, false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 0, dof, iof, ctr + 0);
+            step_kernel<false, true, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 1, dof, iof, ctr + 1);
+            step_kernel<true, false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 2, dof, iof, ctr + 2);
+            step_task_kernel<false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 3, dof, iof, ctr + 3);
+            step_kernel<false, false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 4, dof, iof, ctr + 4);
+            step_kernel<false, true, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 5, dof, iof, ctr + 5);
+            step_kernel<true, false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 6, dof, iof, ctr + 6);
+            step_task_kernel<true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 7, dof, iof, ctr + 7);
             serve_combine_kernel<<<1024, 256, 0, s->stream>>>(st, dof);
             e = hipGetLastError();
         }
@@ -521,13 +549,16 @@ csplat_status csplat_server_add_scene(csplat_server *s, const csplat_scene *sc, 
     return CSPLAT_OK;
 }
 
-csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t kind, int64_t q,
-                                   const float *centers, const float *radii, const csplat_reduce_opts *opts,
-                                   const float *n_sigma, int32_t m, uint64_t *ticket)
+// Spheres (centres, radii) or, with quats, ellipsoidal bodies (centres,
+// quats, axes); host arrays.
+static csplat_status submit_impl(csplat_server *s, int32_t scene_id, int32_t kind, int64_t q, const float *centers,
+                                 const float *radii, const float *quats, const float *axes,
+                                 const csplat_reduce_opts *opts, const float *n_sigma, int32_t m, uint64_t *ticket)
 {
     // latency counts from entry: validation, the host-side sort and the copy
     // below are part of what the caller waits for
     const double t_entry = now_s();
+    const bool ell = quats != nullptr;
     if (!s || !opts || !n_sigma || !ticket) return fail(CSPLAT_E_INVALID, "server_submit: NULL argument");
     *ticket = 0;
     if (kind != CSPLAT_SERVE_COST && kind != CSPLAT_SERVE_LABELS)
@@ -538,13 +569,22 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     if (opts->precision != CSPLAT_PRECISION_FP32)
         return fail(CSPLAT_E_INVALID, "server_submit: the serving form evaluates in float32");
     if (q < 0 || q > (int64_t)0x7FFFFFFF / 8) return fail(CSPLAT_E_INVALID, "server_submit: q out of range");
-    if (q > 0 && (!centers || !radii)) return fail(CSPLAT_E_INVALID, "server_submit: NULL centers or radii");
-    if (q > 0 && (pointer_kind(centers) || pointer_kind(radii)))
-        return fail(CSPLAT_E_INVALID, "server_submit: inputs must be host pointers");
-    for (int64_t j = 0; j < q; ++j) {
-        if (!std::isfinite(centers[3 * j]) || !std::isfinite(centers[3 * j + 1]) ||
-            !std::isfinite(centers[3 * j + 2]) || !(radii[j] > 0.f) || !std::isfinite(radii[j]))
-            return fail(CSPLAT_E_INVALID, "server_submit: query centres must be finite and radii finite and > 0");
+    if (!ell) {
+        if (q > 0 && (!centers || !radii)) return fail(CSPLAT_E_INVALID, "server_submit: NULL centers or radii");
+        if (q > 0 && (pointer_kind(centers) || pointer_kind(radii)))
+            return fail(CSPLAT_E_INVALID, "server_submit: inputs must be host pointers");
+        for (int64_t j = 0; j < q; ++j) {
+            if (!std::isfinite(centers[3 * j]) || !std::isfinite(centers[3 * j + 1]) ||
+                !std::isfinite(centers[3 * j + 2]) || !(radii[j] > 0.f) || !std::isfinite(radii[j]))
+                return fail(CSPLAT_E_INVALID, "server_submit: query centres must be finite and radii finite and > 0");
+        }
+    } else {
+        if (q > 0 && (!centers || !axes)) return fail(CSPLAT_E_INVALID, "server_submit_ellipsoids: NULL body array");
+        if (q > 0 && (pointer_kind(centers) || pointer_kind(quats) || pointer_kind(axes)))
+            return fail(CSPLAT_E_INVALID, "server_submit_ellipsoids: inputs must be host pointers");
+        if (!bodies_valid_host(q, centers, quats, axes))
+            return fail(CSPLAT_E_INVALID, "server_submit_ellipsoids: centres must be finite, quaternions finite and "
+                                          "nonzero, semi-axes finite and > 0");
     }
     Rec r;
     csplat_status st = build_params(n_sigma, 1, *opts, r.p);
@@ -564,7 +604,8 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     r.q = q;
     r.full = kind == CSPLAT_SERVE_COST;
     r.ball = std::isfinite(r.p.rn2);
-    r.sp = split_plan(target_blocks(s->device), (int)q, (int)sc->n, r.full, r.ball);
+    r.ell = ell;
+    r.sp = split_plan(target_blocks(s->device), (int)q, (int)sc->n, r.full, r.ball, ell);
     r.pairs = q * sc->n;
     // the queries in the scene's Hilbert order (as csplat_eval evaluates
     // them): waves hold nearby spheres and the culling skips more; results
@@ -595,21 +636,33 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
         }
         r.perm.resize(qn);
         r.centers.resize(qn * 3);
-        r.radii.resize(qn);
+        if (ell) {
+            r.quats.resize(qn * 4);
+            r.axes.resize(qn * 3);
+        } else {
+            r.radii.resize(qn);
+        }
         parallel_rows(qn, [&](size_t j0, size_t j1) {
             for (size_t j = j0; j < j1; ++j) {
                 const int32_t i = (int32_t)(a[j] & 0xffffffffu);
                 r.perm[j] = i;
                 for (int k = 0; k < 3; ++k) r.centers[3 * j + k] = centers[3 * (size_t)i + k];
-                r.radii[j] = radii[i];
+                if (ell) {
+                    for (int k = 0; k < 4; ++k) r.quats[4 * j + k] = quats[4 * (size_t)i + k];
+                    for (int k = 0; k < 3; ++k) r.axes[3 * j + k] = axes[3 * (size_t)i + k];
+                } else {
+                    r.radii[j] = radii[i];
+                }
             }
         });
     }
     const size_t qn = (size_t)q;
     const int parts = std::max(r.sp.parts, 1);
-    // device arena: inputs, then partial reductions
+    // device arena: inputs (ellipsoids: records, then the raw bodies), then
+    // partial reductions
     r.d_centers = 0;
-    r.d_part = align256(qn * 16);
+    r.d_raw = ell ? align256(qn * kBodyFloats * 4) : 0;
+    r.d_part = ell ? r.d_raw + align256(qn * 40) : align256(qn * 16);
     const uint64_t dev_bytes = r.d_part + align256((size_t)parts * qn * part_words(1, r.full) * 4);
     // pinned host arena: input staging, then outputs
     size_t off = 0;
@@ -618,7 +671,7 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
         off += align256(b);
         return o;
     };
-    r.h_in = take(qn * 16);
+    r.h_in = take(qn * (ell ? 40 : 16));
     r.h_label = take(qn);
     r.h_count = take(qn * 4);
     if (r.full) {
@@ -630,7 +683,7 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     ReqSpec spec;
     spec.tiles = r.sp.n_tiles;
     spec.splits = parts;  // work items per tile
-    spec.variant = (r.full ? 2 : 0) + (r.ball ? 1 : 0);
+    spec.variant = (ell ? 4 : 0) + (r.full ? 2 : 0) + (r.ball ? 1 : 0);
     spec.item_pairs = (int64_t)kBlock * r.sp.qpl * r.sp.per_split;
     spec.dev_bytes = dev_bytes;
     spec.host_bytes = off;
@@ -648,6 +701,24 @@ csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t k
     lk.unlock();
     s->cv_work.notify_all();
     return CSPLAT_OK;
+}
+
+csplat_status csplat_server_submit(csplat_server *s, int32_t scene_id, int32_t kind, int64_t q,
+                                   const float *centers, const float *radii, const csplat_reduce_opts *opts,
+                                   const float *n_sigma, int32_t m, uint64_t *ticket)
+{
+    return submit_impl(s, scene_id, kind, q, centers, radii, nullptr, nullptr, opts, n_sigma, m, ticket);
+}
+
+csplat_status csplat_server_submit_ellipsoids(csplat_server *s, int32_t scene_id, int32_t kind, int64_t q,
+                                              const float *centers, const float *quats, const float *axes,
+                                              const csplat_reduce_opts *opts, const float *n_sigma, int32_t m,
+                                              uint64_t *ticket)
+{
+    if (q > 0 && !quats) return fail(CSPLAT_E_INVALID, "server_submit_ellipsoids: NULL quaternions");
+    static const float kNoBody[4] = {1.f, 0.f, 0.f, 0.f};
+    return submit_impl(s, scene_id, kind, q, centers, nullptr, quats ? quats : kNoBody, axes, opts, n_sigma, m,
+                       ticket);
 }
 
 static csplat_status collect(csplat_server *s, int64_t t, const csplat_outputs *out)

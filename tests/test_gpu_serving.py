@@ -256,3 +256,60 @@ def test_edge_requests(cs, env):
     finally:
         cs.csplat_server_destroy(srv)
         cs.csplat_scene_free(empty_scene)
+
+
+def test_ellipsoid_requests_in_a_mix(cs, env, oracle_mod):
+    """Ellipsoidal bodies (chain-link MPPI batches and labels) served together
+    with sphere requests: each equals csplat_eval_ellipsoids bit for bit (its
+    bodies are prepared on the device by the same kernel), and a sample
+    agrees with the oracle."""
+    from workloads import Bodies, random_ellipsoids
+    eng, scenes, handles = env
+    _say("case: ellipsoid and sphere requests in one serving mix")
+    rng = np.random.default_rng(31)
+    srv = cs.csplat_server_create(0, 512 << 20, 8)
+    try:
+        ids = [cs.csplat_server_add_scene(srv, h) for h in handles]
+        sph = _stream(6, seed=107, scale=0.3)
+        jobs = []
+        for i in range(6):
+            b = random_ellipsoids(int(rng.integers(500, 20_000)), seed=600 + i, box=(10.0, 10.0, 3.0),
+                                  axis_range=(0.03, 0.2))
+            kind = cs.CSPLAT_SERVE_COST if i % 2 == 0 else cs.CSPLAT_SERVE_LABELS
+            ns = float(rng.uniform(0.5, 2.0))
+            jobs.append(("ell", i % 2, kind, b, ns,
+                         cs.csplat_server_submit_ellipsoids(srv, ids[i % 2], kind, b.centers, b.quats, b.axes,
+                                                            _opts(cs, kind), ns)))
+            r = sph[i]
+            k2 = cs.CSPLAT_SERVE_COST if r["kind"] == "mppi" else cs.CSPLAT_SERVE_LABELS
+            jobs.append(("sph", r["scene"], k2, r, r["n_sigma"],
+                         cs.csplat_server_submit(srv, ids[r["scene"]], k2, r["centers"], r["radii"], _opts(cs, k2),
+                                                 r["n_sigma"])))
+        outs = []
+        for typ, sc_i, kind, b, ns, t in jobs:
+            q = b.q if typ == "ell" else b["centers"].shape[0]
+            outs.append(cs.csplat_server_wait(srv, t, q, kind))
+        st = cs.csplat_server_stats(srv)
+        assert st["completed"] == len(jobs)
+        with pytest.raises(cs.CsplatError) as ei:
+            bad = random_ellipsoids(4, seed=1)
+            bad.axes[2, 1] = 0.0
+            cs.csplat_server_submit_ellipsoids(srv, ids[0], cs.CSPLAT_SERVE_LABELS, bad.centers, bad.quats, bad.axes,
+                                               _opts(cs, cs.CSPLAT_SERVE_LABELS), 1.0)
+        assert ei.value.status == cs.CSPLAT_E_INVALID
+    finally:
+        cs.csplat_server_destroy(srv)
+    for (typ, sc_i, kind, b, ns, t), got in zip(jobs, outs):
+        if typ != "ell":
+            continue
+        eng.set_conservatism([ns])
+        want = ("label", "count", "min", "softmin", "cost", "nbr") if kind == cs.CSPLAT_SERVE_COST else ("label", "count")
+        ev = eng.evaluate_ellipsoids(handles[sc_i], b.centers, b.quats, b.axes, _opts(cs, kind), want)
+        for k in got:
+            assert np.array_equal(got[k].reshape(np.asarray(ev[k]).shape).view(np.uint8),
+                                  np.asarray(ev[k]).view(np.uint8)), (k, b.q)
+        sub = np.arange(0, b.q, max(1, b.q // 30))
+        o = _opts(cs, kind)
+        ref = oracle_mod.evaluate_ellipsoids(scenes[sc_i], b.subset(sub), [ns], alpha_f=0.05, extent_f=0.1, k=2,
+                                             tau=o.softmin_tau, r_nbr=o.neighbor_radius)
+        compare({k: v[sub] for k, v in got.items()}, ref, tau=o.softmin_tau, gamma=1.0, where=f"serve-ell-{b.q}")
