@@ -394,6 +394,7 @@ def ellipsoids(cs, eng, steps):
     cs.csplat_ctx_set_timing(eng.ctx, False)
     nbr = int(out["nbr"].cpu().numpy().astype(np.int64).sum())
     cs.csplat_scene_free(h)
+    labels = ellipsoid_labels(cs, eng, sc, b, p)
     ops = (ops_full_in_ball(m) + 18) * nbr   # L d, L^T e: +18 over a sphere
     tight = OPS_ALL_PAIRS * int(st["kernel_pairs"]) + (OPS_ELL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr
     kernel_s = float(np.mean(kms)) / 1e3
@@ -405,7 +406,92 @@ def ellipsoids(cs, eng, steps):
                          "unit": "Gop/s", "frac": ops / kernel_s / PEAK_VALU, "kernel_ms": kernel_s * 1e3,
                          "ops_per_unit": ops_full_in_ball(m) + 18, "unit_of_work": "pair inside the 0.4 m ball",
                          "units_per_launch": nbr, "frac_tight_count": tight / kernel_s / PEAK_VALU,
-                         "evaluated_pairs": int(st["kernel_pairs"])}}
+                         "evaluated_pairs": int(st["kernel_pairs"])},
+            "labels_every_gaussian": labels}
+
+
+# The ellipsoid MFMA kernel per 32 x 32 block: one MFMA for each f_k and three
+# for each e_k (32 x 32 x 16 each), and per pair about 25 VALU operations of
+# epilogue (the squares and sums of f~ and e~, the bounds, the test, the counts).
+FLOP_MFMA_ELL_BLOCK = 12 * 32 * 32 * 16 * 2
+OPS_MFMA_ELL_EPILOGUE = 25
+
+
+def ellipsoid_labels(cs, eng, sc, b, p):
+    """Labels and counts of the same link ellipsoids over every kept Gaussian
+    (n_sigma 1, k 2) in float32, bf16 and fp16 (the MFMA forms: certified
+    bound, fp64 recheck), their time, recheck rate and agreement with the
+    FP64 oracle on 256 seeded bodies plus up to 256 rechecked ones."""
+    import torch
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import compare
+    h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"],
+                       precision_features=cs.CSPLAT_FEATURES_ELL_BF16 | cs.CSPLAT_FEATURES_ELL_FP16)
+    eng.set_conservatism([1.0])
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (b.centers, b.quats, b.axes)]
+    res, outs = {}, {}
+    for name, prec in (("fp32", cs.CSPLAT_PRECISION_FP32), ("bf16", cs.CSPLAT_PRECISION_BF16_RECHECK),
+                       ("fp16", cs.CSPLAT_PRECISION_FP16_RECHECK)):
+        opts = cs.reduce_opts(k=2, r_nbr=math.inf, precision=prec)
+        out = eng.alloc_outputs(b.q, ("label", "count"))
+        eng.evaluate_ellipsoids(h, *t, opts, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            eng.evaluate_ellipsoids(h, *t, opts, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        cs.csplat_ctx_set_timing(eng.ctx, True)
+        eng.evaluate_ellipsoids(h, *t, opts, out=out)
+        st = cs.csplat_last_stats(eng.ctx)
+        rk = cs.csplat_last_rechecked(eng.ctx)
+        cs.csplat_ctx_set_timing(eng.ctx, False)
+        torch.cuda.synchronize()
+        outs[name] = ({k: v.cpu().numpy() for k, v in out.items()}, rk)
+        d = {"ms": dt * 1e3, "kernel_ms": st["kernel_ms"], "rechecked_bodies": int(rk.size)}
+        # labels alone (the RRT's question): a body is certain once its
+        # bracket of counts decides count > k
+        lab = eng.alloc_outputs(b.q, ("label",))
+        eng.evaluate_ellipsoids(h, *t, opts, out=lab)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            eng.evaluate_ellipsoids(h, *t, opts, out=lab)
+        torch.cuda.synchronize()
+        d["labels_only_ms"] = (time.perf_counter() - t0) / 5 * 1e3
+        d["labels_only_rechecked_bodies"] = int(cs.csplat_last_rechecked(eng.ctx).size)
+        assert np.array_equal(lab["label"].cpu().numpy(), outs[name][0]["label"])
+        if prec == cs.CSPLAT_PRECISION_FP32:
+            d["evaluated_pairs"] = int(st["kernel_pairs"])
+        else:
+            blocks = int(st["kernel_pairs"]) // 1024
+            k_s = st["kernel_ms"] / 1e3
+            d["mfma_blocks_32x32"] = blocks
+            d["roofline_mfma"] = {"bound": "mfma", "achieved": FLOP_MFMA_ELL_BLOCK * blocks / k_s / 1e12,
+                                  "peak": PEAK_MFMA_BF16 / 1e12, "unit": "TFLOP/s",
+                                  "frac": FLOP_MFMA_ELL_BLOCK * blocks / k_s / PEAK_MFMA_BF16}
+            d["roofline_valu"] = {"bound": "alu", "ops_per_unit": OPS_MFMA_ELL_EPILOGUE, "unit_of_work":
+                                  "pair of an evaluated 32 x 32 block", "units_per_launch": blocks * 1024,
+                                  "frac": OPS_MFMA_ELL_EPILOGUE * blocks * 1024 / k_s / PEAK_VALU}
+        res[name] = d
+    cs.csplat_scene_free(h)
+    rng = np.random.default_rng(61)
+    sample = np.sort(rng.choice(b.q, 256, replace=False))
+    rk_all = np.unique(np.concatenate([outs["bf16"][1], outs["fp16"][1]]))
+    if rk_all.size > 256:
+        rk_all = np.sort(rng.choice(rk_all, 256, replace=False))
+    idx = np.unique(np.concatenate([sample, rk_all])).astype(np.int64)
+    ref = oracle.evaluate_ellipsoids(sc, b.subset(idx), [1.0], alpha_f=p["alpha_f"], extent_f=p["extent_f"], k=2)
+    for name in res:
+        got = {k: v[idx] for k, v in outs[name][0].items()}
+        s = compare(got, ref, tau=0.0, gamma=1.0, where=f"ell-labels-{name}")
+        amb = ref["ambiguous"].astype(bool)
+        res[name]["oracle_sample"] = int(idx.size)
+        res[name]["label_flips_vs_oracle_outside_band"] = int(((got["label"] != ref["label"]) & ~amb).sum())
+        res[name]["count_exact_fraction"] = s.get("count_exact")
+    res["workload"] = "the same link ellipsoids, labels and counts over every kept Gaussian, n_sigma 1, k 2"
+    return res
 
 
 def paper_context(cs, eng):
