@@ -22,6 +22,20 @@ namespace csplat {
 namespace pair {
 
 constexpr int kBlock = 256;
+// Threads of a full-output task block (its waves' splits are folded into
+// one partial record; labels and the wave walk keep kBlock).  Eight waves
+// (512) halve the partials again but measured slower: 0.893 against 0.868 ms
+// on the navigation batch, 23.2 against 21.7 ms on the manipulation batch.
+#ifndef CSPLAT_FULL_TASK_BLOCK
+#define CSPLAT_FULL_TASK_BLOCK 256
+#endif
+constexpr int kFullTaskBlock = CSPLAT_FULL_TASK_BLOCK;
+static_assert(kFullTaskBlock == 256 || kFullTaskBlock == 512, "four or eight waves per full-output task block");
+template <bool FULL>
+constexpr int task_block()
+{
+    return FULL ? kFullTaskBlock : kBlock;
+}
 constexpr int kChunk = 512;  // Gaussians per first-level softmin/cost sum
 constexpr int kCull = 64;    // Gaussians per culling chunk (consecutive on the curve)
 constexpr int kPiece = kChunk / kCull;  // culling chunks per first-level sum
@@ -387,8 +401,8 @@ __device__ __forceinline__ void split_walk(const float *__restrict__ groups, con
 {
     const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr bool AHEAD = LABELS;
-    __shared__ unsigned long long s_near[LABELS ? 1 : kBlock / 64][LABELS ? 1 : 64];
-    __shared__ int s_near_at[LABELS ? 1 : kBlock / 64][LABELS ? 1 : 64];
+    __shared__ unsigned long long s_near[LABELS ? 1 : kFullTaskBlock / 64][LABELS ? 1 : 64];
+    __shared__ int s_near_at[LABELS ? 1 : kFullTaskBlock / 64][LABELS ? 1 : 64];
     const bool by_group = LABELS && S <= kGroup;
     const int n_units = by_group ? n_groups : n_chunks;
     const int stride = by_group ? 1 : S;
@@ -739,14 +753,14 @@ __device__ __forceinline__ void eval_tile_tasks(const float *__restrict__ gs, in
     static_assert(FULL && BALL, "labels run in eval_tile_label_tasks");
     constexpr int kRing = 128;  // queued tasks per wave: at most 63 waiting + 64 of one sub-chunk
     constexpr int PW = task_words<M, FULL>();
-    constexpr int kWaves = kBlock / 64;
+    constexpr int kWaves = kFullTaskBlock / 64;
     __shared__ int s_task[kWaves][kRing];              // sub-chunk of each queued task
     __shared__ unsigned char s_owner[kWaves][kRing];   // lane of its query
     __shared__ float4 s_part[kWaves][64 * PW / 4];     // partials of a round, PW words per task
     const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     // wave wv: the (wv / G)-th 64 queries of the tile, split item G + wv % G
     const int split = item * G + wv % G;
-    const int jq = tile * (kBlock / G) + (wv / G) * 64 + lane;
+    const int jq = tile * (kFullTaskBlock / G) + (wv / G) * 64 + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
     TaskQuery<ELL> own;
     if constexpr (ELL) {
@@ -948,7 +962,7 @@ __device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__
     static_assert(KQ == 2, "the slot masks hold one bit per entry: two queries per entry");
     constexpr int kRing = 128;  // queued entries per wave: at most 63 waiting + 64 / KQ of one sub-chunk
     constexpr int PW = task_words<M, FULL>();
-    constexpr int kWaves = kBlock / 64;
+    constexpr int kWaves = kFullTaskBlock / 64;
     constexpr unsigned char kNone = 0xFF;
     __shared__ int s_task[kWaves][kRing];                  // sub-chunk of each queued entry
     __shared__ unsigned char s_q[kWaves][KQ][kRing];       // lanes of its queries, kNone for an empty slot
@@ -956,7 +970,7 @@ __device__ __forceinline__ void eval_tile_tasks_shared(const float *__restrict__
     const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     // wave wv: the (wv / G)-th 64 queries of the tile, split item G + wv % G
     const int split = item * G + wv % G;
-    const int jq = tile * (kBlock / G) + (wv / G) * 64 + lane;
+    const int jq = tile * (kFullTaskBlock / G) + (wv / G) * 64 + lane;
     const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
     TaskQuery<ELL> own;
     if constexpr (ELL) {
@@ -1664,7 +1678,8 @@ constexpr int task_waves_per_eu()
 }
 
 template <int M, bool FULL, bool BALL, bool CULL, bool ELL>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(task_waves_per_eu<M, FULL, ELL>())))
+__global__ void __launch_bounds__(task_block<FULL>())
+__attribute__((amdgpu_waves_per_eu(task_waves_per_eu<M, FULL, ELL>())))
 pair_task_kernel(const float *__restrict__ gs, int n, int S, int G, int n_tiles, const float *__restrict__ centers,
                  const float *__restrict__ radii, int q, const EvalParams p, Part part,
                  const float *__restrict__ cull, unsigned long long *__restrict__ task_count)
@@ -1901,25 +1916,29 @@ combine_kernel(int q, int S, const EvalParams p, Part part, EvalOut out, const i
 }
 
 #ifndef CSPLAT_FULL_GROUP
-#define CSPLAT_FULL_GROUP 4
+#define CSPLAT_FULL_GROUP (CSPLAT_FULL_TASK_BLOCK / 64)
 #endif
-constexpr int kFullGroup = CSPLAT_FULL_GROUP;  // splits merged per full-output work item (1, 2 or 4)
+constexpr int kFullGroup = CSPLAT_FULL_GROUP;  // splits merged per full-output work item, at most
 constexpr int kMaxSplitChunks = 2048;          // culling chunks per split of a full-output plan, at most
-static_assert(kFullGroup == 1 || kFullGroup == 2 || kFullGroup == 4, "a work item holds four waves");
+constexpr int kGroupMinSplits = 16;            // splits from which full-output work items fold several
+static_assert(kFullGroup >= 1 && kFullGroup <= kFullTaskBlock / 64 && (kFullTaskBlock / 64) % kFullGroup == 0,
+              "the groups of a work item divide its waves");
 
 // How an evaluation of q queries against n Gaussians is cut into work items.
 // The Gaussian chunks form S splits (split s takes every S-th chunk from s),
 // enough to fill the device several times over with at least 16 chunks per
-// split.  A work item is a block of four waves: with G = 1, kBlock x QPL
-// queries against one split; with G = 4 (full outputs as tasks), 64 queries
-// against G consecutive splits, merged in LDS into one partial record, so
-// the partials hold S / G records per query.  Depends only on (q, n, mode,
+// split.  A work item is a block: with G = 1, kBlock x QPL queries against
+// one split; for full outputs as tasks over at least kGroupMinSplits splits,
+// groups of G waves that take 64 queries against G consecutive splits,
+// merged in LDS into one partial record, so the partials hold S / G records
+// per query.  Depends only on (q, n, mode,
 // device), so a request gives the same partial reductions wherever it runs.
 // per_split: Gaussians of the largest split.
 struct SplitPlan {
     int n_tiles, S, per_split, qpl;
-    int G;      // splits per work item (full outputs as tasks: 4 when S allows, else 1)
+    int G;      // splits per work item (full outputs as tasks: up to kFullGroup when S allows, else 1)
     int parts;  // partial records per query: S / G
+    int block;  // threads of a work item
 };
 
 inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool ball, bool ell = false)
@@ -1941,13 +1960,25 @@ inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool bal
         if (full) S = std::max(S, (n_chunks + kMaxSplitChunks - 1) / kMaxSplitChunks);
         S = std::max(1, std::min(S, n_chunks / 16));
     }
-    // full outputs as tasks merge the splits of four waves in LDS (a work
-    // item: 64 queries x 4 splits); S rounds up to a multiple of four
-    sp.G = full && tasks && S >= kFullGroup ? kFullGroup : 1;
+    // full outputs as tasks over many splits merge the splits of a block's
+    // waves in LDS (a work item: 64 queries x G splits); S rounds up to a
+    // multiple of G.  Over few splits (much work per split) a block keeps
+    // four query tiles on one split: its waves share the split's records,
+    // and none waits for the others' splits before the block retires (the
+    // manipulation batch, S = 6: 15.7 ms with one split per item, 21.2 with
+    // four).
+    sp.block = full && tasks ? kFullTaskBlock : kBlock;
+    sp.G = 1;
+    if (full && tasks && S >= kGroupMinSplits)
+        for (int g = kFullGroup; g > 1; g >>= 1)
+            if (S >= g) {
+                sp.G = g;
+                break;
+            }
     if (sp.G > 1) S = (S + sp.G - 1) / sp.G * sp.G;
     sp.S = S;
     sp.parts = S / sp.G;
-    sp.n_tiles = (q + kBlock / sp.G * sp.qpl - 1) / (kBlock / sp.G * sp.qpl);
+    sp.n_tiles = (q + sp.block / sp.G * sp.qpl - 1) / (sp.block / sp.G * sp.qpl);
     sp.per_split = S > 0 ? (n_chunks + S - 1) / S * kCull : 0;
     return sp;
 }

@@ -54,10 +54,10 @@ void launch_pair(const Launch &L)
             pair_kernel<M, FULL, BALL, QPL, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
                 L.gs, L.n, L.S, L.G, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
         else if (L.ell)
-            pair_task_kernel<M, FULL, BALL, CULL, true><<<L.grid, kBlock, 0, L.st>>>(
+            pair_task_kernel<M, FULL, BALL, CULL, true><<<L.grid, task_block<FULL>(), 0, L.st>>>(
                 L.gs, L.n, L.S, L.G, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
         else
-            pair_task_kernel<M, FULL, BALL, CULL, false><<<L.grid, kBlock, 0, L.st>>>(
+            pair_task_kernel<M, FULL, BALL, CULL, false><<<L.grid, task_block<FULL>(), 0, L.st>>>(
                 L.gs, L.n, L.S, L.G, L.n_tiles, L.c, L.r, L.q, L.p, L.part, L.cull, L.chunk_count);
     } else {
         if (L.ell)

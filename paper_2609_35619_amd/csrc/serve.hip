@@ -115,9 +115,16 @@ __global__ void __launch_bounds__(kBlock) CSPLAT_OCCUPANCY step_kernel(const cha
     step_body<FULL, BALL, ELL>(stage, variant, desc_off, items_off, next);
 }
 
-// Full outputs over a ball (the task walk), at its own occupancy target.
+// Full outputs over a ball (the task walk, eight-wave blocks; ellipsoids
+// without it: the wave walk, kBlock), at its own occupancy target.
 template <bool ELL>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(task_waves_per_eu<1, true, ELL>())))
+constexpr int full_ball_block()
+{
+    return uses_tasks<true, true, 1, ELL>() ? kFullTaskBlock : kBlock;
+}
+template <bool ELL>
+__global__ void __launch_bounds__(full_ball_block<ELL>())
+__attribute__((amdgpu_waves_per_eu(task_waves_per_eu<1, true, ELL>())))
 step_task_kernel(const char *__restrict__ stage, int variant, size_t desc_off, size_t items_off,
                  int32_t *__restrict__ next)
 {
@@ -428,11 +435,11 @@ csplat_status capture_graphs(csplat_server *s)
             step_kernel<false, false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 0, dof, iof, ctr + 0);
             step_kernel<false, true, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 1, dof, iof, ctr + 1);
             step_kernel<true, false, false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 2, dof, iof, ctr + 2);
-            step_task_kernel<false><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 3, dof, iof, ctr + 3);
+            step_task_kernel<false><<<kStepBlocks, full_ball_block<false>(), 0, s->stream>>>(st, 3, dof, iof, ctr + 3);
             step_kernel<false, false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 4, dof, iof, ctr + 4);
             step_kernel<false, true, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 5, dof, iof, ctr + 5);
             step_kernel<true, false, true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 6, dof, iof, ctr + 6);
-            step_task_kernel<true><<<kStepBlocks, kBlock, 0, s->stream>>>(st, 7, dof, iof, ctr + 7);
+            step_task_kernel<true><<<kStepBlocks, full_ball_block<true>(), 0, s->stream>>>(st, 7, dof, iof, ctr + 7);
             serve_combine_kernel<<<1024, 256, 0, s->stream>>>(st, dof);
             e = hipGetLastError();
         }
@@ -684,7 +691,7 @@ static csplat_status submit_impl(csplat_server *s, int32_t scene_id, int32_t kin
     spec.tiles = r.sp.n_tiles;
     spec.splits = parts;  // work items per tile
     spec.variant = (ell ? 4 : 0) + (r.full ? 2 : 0) + (r.ball ? 1 : 0);
-    spec.item_pairs = (int64_t)kBlock * r.sp.qpl * r.sp.per_split;
+    spec.item_pairs = (int64_t)r.sp.block * r.sp.qpl * r.sp.per_split;
     spec.dev_bytes = dev_bytes;
     spec.host_bytes = off;
     // the sort above ran without the lock (the worker keeps scheduling)
