@@ -381,19 +381,25 @@ constexpr int kFine = 16;                // Gaussians per task
 constexpr int kFinePer = kCull / kFine;  // sub-chunks per culling chunk
 constexpr int kGroup = 16;               // culling chunks per group (the task walk's coarsest level)
 
-// The task walk's culling.  Split `split` of S takes the chunks split,
-// split + S, ... (< n_chunks) as in cull_walk, visited in ascending order:
-// visit(c, lanes) for chunk c with the mask of its near lanes.  When S <= 16
-// every group of 16 chunks holds chunks of every split, and the walk goes
-// through the groups instead: 64 groups at a time against the wave
-// (`coarse`), then the split's chunks of a surviving group (`coarse` again),
-// then each surviving chunk against every query of the wave (`near`).  A
-// walk with a short reach (labels) culls nearly every batch, and the group
-// level cuts its batches by up to 16/S.  With AHEAD the next batch is
-// requested before the current one is tested (for walks that are mostly
-// culled; it holds five more registers).  The group level and AHEAD are
-// compiled in with LABELS only (full outputs over a 1 m ball rarely cull a
-// group, and the registers they hold would spill the full-output kernel).
+// The task walk's culling: visit(c, lanes) for each chunk c of split `split`
+// (of S) whose bounding sphere reaches some query of the wave, with the mask
+// of its near lanes, in ascending order.
+//  * Full outputs: split s takes the chunks s, s + S, ... (< n_chunks) as in
+//    cull_walk: 64 of them at a time against the wave (`coarse`), then each
+//    survivor against every query of the wave (`near`).
+//  * Labels: split s takes the groups of 16 chunks s, s + S, ..., each with
+//    all of its chunks: 64 groups at a time against the wave (`coarse`), then
+//    the 16 chunks of a surviving group (`coarse` again), then each surviving
+//    chunk against every query (`near`).  A walk with a short reach culls
+//    nearly every batch; dealing whole groups to the splits means that the
+//    splits of a query tile together scan each group and open each near group
+//    once (with strided chunks every split scanned every group and opened
+//    every near group for its one or two chunks in it, which made the scan
+//    most of the label kernel's time).  With AHEAD the next batch is
+//    requested before the current one is tested (it holds five more
+//    registers).  The group level and AHEAD are compiled in with LABELS only
+//    (full outputs over a 1 m ball rarely cull a group, and the registers
+//    they hold would spill the full-output kernel).
 template <bool LABELS, class Coarse, class Near, class Visit>
 __device__ __forceinline__ void split_walk(const float *__restrict__ groups, const float *__restrict__ chunks,
                                            int n_groups, int n_chunks, int split, int S, Coarse coarse, Near near,
@@ -403,10 +409,9 @@ __device__ __forceinline__ void split_walk(const float *__restrict__ groups, con
     constexpr bool AHEAD = LABELS;
     __shared__ unsigned long long s_near[LABELS ? 1 : kFullTaskBlock / 64][LABELS ? 1 : 64];
     __shared__ int s_near_at[LABELS ? 1 : kFullTaskBlock / 64][LABELS ? 1 : 64];
-    const bool by_group = LABELS && S <= kGroup;
+    constexpr bool by_group = LABELS;
     const int n_units = by_group ? n_groups : n_chunks;
-    const int stride = by_group ? 1 : S;
-    const int first = by_group ? 0 : split;
+    const int stride = S, first = split;
     const float *meta = by_group ? groups : chunks;
     auto fetch = [&](int ib, ChunkMeta &m) {
         const int u = first + (ib + lane) * stride;
@@ -435,15 +440,14 @@ __device__ __forceinline__ void split_walk(const float *__restrict__ groups, con
             unsigned long long cmask = mask;
             int c0 = first + ib * stride, cs = stride;
             if (by_group) {
-                // the split's chunks of group gi: gi*16 <= c < gi*16 + 16, c = split (mod S)
-                const int gi = ib + __builtin_ctzll(gmask);
-                const int base = gi * kGroup;
-                c0 = base + ((split - base) % S + S) % S;
-                cs = S;
-                const int c = c0 + lane * S;
+                // the chunks of group gi: gi*16 <= c < gi*16 + 16, one per lane
+                const int gi = first + (ib + __builtin_ctzll(gmask)) * stride;
+                c0 = gi * kGroup;
+                cs = 1;
+                const int c = c0 + lane;
                 bool cok = false;
                 cm = ChunkMeta{0.f, 0.f, 0.f, 0.f, 0.f};
-                if (c < base + kGroup && c < n_chunks) {
+                if (lane < kGroup && c < n_chunks) {
                     cm = load_chunk(chunks, c);
                     cok = coarse(cm);
                 }
