@@ -281,11 +281,12 @@ __device__ __forceinline__ ChunkMeta lane_chunk(const ChunkMeta &m, int lane)
 }
 
 // Bounding sphere of every query the wave holds (centre w = middle of their
-// bounding box, radius `spread`) and their largest r^2.
+// bounding box, radius `spread`) and their largest r^2; with `half`, also the
+// half extents of that box about w.
 template <int QPL>
 __device__ __forceinline__ void wave_sphere(const float (&cx)[QPL], const float (&cy)[QPL], const float (&cz)[QPL],
                                             const float (&r2)[QPL], float &wx, float &wy, float &wz, float &spread,
-                                            float &r2max)
+                                            float &r2max, float *half = nullptr)
 {
     float lo[3] = {cx[0], cy[0], cz[0]}, hi[3] = {cx[0], cy[0], cz[0]};
     r2max = r2[0];
@@ -308,6 +309,11 @@ __device__ __forceinline__ void wave_sphere(const float (&cx)[QPL], const float 
     // after the butterflies every lane holds the same values
     wx = wave_uniform(0.5f * (lo[0] + hi[0])), wy = wave_uniform(0.5f * (lo[1] + hi[1]));
     wz = wave_uniform(0.5f * (lo[2] + hi[2])), r2max = wave_uniform(r2max);
+    if (half) {
+        half[0] = wave_uniform(fmaxf(hi[0] - wx, wx - lo[0]));
+        half[1] = wave_uniform(fmaxf(hi[1] - wy, wy - lo[1]));
+        half[2] = wave_uniform(fmaxf(hi[2] - wz, wz - lo[2]));
+    }
     spread = 0.f;
 #pragma unroll
     for (int u = 0; u < QPL; ++u) {
@@ -324,6 +330,21 @@ __device__ __forceinline__ void wave_sphere(const float (&cx)[QPL], const float 
 __device__ __forceinline__ bool within(const ChunkMeta &m, float x, float y, float z, float reach)
 {
     const float ex = m.x - x, ey = m.y - y, ez = m.z - z;
+    const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+    const float thr = reach * kCullMargin;
+    return d2 <= thr * thr;
+}
+
+// The culling test of a chunk against a box of centre b and half extents h:
+// the distance from the chunk centre to the box at most (reach + extra), with
+// the relative margin kCullMargin.  Every query in the box lies at least that
+// far from the centre, so a chunk that fails lies beyond `reach` of them all.
+__device__ __forceinline__ bool within_box(const ChunkMeta &m, float bx, float by, float bz, const float *h,
+                                           float reach)
+{
+    const float ex = fmaxf(fabsf(m.x - bx) - h[0], 0.f);
+    const float ey = fmaxf(fabsf(m.y - by) - h[1], 0.f);
+    const float ez = fmaxf(fabsf(m.z - bz) - h[2], 0.f);
     const float d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
     const float thr = reach * kCullMargin;
     return d2 <= thr * thr;
@@ -380,26 +401,30 @@ __device__ __forceinline__ void cull_walk(const float *__restrict__ cull, int n_
 constexpr int kFine = 16;                // Gaussians per task
 constexpr int kFinePer = kCull / kFine;  // sub-chunks per culling chunk
 constexpr int kGroup = 16;               // culling chunks per group (the task walk's coarsest level)
+constexpr int kGroupDealChunks = 1024;   // chunks per split above which label walks deal whole groups
 
 // The task walk's culling: visit(c, lanes) for each chunk c of split `split`
 // (of S) whose bounding sphere reaches some query of the wave, with the mask
 // of its near lanes, in ascending order.
-//  * Full outputs: split s takes the chunks s, s + S, ... (< n_chunks) as in
-//    cull_walk: 64 of them at a time against the wave (`coarse`), then each
-//    survivor against every query of the wave (`near`).
-//  * Labels: split s takes the groups of 16 chunks s, s + S, ..., each with
-//    all of its chunks: 64 groups at a time against the wave (`coarse`), then
-//    the 16 chunks of a surviving group (`coarse` again), then each surviving
-//    chunk against every query (`near`).  A walk with a short reach culls
-//    nearly every batch; dealing whole groups to the splits means that the
-//    splits of a query tile together scan each group and open each near group
-//    once (with strided chunks every split scanned every group and opened
-//    every near group for its one or two chunks in it, which made the scan
-//    most of the label kernel's time).  With AHEAD the next batch is
-//    requested before the current one is tested (it holds five more
-//    registers).  The group level and AHEAD are compiled in with LABELS only
-//    (full outputs over a 1 m ball rarely cull a group, and the registers
-//    they hold would spill the full-output kernel).
+//  * Split s takes the chunks s, s + S, ... (< n_chunks) as in cull_walk: 64
+//    of them at a time against the wave (`coarse`), then each survivor
+//    against every query of the wave (`near`).
+//  * Labels with more than kGroupDealChunks chunks per split: split s takes
+//    the groups of 16 chunks s, s + S, ..., each with all of its chunks: 64
+//    groups at a time against the wave (`coarse`), then the 16 chunks of a
+//    surviving group (`coarse` again), then each surviving chunk against
+//    every query (`near`).  A walk with a short reach culls nearly every
+//    batch, so over a large scene its time goes into the batches: dealt
+//    whole groups, the splits of a query tile together scan each group and
+//    open each near group once (precision workload: labels 1.39 -> 1.08 ms).
+//    Over a small scene the splits are many and short, a query tile's near
+//    groups would fall on a few of them, and strided chunks spread its work
+//    more evenly (a 200k-Gaussian scene over 64 splits: 0.52 ms with strided
+//    chunks, 0.61 with dealt groups).
+// With AHEAD the next batch is requested before the current one is tested
+// (it holds five more registers).  The group level and AHEAD are compiled in
+// with LABELS only (full outputs over a 1 m ball rarely cull a group, and the
+// registers they hold would spill the full-output kernel).
 template <bool LABELS, class Coarse, class Near, class Visit>
 __device__ __forceinline__ void split_walk(const float *__restrict__ groups, const float *__restrict__ chunks,
                                            int n_groups, int n_chunks, int split, int S, Coarse coarse, Near near,
@@ -409,7 +434,7 @@ __device__ __forceinline__ void split_walk(const float *__restrict__ groups, con
     constexpr bool AHEAD = LABELS;
     __shared__ unsigned long long s_near[LABELS ? 1 : kFullTaskBlock / 64][LABELS ? 1 : 64];
     __shared__ int s_near_at[LABELS ? 1 : kFullTaskBlock / 64][LABELS ? 1 : 64];
-    constexpr bool by_group = LABELS;
+    const bool by_group = LABELS && n_chunks > kGroupDealChunks * S;
     const int n_units = by_group ? n_groups : n_chunks;
     const int stride = S, first = split;
     const float *meta = by_group ? groups : chunks;
@@ -1364,8 +1389,8 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
         const float *fine = cull + (size_t)n_chunks * kCullFloats;  // the sub-chunk level
         const float *groups = fine + (size_t)n_fine * kCullFloats;  // the group level
         float cx[1] = {own.cx}, cy[1] = {own.cy}, cz[1] = {own.cz}, qv[1] = {qa};
-        float wx, wy, wz, spread, qamax;
-        wave_sphere<1>(cx, cy, cz, qv, wx, wy, wz, spread, qamax);
+        float wx, wy, wz, spread, qamax, half[3];
+        wave_sphere<1>(cx, cy, cz, qv, wx, wy, wz, spread, qamax, half);
         float qkmax = qk;
         if constexpr (ELL) {
 #pragma unroll
@@ -1382,7 +1407,12 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
         };
         split_walk<true>(
             groups, cull, n_groups, n_chunks, split, S,
-            [&](const ChunkMeta &m) { return within(m, wx, wy, wz, spread + m.rad + reach_of(m, qamax, qkmax)); },
+            [&](const ChunkMeta &m) {
+                // the wave's bounding sphere and box (the box is the tighter
+                // bound for the flat blocks a wave of grid points forms)
+                const float reach = m.rad + reach_of(m, qamax, qkmax);
+                return within(m, wx, wy, wz, spread + reach) && within_box(m, wx, wy, wz, half, reach);
+            },
             [&](const ChunkMeta &m) { return within(m, own.cx, own.cy, own.cz, m.rad + reach_of(m, qa, qk)); },
             [&](int ci, unsigned long long lanes) {
                 static_assert(kFinePer == 4, "sub-chunk rotation below assumes four");

@@ -387,7 +387,8 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
                   int n_tiles, int S, int n_qblocks, const float *__restrict__ cull, int n_chunks,
                   const float *__restrict__ centers, const float *__restrict__ radii, int q, float four_n2,
                   float n_sigma, int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out,
-                  const float *__restrict__ thr = nullptr, float *__restrict__ mlo_out = nullptr,
+                  const float *__restrict__ groups, const float *__restrict__ thr = nullptr,
+                  float *__restrict__ mlo_out = nullptr,
                   float *__restrict__ mup_out = nullptr, unsigned long long *__restrict__ blocks_done = nullptr)
 {
     static_assert(COUNT || MINW, "nothing to compute");
@@ -507,47 +508,92 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         for (int cb = 0; cb < kCB; ++cb) all[cb] = 0xffffu;
         for (int t = split; t < n_tiles; t += S) do_tile(t, all);
     } else {
-        float wx, wy, wz, spread, r2max;
-        pair::wave_sphere<kCB>(cx, cy, cz, qa, wx, wy, wz, spread, r2max);
+        float wx, wy, wz, spread, r2max, half[3];
+        pair::wave_sphere<kCB>(cx, cy, cz, qa, wx, wy, wz, spread, r2max, half);
         auto reach_of = [&](const pair::ChunkMeta &m, float rr2) {
             const float ns = n_sigma * m.smax;
             return ns + pair::fast_sqrt(fmaf(ns, ns, rr2));  // ~1 ulp, far inside the culling margin
         };
-        for (int ib = 0; split + ib * S < n_tiles; ib += 64 / kChunksPerTile) {
-            const int t = split + (ib + lane / kChunksPerTile) * S;
-            const int ci = t * kChunksPerTile + lane % kChunksPerTile;
-            pair::ChunkMeta m{0.f, 0.f, 0.f, 0.f, 0.f};
-            bool pass = false;
-            if (t < n_tiles && ci < n_chunks) {
-                m = pair::load_chunk(cull, ci);
-                pass = pair::within(m, wx, wy, wz, spread + m.rad + reach_of(m, r2max));
-            }
-            unsigned long long mask = __ballot(pass);
-            while (mask) {
-                const int g = __builtin_ctzll(mask) / kChunksPerTile;  // tile of the batch
-                unsigned tm = (unsigned)(mask >> (kChunksPerTile * g)) & ((1u << kChunksPerTile) - 1u);
-                mask &= ~((((unsigned long long)1 << kChunksPerTile) - 1ull) << (kChunksPerTile * g));
-                // per column block: the chunk's two row blocks where some
-                // query of the block is within reach (testing each row block
-                // through its two 16-Gaussian sub-chunks cost more than the
-                // blocks it skipped: 1.19 -> 1.30 ms on the precision workload)
-                const int t = split + (ib + g) * S;
-                unsigned rbm[kCB];
-#pragma unroll
-                for (int cb = 0; cb < kCB; ++cb) rbm[cb] = 0;
-                unsigned any = 0;
-                while (tm) {
-                    const int k = __builtin_ctz(tm);
-                    tm &= tm - 1;
-                    const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
-#pragma unroll
-                    for (int cb = 0; cb < kCB; ++cb)
-                        if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, qa[cb]))))
-                            rbm[cb] |= 3u << (2 * k);
+        // against the wave's bounding sphere and box
+        auto coarse = [&](const pair::ChunkMeta &m) {
+            const float reach = m.rad + reach_of(m, r2max);
+            return pair::within(m, wx, wy, wz, spread + reach) && pair::within_box(m, wx, wy, wz, half, reach);
+        };
+        // Over a large scene (more than kGroupDealChunks chunks per split)
+        // split s takes the groups of 16 chunks (two tiles) s, s + S, ...: 64
+        // groups at a time against the wave, then the 16 chunks of a
+        // surviving group; otherwise it takes the tiles s, s + S, ...: the
+        // chunks of 8 tiles at a time against the wave (the choice and its
+        // reason as in the float32 label walk).  Then per tile each surviving
+        // chunk against the queries of every column block.
+        const int n_groups = (n_chunks + pair::kGroup - 1) / pair::kGroup;
+        static_assert(pair::kGroup == 2 * kChunksPerTile, "a group holds two tiles");
+        const bool by_group = n_chunks > pair::kGroupDealChunks * S;
+        const int n_units = by_group ? n_groups : n_tiles;
+        const int per_batch = by_group ? 64 : 64 / kChunksPerTile;
+        for (int ib = 0; split + ib * S < n_units; ib += per_batch) {
+            // one group per lane, or one chunk per lane (8 per tile)
+            pair::ChunkMeta bm{0.f, 0.f, 0.f, 0.f, 0.f};
+            bool bpass = false;
+            if (by_group) {
+                const int gl = split + (ib + lane) * S;
+                if (gl < n_groups) {
+                    bm = pair::load_chunk(groups, gl);
+                    bpass = coarse(bm);
                 }
+            } else {
+                const int t = split + (ib + lane / kChunksPerTile) * S;
+                const int ci = t * kChunksPerTile + lane % kChunksPerTile;
+                if (t < n_tiles && ci < n_chunks) {
+                    bm = pair::load_chunk(cull, ci);
+                    bpass = coarse(bm);
+                }
+            }
+            const unsigned long long bmask = __ballot(bpass);
+            // the surviving groups to open, or the batch itself as one set of chunks
+            unsigned long long gmask = by_group ? bmask : 1ull;
+            while (gmask) {
+                pair::ChunkMeta m = bm;
+                unsigned long long mask = bmask;
+                int gi = 0;
+                if (by_group) {
+                    gi = split + (ib + __builtin_ctzll(gmask)) * S;
+                    const int ci = gi * pair::kGroup + lane;  // the group's chunks, one per lane
+                    bool pass = false;
+                    m = pair::ChunkMeta{0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (lane < pair::kGroup && ci < n_chunks) {
+                        m = pair::load_chunk(cull, ci);
+                        pass = coarse(m);
+                    }
+                    mask = __ballot(pass);
+                }
+                gmask &= gmask - 1;
+                while (mask) {
+                    const int g = __builtin_ctzll(mask) / kChunksPerTile;  // tile of the set
+                    unsigned tm = (unsigned)(mask >> (kChunksPerTile * g)) & ((1u << kChunksPerTile) - 1u);
+                    mask &= ~((((unsigned long long)1 << kChunksPerTile) - 1ull) << (kChunksPerTile * g));
+                    // per column block: the chunk's two row blocks where some
+                    // query of the block is within reach (testing each row block
+                    // through its two 16-Gaussian sub-chunks cost more than the
+                    // blocks it skipped: 1.19 -> 1.30 ms on the precision workload)
+                    const int t = by_group ? gi * (pair::kGroup / kChunksPerTile) + g : split + (ib + g) * S;
+                    unsigned rbm[kCB];
 #pragma unroll
-                for (int cb = 0; cb < kCB; ++cb) any |= rbm[cb];
-                if (any) do_tile(t, rbm);
+                    for (int cb = 0; cb < kCB; ++cb) rbm[cb] = 0;
+                    unsigned any = 0;
+                    while (tm) {
+                        const int k = __builtin_ctz(tm);
+                        tm &= tm - 1;
+                        const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
+#pragma unroll
+                        for (int cb = 0; cb < kCB; ++cb)
+                            if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, qa[cb]))))
+                                rbm[cb] |= 3u << (2 * k);
+                    }
+#pragma unroll
+                    for (int cb = 0; cb < kCB; ++cb) any |= rbm[cb];
+                    if (any) do_tile(t, rbm);
+                }
             }
         }
     }
@@ -1150,7 +1196,7 @@ __global__ void __launch_bounds__(256)
 mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *__restrict__ meta, int n_tiles,
                       int S, int n_qblocks, const float *__restrict__ cull, int n_chunks,
                       const float *__restrict__ rec, const float *__restrict__ bq, int q, float n_sigma,
-                      int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out,
+                      int32_t *__restrict__ lo_out, int32_t *__restrict__ hi_out, const float *__restrict__ groups,
                       unsigned long long *__restrict__ blocks_done)
 {
     using T = Prec<P>;
@@ -1268,8 +1314,8 @@ mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const floa
         const unsigned all[kCB] = {0xffffu, 0xffffu};
         for (int t = split; t < n_tiles; t += S) do_tile(t, all);
     } else {
-        float wx, wy, wz, spread, qamax;
-        pair::wave_sphere<kCB>(cx, cy, cz, qa, wx, wy, wz, spread, qamax);
+        float wx, wy, wz, spread, qamax, half[3];
+        pair::wave_sphere<kCB>(cx, cy, cz, qa, wx, wy, wz, spread, qamax, half);
         float qkmax = fmaxf(qk[0], qk[1]);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) qkmax = fmaxf(qkmax, __shfl_xor(qkmax, off));
@@ -1278,32 +1324,68 @@ mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const floa
             const float ns = n_sigma * m.smax;
             return kk * (ns + pair::fast_sqrt(fmaf(ns, ns, a2)));  // ~1 ulp, far inside the culling margin
         };
-        for (int ib = 0; split + ib * S < n_tiles; ib += 64 / kChunksPerTile) {
-            const int t = split + (ib + lane / kChunksPerTile) * S;
-            const int ci = t * kChunksPerTile + lane % kChunksPerTile;
-            pair::ChunkMeta m{0.f, 0.f, 0.f, 0.f, 0.f};
-            bool pass = false;
-            if (t < n_tiles && ci < n_chunks) {
-                m = pair::load_chunk(cull, ci);
-                pass = pair::within(m, wx, wy, wz, spread + m.rad + reach_of(m, qamax, qkmax));
-            }
-            unsigned long long mask = __ballot(pass);
-            while (mask) {
-                const int g = __builtin_ctzll(mask) / kChunksPerTile;
-                unsigned tm = (unsigned)(mask >> (kChunksPerTile * g)) & ((1u << kChunksPerTile) - 1u);
-                mask &= ~((((unsigned long long)1 << kChunksPerTile) - 1ull) << (kChunksPerTile * g));
-                const int t = split + (ib + g) * S;
-                unsigned rbm[kCB] = {0u, 0u};
-                while (tm) {
-                    const int k = __builtin_ctz(tm);
-                    tm &= tm - 1;
-                    const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
-#pragma unroll
-                    for (int cb = 0; cb < kCB; ++cb)
-                        if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, qa[cb], qk[cb]))))
-                            rbm[cb] |= 3u << (2 * k);
+        auto coarse = [&](const pair::ChunkMeta &m) {
+            const float reach = m.rad + reach_of(m, qamax, qkmax);
+            return pair::within(m, wx, wy, wz, spread + reach) && pair::within_box(m, wx, wy, wz, half, reach);
+        };
+        // groups dealt to the splits over a large scene, tiles otherwise, as
+        // in mfma_label_kernel
+        const int n_groups = (n_chunks + pair::kGroup - 1) / pair::kGroup;
+        const bool by_group = n_chunks > pair::kGroupDealChunks * S;
+        const int n_units = by_group ? n_groups : n_tiles;
+        const int per_batch = by_group ? 64 : 64 / kChunksPerTile;
+        for (int ib = 0; split + ib * S < n_units; ib += per_batch) {
+            pair::ChunkMeta bm{0.f, 0.f, 0.f, 0.f, 0.f};
+            bool bpass = false;
+            if (by_group) {
+                const int gl = split + (ib + lane) * S;
+                if (gl < n_groups) {
+                    bm = pair::load_chunk(groups, gl);
+                    bpass = coarse(bm);
                 }
-                if (rbm[0] | rbm[1]) do_tile(t, rbm);
+            } else {
+                const int t = split + (ib + lane / kChunksPerTile) * S;
+                const int ci = t * kChunksPerTile + lane % kChunksPerTile;
+                if (t < n_tiles && ci < n_chunks) {
+                    bm = pair::load_chunk(cull, ci);
+                    bpass = coarse(bm);
+                }
+            }
+            const unsigned long long bmask = __ballot(bpass);
+            unsigned long long gmask = by_group ? bmask : 1ull;
+            while (gmask) {
+                pair::ChunkMeta m = bm;
+                unsigned long long mask = bmask;
+                int gi = 0;
+                if (by_group) {
+                    gi = split + (ib + __builtin_ctzll(gmask)) * S;
+                    const int ci = gi * pair::kGroup + lane;
+                    bool pass = false;
+                    m = pair::ChunkMeta{0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (lane < pair::kGroup && ci < n_chunks) {
+                        m = pair::load_chunk(cull, ci);
+                        pass = coarse(m);
+                    }
+                    mask = __ballot(pass);
+                }
+                gmask &= gmask - 1;
+                while (mask) {
+                    const int g = __builtin_ctzll(mask) / kChunksPerTile;
+                    unsigned tm = (unsigned)(mask >> (kChunksPerTile * g)) & ((1u << kChunksPerTile) - 1u);
+                    mask &= ~((((unsigned long long)1 << kChunksPerTile) - 1ull) << (kChunksPerTile * g));
+                    const int t = by_group ? gi * (pair::kGroup / kChunksPerTile) + g : split + (ib + g) * S;
+                    unsigned rbm[kCB] = {0u, 0u};
+                    while (tm) {
+                        const int k = __builtin_ctz(tm);
+                        tm &= tm - 1;
+                        const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
+#pragma unroll
+                        for (int cb = 0; cb < kCB; ++cb)
+                            if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, qa[cb], qk[cb]))))
+                                rbm[cb] |= 3u << (2 * k);
+                    }
+                    if (rbm[0] | rbm[1]) do_tile(t, rbm);
+                }
             }
         }
     }
@@ -1506,26 +1588,29 @@ void launch_mfma(int precision, bool cull, dim3 grid, hipStream_t st, const cspl
                  int32_t *hi, const float *thr, float *mlo, float *mup, unsigned long long *blocks)
 {
     const int n_tiles = (int)sc->n_tiles;
+    // the group level of the culling metadata: after the chunks and the sub-chunks
+    const int64_t n_fine = (sc->n + pair::kFine - 1) / pair::kFine;
+    const float *groups = sc->cull ? sc->cull + ((size_t)n_chunks + (size_t)n_fine) * pair::kCullFloats : nullptr;
     if (precision == CSPLAT_PRECISION_BF16_RECHECK) {
         const auto *f = static_cast<const bf16x8 *>(sc->feat_bf16);
         if (cull)
             mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, true, COUNT, MINW><<<grid, 256, 0, st>>>(
-                f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, thr, mlo,
-                mup, blocks);
+                f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, groups, thr,
+                mlo, mup, blocks);
         else
             mfma_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, false, COUNT, MINW><<<grid, 256, 0, st>>>(
-                f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, thr, mlo,
-                mup, blocks);
+                f, sc->meta_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, groups, thr,
+                mlo, mup, blocks);
     } else {
         const auto *f = static_cast<const f16x8 *>(sc->feat_fp16);
         if (cull)
             mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, true, COUNT, MINW><<<grid, 256, 0, st>>>(
-                f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, thr, mlo,
-                mup, blocks);
+                f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, groups, thr,
+                mlo, mup, blocks);
         else
             mfma_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, false, COUNT, MINW><<<grid, 256, 0, st>>>(
-                f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, thr, mlo,
-                mup, blocks);
+                f, sc->meta_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, c, r, q, four_n2, nv, lo, hi, groups, thr,
+                mlo, mup, blocks);
     }
 }
 
@@ -1761,22 +1846,24 @@ void launch_mfma_ell(int precision, bool cull, dim3 grid, hipStream_t st, const 
                      unsigned long long *blocks)
 {
     const int n_tiles = (int)sc->n_tiles;
+    const int64_t n_fine = (sc->n + pair::kFine - 1) / pair::kFine;
+    const float *groups = sc->cull ? sc->cull + ((size_t)n_chunks + (size_t)n_fine) * pair::kCullFloats : nullptr;
     if (precision == CSPLAT_PRECISION_BF16_RECHECK) {
         const auto *f = static_cast<const bf16x8 *>(sc->feat_ell_bf16);
         if (cull)
             mfma_ell_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, true><<<grid, 256, 0, st>>>(
-                f, sc->meta_ell_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, blocks);
+                f, sc->meta_ell_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, groups, blocks);
         else
             mfma_ell_label_kernel<CSPLAT_PRECISION_BF16_RECHECK, false><<<grid, 256, 0, st>>>(
-                f, sc->meta_ell_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, blocks);
+                f, sc->meta_ell_bf16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, groups, blocks);
     } else {
         const auto *f = static_cast<const f16x8 *>(sc->feat_ell_fp16);
         if (cull)
             mfma_ell_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, true><<<grid, 256, 0, st>>>(
-                f, sc->meta_ell_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, blocks);
+                f, sc->meta_ell_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, groups, blocks);
         else
             mfma_ell_label_kernel<CSPLAT_PRECISION_FP16_RECHECK, false><<<grid, 256, 0, st>>>(
-                f, sc->meta_ell_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, blocks);
+                f, sc->meta_ell_fp16, n_tiles, S, n_qblocks, sc->cull, n_chunks, rec, bq, q, nv, lo, hi, groups, blocks);
     }
 }
 }  // namespace

@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 from parity import compare
-from workloads import Queries, Scene, common_attrs, config, uniform_box_scene, uniform_queries
+from workloads import (Queries, Scene, common_attrs, config, grid_queries, room_scene, uniform_box_scene,
+                       uniform_queries)
 
 pytestmark = pytest.mark.gpu
 
@@ -166,6 +167,32 @@ def test_precision_cull_matches_dense(cs, eng, prec):
     _say(f"{prec}: rechecked dense {st0['flagged']} culled {st1['flagged']} of {qs.q * 3}")
     for k in dense:
         assert np.array_equal(dense[k], culled[k]), k
+
+
+def test_group_dealt_walks_match_dense(cs, eng):
+    """Over a large scene (more than 1024 culling chunks per split) the label
+    walks, float32 tasks and the MFMA form, deal whole 16-chunk groups to
+    their splits instead of single chunks or tiles: culled and dense
+    evaluations give the same labels and counts."""
+    _say("case: group-dealt label walks vs dense, 1M-Gaussian room, 64^3 and 81^3 grid spheres")
+    sc = room_scene(1_000_000, seed=311)
+    p = dict(n_sigma=[1.0], k=2, alpha_f=0.05, extent_f=0.1)
+    h = _load(cs, eng, sc, p)
+    n_kept, _ = cs.csplat_scene_info(h)
+    n_chunks = (int(n_kept) + 63) // 64
+    try:
+        for prec, res in ((cs.CSPLAT_PRECISION_FP32, 64), (_prec(cs, "bf16"), 81)):
+            qs = grid_queries(res)
+            dense, _ = _eval(cs, eng, h, qs, p, prec, cull=0)
+            culled, st = _eval(cs, eng, h, qs, p, prec, cull=1)
+            _say(f"precision {prec}: {qs.q} queries, {st['splits']} splits of {n_chunks} chunks, "
+                 f"{int(dense['label'].sum())} labels set")
+            assert n_chunks > 1024 * st["splits"], "the walk under test deals groups only over long splits"
+            assert dense["label"].any() and not dense["label"].all()
+            for k in dense:
+                assert np.array_equal(dense[k], culled[k]), k
+    finally:
+        cs.csplat_scene_free(h)
 
 
 def test_precision_requires_features(cs, eng):
