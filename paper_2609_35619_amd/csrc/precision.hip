@@ -368,6 +368,10 @@ __device__ __forceinline__ bool build_query(float cx, float cy, float cz, float 
 constexpr int kCB = CSPLAT_MFMA_COLUMN_BLOCKS;
 static_assert(kCB == 2 || kCB == 4, "column blocks per wave: 2 or 4");
 constexpr int kQueriesPerBlock = 4 * 32 * kCB;
+// the ellipsoid MFMA kernel keeps two column blocks per wave (one body per lane
+// builds its features) whatever kCB is
+constexpr int kEllCB = 2;
+constexpr int kEllQueriesPerBlock = 4 * 32 * kEllCB;
 
 // The minimum (MINW): per pair v~ = a~ - sqrt(max(w~, 0)), the computed value
 // of v = a - sqrt(w) = r^2 (s~^2 - 1) before the clamp, and a certified bound
@@ -450,11 +454,27 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
         unsigned rbm = 0;
 #pragma unroll
         for (int cb = 0; cb < kCB; ++cb) rbm |= rbm_cb[cb];
-        while (rbm) {
-            const int rb = __builtin_ctz(rbm);
-            rbm &= rbm - 1;
-            const vec *fp = ft + (size_t)rb * kOps * kLanes;
-            const vec Aa = fp[0], Aw0 = fp[kLanes], Aw1 = fp[2 * kLanes];
+        if (!rbm) return;
+        // the next row block's operands are requested before the current
+        // one is evaluated, so their loads overlap its MFMAs and epilogue
+        // (loaded just before use, every row block waited a memory round trip)
+        int nrb = __builtin_ctz(rbm);
+        rbm &= rbm - 1;
+        vec nAa, nAw0, nAw1;
+        {
+            const vec *fp = ft + (size_t)nrb * kOps * kLanes;
+            nAa = fp[0], nAw0 = fp[kLanes], nAw1 = fp[2 * kLanes];
+        }
+        for (;;) {
+            const int rb = nrb;
+            const vec Aa = nAa, Aw0 = nAw0, Aw1 = nAw1;
+            const bool more = rbm != 0;
+            if (more) {
+                nrb = __builtin_ctz(rbm);
+                rbm &= rbm - 1;
+                const vec *fp = ft + (size_t)nrb * kOps * kLanes;
+                nAa = fp[0], nAw0 = fp[kLanes], nAw1 = fp[2 * kLanes];
+            }
 #pragma unroll
             for (int cb = 0; cb < kCB; ++cb) {
                 if (!((rbm_cb[cb] >> rb) & 1u)) continue;  // no query of cb near the row block
@@ -500,6 +520,7 @@ mfma_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const float *_
                     }
                 }
             }
+            if (!more) break;
         }
     };
     if constexpr (!CULL) {
@@ -1186,7 +1207,7 @@ __device__ __forceinline__ bool build_query_ell(float cx, float cy, float cz, co
 }
 
 // Certification kernel for ellipsoids: the layout of mfma_label_kernel (block
-// = 4 waves x kCB 32-body column blocks; grid = query blocks x S tile splits)
+// = 4 waves x kEllCB 32-body column blocks; grid = query blocks x S tile splits)
 // with the operands above; labels and counts.  With CULL a column block skips
 // a chunk's two row blocks when each of its bodies is beyond the chunk's
 // reach qk (n s_c + sqrt(n^2 s_c^2 + qa)) plus its radius (qa: the smallest
@@ -1201,18 +1222,18 @@ mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const floa
 {
     using T = Prec<P>;
     using vec = typename T::vec;
-    static_assert(kCB == 2, "one body per lane builds its features (two column blocks per wave)");
+    static_assert(kEllCB == 2, "one body per lane builds its features (two column blocks per wave)");
     int b = blockIdx.x;
     const int Bn = gridDim.x;
     if ((Bn & 7) == 0) b = (b & 7) * (Bn >> 3) + (b >> 3);  // XCD-major: one XCD, few splits
     const int split = b / n_qblocks;
     const int qb = b - split * n_qblocks;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-    float cx[kCB], cy[kCB], cz[kCB], qa[kCB], qk[kCB];
-    int jq[kCB];
+    float cx[kEllCB], cy[kEllCB], cz[kEllCB], qa[kEllCB], qk[kEllCB];
+    int jq[kEllCB];
 #pragma unroll
-    for (int cb = 0; cb < kCB; ++cb) {
-        jq[cb] = qb * kQueriesPerBlock + wave * (32 * kCB) + cb * 32 + col;
+    for (int cb = 0; cb < kEllCB; ++cb) {
+        jq[cb] = qb * kEllQueriesPerBlock + wave * (32 * kEllCB) + cb * 32 + col;
         const int jj = jq[cb] < q ? jq[cb] : q - 1;
         const float *rj = rec + (size_t)kBodyFloats * jj;
         cx[cb] = rj[0];
@@ -1231,10 +1252,10 @@ mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const floa
     const float ox = h ? cx[1] : cx[0], oy = h ? cy[1] : cy[0], oz = h ? cz[1] : cz[0];
     const float two_n = 2.f * n_sigma;
     unsigned long long n_blocks = 0;
-    int lo[kCB] = {0, 0}, hi[kCB] = {0, 0};
+    int lo[kEllCB] = {0, 0}, hi[kEllCB] = {0, 0};
     bool bad = false;
     const f32x16 zero = {};
-    auto do_tile = [&](int t, const unsigned (&rbm_cb)[kCB]) {
+    auto do_tile = [&](int t, const unsigned (&rbm_cb)[kEllCB]) {
         const float *mt = meta + (size_t)t * kEllMeta;  // wave-uniform: scalar loads
         QFeatE<P> Q[2];
         bad |= !build_query_ell<P>(ox, oy, oz, Lm, Bm, two_n, mt, Q);
@@ -1248,7 +1269,7 @@ mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const floa
 #pragma unroll
             for (int k = 0; k < kEllOps; ++k) G[k] = fp[(size_t)k * kLanes];
 #pragma unroll
-            for (int cb = 0; cb < kCB; ++cb) {
+            for (int cb = 0; cb < kEllCB; ++cb) {
                 if (!((rbm_cb[cb] >> rb) & 1u)) continue;  // no body of cb near the row block
                 ++n_blocks;
                 // a~ = sum f~_k^2 - 1 and its bound E_a per pair
@@ -1311,11 +1332,11 @@ mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const floa
         }
     };
     if constexpr (!CULL) {
-        const unsigned all[kCB] = {0xffffu, 0xffffu};
+        const unsigned all[kEllCB] = {0xffffu, 0xffffu};
         for (int t = split; t < n_tiles; t += S) do_tile(t, all);
     } else {
         float wx, wy, wz, spread, qamax, half[3];
-        pair::wave_sphere<kCB>(cx, cy, cz, qa, wx, wy, wz, spread, qamax, half);
+        pair::wave_sphere<kEllCB>(cx, cy, cz, qa, wx, wy, wz, spread, qamax, half);
         float qkmax = fmaxf(qk[0], qk[1]);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) qkmax = fmaxf(qkmax, __shfl_xor(qkmax, off));
@@ -1374,13 +1395,13 @@ mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const floa
                     unsigned tm = (unsigned)(mask >> (kChunksPerTile * g)) & ((1u << kChunksPerTile) - 1u);
                     mask &= ~((((unsigned long long)1 << kChunksPerTile) - 1ull) << (kChunksPerTile * g));
                     const int t = by_group ? gi * (pair::kGroup / kChunksPerTile) + g : split + (ib + g) * S;
-                    unsigned rbm[kCB] = {0u, 0u};
+                    unsigned rbm[kEllCB] = {0u, 0u};
                     while (tm) {
                         const int k = __builtin_ctz(tm);
                         tm &= tm - 1;
                         const pair::ChunkMeta c = pair::lane_chunk(m, kChunksPerTile * g + k);
 #pragma unroll
-                        for (int cb = 0; cb < kCB; ++cb)
+                        for (int cb = 0; cb < kEllCB; ++cb)
                             if (__any(pair::within(c, cx[cb], cy[cb], cz[cb], c.rad + reach_of(c, qa[cb], qk[cb]))))
                                 rbm[cb] |= 3u << (2 * k);
                     }
@@ -1390,7 +1411,7 @@ mfma_ell_label_kernel(const typename Prec<P>::vec *__restrict__ feat, const floa
         }
     }
 #pragma unroll
-    for (int cb = 0; cb < kCB; ++cb) {
+    for (int cb = 0; cb < kEllCB; ++cb) {
         lo[cb] += __shfl_xor(lo[cb], 32);
         hi[cb] += __shfl_xor(hi[cb], 32);
         // body cb was built by the lanes of half cb
@@ -1620,10 +1641,10 @@ __global__ void fill_u64_kernel(unsigned long long *p, int n, unsigned long long
     if (i < n) p[i] = v;
 }
 
-// Splits of a launch over q queries (blocks of kQueriesPerBlock).
-int mfma_splits(const csplat_ctx *ctx, int q, int n_tiles)
+// Splits of a launch over q queries (blocks of `per_block`).
+int mfma_splits(const csplat_ctx *ctx, int q, int n_tiles, int per_block = kQueriesPerBlock)
 {
-    const int n_qblocks = (q + kQueriesPerBlock - 1) / kQueriesPerBlock;
+    const int n_qblocks = (q + per_block - 1) / per_block;
     if (n_tiles <= 0) return 1;
     const int S = (ctx_target_blocks(ctx) + n_qblocks - 1) / n_qblocks;
     return std::max(1, std::min(S, n_tiles));
@@ -1876,8 +1897,8 @@ csplat_status precision_eval_ell(csplat_ctx *ctx, const csplat_scene *sc, int64_
     const int m = p.m;
     hipStream_t st = ctx->stream;
     const int n_tiles = (int)sc->n_tiles;
-    const int n_qblocks = (q + kQueriesPerBlock - 1) / kQueriesPerBlock;
-    const int S = mfma_splits(ctx, q, n_tiles);
+    const int n_qblocks = (q + kEllQueriesPerBlock - 1) / kEllQueriesPerBlock;
+    const int S = mfma_splits(ctx, q, n_tiles, kEllQueriesPerBlock);
     const int n_chunks = (n + pair::kCull - 1) / pair::kCull;
     const bool cull = p.cull && n > 0 && sc->cull;
     const float *rec = rec_in;
