@@ -1257,7 +1257,11 @@ __device__ __forceinline__ void eval_tile_label_tasks(const float *__restrict__ 
     __shared__ int s_mt[kWaves][MINW ? 64 * M : 1];   // the wave's minima (float bits), query-major
     const int lane = (int)(threadIdx.x & 63u), wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int jq = tile * kBlock + (int)(threadIdx.x & ~63u) + lane;
-    const int jj = jq < q ? jq : q - 1;  // past the end: evaluate a real query, write nothing
+    // a wave wholly past the last query has nothing to do (the walk has no
+    // block-wide barrier); a ragged wave evaluates a real query in its place
+    // and writes nothing for it
+    if (__builtin_amdgcn_readfirstlane(tile * kBlock + (int)(threadIdx.x & ~63u)) >= q) return;
+    const int jj = jq < q ? jq : q - 1;
     TaskQuery<ELL> own;
     float qa, qk;  // reach constants: smallest semi-axis squared, largest / smallest
     if constexpr (ELL) {
@@ -1808,7 +1812,7 @@ template <int M>
 __global__ void __launch_bounds__(256)
 min_gather_kernel(int nl, const int32_t *__restrict__ list, const float *__restrict__ centers,
                   const float *__restrict__ radii, const float *__restrict__ st_mt, float *__restrict__ st_thr,
-                  float *__restrict__ cc, float *__restrict__ rr, float *__restrict__ tt)
+                  float *__restrict__ cc, float *__restrict__ rr, float *__restrict__ tt, bool dense)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nl) return;
@@ -1818,8 +1822,9 @@ min_gather_kernel(int nl, const int32_t *__restrict__ list, const float *__restr
 #pragma unroll
     for (int v = 0; v < M; ++v) mx = fmaxf(mx, st_mt[(size_t)j * M + v]);
     // just above the minimum so far (an upper bound of the true minimum), or
-    // four times the last threshold when no pair was in reach
-    const float t = mx < INFINITY ? mx / r2 * kMinNext : 4.f * st_thr[j];
+    // four times the last threshold when no pair was in reach; a dense pass
+    // (every pair) has no threshold
+    const float t = dense ? INFINITY : mx < INFINITY ? mx / r2 * kMinNext : 4.f * st_thr[j];
     st_thr[j] = t;
     tt[i] = t;
     cc[3 * i] = centers[3 * j];

@@ -70,8 +70,8 @@ def test_min_search_matches_oracle(cs, eng, oracle_mod, name, scale, n_sigma):
 
 
 def test_min_search_far_queries_and_min_only(cs, eng, oracle_mod):
-    """Queries far outside the scene need several passes (the threshold is
-    raised fourfold until a pair is in reach); min alone (no labels)."""
+    """Queries far outside the scene: a short unresolved list is finished by
+    one dense pass over every Gaussian; min alone (no labels)."""
     _say("case: min search with queries far outside the scene")
     sc = room_scene(30_000, seed=41)
     rng = np.random.default_rng(42)
@@ -88,7 +88,35 @@ def test_min_search_far_queries_and_min_only(cs, eng, oracle_mod):
     ref = _oracle(oracle_mod, sc, qs, [1.0])
     compare(gpu, ref, tau=0.0, gamma=1.0, where="min-far")
     _say(f"far: passes {st['min_passes']}")
+    assert st["min_passes"] >= 2
+
+
+def test_min_search_threshold_growth(cs, eng, oracle_mod):
+    """A long list of queries far from every Gaussian (4,096 of them 20-80 m
+    from a 1M-Gaussian room) keeps the culled passes, whose thresholds grow
+    fourfold until a pair is in reach: the same bits as a dense search, and
+    the oracle's minimum on a sample."""
+    _say("case: min search threshold growth, 1M room, 4096 far + 4096 inner queries")
+    sc = room_scene(1_000_000, seed=43)
+    rng = np.random.default_rng(44)
+    u = rng.normal(size=(4096, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    far = np.array([5.0, 5.0, 1.5]) + u * rng.uniform(20.0, 80.0, (4096, 1))
+    inner = rng.uniform(0, 1, (4096, 3)) * [10, 10, 3]
+    c = np.concatenate([far, inner]).astype(np.float32)
+    r = rng.uniform(0.03, 0.4, c.shape[0]).astype(np.float32)
+    qs = Queries(c, r)
+    h = eng.load_scene(sc)
+    gpu, st = _eval(cs, eng, h, qs, [1.0])
+    dense, _ = _eval(cs, eng, h, qs, [1.0], cull=0)
+    cs.csplat_scene_free(h)
+    _say(f"growth: passes {st['min_passes']}")
     assert st["min_passes"] >= 4
+    for k_ in gpu:
+        assert np.array_equal(gpu[k_], dense[k_]), k_
+    idx = np.concatenate([rng.choice(4096, 48, replace=False), 4096 + rng.choice(4096, 48, replace=False)])
+    ref = _oracle(oracle_mod, sc, qs.subset(idx), [1.0])
+    compare({k_: v[idx] for k_, v in gpu.items()}, ref, tau=0.0, gamma=1.0, where="min-growth")
 
 
 def test_min_search_degenerate(cs, eng, oracle_mod):
