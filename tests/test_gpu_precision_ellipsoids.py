@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from parity import compare
-from workloads import Bodies, Scene, common_attrs, config, random_ellipsoids, uniform_box_scene
+from workloads import Bodies, Scene, common_attrs, config, random_ellipsoids, room_scene, uniform_box_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -135,6 +135,32 @@ def test_chain_links_culled_and_dense(cs, eng, oracle_mod, prec):
         assert np.array_equal(cul[k], den[k]), k
     ref = _oracle(oracle_mod, sc, b, p)
     _say(f"{prec}: {compare(cul, ref, tau=0.0, gamma=1.0, where=f'ell-chain-{prec}')}, rechecked {st['flagged']}")
+
+
+def test_group_dealt_ellipsoid_walks_match_dense(cs, eng):
+    """Over a large scene (more than 1024 culling chunks per split) the
+    ellipsoid label walks, float32 tasks and the MFMA form, deal whole
+    16-chunk groups to their splits: culled and dense evaluations give the
+    same labels and counts."""
+    _say("case: group-dealt ellipsoid label walks vs dense, 1M-Gaussian room, 300k random bodies")
+    sc = room_scene(1_000_000, seed=511)
+    b = random_ellipsoids(300_000, seed=512, box=(10.0, 10.0, 3.0), axis_range=(0.02, 0.2))
+    p = dict(n_sigma=[1.0], k=2, alpha_f=0.05, extent_f=0.1)
+    h = _load(cs, eng, sc, p)
+    n_kept, _ = cs.csplat_scene_info(h)
+    n_chunks = (int(n_kept) + 63) // 64
+    try:
+        for prec in (cs.CSPLAT_PRECISION_FP32, _prec(cs, "bf16")):
+            dense, _ = _eval(cs, eng, h, b, p, prec, cull=0)
+            culled, st = _eval(cs, eng, h, b, p, prec, cull=1)
+            _say(f"precision {prec}: {st['splits']} splits of {n_chunks} chunks, "
+                 f"{int(dense['label'].sum())} of {b.q} labels set")
+            assert n_chunks > 1024 * st["splits"], "the walk under test deals groups only over long splits"
+            assert dense["label"].any() and not dense["label"].all()
+            for k in dense:
+                assert np.array_equal(dense[k], culled[k]), k
+    finally:
+        cs.csplat_scene_free(h)
 
 
 def test_refusals(cs, eng):
