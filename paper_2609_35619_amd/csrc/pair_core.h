@@ -336,9 +336,9 @@ __device__ __forceinline__ bool within(const ChunkMeta &m, float x, float y, flo
 }
 
 // The culling test of a chunk against a box of centre b and half extents h:
-// the distance from the chunk centre to the box at most (reach + extra), with
-// the relative margin kCullMargin.  Every query in the box lies at least that
-// far from the centre, so a chunk that fails lies beyond `reach` of them all.
+// the distance from the chunk centre to the box at most `reach`, with the
+// relative margin kCullMargin.  Every query in the box lies at least that far
+// from the chunk centre, so a chunk that fails lies beyond `reach` of them all.
 __device__ __forceinline__ bool within_box(const ChunkMeta &m, float bx, float by, float bz, const float *h,
                                            float reach)
 {

@@ -358,8 +358,10 @@ __device__ __forceinline__ bool build_query(float cx, float cy, float cz, float 
 // With CULL, a column block skips row blocks in pairs (one culling chunk of
 // 64 Gaussians) when each of its 32 queries is beyond the chunk's reach
 // bound n s_c + sqrt(n^2 s_c^2 + r^2) plus its radius: no pair of them can
-// collide.  Chunks are tested 64 at a time (8 tiles x 8 chunks, one per lane)
-// against the wave's bounding sphere, then each survivor against every query.
+// collide.  Chunks are tested 64 at a time (8 tiles x 8 chunks, one per lane;
+// over a large scene the 16 chunks of each group that survived a test of 64
+// groups) against the wave's bounding sphere and box, then each survivor
+// against every query.
 // Column blocks of 32 queries per wave: the A operands of a row block are
 // loaded once and multiplied against every column block that needs them.
 #ifndef CSPLAT_MFMA_COLUMN_BLOCKS
