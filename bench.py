@@ -246,6 +246,10 @@ def main():
                                "outputs label, count, min, softmin, cost, nbr",
                    "n_gaussians": int(sc.n), "n_kept": int(n_kept), "queries": int(qs.q), "m": m,
                    "global_batch": int(qs.q), "parallelism": "single GPU", "inputs_sha256": inputs_sha256},
+        "value_definition": "dense-equivalent sphere-Gaussian pair evaluations per second: Q x N_kept per step; "
+                            "exact culling answers most pairs without evaluating them (their contribution is "
+                            "provably none), evaluated_pair_evals_per_s counts the pairs the kernel evaluated",
+        "evaluated_pair_evals_per_s": evaluated / step_s,
         "queries_per_s": qs.q / step_s,
         "rollout_epilogue": {"rollouts": n_roll, "in_collision_per_n_sigma": seg_any.sum(0).tolist()},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
