@@ -595,25 +595,20 @@ csplat_status csplat_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q, co
     std::function<csplat_status()> gate;
     if (kind == 1) {
         // device inputs: checked on the device before any output is touched.
-        // The float32 path queues its sort and pair kernel (which write only
-        // the workspace) before it waits for the check; the precision forms
-        // write labels early and wait first.
+        // Both paths queue their sort and first pair pass (which write only
+        // the workspace) before they wait for the check.
         auto check = [&](int *bad) {
             check_queries_kernel<<<(unsigned)((q + 255) / 256), 256, 0, ctx->stream>>>(q, centers, radii, bad);
         };
-        if (opts->precision == CSPLAT_PRECISION_FP32) {
-            s = queue_device_check(ctx, check);
-            gate = [&]() { return wait_device_check(ctx, bad_msg); };
-        } else {
-            s = device_check(ctx, check, bad_msg);
-        }
+        s = queue_device_check(ctx, check);
+        gate = [&]() { return wait_device_check(ctx, bad_msg); };
         if (s != CSPLAT_OK) return s;
     }
     s = on_device(ctx, kind, q, ctx->m, {centers, radii}, {(size_t)q * 12, (size_t)q * 4}, out,
                   [&](const std::vector<const void *> &in, const EvalOut &eo) {
                       const float *c = static_cast<const float *>(in[0]), *r = static_cast<const float *>(in[1]);
                       if (opts->precision != CSPLAT_PRECISION_FP32)
-                          return precision_eval(ctx, sc, q, c, r, p, eo, opts->precision);
+                          return precision_eval(ctx, sc, q, c, r, p, eo, opts->precision, gate);
                       return fp32_eval(ctx, sc, q, c, r, p, eo, !want_dist, false, gate);
                   });
     scene_note_use(sc, ctx->stream);

@@ -327,9 +327,12 @@ csplat_status fp32_min_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t 
                             const std::function<csplat_status()> &gate = {});
 
 // precision.hip: MFMA form with certified recheck (labels and counts).
+// gate: called once before the first kernel that writes an output (the
+// caller's check of device inputs); an error from it is returned as is.
 csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *scene, int64_t q,
                              const float *centers, const float *radii, const EvalParams &p,
-                             const EvalOut &out, int precision);
+                             const EvalOut &out, int precision,
+                             const std::function<csplat_status()> &gate = {});
 // Labels and counts of ellipsoid records (kBodyFloats floats each, the
 // caller's order) in an MFMA precision form.
 csplat_status precision_eval_ell(csplat_ctx *ctx, const csplat_scene *scene, int64_t q, const float *rec,

@@ -1654,7 +1654,8 @@ int mfma_splits(const csplat_ctx *ctx, int q, int n_tiles, int per_block = kQuer
 }  // namespace
 
 csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, const float *centers,
-                             const float *radii, const EvalParams &p, const EvalOut &out, int precision)
+                             const float *radii, const EvalParams &p, const EvalOut &out, int precision,
+                             const std::function<csplat_status()> &gate)
 {
     const int q = (int)q64;
     const int n = (int)sc->n;
@@ -1746,6 +1747,7 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
         total_ms += ms;
         return CSPLAT_OK;
     };
+    bool gated = false;
     for (int v = 0; v < m; ++v) {
         const float nv = p.n_sigma[v];
         // pass 1: labels (certified counts) and the minimum's interval
@@ -1765,6 +1767,14 @@ csplat_status precision_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q6
             CSPLAT_HIP(hipGetLastError());
             csplat_status ts = add_ms();
             if (ts != CSPLAT_OK) return ts;
+        }
+        if (gate && !gated) {
+            // nothing that writes an output is queued before the caller's
+            // check of its inputs has passed (the sort and the first MFMA
+            // pass write only the workspace and overlap the check)
+            gated = true;
+            csplat_status gs = gate();
+            if (gs != CSPLAT_OK) return gs;
         }
         if (want_count) {
             decide_kernel<<<qb, 256, 0, st>>>(q, n_tiles > 0 ? S : 0, m, v, p.k, out.count != nullptr, lo, hi, perm,

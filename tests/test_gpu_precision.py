@@ -195,6 +195,39 @@ def test_group_dealt_walks_match_dense(cs, eng):
         cs.csplat_scene_free(h)
 
 
+def test_precision_invalid_device_inputs(cs, eng):
+    """Invalid device queries are refused with CSPLAT_E_INVALID and no output
+    written, although the sort and the first MFMA pass are queued before the
+    check has returned; the next valid call is unaffected."""
+    import torch
+    _say("case: precision form, invalid device inputs")
+    sc, qs, p = config("tiny", 0.1)
+    p = dict(p, n_sigma=[1.0], k=0)
+    h = _load(cs, eng, sc, p)
+    eng.set_conservatism([1.0])
+    opts = cs.reduce_opts(k=0, r_nbr=math.inf, precision=_prec(cs, "bf16"))
+    try:
+        for bad in ("nan_center", "zero_radius", "neg_radius"):
+            c, r = qs.centers.copy(), qs.radii.copy()
+            if bad == "nan_center":
+                c[5, 2] = np.nan
+            elif bad == "zero_radius":
+                r[9] = 0
+            else:
+                r[0] = -1
+            ll = torch.full((qs.q, 1), 7, dtype=torch.uint8, device="cuda")
+            with pytest.raises(cs.CsplatError) as ei:
+                cs.csplat_eval_labels(eng.ctx, h, torch.from_numpy(c).cuda(), torch.from_numpy(r).cuda(), opts, ll)
+            assert ei.value.status == cs.CSPLAT_E_INVALID
+            assert torch.all(ll == 7).item(), "outputs written on error"
+            cs.csplat_eval_labels(eng.ctx, h, torch.from_numpy(qs.centers).cuda(), torch.from_numpy(qs.radii).cuda(),
+                                  opts, ll)
+            torch.cuda.synchronize()
+            assert torch.all(ll <= 1).item()
+    finally:
+        cs.csplat_scene_free(h)
+
+
 def test_precision_requires_features(cs, eng):
     sc, qs, p = config("tiny", 0.05)
     h = eng.load_scene(sc)   # no precision features
