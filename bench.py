@@ -115,7 +115,7 @@ def main():
     ap.add_argument("--serving-reduced", action="store_true",
                     help="serve a reduced request law (MPPI K <= 512 x 32 x <= 8 spheres; quick)")
     ap.add_argument("--section", choices=("all", "main", "precision", "precision-kernels", "serving", "ellipsoids",
-                                          "manip", "paper", "tiny", "rrt", "copy", "digest"), default="all",
+                                          "manip", "paper", "tiny", "rrt", "copy", "digest", "sizes"), default="all",
                     help="run one part only (for profiling); 'copy' is a plain 1 GiB device copy "
                          "used to calibrate the HBM traffic counters")
     args = ap.parse_args()
@@ -129,6 +129,12 @@ def main():
         cs.load_library()
         with cs.Engine(0) as eng:
             print(json.dumps(precision_kernels(cs, eng)), flush=True)
+        return None
+    if args.section == "sizes":
+        import paper_2609_35619_amd as cs
+        cs.load_library()
+        with cs.Engine(0) as eng:
+            print(json.dumps(sizes(cs, eng)), flush=True)
         return None
     if args.section != "all":
         args.no_precision = args.section not in ("precision",)
@@ -752,6 +758,52 @@ def tiny(cs, eng, steps):
     return {"workload": "tiny: 10k Gaussians uniform in 4x4x2 m, 4,096 spheres r = 0.1 m, n_sigma 1, all outputs",
             "n_kept": int(n_kept), "queries": int(qs.q), "ms_per_step": dt * 1e3,
             "pair_evals_per_s": qs.q * n_kept / dt, "queries_per_s": qs.q / dt, "kernel_ms": st["kernel_ms"]}
+
+
+def sizes(cs, eng):
+    """The navigation workload's law at other sizes: room scenes of 250k, 1M
+    and 4M Gaussians against 256, 1,024 and 4,096 rollouts x 32 steps (8,192
+    to 131,072 spheres, r = 0.2 m), three n_sigma values, every output over
+    the 1 m ball.  Per size: time per evaluation, the pair kernel's time and
+    its roofline fraction by the method's count, dense-equivalent and
+    evaluated pairs per second."""
+    import torch
+    from workloads import config, mppi_walk_queries, room_scene
+    _, _, p = config("mppi_nav", 0.001)
+    m = len(p["n_sigma"])
+    opts = cs.reduce_opts(k=p["k"], tau=p["tau"], r_nbr=p["r_nbr"], d_max=p["d_max"], gamma=p["gamma"],
+                          s_min=p["s_min"])
+    res = []
+    for n in (250_000, 1_000_000, 4_000_000):
+        log(f"bench: sizes, {n} Gaussians")
+        sc = room_scene(n, seed=2)
+        h = eng.load_scene(sc, floater_opacity_max=p["alpha_f"], floater_extent_min=p["extent_f"])
+        n_kept, _ = cs.csplat_scene_info(h)
+        eng.set_conservatism(p["n_sigma"])
+        for rollouts in (256, 1024, 4096):
+            qs = mppi_walk_queries(rollouts, 32, seed=102)
+            c = torch.from_numpy(qs.centers).cuda()
+            r = torch.from_numpy(qs.radii).cuda()
+            dt, st, _, o = _timed(cs, eng, h, c, r, opts, ("label", "count", "min", "softmin", "cost", "nbr"),
+                                  reps=10)
+            k_s = st["kernel_ms"] / 1e3
+            nbr = int(o["nbr"].astype(np.int64).sum())
+            ev = int(st["kernel_pairs"])
+            tight = OPS_ALL_PAIRS * ev + (OPS_IN_BALL_SHARED + OPS_IN_BALL_PER_NSIGMA * m) * nbr
+            res.append({"n_kept": int(n_kept), "queries": int(qs.q), "splits": int(st["splits"]),
+                        "ms_per_step": dt * 1e3, "kernel_ms": k_s * 1e3,
+                        "roofline_frac": ops_full_in_ball(m) * nbr / k_s / PEAK_VALU,
+                        "roofline_frac_tight_count": tight / k_s / PEAK_VALU, "evaluated_pairs": ev,
+                        "dense_pair_evals_per_s": qs.q * n_kept / dt,
+                        "evaluated_pair_evals_per_s": int(st["kernel_pairs"]) / dt,
+                        "in_ball_pairs": nbr})
+        cs.csplat_scene_free(h)
+    return {"workload": "mppi_nav law at other sizes: room scenes x rollouts x 32 steps x 1 sphere r = 0.2 m, "
+                        "n_sigma {0,1,2}, ball 1 m, every output",
+            "note": "roofline_frac prices a transcendental at 4 VALU slots (the method's count); the kernels "
+                    "issue them in 2, so by that count a launch dominated by in-ball pairs can exceed 1; "
+                    "roofline_frac_tight_count is the kernel's own count",
+            "runs": res}
 
 
 def serving(cs, eng, sc_nav, h_nav, n_requests, reduced):
