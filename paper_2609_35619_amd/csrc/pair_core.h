@@ -1982,7 +1982,10 @@ struct SplitPlan {
     int block;  // threads of a work item
 };
 
-inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool ball, bool ell = false)
+// dense: a label walk without culling (every pair), which has no walk to
+// amortise and keeps splits of 16 chunks.
+inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool ball, bool ell = false,
+                            bool dense = false)
 {
     SplitPlan sp;
     sp.qpl = full ? kQplFull : kQplLabels;
@@ -2007,7 +2010,7 @@ inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool bal
         // 0.14 ms with 32 of 122 (256 chunks: 0.18).  Labels: 4,096 spheres
         // on a 200k-Gaussian scene 0.24 ms with 16 chunks per split, 0.15
         // with 64, 0.20 with 128.
-        const int min_chunks = full ? (tasks ? kMinSplitChunksFull : 16) : kMinSplitChunksLabels;
+        const int min_chunks = full ? (tasks ? kMinSplitChunksFull : 16) : dense ? 16 : kMinSplitChunksLabels;
         S = std::max(1, std::min(S, n_chunks / min_chunks));
     }
     // full outputs as tasks over many splits merge the splits of a block's

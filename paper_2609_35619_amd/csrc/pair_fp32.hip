@@ -302,7 +302,7 @@ csplat_status min_search(csplat_ctx *ctx, const csplat_scene *sc, int q, const f
     // culled: skip what lies beyond the thresholds' reach)
     auto pass = [&](bool first, int nq, const float *pc, const float *pr, const float *pt, Part &part, int &S,
                     bool culled) {
-        SplitPlan sp = split_plan(ctx_target_blocks(ctx), nq, n, false, false);
+        SplitPlan sp = split_plan(ctx_target_blocks(ctx), nq, n, false, false, false, !culled);
         S = std::max(sp.S, 1);
         const size_t words = (size_t)S * nq * M * (first && want_count ? 2 : 1);
         hipError_t pe = ctx->partial.reserve(words * 4);
@@ -449,7 +449,7 @@ csplat_status fp32_eval(csplat_ctx *ctx, const csplat_scene *sc, int64_t q64, co
     const bool ball = std::isfinite(p.rn2);
     // culling applies to labels, and to full outputs over a finite ball
     const bool cull = p.cull && n > 0 && sc->cull && (!full || ball);
-    SplitPlan sp = split_plan(ctx_target_blocks(ctx), q, n, full, ball, ell);
+    SplitPlan sp = split_plan(ctx_target_blocks(ctx), q, n, full, ball, ell, !cull);
     const int M = p.m;
     // the sorted queries and the partials: the context's buffers, or the
     // caller's workspace (sort first, then as many splits as fit)
