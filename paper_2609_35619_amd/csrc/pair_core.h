@@ -1961,6 +1961,7 @@ constexpr int kFullGroup = CSPLAT_FULL_GROUP;  // splits merged per full-output 
 constexpr int kMaxSplitChunks = 2048;          // culling chunks per split of a full-output plan, at most
 constexpr int kMinSplitChunksFull = 128;       // ... and at least, for full outputs as tasks (when there are that many)
 constexpr int kMinSplitChunksLabels = 64;      // culling chunks per split of a label plan, at least (idem)
+constexpr int kMinSplitChunksWave = 4;         // ... of a full-output plan on the wave walk, at least (idem)
 constexpr int kGroupMinSplits = 16;            // splits from which full-output work items fold several
 static_assert(kFullGroup >= 1 && kFullGroup <= kFullTaskBlock / 64 && (kFullTaskBlock / 64) % kFullGroup == 0,
               "the groups of a work item divide its waves");
@@ -2003,14 +2004,18 @@ inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool bal
         // device (a serving step lasts as long as its slowest item)
         if (full) S = std::max(S, (n_chunks + kMaxSplitChunks - 1) / kMaxSplitChunks);
         // at least 128 chunks per split for full outputs as tasks and 64 for
-        // labels (16 for the wave walk): a work item carries a fixed cost
-        // (query state, the walk's first metadata loads, the partial record)
-        // that short splits repeat.  Full outputs: a batch of 8,192 spheres
-        // took 0.40 ms on a 250k-Gaussian scene with 244 splits of 16 chunks,
-        // 0.14 ms with 32 of 122 (256 chunks: 0.18).  Labels: 4,096 spheres
-        // on a 200k-Gaussian scene 0.24 ms with 16 chunks per split, 0.15
-        // with 64, 0.20 with 128.
-        const int min_chunks = full ? (tasks ? kMinSplitChunksFull : 16) : dense ? 16 : kMinSplitChunksLabels;
+        // labels: a task work item carries a fixed cost (query state, the
+        // walk's first metadata loads, the partial record) that short splits
+        // repeat.  Full outputs: a batch of 8,192 spheres took 0.40 ms on a
+        // 250k-Gaussian scene with 244 splits of 16 chunks, 0.14 ms with 32
+        // of 122 (256 chunks: 0.18).  Labels: 4,096 spheres on a
+        // 200k-Gaussian scene 0.24 ms with 16 chunks per split, 0.15 with 64,
+        // 0.20 with 128.  The wave walk (full outputs over every Gaussian)
+        // has no task set-up and wants many splits over a small scene (10k
+        // Gaussians x 4,096 spheres: kernel 0.124 ms with 16 chunks per
+        // split, 0.060 with 4); dense label walks keep 16.
+        const int min_chunks = full ? (tasks ? kMinSplitChunksFull : kMinSplitChunksWave)
+                                    : dense ? 16 : kMinSplitChunksLabels;
         S = std::max(1, std::min(S, n_chunks / min_chunks));
     }
     // full outputs as tasks over many splits merge the splits of a block's
