@@ -1962,6 +1962,7 @@ constexpr int kMaxSplitChunks = 2048;          // culling chunks per split of a 
 constexpr int kMinSplitChunksFull = 128;       // ... and at least, for full outputs as tasks (when there are that many)
 constexpr int kMinSplitChunksLabels = 64;      // culling chunks per split of a label plan, at least (idem)
 constexpr int kMinSplitChunksWave = 4;         // ... of a full-output plan on the wave walk, at least (idem)
+constexpr int kMinFullSplits = 32;             // splits of a full-output task plan, at least (see split_plan)
 constexpr int kGroupMinSplits = 16;            // splits from which full-output work items fold several
 static_assert(kFullGroup >= 1 && kFullGroup <= kFullTaskBlock / 64 && (kFullTaskBlock / 64) % kFullGroup == 0,
               "the groups of a work item divide its waves");
@@ -2003,6 +2004,16 @@ inline SplitPlan split_plan(int target_blocks, int q, int n, bool full, bool bal
         // milliseconds of one block even when the queries alone fill the
         // device (a serving step lasts as long as its slowest item)
         if (full) S = std::max(S, (n_chunks + kMaxSplitChunks - 1) / kMaxSplitChunks);
+        // full outputs as tasks: at least kMinFullSplits splits while their
+        // partial records stay within 256 MiB (S / 4 records of up to 52 B
+        // per query): a large batch would otherwise get a few long splits,
+        // whose items balance badly (the manipulation batch, 393,216 spheres
+        // on 500k Gaussians: 6 splits 16.5 ms, 16 splits 15.3 ms, 32 splits
+        // 11.7 ms, 64 splits 12.4 ms)
+        if (full && tasks) {
+            const int64_t mem_cap = (int64_t(256) << 20) / (13 * (int64_t)std::max(q, 1));
+            S = std::max(S, (int)std::min<int64_t>(kMinFullSplits, mem_cap));
+        }
         // at least 128 chunks per split for full outputs as tasks and 64 for
         // labels: a task work item carries a fixed cost (query state, the
         // walk's first metadata loads, the partial record) that short splits
