@@ -116,6 +116,99 @@ __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride
     idx[j] = j;
 }
 
+// Batches of 2 to kSortRuns runs of kSortRun queries are sorted by two
+// kernels instead of the library's radix sort (which, at these sizes, is a
+// block sort followed by one launch per merge level: about 50 us for 32,768
+// keys):
+//  1. each run of kSortRun consecutive queries is sorted in LDS (a block
+//     radix sort, stable), keys and indices in place;
+//  2. a query at position p of run r goes to p plus, for every other run,
+//     the number of its keys below the query's key (runs after r) or at most
+//     equal to it (runs before r): equal keys keep their input order, so the
+//     permutation is the one a stable sort of all keys gives.  A block holds
+//     64 consecutive queries of one run; its wave w binary-searches runs w,
+//     w + 16, ... for all 64 (neighbouring keys share the search's cache
+//     lines), and the counts are summed in LDS.
+// Measured (wall time per evaluation): the navigation batch of 32,768
+// spheres 0.998 -> 0.987 ms, the paper-shaped batch of 32,768 0.428 -> 0.423
+// ms.  A single run stays with the library (its one-block sort: 0.150 against
+// 0.160 ms for 4,096 spheres), and so do batches over 16 runs, where the
+// searches cost more than the library's merge levels (262,144 spheres: 1.249
+// against 1.223 ms with up to 128 runs; 8-bit radix passes no better).
+constexpr int kSortThreads = 256, kSortItems = 16;
+constexpr int kSortRun = kSortThreads * kSortItems;  // 4,096 keys per run
+constexpr int kMergeWaves = 16;                       // 1,024 threads per merge block
+#ifndef CSPLAT_SORT_MAX_RUNS
+#define CSPLAT_SORT_MAX_RUNS 16
+#endif
+#ifndef CSPLAT_SORT_RADIX_BITS
+#define CSPLAT_SORT_RADIX_BITS 4
+#endif
+constexpr int kSortRuns = CSPLAT_SORT_MAX_RUNS;       // at most kSortRuns / 16 searches per wave and query
+constexpr uint32_t kSortPad = (1u << 30) - 1u;        // the largest key: padding sorts last (after equal keys)
+
+__global__ void __launch_bounds__(kSortThreads) run_sort_kernel(int q, const uint32_t *__restrict__ code,
+                                                                uint32_t *__restrict__ code2,
+                                                                int32_t *__restrict__ idx)
+{
+    using Sort = hipcub::BlockRadixSort<uint32_t, kSortThreads, kSortItems, int32_t, CSPLAT_SORT_RADIX_BITS>;
+    __shared__ typename Sort::TempStorage tmp;
+    const int base = blockIdx.x * kSortRun + (int)threadIdx.x * kSortItems;  // blocked arrangement
+    uint32_t k[kSortItems];
+    int32_t v[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int j = base + i;
+        k[i] = j < q ? code[j] : kSortPad;
+        v[i] = j;
+    }
+    Sort(tmp).Sort(k, v, 0, 30);
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (base + i < q) {  // the run's real keys fill its first positions
+            code2[base + i] = k[i];
+            idx[base + i] = v[i];
+        }
+}
+
+__global__ void __launch_bounds__(64 * kMergeWaves) run_merge_kernel(int q, int n_runs,
+                                                                     const uint32_t *__restrict__ code2,
+                                                                     const int32_t *__restrict__ idx,
+                                                                     int32_t *__restrict__ perm)
+{
+    __shared__ int s_cnt[kMergeWaves][64];
+    const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+    const int g = blockIdx.x * 64 + lane;  // position in the run-sorted array
+    const int gg = g < q ? g : q - 1;
+    const int r = gg / kSortRun;
+    const uint32_t key = code2[gg];
+    int cnt = 0;
+    for (int x = w; x < n_runs; x += kMergeWaves) {
+        if (x == r) {
+            cnt += gg - r * kSortRun;
+            continue;
+        }
+        const uint32_t *run = code2 + (size_t)x * kSortRun;
+        int lo = 0, hi = min(kSortRun, q - x * kSortRun);
+        const bool upper = x < r;  // runs before r: keys <= key go first
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const uint32_t km = run[mid];
+            if (upper ? km <= key : km < key) lo = mid + 1;
+            else hi = mid;
+        }
+        cnt += lo;
+    }
+    s_cnt[w][lane] = cnt;
+    __syncthreads();
+    if (w == 0 && g < q) {
+        int rank = 0;
+#pragma unroll
+        for (int k = 0; k < kMergeWaves; ++k) rank += s_cnt[k][lane];
+        perm[rank] = idx[g];
+    }
+}
+
 __global__ void query_gather_kernel(int q, const int32_t *__restrict__ perm, const float *__restrict__ c,
                                     const float *__restrict__ r, float *__restrict__ sc, float *__restrict__ sr)
 {
@@ -236,7 +329,15 @@ csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const 
                                           make_float3(sc->box_scale[0], sc->box_scale[1], sc->box_scale[2]), code,
                                           idx, counter);
     CSPLAT_HIP(hipGetLastError());
-    CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(b + off_tmp, tbytes, code, code2, idx, perm, q, 0, 30, st));
+    if (q > kSortRun && q <= kSortRuns * kSortRun) {
+        const int n_runs = (q + kSortRun - 1) / kSortRun;
+        run_sort_kernel<<<(unsigned)n_runs, kSortThreads, 0, st>>>(q, code, code2, idx);
+        CSPLAT_HIP(hipGetLastError());
+        run_merge_kernel<<<(unsigned)((q + 63) / 64), 64 * kMergeWaves, 0, st>>>(q, n_runs, code2, idx, perm);
+        CSPLAT_HIP(hipGetLastError());
+    } else {
+        CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(b + off_tmp, tbytes, code, code2, idx, perm, q, 0, 30, st));
+    }
     if (ell)
         body_gather_kernel<<<(unsigned)(((size_t)q * 4 + 255) / 256), 256, 0, st>>>(
             q, perm, reinterpret_cast<const float4 *>(centers), reinterpret_cast<float4 *>(sc_c));
