@@ -118,7 +118,7 @@ __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride
 
 // Batches of 2 to kSortRuns runs of kSortRun queries are sorted by two
 // kernels instead of the library's radix sort (which, at these sizes, is a
-// block sort followed by one launch per merge level: about 50 us for 32,768
+// block sort followed by one launch per merge level: about 43 us for 32,768
 // keys):
 //  1. each run of kSortRun consecutive queries is sorted in LDS (a block
 //     radix sort, stable), keys and indices in place;
@@ -129,17 +129,21 @@ __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride
 //     64 consecutive queries of one run; its wave w binary-searches runs w,
 //     w + 16, ... for all 64 (neighbouring keys share the search's cache
 //     lines), and the counts are summed in LDS.
-// Measured (wall time per evaluation): the navigation batch of 32,768
-// spheres 0.998 -> 0.987 ms, the paper-shaped batch of 32,768 0.428 -> 0.423
-// ms.  A single run stays with the library (its one-block sort: 0.150 against
-// 0.160 ms for 4,096 spheres), and so do batches over 16 runs, where the
-// searches cost more than the library's merge levels (262,144 spheres: 1.249
-// against 1.223 ms with up to 128 runs; 8-bit radix passes no better).
-constexpr int kSortThreads = 256, kSortItems = 16;
-constexpr int kSortRun = kSortThreads * kSortItems;  // 4,096 keys per run
+// Measured on 32,768 keys (kernel averages under the tracer, sort + merge):
+// runs of 4,096 keys 25.9 + 5.4 us, 2,048 14.6 + 5.6 us, 1,024 9.4 + 8.4 us
+// (8-bit radix passes no better); wall time per evaluation with runs of
+// 1,024: the navigation batch 0.995 -> 0.987 ms, the paper-shaped batches of
+// 32,768 and 4,096 spheres 0.429 -> 0.412 ms and 0.150 -> 0.147 ms.  Larger
+// batches stay with the library, whose merge levels cost less than the
+// searches there (262,144 spheres in runs of 4,096: 1.249 against 1.223 ms).
+#ifndef CSPLAT_SORT_ITEMS
+#define CSPLAT_SORT_ITEMS 4
+#endif
+constexpr int kSortThreads = 256, kSortItems = CSPLAT_SORT_ITEMS;
+constexpr int kSortRun = kSortThreads * kSortItems;  // keys per run
 constexpr int kMergeWaves = 16;                       // 1,024 threads per merge block
 #ifndef CSPLAT_SORT_MAX_RUNS
-#define CSPLAT_SORT_MAX_RUNS 16
+#define CSPLAT_SORT_MAX_RUNS 64
 #endif
 #ifndef CSPLAT_SORT_RADIX_BITS
 #define CSPLAT_SORT_RADIX_BITS 4
