@@ -101,6 +101,15 @@ csplat_status launch_m(csplat_ctx *ctx, bool full, bool ball, bool cull, const L
 
 // Hilbert key of each query centre on the scene's grid (the scene's curve);
 // thread 0 also clears the pair kernel's task counter.
+__device__ __forceinline__ uint32_t query_key(const float *__restrict__ c, int stride, float3 lo, float3 scale, int j)
+{
+    const float *cj = c + (size_t)stride * j;
+    const float fx = (cj[0] - lo.x) * scale.x, fy = (cj[1] - lo.y) * scale.y, fz = (cj[2] - lo.z) * scale.z;
+    const uint32_t ix = (uint32_t)fminf(fmaxf(fx, 0.f), 1023.f), iy = (uint32_t)fminf(fmaxf(fy, 0.f), 1023.f),
+                   iz = (uint32_t)fminf(fmaxf(fz, 0.f), 1023.f);
+    return hilbert_key(ix, iy, iz);
+}
+
 __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride, float3 lo, float3 scale,
                                   uint32_t *__restrict__ code, int32_t *__restrict__ idx,
                                   unsigned long long *__restrict__ counter)
@@ -108,11 +117,7 @@ __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j == 0) *counter = 0;
     if (j >= q) return;
-    const float *cj = c + (size_t)stride * j;
-    const float fx = (cj[0] - lo.x) * scale.x, fy = (cj[1] - lo.y) * scale.y, fz = (cj[2] - lo.z) * scale.z;
-    const uint32_t ix = (uint32_t)fminf(fmaxf(fx, 0.f), 1023.f), iy = (uint32_t)fminf(fmaxf(fy, 0.f), 1023.f),
-                   iz = (uint32_t)fminf(fmaxf(fz, 0.f), 1023.f);
-    code[j] = hilbert_key(ix, iy, iz);
+    code[j] = query_key(c, stride, lo, scale, j);
     idx[j] = j;
 }
 
@@ -121,14 +126,15 @@ __global__ void query_code_kernel(int q, const float *__restrict__ c, int stride
 // block sort followed by one launch per merge level: about 43 us for 32,768
 // keys):
 //  1. each run of kSortRun consecutive queries is sorted in LDS (a block
-//     radix sort, stable), keys and indices in place;
+//     radix sort, stable), its keys computed on the way in;
 //  2. a query at position p of run r goes to p plus, for every other run,
 //     the number of its keys below the query's key (runs after r) or at most
 //     equal to it (runs before r): equal keys keep their input order, so the
 //     permutation is the one a stable sort of all keys gives.  A block holds
 //     64 consecutive queries of one run; its wave w binary-searches runs w,
 //     w + 16, ... for all 64 (neighbouring keys share the search's cache
-//     lines), and the counts are summed in LDS.
+//     lines), the counts are summed in LDS, and the query's record is
+//     gathered to its rank.
 // Measured on 32,768 keys (kernel averages under the tracer, sort + merge):
 // runs of 4,096 keys 25.9 + 5.4 us, 2,048 14.6 + 5.6 us, 1,024 9.4 + 8.4 us
 // (8-bit radix passes no better); wall time per evaluation with runs of
@@ -149,24 +155,29 @@ constexpr int kMergeWaves = 16;                       // 1,024 threads per merge
 #define CSPLAT_SORT_RADIX_BITS 4
 #endif
 constexpr int kSortRuns = CSPLAT_SORT_MAX_RUNS;       // at most kSortRuns / 16 searches per wave and query
-constexpr uint32_t kSortPad = (1u << 30) - 1u;        // the largest key: padding sorts last (after equal keys)
+constexpr uint32_t kSortPad = 1u << 30;               // above every 30-bit key: padding sorts last
 
-__global__ void __launch_bounds__(kSortThreads) run_sort_kernel(int q, const uint32_t *__restrict__ code,
+// (the keys are computed here, as query_code_kernel computes them; thread 0
+// of block 0 also clears the pair kernel's task counter)
+__global__ void __launch_bounds__(kSortThreads) run_sort_kernel(int q, const float *__restrict__ c, int stride,
+                                                                float3 lo, float3 scale,
                                                                 uint32_t *__restrict__ code2,
-                                                                int32_t *__restrict__ idx)
+                                                                int32_t *__restrict__ idx,
+                                                                unsigned long long *__restrict__ counter)
 {
     using Sort = hipcub::BlockRadixSort<uint32_t, kSortThreads, kSortItems, int32_t, CSPLAT_SORT_RADIX_BITS>;
     __shared__ typename Sort::TempStorage tmp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
     const int base = blockIdx.x * kSortRun + (int)threadIdx.x * kSortItems;  // blocked arrangement
     uint32_t k[kSortItems];
     int32_t v[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const int j = base + i;
-        k[i] = j < q ? code[j] : kSortPad;
+        k[i] = j < q ? query_key(c, stride, lo, scale, j) : kSortPad;
         v[i] = j;
     }
-    Sort(tmp).Sort(k, v, 0, 30);
+    Sort(tmp).Sort(k, v, 0, 31);  // 31 bits: the padding's key among them
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i)
         if (base + i < q) {  // the run's real keys fill its first positions
@@ -175,10 +186,16 @@ __global__ void __launch_bounds__(kSortThreads) run_sort_kernel(int q, const uin
         }
 }
 
+// (each query's record is gathered to its rank here: centre and radius, or
+// the 16-float body record when sc_r is NULL)
 __global__ void __launch_bounds__(64 * kMergeWaves) run_merge_kernel(int q, int n_runs,
                                                                      const uint32_t *__restrict__ code2,
                                                                      const int32_t *__restrict__ idx,
-                                                                     int32_t *__restrict__ perm)
+                                                                     int32_t *__restrict__ perm,
+                                                                     const float *__restrict__ src_c,
+                                                                     const float *__restrict__ src_r,
+                                                                     float *__restrict__ sc_c,
+                                                                     float *__restrict__ sc_r)
 {
     __shared__ int s_cnt[kMergeWaves][64];
     const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
@@ -209,7 +226,19 @@ __global__ void __launch_bounds__(64 * kMergeWaves) run_merge_kernel(int q, int 
         int rank = 0;
 #pragma unroll
         for (int k = 0; k < kMergeWaves; ++k) rank += s_cnt[k][lane];
-        perm[rank] = idx[g];
+        const int i = idx[g];
+        perm[rank] = i;
+        if (sc_r) {
+            sc_c[3 * rank] = src_c[3 * i];
+            sc_c[3 * rank + 1] = src_c[3 * i + 1];
+            sc_c[3 * rank + 2] = src_c[3 * i + 2];
+            sc_r[rank] = src_r[i];
+        } else {
+            const float4 *src = reinterpret_cast<const float4 *>(src_c) + (size_t)i * (kBodyFloats / 4);
+            float4 *dst = reinterpret_cast<float4 *>(sc_c) + (size_t)rank * (kBodyFloats / 4);
+#pragma unroll
+            for (int k = 0; k < kBodyFloats / 4; ++k) dst[k] = src[k];
+        }
     }
 }
 
@@ -328,26 +357,28 @@ csplat_status sort_bodies(csplat_ctx *ctx, const csplat_scene *sc, int q, const 
     float *sc_c = reinterpret_cast<float *>(b + off_c), *sc_r = reinterpret_cast<float *>(b + off_r);
     auto *counter = reinterpret_cast<unsigned long long *>(b + off_cnt);
     const unsigned qb = (unsigned)((q + 255) / 256);
-    query_code_kernel<<<qb, 256, 0, st>>>(q, centers, ell ? kBodyFloats : 3,
-                                          make_float3(sc->box_lo[0], sc->box_lo[1], sc->box_lo[2]),
-                                          make_float3(sc->box_scale[0], sc->box_scale[1], sc->box_scale[2]), code,
-                                          idx, counter);
-    CSPLAT_HIP(hipGetLastError());
+    const int stride = ell ? kBodyFloats : 3;
+    const float3 lo = make_float3(sc->box_lo[0], sc->box_lo[1], sc->box_lo[2]);
+    const float3 scale = make_float3(sc->box_scale[0], sc->box_scale[1], sc->box_scale[2]);
     if (q > kSortRun && q <= kSortRuns * kSortRun) {
+        // keys computed by the run sort, records gathered by the merge
         const int n_runs = (q + kSortRun - 1) / kSortRun;
-        run_sort_kernel<<<(unsigned)n_runs, kSortThreads, 0, st>>>(q, code, code2, idx);
+        run_sort_kernel<<<(unsigned)n_runs, kSortThreads, 0, st>>>(q, centers, stride, lo, scale, code2, idx, counter);
         CSPLAT_HIP(hipGetLastError());
-        run_merge_kernel<<<(unsigned)((q + 63) / 64), 64 * kMergeWaves, 0, st>>>(q, n_runs, code2, idx, perm);
+        run_merge_kernel<<<(unsigned)((q + 63) / 64), 64 * kMergeWaves, 0, st>>>(
+            q, n_runs, code2, idx, perm, centers, ell ? nullptr : radii, sc_c, ell ? nullptr : sc_r);
         CSPLAT_HIP(hipGetLastError());
     } else {
+        query_code_kernel<<<qb, 256, 0, st>>>(q, centers, stride, lo, scale, code, idx, counter);
+        CSPLAT_HIP(hipGetLastError());
         CSPLAT_HIP(hipcub::DeviceRadixSort::SortPairs(b + off_tmp, tbytes, code, code2, idx, perm, q, 0, 30, st));
+        if (ell)
+            body_gather_kernel<<<(unsigned)(((size_t)q * 4 + 255) / 256), 256, 0, st>>>(
+                q, perm, reinterpret_cast<const float4 *>(centers), reinterpret_cast<float4 *>(sc_c));
+        else
+            query_gather_kernel<<<qb, 256, 0, st>>>(q, perm, centers, radii, sc_c, sc_r);
+        CSPLAT_HIP(hipGetLastError());
     }
-    if (ell)
-        body_gather_kernel<<<(unsigned)(((size_t)q * 4 + 255) / 256), 256, 0, st>>>(
-            q, perm, reinterpret_cast<const float4 *>(centers), reinterpret_cast<float4 *>(sc_c));
-    else
-        query_gather_kernel<<<qb, 256, 0, st>>>(q, perm, centers, radii, sc_c, sc_r);
-    CSPLAT_HIP(hipGetLastError());
     out->c = sc_c;
     out->r = ell ? nullptr : sc_r;
     out->perm = perm;
