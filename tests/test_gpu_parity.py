@@ -238,16 +238,22 @@ def test_task_walk_queue_edges(cs, eng, oracle_mod, n_sigma):
 def test_query_order_and_crowded_cells(cs, eng, oracle_mod):
     """Queries are evaluated in the scene's curve order and scattered back:
     2,000 queries at one point (equal keys), queries outside the scene's box
-    (clamped to its edge cells) and uniform ones.  Parity with the oracle,
-    the same bits for the queries given in a shuffled order (a query's
-    results do not depend on which queries share its wave), and the same
-    bits on a repeat."""
-    _say("case: crowded cell, out-of-box and shuffled queries")
+    (clamped to its edge cells), 1,200 far beyond its eight corners (clamped
+    to the corner cells, one of which holds the curve's largest key; equal
+    keys spread over the sort's runs) and uniform ones.  Parity with the
+    oracle, the same bits for the queries given in a shuffled order (a
+    query's results do not depend on which queries share its wave), and the
+    same bits on a repeat."""
+    _say("case: crowded cell, out-of-box, corner and shuffled queries")
     sc, qs0, p = config("tiny", 0.5)
     rng = np.random.default_rng(5)
     same = np.tile(np.array([[1.0, 2.0, 1.0]], np.float32), (2000, 1))
     out_box = rng.uniform(-3.0, 7.0, (300, 3)).astype(np.float32)
-    centers = np.concatenate([same, out_box, qs0.centers[:700]]).astype(np.float32)
+    signs = np.array([[x, y, z] for x in (-1, 1) for y in (-1, 1) for z in (-1, 1)], np.float32)
+    corners = np.repeat(signs * 50.0 + 2.0, 150, axis=0)
+    corners = corners[rng.permutation(corners.shape[0])]
+    centers = np.concatenate([same[:1000], corners[:600], out_box, same[1000:], qs0.centers[:700],
+                              corners[600:]]).astype(np.float32)
     radii = rng.uniform(0.05, 0.3, centers.shape[0]).astype(np.float32)
     qs = Queries(centers, radii)
     p = dict(p, k=1, tau=0.1, r_nbr=0.6)
